@@ -1,0 +1,211 @@
+// Device generators: the same Kronecker and Chung-Lu tuples as the host
+// generators (same counter-based draws), turned into the canonical undirected
+// CSR on the GPU.  Used to build the large graphs quickly; the canonical CSR
+// is unique for a tuple multiset, so it equals the host result bit for bit.
+// The sort and unique steps use rocPRIM: this is input preparation, not part
+// of the traversal library.
+#include <string.h>
+#include <hip/hip_runtime.h>
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_select.hpp>
+#include <stdint.h>
+#include <stdio.h>
+#include <string>
+#include <vector>
+
+#include "gg_rng.h"
+
+static thread_local std::string g_err;
+
+#define GG_CHECK(x)                                                              \
+  do {                                                                           \
+    hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess) {                                                      \
+      g_err = std::string(#x) + ": " + hipGetErrorString(e_);                    \
+      goto fail;                                                                 \
+    }                                                                            \
+  } while (0)
+
+namespace {
+
+__global__ void kron_keys_kernel(gg_kron_t k, gg_perm_t p, int64_t m, int b, uint64_t* keys) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t sentinel = (uint64_t)p.n << b;
+  for (; e < m; e += stride) {
+    uint32_t u0, v0;
+    gg_kron_edge(k, e, &u0, &v0);
+    uint64_t u = (uint64_t)gg_perm_apply(p, u0);
+    uint64_t v = (uint64_t)gg_perm_apply(p, v0);
+    if (u == v) {
+      keys[2 * e] = sentinel;
+      keys[2 * e + 1] = sentinel;
+    } else {
+      keys[2 * e] = (u << b) | v;
+      keys[2 * e + 1] = (v << b) | u;
+    }
+  }
+}
+
+__global__ void cl_keys_kernel(uint64_t key, gg_perm_t p, const double* cdf, int64_t ncore,
+                               int64_t m, int b, uint64_t* keys) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t sentinel = (uint64_t)p.n << b;
+  for (; e < m; e += stride) {
+    uint64_t u = (uint64_t)gg_perm_apply(p, gg_cl_draw(key, 2 * (uint64_t)e, cdf, ncore));
+    uint64_t v = (uint64_t)gg_perm_apply(p, gg_cl_draw(key, 2 * (uint64_t)e + 1, cdf, ncore));
+    if (u == v) {
+      keys[2 * e] = sentinel;
+      keys[2 * e + 1] = sentinel;
+    } else {
+      keys[2 * e] = (u << b) | v;
+      keys[2 * e + 1] = (v << b) | u;
+    }
+  }
+}
+
+// keys: sorted unique (row << b | col) with the sentinel possibly last.
+__global__ void csr_from_keys_kernel(const uint64_t* keys, int64_t nnz, int64_t n, int b,
+                                     int64_t* off, int32_t* cols) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const uint64_t mask = (1ull << b) - 1ull;
+  for (; i <= nnz; i += stride) {
+    int64_t s = (i < nnz) ? (int64_t)(keys[i] >> b) : n;
+    int64_t prev = (i == 0) ? -1 : (int64_t)(keys[i - 1] >> b);
+    for (int64_t v = prev + 1; v <= s; ++v) off[v] = i;
+    if (i < nnz) cols[i] = (int32_t)(keys[i] & mask);
+  }
+}
+
+int launch_blocks(int64_t work) {
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+// Sort + unique + CSR assembly over 2m keys already in `keys`.
+int64_t finish_csr(uint64_t* keys, int64_t m2, int64_t n, int b, int64_t* off, int32_t* cols,
+                   int64_t cols_cap, hipStream_t stream) {
+  uint64_t* keys2 = nullptr;
+  void* tmp = nullptr;
+  size_t tmp_bytes = 0, tmp2 = 0;
+  int64_t* d_count = nullptr;
+  int64_t h_count = 0, nnz = 0;
+  uint64_t h_last = 0;
+  const uint64_t sentinel = (uint64_t)n << b;
+  GG_CHECK(hipMalloc(&keys2, sizeof(uint64_t) * (m2 > 0 ? m2 : 1)));
+  GG_CHECK(hipMalloc(&d_count, sizeof(int64_t)));
+  if (m2 > 0) {
+    GG_CHECK(rocprim::radix_sort_keys(nullptr, tmp_bytes, keys, keys2, (size_t)m2, 0u,
+                                      (unsigned)(2 * b + 1), stream));
+    GG_CHECK(rocprim::unique(nullptr, tmp2, keys2, keys, d_count, (size_t)m2,
+                             rocprim::equal_to<uint64_t>(), stream));
+    if (tmp2 > tmp_bytes) tmp_bytes = tmp2;
+    GG_CHECK(hipMalloc(&tmp, tmp_bytes));
+    tmp2 = tmp_bytes;
+    GG_CHECK(rocprim::radix_sort_keys(tmp, tmp2, keys, keys2, (size_t)m2, 0u,
+                                      (unsigned)(2 * b + 1), stream));
+    tmp2 = tmp_bytes;
+    GG_CHECK(rocprim::unique(tmp, tmp2, keys2, keys, d_count, (size_t)m2,
+                             rocprim::equal_to<uint64_t>(), stream));
+    GG_CHECK(hipMemcpyAsync(&h_count, d_count, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    GG_CHECK(hipStreamSynchronize(stream));
+    nnz = h_count;
+    if (nnz > 0) {
+      GG_CHECK(hipMemcpyAsync(&h_last, keys + (nnz - 1), sizeof(uint64_t),
+                              hipMemcpyDeviceToHost, stream));
+      GG_CHECK(hipStreamSynchronize(stream));
+      if (h_last == sentinel) --nnz;
+    }
+  }
+  if (nnz > cols_cap) {
+    g_err = "cols capacity too small";
+    goto fail;
+  }
+  hipLaunchKernelGGL(csr_from_keys_kernel, dim3(launch_blocks(nnz + 1)), dim3(256), 0, stream,
+                     keys, nnz, n, b, off, cols);
+  GG_CHECK(hipGetLastError());
+  GG_CHECK(hipStreamSynchronize(stream));
+  (void)hipFree(keys2);
+  (void)hipFree(tmp);
+  (void)hipFree(d_count);
+  return nnz;
+fail:
+  if (keys2) (void)hipFree(keys2);
+  if (tmp) (void)hipFree(tmp);
+  if (d_count) (void)hipFree(d_count);
+  return -4;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gg_dev_last_error(void) { return g_err.c_str(); }
+
+// Kronecker graph with m = edgefactor * 2^scale tuples, canonical CSR written
+// to device buffers off (2^scale + 1) and cols (capacity cols_cap >= nnz).
+// Returns nnz, or a negative value on error.
+int64_t gg_dev_kron_csr(int scale, int64_t edgefactor, uint64_t seed, double A, double B,
+                        double C, int64_t* off, int32_t* cols, int64_t cols_cap, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (scale < 1 || scale > 30 || edgefactor < 0 || !off || !cols) {
+    g_err = "bad arguments";
+    return -1;
+  }
+  const int64_t n = (int64_t)1 << scale;
+  const int64_t m = edgefactor * n;
+  const int b = gg_bits_for(n);
+  uint64_t* keys = nullptr;
+  int64_t r;
+  gg_kron_t k = gg_kron_make(seed, scale, A, B, C);
+  gg_perm_t p = gg_perm_make(seed, n);
+  GG_CHECK(hipMalloc(&keys, sizeof(uint64_t) * (2 * m > 0 ? 2 * m : 1)));
+  hipLaunchKernelGGL(kron_keys_kernel, dim3(launch_blocks(m)), dim3(256), 0, stream, k, p, m, b,
+                     keys);
+  GG_CHECK(hipGetLastError());
+  r = finish_csr(keys, 2 * m, n, b, off, cols, cols_cap, stream);
+  (void)hipFree(keys);
+  return r;
+fail:
+  if (keys) (void)hipFree(keys);
+  return -4;
+}
+
+// Chung-Lu graph: m tuples drawn from the host-built cumulative table
+// (ncore entries), vertices relabelled over [0, n_total).
+int64_t gg_dev_cl_csr(int64_t ncore, int64_t n_total, int64_t m, uint64_t seed,
+                      const double* cdf_host, int64_t* off, int32_t* cols, int64_t cols_cap,
+                      void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (ncore < 2 || n_total < ncore || n_total > 0x7FFFFFFFll || m < 0 || !cdf_host || !off ||
+      !cols) {
+    g_err = "bad arguments";
+    return -1;
+  }
+  const int b = gg_bits_for(n_total);
+  uint64_t* keys = nullptr;
+  double* cdf = nullptr;
+  int64_t r;
+  gg_perm_t p = gg_perm_make(seed, n_total);
+  uint64_t key = gg_key(seed, GG_STREAM_CL);
+  GG_CHECK(hipMalloc(&cdf, sizeof(double) * ncore));
+  GG_CHECK(hipMemcpy(cdf, cdf_host, sizeof(double) * ncore, hipMemcpyHostToDevice));
+  GG_CHECK(hipMalloc(&keys, sizeof(uint64_t) * (2 * m > 0 ? 2 * m : 1)));
+  hipLaunchKernelGGL(cl_keys_kernel, dim3(launch_blocks(m)), dim3(256), 0, stream, key, p, cdf,
+                     ncore, m, b, keys);
+  GG_CHECK(hipGetLastError());
+  r = finish_csr(keys, 2 * m, n_total, b, off, cols, cols_cap, stream);
+  (void)hipFree(keys);
+  (void)hipFree(cdf);
+  return r;
+fail:
+  if (keys) (void)hipFree(keys);
+  if (cdf) (void)hipFree(cdf);
+  return -4;
+}
+
+}  // extern "C"

@@ -1,0 +1,418 @@
+/*
+ * CPU oracle -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, single-threaded, slow reference for the RCM-relabelled
+ * direction-optimizing BFS of "Fast and Efficient Parallel Breadth-First
+ * Search with Power-law Graph Transformation" (Jiang et al., PPoPP'21
+ * poster).  Only the tests, the package's smoke check and the benchmark's
+ * CPU-baseline leg may load it.  It shares no code with the GPU library.
+ *
+ * Graphs are canonical undirected CSR (section 3.1, Eq. 2): off[n+1] int64,
+ * cols[nnz] int32, every edge stored in both directions, rows ascending,
+ * no self-loops, no duplicates.  deg(v) = off[v+1] - off[v].
+ *
+ * Functions and the passages they follow:
+ *   orc_bandwidth         Eq. 1 (matrix bandwidth), in a given labelling.
+ *   orc_canonical_csr     section 3.1 / Eq. 2: CSR of the undirected edge set.
+ *   orc_rcm               Algorithm 3 (RCM) taken step by step: V+ sorted by
+ *                         (degree, id), per component a start of minimal
+ *                         (degree, id), neighbours appended in (degree, id)
+ *                         order, reversal, isolated vertices appended.
+ *   orc_bfs               Algorithms 1-2 output: hop distance from the source
+ *                         and the predecessor map (pi(s) = s, -1 when
+ *                         unreachable) with the minimum-label parent rule.
+ *   orc_level_counters    per-level frontier / unvisited sizes that drive the
+ *                         direction switch of Algorithm 2 and the work the
+ *                         bottom-up step of Algorithm 2 / 5 does.
+ *   orc_heuristic_schedule the alpha/beta direction rule (section 2.1 and
+ *                         "Parameter Tuning"), integer form.
+ *   orc_certify_bfs       O(nnz) certificate that (depth, parent) is the
+ *                         unique BFS result under the minimum-label rule.
+ *   orc_certify_rcm       O(nnz) certificate that a permutation is exactly
+ *                         the one Algorithm 3 produces.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 1: BW(A) = max { i - j : A_ij != 0, i > j }, with vertex v carrying
+ * label ell[v] (identity if ell is NULL). */
+int64_t orc_bandwidth(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* ell) {
+  int64_t bw = 0;
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t i = ell ? ell[v] : v;
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      int64_t j = ell ? ell[cols[e]] : cols[e];
+      if (i > j && i - j > bw) bw = i - j;
+    }
+  }
+  return bw;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Canonical CSR of the undirected edge set {{u, v} : (u, v) a tuple, u != v}.
+ * Writes off[n+1] and cols (capacity 2m); returns nnz. */
+static int cmp_u64(const void* a, const void* b) {
+  uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+  return (x > y) - (x < y);
+}
+
+int64_t orc_canonical_csr(int64_t n, int64_t m, const int32_t* src, const int32_t* dst,
+                          int64_t* off, int32_t* cols) {
+  uint64_t* pairs = (uint64_t*)malloc(sizeof(uint64_t) * (2 * m + 1));
+  int64_t np = 0;
+  for (int64_t i = 0; i < m; ++i) {
+    uint64_t u = (uint32_t)src[i], v = (uint32_t)dst[i];
+    if (u == v) continue;
+    pairs[np++] = (u << 32) | v;
+    pairs[np++] = (v << 32) | u;
+  }
+  qsort(pairs, (size_t)np, sizeof(uint64_t), cmp_u64);
+  int64_t nnz = 0;
+  for (int64_t v = 0; v <= n; ++v) off[v] = 0;
+  for (int64_t i = 0; i < np; ++i) {
+    if (i > 0 && pairs[i] == pairs[i - 1]) continue;
+    cols[nnz++] = (int32_t)(pairs[i] & 0xFFFFFFFFu);
+    off[(pairs[i] >> 32) + 1] += 1;
+  }
+  for (int64_t v = 0; v < n; ++v) off[v + 1] += off[v];
+  free(pairs);
+  return nnz;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 3.  The order "increasing degree" is read as increasing
+ * (degree, vertex id): ties between equal degrees go to the smaller id. */
+static const int64_t* g_sort_off; /* degree lookup for the comparator */
+
+static int cmp_deg_id(const void* a, const void* b) {
+  int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
+  int64_t dx = g_sort_off[x + 1] - g_sort_off[x];
+  int64_t dy = g_sort_off[y + 1] - g_sort_off[y];
+  if (dx != dy) return dx < dy ? -1 : 1;
+  return (x > y) - (x < y);
+}
+
+/* P[k] = original vertex that receives label k; perm[v] = label of v.
+ * Returns n+ = |V+|, the number of non-isolated vertices. */
+int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, int32_t* perm) {
+  g_sort_off = off;
+  /* V+: all non-isolated vertices, sorted by (degree, id). */
+  int32_t* vplus = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  int64_t nplus = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] > off[v]) vplus[nplus++] = (int32_t)v;
+  qsort(vplus, (size_t)nplus, sizeof(int32_t), cmp_deg_id);
+
+  char* visited = (char*)calloc((size_t)n + 1, 1);
+  int32_t* nb = NULL; /* scratch for sorted_neighbors */
+  int64_t nb_cap = 0;
+  int64_t min_index = 0, slow = 0, fast = 0;
+  while (slow < nplus) {
+    /* next unvisited vertex of minimal (degree, id) starts a component */
+    for (int64_t i = min_index; i < nplus; ++i) {
+      if (!visited[vplus[i]]) {
+        P[slow] = vplus[i];
+        visited[vplus[i]] = 1;
+        min_index = i + 1;
+        fast = slow + 1;
+        break;
+      }
+    }
+    /* explore the component, appending unvisited neighbours of P[slow] in
+     * increasing (degree, id) order */
+    while (slow < fast) {
+      int32_t u = P[slow];
+      int64_t d = off[u + 1] - off[u];
+      if (d > nb_cap) {
+        free(nb);
+        nb_cap = d;
+        nb = (int32_t*)malloc(sizeof(int32_t) * nb_cap);
+      }
+      memcpy(nb, cols + off[u], sizeof(int32_t) * d);
+      qsort(nb, (size_t)d, sizeof(int32_t), cmp_deg_id);
+      for (int64_t j = 0; j < d; ++j) {
+        if (!visited[nb[j]]) {
+          visited[nb[j]] = 1;
+          P[fast++] = nb[j];
+        }
+      }
+      slow++;
+    }
+  }
+  /* reverse, then append the isolated vertices in increasing id */
+  for (int64_t i = 0, j = nplus - 1; i < j; ++i, --j) {
+    int32_t t = P[i];
+    P[i] = P[j];
+    P[j] = t;
+  }
+  int64_t k = nplus;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] == off[v]) P[k++] = (int32_t)v;
+  for (int64_t i = 0; i < n; ++i) perm[P[i]] = (int32_t)i;
+  free(nb);
+  free(visited);
+  free(vplus);
+  return nplus;
+}
+
+/* ------------------------------------------------------------------------ */
+/* BFS result.  depth[v] = hop distance from root (-1 if unreachable);
+ * parent[root] = root; parent[v] = the neighbour u with depth[u] =
+ * depth[v] - 1 of smallest label ell[u] (identity labels if ell is NULL);
+ * parent[v] = -1 if unreachable.  Returns the number of levels (max depth+1).
+ */
+int32_t orc_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root,
+                const int32_t* ell, int32_t* depth, int32_t* parent) {
+  for (int64_t v = 0; v < n; ++v) {
+    depth[v] = -1;
+    parent[v] = -1;
+  }
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  int64_t head = 0, tail = 0;
+  depth[root] = 0;
+  queue[tail++] = root;
+  int32_t maxd = 0;
+  while (head < tail) {
+    int32_t u = queue[head++];
+    for (int64_t e = off[u]; e < off[u + 1]; ++e) {
+      int32_t w = cols[e];
+      if (depth[w] < 0) {
+        depth[w] = depth[u] + 1;
+        if (depth[w] > maxd) maxd = depth[w];
+        queue[tail++] = w;
+      }
+    }
+  }
+  free(queue);
+  for (int64_t v = 0; v < n; ++v) {
+    if (depth[v] <= 0) continue;
+    int32_t best = -1;
+    int64_t best_label = INT64_MAX;
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      int32_t u = cols[e];
+      if (depth[u] == depth[v] - 1) {
+        int64_t lab = ell ? ell[u] : u;
+        if (lab < best_label) {
+          best_label = lab;
+          best = u;
+        }
+      }
+    }
+    parent[v] = best;
+  }
+  parent[root] = root;
+  return maxd + 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Per-level counters for levels d = 0 .. nlev-1 (arrays of length nlev):
+ *   nf[d]  = |F_d|, F_d = {v : depth[v] = d}
+ *   mf[d]  = sum of deg over F_d
+ *   nu[d]  = |U_d|, U_d = {v in the swept set : depth[v] > d or unreached}
+ *   mu[d]  = sum of deg over U_d
+ *   ebu[d] = edges a bottom-up pass over U_d examines when every row is
+ *            scanned in increasing label order and stops at the first
+ *            neighbour in F_d: 1 + (number of neighbours of smaller label
+ *            than that neighbour), or deg(v) when there is none.
+ * The swept set is the first n_sweep vertices in label order (the
+ * non-isolated prefix after RCM, or every vertex without it). */
+void orc_level_counters(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* ell,
+                        int64_t n_sweep, const int32_t* depth, int32_t nlev, int64_t* nf,
+                        int64_t* mf, int64_t* nu, int64_t* mu, int64_t* ebu) {
+  for (int32_t d = 0; d < nlev; ++d) {
+    nf[d] = mf[d] = nu[d] = mu[d] = ebu[d] = 0;
+  }
+  for (int64_t v = 0; v < n; ++v) {
+    int64_t lab = ell ? ell[v] : v;
+    int64_t dv = depth[v];
+    int64_t deg = off[v + 1] - off[v];
+    if (dv >= 0 && dv < nlev) {
+      nf[dv] += 1;
+      mf[dv] += deg;
+    }
+    if (lab >= n_sweep) continue;
+    for (int32_t d = 0; d < nlev; ++d) {
+      if (dv >= 0 && dv <= d) continue; /* reached by level d */
+      nu[d] += 1;
+      mu[d] += deg;
+      /* bottom-up work on v at level d */
+      int64_t first = INT64_MAX;
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        int32_t w = cols[e];
+        int64_t lw = ell ? ell[w] : w;
+        if (depth[w] == d && lw < first) first = lw;
+      }
+      if (first == INT64_MAX) {
+        ebu[d] += deg;
+      } else {
+        int64_t smaller = 0;
+        for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+          int32_t w = cols[e];
+          int64_t lw = ell ? ell[w] : w;
+          if (lw < first) smaller++;
+        }
+        ebu[d] += 1 + smaller;
+      }
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direction rule (0 = top-down, 1 = bottom-up) for levels 0 .. nlev-1, where
+ * level d expands F_d.  Level 0 is top-down.  For d >= 1, with the counters
+ * of F_d and U_d:
+ *   top-down  -> bottom-up  if mf[d] * alpha > mu[d]
+ *   bottom-up -> top-down   if nf[d] * beta < n_sweep and nf[d] < nf[d-1]
+ *   otherwise the direction is kept. */
+void orc_heuristic_schedule(int32_t nlev, const int64_t* nf, const int64_t* mf,
+                            const int64_t* mu, int64_t n_sweep, int64_t alpha, int64_t beta,
+                            int8_t* dir) {
+  if (nlev <= 0) return;
+  dir[0] = 0;
+  for (int32_t d = 1; d < nlev; ++d) {
+    int8_t prev = dir[d - 1];
+    int8_t next = prev;
+    if (prev == 0) {
+      if (mf[d] * alpha > mu[d]) next = 1;
+    } else {
+      if (nf[d] * beta < n_sweep && nf[d] < nf[d - 1]) next = 0;
+    }
+    dir[d] = next;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* BFS certificate.  Returns 0 when (depth, parent) is the BFS result from
+ * root under the minimum-label parent rule, else a negative code naming the
+ * first failed rule:
+ *   -1 root entries wrong            -2 an edge joins reached and unreached
+ *   -3 an edge spans > 1 level        -4 unreached vertex with a parent
+ *   -5 parent not a neighbour one level up
+ *   -6 a neighbour one level up has a smaller label than the parent
+ *   -7 depth/parent out of range.
+ * Rules: the parent chain gives depth >= distance; the edge rule gives
+ * depth <= distance; so depth is the distance and the reached set is the
+ * component, and the parent is the unique minimum. */
+int32_t orc_certify_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root,
+                        const int32_t* ell, const int32_t* depth, const int32_t* parent) {
+  if (root < 0 || root >= n) return -7;
+  if (depth[root] != 0 || parent[root] != root) return -1;
+  for (int64_t v = 0; v < n; ++v) {
+    int32_t dv = depth[v];
+    if (dv < -1 || parent[v] < -1 || parent[v] >= n) return -7;
+    if (dv == -1 && parent[v] != -1) return -4;
+    if (dv == 0 && v != root) return -1;
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      int32_t dw = depth[cols[e]];
+      if ((dv < 0) != (dw < 0)) return -2;
+      if (dv >= 0 && (dv - dw > 1 || dw - dv > 1)) return -3;
+    }
+    if (dv > 0) {
+      int32_t p = parent[v];
+      if (p < 0 || depth[p] != dv - 1) return -5;
+      int found = 0;
+      int64_t lp = ell ? ell[p] : p;
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        int32_t w = cols[e];
+        if (w == p) found = 1;
+        if (depth[w] == dv - 1) {
+          int64_t lw = ell ? ell[w] : w;
+          if (lw < lp) return -6;
+        }
+      }
+      if (!found) return -5;
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* RCM certificate.  Returns 0 iff perm is exactly Algorithm 3's permutation
+ * (under the (degree, id) reading of its orderings), else a negative code.
+ *
+ * Let n+ = |V+|, cm(v) = n+ - 1 - perm[v] the label before reversal and
+ * order[k] the vertex with cm = k.  Algorithm 3 labels vertex k as follows:
+ * if some already-labelled vertex still has an unlabelled neighbour, take the
+ * smallest label j with one, and give k to the unlabelled neighbour of
+ * order[j] with the least (degree, id); otherwise k starts a new component
+ * and goes to the unlabelled vertex of least (degree, id).  Equivalently,
+ * with p(v) = min cm over N(v) and M(k) = max cm over the neighbours of
+ * labels < k:
+ *   (a) M(k) < k  (nothing pending): order[k] has the least (degree, id)
+ *       among labels >= k;
+ *   (b) M(k) >= k: p(order[k]) < k, and over these "appended" vertices the
+ *       key (p(v), degree, id) strictly increases with the label.
+ *   (c) isolated vertices hold labels n+ .. n-1 in increasing id.
+ * Codes: -1 not a bijection, -2 isolated placement, -3 start not minimal,
+ *        -4 appended vertex without an earlier neighbour, -5 appended order. */
+int32_t orc_certify_rcm(int64_t n, const int64_t* off, const int32_t* cols,
+                        const int32_t* perm) {
+  int32_t rc = 0;
+  int32_t* order = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  int32_t* cm = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  uint64_t* sufmin = (uint64_t*)malloc(sizeof(uint64_t) * (n + 2));
+  for (int64_t k = 0; k < n; ++k) order[k] = -1;
+  for (int64_t v = 0; v < n; ++v) {
+    if (perm[v] < 0 || perm[v] >= n || order[perm[v]] != -1) { rc = -1; goto done; }
+    order[perm[v]] = (int32_t)v;
+  }
+  int64_t nplus = 0;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] > off[v]) nplus++;
+  {
+    int64_t k = nplus;
+    for (int64_t v = 0; v < n; ++v) {
+      if (off[v + 1] == off[v]) {
+        if (perm[v] != k) { rc = -2; goto done; }
+        k++;
+      }
+    }
+  }
+  /* cm labels: order_cm[k] = order[n+ - 1 - k] */
+  for (int64_t k = 0; k < nplus; ++k) {
+    int32_t v = order[nplus - 1 - k];
+    cm[v] = (int32_t)k;
+  }
+  /* key(v) = deg << 32 | id ; suffix minimum over cm labels >= k */
+  sufmin[nplus] = UINT64_MAX;
+  for (int64_t k = nplus - 1; k >= 0; --k) {
+    int32_t v = order[nplus - 1 - k];
+    uint64_t key = ((uint64_t)(off[v + 1] - off[v]) << 32) | (uint32_t)v;
+    sufmin[k] = key < sufmin[k + 1] ? key : sufmin[k + 1];
+  }
+  {
+    int64_t M = -1; /* max cm over neighbours of labels < k */
+    int64_t have_prev = 0;
+    int64_t prev_p = 0;
+    uint64_t prev_key = 0;
+    for (int64_t k = 0; k < nplus; ++k) {
+      int32_t v = order[nplus - 1 - k];
+      uint64_t key = ((uint64_t)(off[v + 1] - off[v]) << 32) | (uint32_t)v;
+      int64_t p = INT64_MAX, mx = -1;
+      for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+        int64_t c = cm[cols[e]];
+        if (c < p) p = c;
+        if (c > mx) mx = c;
+      }
+      if (M < k) {
+        if (key != sufmin[k]) { rc = -3; goto done; }
+      } else {
+        if (p >= k) { rc = -4; goto done; }
+        if (have_prev) {
+          if (p < prev_p || (p == prev_p && key <= prev_key)) { rc = -5; goto done; }
+        }
+        have_prev = 1;
+        prev_p = p;
+        prev_key = key;
+      }
+      if (mx > M) M = mx;
+    }
+  }
+done:
+  free(order);
+  free(cm);
+  free(sufmin);
+  return rc;
+}
