@@ -1,0 +1,225 @@
+/*
+ * rbfs -- RCM-relabelled, direction-optimizing breadth-first search on AMD
+ * Instinct MI355X (gfx950).  C ABI.
+ *
+ * The library implements the method of "Fast and Efficient Parallel
+ * Breadth-First Search with Power-law Graph Transformation" (Jiang et al.,
+ * PPoPP'21 poster): a graph given as undirected CSR (section 3.1, Eq. 2) is
+ * relabelled by Reverse Cuthill-McKee with isolated vertices moved to the end
+ * (Algorithm 3, section 3.2), then searched level by level, top-down from a
+ * frontier queue or bottom-up over the unvisited vertices (Algorithm 2), with
+ * the work of each direction spread evenly over the GPU (sections 3.3-3.4).
+ * The problem statement (section 2.1): given G = (V, E) and a source s,
+ * produce the predecessor map pi with pi(s) = s and pi(v) = -1 when v is not
+ * reachable.
+ *
+ * Determinism.  The paper's parent choice depends on thread timing.  Here
+ * every parent is fixed: parent(v) is the neighbour one level closer to the
+ * source that has the smallest label in the graph's current labelling
+ * (original IDs before rbfs_rcm_reorder, RCM labels after it).  depth(v) is
+ * the hop distance, -1 if unreachable.  Both arrays are therefore unique and
+ * independent of the direction schedule, of batching and of timing.
+ *
+ * Conventions for every function:
+ *   - returns RBFS_OK (0) or a negative RBFS_E_* code; nothing throws;
+ *   - on error, rbfs_last_error() gives a message (thread-local); output
+ *     buffers hold unspecified contents and no handle is leaked;
+ *   - "device pointer" means memory on the GPU the graph lives on;
+ *   - `stream` is a hipStream_t (NULL = the default stream); work is ordered
+ *     on it.  Calls that report results on the host synchronise it;
+ *   - a handle must not be used by two host threads at once; distinct
+ *     handles are independent.
+ */
+#ifndef RBFS_H
+#define RBFS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------ */
+#define RBFS_OK 0
+#define RBFS_E_INVAL (-1)       /* bad argument or non-canonical CSR */
+#define RBFS_E_RANGE (-2)       /* root / n / nnz out of the supported range */
+#define RBFS_E_NOMEM (-3)       /* device allocation failed */
+#define RBFS_E_DEVICE (-4)      /* HIP runtime or kernel error */
+#define RBFS_E_STATE (-5)       /* handles in incompatible states */
+#define RBFS_E_NODEV (-6)       /* no usable GPU */
+#define RBFS_E_UNSUPPORTED (-7) /* request outside what this build supports */
+
+/* ---- graph creation flags --------------------------------------------- */
+#define RBFS_HOST_PTRS 1u /* row_offsets / cols are host pointers */
+#define RBFS_VALIDATE 2u  /* check the canonical form on the GPU (O(nnz)) */
+
+/* ---- direction modes --------------------------------------------------- */
+#define RBFS_DIR_HEURISTIC 0 /* alpha/beta rule, see rbfs_opts_t */
+#define RBFS_DIR_TD_ONLY 1   /* every level top-down */
+#define RBFS_DIR_BU_ONLY 2   /* level 0 top-down, every later level bottom-up */
+#define RBFS_DIR_SCHEDULE 3  /* per-level directions given by the caller */
+#define RBFS_DIR_LEARNED 4   /* on-device MLP, heuristic outside its range */
+
+#define RBFS_OUT_ORIGINAL 0 /* outputs indexed by and holding original IDs */
+#define RBFS_OUT_INTERNAL 1 /* outputs in the graph's internal labels */
+
+#define RBFS_STATS_MAX_LEVELS 64
+
+typedef struct rbfs_graph rbfs_graph_t;
+typedef struct rbfs_multi rbfs_multi_t;
+
+/* Options of a search.  A NULL opts pointer means: heuristic direction with
+ * alpha = 14, beta = 24, original output space.
+ *
+ * Heuristic (alpha/beta switch of Algorithm 2, named in section 2.1 and tuned
+ * in "Parameter Tuning"; the paper gives no formula, this integer form is
+ * used): level 0 is top-down; before level d >= 1, with n_f / m_f the vertex
+ * and edge (degree) counts of the frontier F_d, m_u the degree sum of the
+ * vertices not yet reached and n the number of vertices the bottom-up sweep
+ * covers, switch top-down -> bottom-up when m_f * alpha > m_u, and
+ * bottom-up -> top-down when n_f * beta < n and n_f < n_f of the previous
+ * level. */
+typedef struct rbfs_opts {
+  int32_t direction;       /* RBFS_DIR_* */
+  int32_t alpha;           /* > 0 */
+  int32_t beta;            /* > 0 */
+  int32_t output_space;    /* RBFS_OUT_* */
+  const int8_t* schedule;  /* host; RBFS_DIR_SCHEDULE: 0 = TD, 1 = BU for level
+                              d; levels past schedule_len repeat the last entry;
+                              level 0 is always top-down */
+  int32_t schedule_len;
+  int32_t tune_profile;    /* 0 = default launch shape, else an autotuned
+                              profile id (rbfs_tune) */
+  int32_t flags;           /* RBFS_OPT_* */
+} rbfs_opts_t;
+
+/* opts flags */
+#define RBFS_OPT_TIMING 1 /* record HIP events around the search kernel and
+                             the whole call; read them with rbfs_graph_timings */
+
+/* Per-search statistics; asking for them synchronises the stream.  Level d
+ * arrays describe the level that expands frontier F_d. */
+typedef struct rbfs_stats {
+  int32_t levels;                            /* number of levels expanded */
+  int32_t status;                            /* device status word, 0 = ok */
+  int8_t dir[RBFS_STATS_MAX_LEVELS];         /* 0 = TD, 1 = BU */
+  int64_t nf[RBFS_STATS_MAX_LEVELS];         /* |F_d| */
+  int64_t mf[RBFS_STATS_MAX_LEVELS];         /* degree sum over F_d */
+  int64_t mu[RBFS_STATS_MAX_LEVELS];         /* degree sum of unreached after F_d */
+  int64_t edges[RBFS_STATS_MAX_LEVELS];      /* adjacency entries read at level d */
+  int64_t reached;                           /* vertices with depth >= 0 */
+  int64_t component_edges;                   /* undirected edges among reached */
+  float ms_kernel;                           /* search kernel time */
+  float ms_total;                            /* incl. output translation */
+} rbfs_stats_t;
+
+typedef struct rbfs_graph_info {
+  int64_t n;          /* vertices */
+  int64_t nnz;        /* adjacency entries (2 x undirected edges) */
+  int64_t n_plus;     /* non-isolated vertices */
+  int32_t reordered;  /* 1 after rbfs_rcm_reorder */
+  int32_t device;     /* HIP device ordinal */
+  int64_t max_degree;
+  int64_t device_bytes; /* device memory held by the handle */
+} rbfs_graph_info_t;
+
+typedef struct rbfs_device_info {
+  int32_t device;
+  int32_t compute_units;
+  int32_t wavefront_size;
+  int32_t clock_khz;
+  int64_t global_mem_bytes;
+  int64_t l2_bytes;
+  char arch[64];
+} rbfs_device_info_t;
+
+/* Message for the last failing call on this host thread ("" if none). */
+const char* rbfs_last_error(void);
+
+/* Current HIP device; RBFS_E_NODEV when there is none. */
+int rbfs_device_info(rbfs_device_info_t* out);
+
+/* Create a graph handle on the current HIP device from a canonical undirected
+ * CSR (section 3.1, Eq. 2): row_offsets[n+1] (int64, row_offsets[0] = 0,
+ * non-decreasing, row_offsets[n] = nnz) and cols[nnz] (int32 in [0, n), each
+ * row strictly ascending, no self-loops, every edge present in both
+ * directions).  0 <= n < 2^31.  Pointers are device pointers unless flags has
+ * RBFS_HOST_PTRS.  With RBFS_VALIDATE the form is checked on the GPU and a
+ * violation returns RBFS_E_INVAL.  The library copies the CSR: the caller may
+ * free its buffers once the call returns (it synchronises `stream`). */
+int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const int32_t* cols,
+                      uint32_t flags, void* stream, rbfs_graph_t** out);
+
+/* Release a handle and its device memory.  NULL is accepted. */
+int rbfs_graph_destroy(rbfs_graph_t* g);
+
+int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
+
+/* Relabel the graph by Reverse Cuthill-McKee (Algorithm 3, section 3.2):
+ * V+ (non-isolated vertices) sorted by increasing (degree, id); each
+ * connected component is explored from its unvisited vertex of least
+ * (degree, id), neighbours appended in increasing (degree, id) order; the
+ * sequence is reversed and the isolated vertices are appended in increasing
+ * id.  The result is exactly the permutation of that sequential algorithm.
+ * The internal CSR is replaced by the relabelled one (rows ascending) and
+ * later searches sweep only the n+ non-isolated vertices.
+ * perm_out (nullable, device, int32[n]) receives perm[old] = new.
+ * ms_out (nullable, host) receives the elapsed time.  Synchronises `stream`.
+ * A second call returns RBFS_OK and changes nothing. */
+int rbfs_rcm_reorder(rbfs_graph_t* g, int32_t* perm_out, void* stream, float* ms_out);
+
+/* Inverse of the current relabelling: iperm_out[new] = old (device int32[n]).
+ * Identity before rbfs_rcm_reorder. */
+int rbfs_graph_iperm(const rbfs_graph_t* g, int32_t* iperm_out, void* stream);
+
+/* Breadth-first search from `root` (an original ID in [0, n)).
+ * depth, parent: device int32[n], fully overwritten: depth = hop distance or
+ * -1; parent(root) = root; parent = -1 when unreachable; otherwise the
+ * smallest-label neighbour one level up.  With output_space
+ * RBFS_OUT_ORIGINAL (default) both are indexed by original ID and parents
+ * are original IDs; with RBFS_OUT_INTERNAL, by internal label.
+ * Enqueued on `stream` without a host round trip; `stats` (nullable, host)
+ * forces a synchronisation and fills per-level counters. */
+int rbfs_bfs(rbfs_graph_t* g, int32_t root, int32_t* depth, int32_t* parent,
+             const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
+
+/* Synchronise `stream` and report any sticky device status (queue overflow,
+ * barrier timeout, corrupt input detected by a kernel) raised by searches on
+ * this graph since the last check: RBFS_OK or RBFS_E_DEVICE. */
+int rbfs_graph_check(rbfs_graph_t* g, void* stream);
+
+/* Durations of the calls made with RBFS_OPT_TIMING since the last read
+ * (oldest first, at most 1024 kept): kernel_ms[i] = search kernel(s) only,
+ * total_ms[i] = whole call incl. output translation.  Synchronises `stream`;
+ * *count receives the number written (<= cap).  Clears the record. */
+int rbfs_graph_timings(rbfs_graph_t* g, float* kernel_ms, float* total_ms, int32_t cap,
+                       int32_t* count, void* stream);
+
+/* k searches at once, 64 roots per bit-parallel pass (one 64-bit visit word
+ * per vertex).  roots: host int32[k] original IDs (duplicates allowed).
+ * depth, parent: device int32[k][n] root-major; row j equals rbfs_bfs from
+ * roots[j] bit for bit.  stats (nullable): levels and counters of the last
+ * 64-root pass, synchronises. */
+int rbfs_bfs_batch(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t* depth,
+                   int32_t* parent, const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
+
+/* Multi-graph batch: the graphs are packed as one disjoint union (each keeps
+ * its own labels, offset by the vertex counts of the graphs before it) and
+ * searched together, root j of every graph sharing bit j.  All graphs must be
+ * in the same state (all reordered or none) on the same device. */
+int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream,
+                      rbfs_multi_t** out);
+int rbfs_multi_destroy(rbfs_multi_t* m);
+
+/* roots: host int32[count][k] (k <= 64, original IDs of each graph).
+ * depth, parent: device int32, graph after graph, each graph's block
+ * root-major [k][n_g].  The whole search runs as one captured HIP graph that
+ * is replayed on later calls with the same k. */
+int rbfs_bfs_multi(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t* depth,
+                   int32_t* parent, const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RBFS_H */

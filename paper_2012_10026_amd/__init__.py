@@ -1,0 +1,320 @@
+"""Python binding of librbfs (RCM-relabelled direction-optimizing BFS on
+MI355X).
+
+Argument marshalling only: every step of the search runs in the library's
+HIP kernels.  PyTorch supplies device memory and streams.  The library must
+have been built (``python -m paper_2012_10026_amd._build``); importing the
+binding without it raises, there is no fallback.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librbfs.so")
+
+RBFS_OK = 0
+ERRORS = {-1: "INVAL", -2: "RANGE", -3: "NOMEM", -4: "DEVICE", -5: "STATE", -6: "NODEV",
+          -7: "UNSUPPORTED"}
+HOST_PTRS = 1
+VALIDATE = 2
+DIR_HEURISTIC, DIR_TD_ONLY, DIR_BU_ONLY, DIR_SCHEDULE, DIR_LEARNED = 0, 1, 2, 3, 4
+OUT_ORIGINAL, OUT_INTERNAL = 0, 1
+STATS_MAX_LEVELS = 64
+MLP_PARAMS = 8 * 32 + 32 + 32 * 32 + 32 + 32 * 2 + 2
+
+
+class RbfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (ERRORS.get(code, "?"), code, msg))
+        self.code = code
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("direction", ctypes.c_int32), ("alpha", ctypes.c_int32),
+                ("beta", ctypes.c_int32), ("output_space", ctypes.c_int32),
+                ("schedule", ctypes.c_void_p), ("schedule_len", ctypes.c_int32),
+                ("tune_profile", ctypes.c_int32), ("flags", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    L = STATS_MAX_LEVELS
+    _fields_ = [("levels", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("dir", ctypes.c_int8 * L), ("nf", ctypes.c_int64 * L),
+                ("mf", ctypes.c_int64 * L), ("mu", ctypes.c_int64 * L),
+                ("edges", ctypes.c_int64 * L), ("reached", ctypes.c_int64),
+                ("component_edges", ctypes.c_int64), ("ms_kernel", ctypes.c_float),
+                ("ms_total", ctypes.c_float)]
+
+    def as_dict(self):
+        n = min(self.levels, STATS_MAX_LEVELS)
+        return {"levels": self.levels, "status": self.status,
+                "dir": list(self.dir[:n]), "nf": list(self.nf[:n]), "mf": list(self.mf[:n]),
+                "mu": list(self.mu[:n]), "edges": list(self.edges[:n]),
+                "reached": self.reached, "component_edges": self.component_edges,
+                "ms_kernel": self.ms_kernel, "ms_total": self.ms_total}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_plus", ctypes.c_int64),
+                ("reordered", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+
+
+class DeviceInfo(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("compute_units", ctypes.c_int32),
+                ("wavefront_size", ctypes.c_int32), ("clock_khz", ctypes.c_int32),
+                ("global_mem_bytes", ctypes.c_int64), ("l2_bytes", ctypes.c_int64),
+                ("arch", ctypes.c_char * 64)]
+
+
+# exported symbols with their ctypes signatures; tests check that every one
+# declared in include/rbfs.h is listed and exported
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+SIGNATURES = {
+    "rbfs_last_error": (ctypes.c_char_p, []),
+    "rbfs_device_info": (ctypes.c_int, [_P]),
+    "rbfs_graph_create": (ctypes.c_int, [_I64, _I64, _P, _P, ctypes.c_uint32, _P, _P]),
+    "rbfs_graph_destroy": (ctypes.c_int, [_P]),
+    "rbfs_graph_info": (ctypes.c_int, [_P, _P]),
+    "rbfs_graph_check": (ctypes.c_int, [_P, _P]),
+    "rbfs_graph_timings": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
+    "rbfs_rcm_reorder": (ctypes.c_int, [_P, _P, _P, _P]),
+    "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
+    "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
+    "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "rbfs_multi_create": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "rbfs_multi_destroy": (ctypes.c_int, [_P]),
+    "rbfs_bfs_multi": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load librbfs.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librbfs.so not built: run python -m paper_2012_10026_amd._build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != RBFS_OK:
+        raise RbfsError(rc, lib().rbfs_last_error().decode())
+
+
+def _stream_ptr(device=None):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def device_info():
+    d = DeviceInfo()
+    _check(lib().rbfs_device_info(ctypes.byref(d)))
+    return {"device": d.device, "compute_units": d.compute_units,
+            "wavefront_size": d.wavefront_size, "clock_khz": d.clock_khz,
+            "global_mem_bytes": d.global_mem_bytes, "l2_bytes": d.l2_bytes,
+            "arch": d.arch.decode()}
+
+
+OPT_TIMING = 1
+
+
+def make_opts(direction=DIR_HEURISTIC, alpha=14, beta=24, output_space=OUT_ORIGINAL,
+              schedule=None, tune_profile=0, timing=False):
+    o = Opts()
+    o.flags = OPT_TIMING if timing else 0
+    o.direction = direction
+    o.alpha = alpha
+    o.beta = beta
+    o.output_space = output_space
+    o.tune_profile = tune_profile
+    o._sched = None
+    if schedule is not None:
+        arr = (ctypes.c_int8 * len(schedule))(*[int(x) for x in schedule])
+        o._sched = arr  # keep alive
+        o.schedule = ctypes.cast(arr, ctypes.c_void_p)
+        o.schedule_len = len(schedule)
+    return o
+
+
+class Graph:
+    """Handle on a graph resident on the current GPU.
+
+    off, cols: canonical undirected CSR (int64 offsets, int32 columns), as
+    torch tensors on the GPU or numpy arrays on the host.
+    """
+
+    def __init__(self, off, cols, validate=False):
+        import torch
+        self._h = ctypes.c_void_p()
+        flags = VALIDATE if validate else 0
+        if isinstance(off, np.ndarray):
+            off = np.ascontiguousarray(off, np.int64)
+            cols = np.ascontiguousarray(cols, np.int32)
+            flags |= HOST_PTRS
+            n = off.shape[0] - 1
+            nnz = cols.shape[0]
+            p_off = off.ctypes.data_as(ctypes.c_void_p)
+            p_cols = cols.ctypes.data_as(ctypes.c_void_p) if nnz else None
+            self.device = torch.device("cuda", torch.cuda.current_device())
+        else:
+            assert off.dtype == torch.int64 and cols.dtype == torch.int32
+            off = off.contiguous()
+            cols = cols.contiguous()
+            n = off.numel() - 1
+            nnz = cols.numel()
+            p_off = _dptr(off)
+            p_cols = _dptr(cols) if nnz else None
+            self.device = off.device
+        self.n = n
+        self.nnz = nnz
+        _check(lib().rbfs_graph_create(n, nnz, p_off, p_cols, flags, _stream_ptr(self.device),
+                                       ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().rbfs_graph_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self):
+        i = GraphInfo()
+        _check(lib().rbfs_graph_info(self._h, ctypes.byref(i)))
+        return {"n": i.n, "nnz": i.nnz, "n_plus": i.n_plus, "reordered": i.reordered,
+                "device": i.device, "max_degree": i.max_degree,
+                "device_bytes": i.device_bytes}
+
+    def rcm_reorder(self, want_perm=True):
+        """Relabel by RCM; returns (perm tensor or None, milliseconds)."""
+        import torch
+        perm = torch.empty(self.n, dtype=torch.int32, device=self.device) if want_perm else None
+        ms = ctypes.c_float(0.0)
+        _check(lib().rbfs_rcm_reorder(self._h, _dptr(perm) if perm is not None else None,
+                                      _stream_ptr(self.device), ctypes.byref(ms)))
+        return perm, ms.value
+
+    def iperm(self):
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(lib().rbfs_graph_iperm(self._h, _dptr(out), _stream_ptr(self.device)))
+        return out
+
+    def bfs(self, root, depth=None, parent=None, opts=None, stats=False):
+        """Returns (depth, parent[, stats dict]) as int32 device tensors."""
+        import torch
+        if depth is None:
+            depth = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        if parent is None:
+            parent = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        st = Stats() if stats else None
+        _check(lib().rbfs_bfs(self._h, int(root), _dptr(depth), _dptr(parent),
+                              ctypes.byref(opts) if opts is not None else None,
+                              _stream_ptr(self.device),
+                              ctypes.byref(st) if st is not None else None))
+        if stats:
+            return depth, parent, st.as_dict()
+        return depth, parent
+
+    def bfs_batch(self, roots, depth=None, parent=None, opts=None, stats=False):
+        """k roots at once; returns root-major (k, n) depth and parent."""
+        import torch
+        k = len(roots)
+        r = (ctypes.c_int32 * k)(*[int(x) for x in roots])
+        if depth is None:
+            depth = torch.empty((k, self.n), dtype=torch.int32, device=self.device)
+        if parent is None:
+            parent = torch.empty((k, self.n), dtype=torch.int32, device=self.device)
+        st = Stats() if stats else None
+        _check(lib().rbfs_bfs_batch(self._h, r, k, _dptr(depth), _dptr(parent),
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    _stream_ptr(self.device),
+                                    ctypes.byref(st) if st is not None else None))
+        if stats:
+            return depth, parent, st.as_dict()
+        return depth, parent
+
+    def check(self):
+        _check(lib().rbfs_graph_check(self._h, _stream_ptr(self.device)))
+
+    def timings(self, cap=1024):
+        """(kernel_ms, total_ms) lists of the calls made with timing=True."""
+        k = (ctypes.c_float * cap)()
+        t = (ctypes.c_float * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().rbfs_graph_timings(self._h, k, t, cap, ctypes.byref(cnt),
+                                        _stream_ptr(self.device)))
+        return list(k[:cnt.value]), list(t[:cnt.value])
+
+
+class MultiGraph:
+    """Several graphs searched together in one launch (disjoint union)."""
+
+    def __init__(self, graphs):
+        self.graphs = list(graphs)
+        self._h = ctypes.c_void_p()
+        arr = (ctypes.c_void_p * len(self.graphs))(*[g.handle.value for g in self.graphs])
+        self.device = self.graphs[0].device
+        _check(lib().rbfs_multi_create(arr, len(self.graphs), _stream_ptr(self.device),
+                                       ctypes.byref(self._h)))
+
+    def close(self):
+        if self._h:
+            lib().rbfs_multi_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def bfs(self, roots, opts=None, stats=False):
+        """roots: list (per graph) of k root lists.  Returns a list of
+        (depth, parent) views, each (k, n_g)."""
+        import torch
+        k = len(roots[0])
+        flat = [int(r) for rs in roots for r in rs]
+        r = (ctypes.c_int32 * len(flat))(*flat)
+        total = sum(k * g.n for g in self.graphs)
+        depth = torch.empty(total, dtype=torch.int32, device=self.device)
+        parent = torch.empty(total, dtype=torch.int32, device=self.device)
+        st = Stats() if stats else None
+        _check(lib().rbfs_bfs_multi(self._h, r, k, _dptr(depth), _dptr(parent),
+                                    ctypes.byref(opts) if opts is not None else None,
+                                    _stream_ptr(self.device),
+                                    ctypes.byref(st) if st is not None else None))
+        out, o = [], 0
+        for g in self.graphs:
+            sz = k * g.n
+            out.append((depth[o:o + sz].view(k, g.n), parent[o:o + sz].view(k, g.n)))
+            o += sz
+        if stats:
+            return out, st.as_dict()
+        return out

@@ -1,0 +1,435 @@
+// C ABI of librbfs: argument checking, handle lifetime, CSR validation and
+// dispatch to the passes.  Nothing here computes any part of the search.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <string>
+
+#include "../../include/rbfs.h"
+#include "common.cuh"
+#include "graph.h"
+
+struct rbfs_graph {
+  rbfs::Graph g;
+};
+
+namespace rbfs {
+
+static thread_local std::string t_last_error;
+
+void set_error(const std::string& msg) { t_last_error = msg; }
+
+hipError_t TimingRing::next(hipEvent_t** out) {
+  *out = nullptr;
+  if (count >= kCap) return hipSuccess;  // full: the call is not recorded
+  while (created <= count) {
+    for (int j = 0; j < 3; ++j) {
+      hipError_t e = hipEventCreate(&ev[created][j]);
+      if (e != hipSuccess) return e;
+    }
+    ++created;
+  }
+  *out = ev[count++];
+  return hipSuccess;
+}
+
+void TimingRing::destroy() {
+  for (int i = 0; i < created; ++i)
+    for (int j = 0; j < 3; ++j) (void)hipEventDestroy(ev[i][j]);
+  created = 0;
+  count = 0;
+}
+
+int bfs_check_status(Graph* g, hipStream_t stream);
+
+namespace {
+
+constexpr int kVBadOffsets = 1, kVColRange = 2, kVSelfLoop = 4, kVUnsorted = 8,
+              kVAsymmetric = 16;
+
+__global__ void check_offsets_kernel(const int64_t* off, int64_t n, int64_t nnz, int* flags,
+                                     unsigned long long* maxdeg, unsigned long long* nonzero) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t a = off[v], b = off[v + 1];
+    if (a < 0 || b < a || b > nnz) {
+      atomicOr(flags, kVBadOffsets);
+      continue;
+    }
+    if (b > a) {
+      atomicMax(maxdeg, (unsigned long long)(b - a));
+      atomicAdd(nonzero, 1ull);
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != nnz))
+    atomicOr(flags, kVBadOffsets);
+}
+
+__global__ void check_cols_kernel(const int32_t* cols, int64_t nnz, int64_t n, int* flags) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t c = cols[e];
+    if (c < 0 || c >= n) atomicOr(flags, kVColRange);
+  }
+}
+
+// Canonical form: rows strictly ascending, no self-loops, (w, v) present for
+// every (v, w).  Requires valid offsets and column range.
+__global__ __launch_bounds__(kBlock) void check_canonical_kernel(const int64_t* off,
+                                                                 const int32_t* cols, int64_t n,
+                                                                 int* flags) {
+  const int64_t nwords = ceil_div(n, kWave);
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nwords;
+       word += (int64_t)gridDim.x * kWavesPerBlock) {
+    word_edges(off, cols, n, word, [&](int64_t v, int32_t w, int64_t e) {
+      if (w == v) atomicOr(flags, kVSelfLoop);
+      if (e > off[v] && cols[e - 1] >= w) atomicOr(flags, kVUnsorted);
+      int64_t lo = off[w], hi = off[w + 1];
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (cols[mid] < v) lo = mid + 1; else hi = mid;
+      }
+      if (lo >= off[w + 1] || cols[lo] != v) atomicOr(flags, kVAsymmetric);
+    });
+  }
+}
+
+int grid_for(int64_t work) {
+  int64_t b = ceil_div(work, kBlock);
+  if (b < 1) b = 1;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (int)b;
+}
+
+int device_ok() {
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    set_error("no HIP device");
+    return RBFS_E_NODEV;
+  }
+  return 0;
+}
+
+}  // namespace
+
+#define API_CHECK(x)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (x);                                                        \
+    if (e_ != hipSuccess) {                                                     \
+      set_error(std::string(#x) + ": " + hipGetErrorString(e_));                \
+      rc = (e_ == hipErrorOutOfMemory) ? RBFS_E_NOMEM : RBFS_E_DEVICE;          \
+      goto fail;                                                                \
+    }                                                                           \
+  } while (0)
+
+static int graph_setup(Graph* g, uint32_t flags, hipStream_t stream) {
+  int rc = 0;
+  int* d_flags = nullptr;
+  unsigned long long* d_stats = nullptr;
+  int hflags = 0;
+  unsigned long long hstats[2] = {0, 0};
+  const int64_t n = g->n, nnz = g->nnz;
+  API_CHECK(hipMalloc(&d_flags, sizeof(int)));
+  API_CHECK(hipMalloc(&d_stats, 2 * sizeof(unsigned long long)));
+  API_CHECK(hipMemsetAsync(d_flags, 0, sizeof(int), stream));
+  API_CHECK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), stream));
+  hipLaunchKernelGGL(check_offsets_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n,
+                     nnz, d_flags, d_stats, d_stats + 1);
+  API_CHECK(hipGetLastError());
+  if (nnz > 0) {
+    hipLaunchKernelGGL(check_cols_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, g->cols,
+                       nnz, n, d_flags);
+    API_CHECK(hipGetLastError());
+  }
+  API_CHECK(hipMemcpyAsync(&hflags, d_flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+  API_CHECK(hipMemcpyAsync(hstats, d_stats, sizeof(hstats), hipMemcpyDeviceToHost, stream));
+  API_CHECK(hipStreamSynchronize(stream));
+  if (hflags) {
+    set_error(hflags & kVBadOffsets ? "row_offsets not monotone / not ending at nnz"
+                                    : "column index out of range");
+    rc = RBFS_E_INVAL;
+    goto fail;
+  }
+  if ((flags & RBFS_VALIDATE) && n > 0) {
+    const int64_t nwords = ceil_div(n, kWave);
+    const int64_t blocks = std::min<int64_t>(ceil_div(nwords, kWavesPerBlock), 1 << 18);
+    hipLaunchKernelGGL(check_canonical_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream,
+                       g->off, g->cols, n, d_flags);
+    API_CHECK(hipGetLastError());
+    API_CHECK(hipMemcpyAsync(&hflags, d_flags, sizeof(int), hipMemcpyDeviceToHost, stream));
+    API_CHECK(hipStreamSynchronize(stream));
+    if (hflags) {
+      std::string m = "non-canonical CSR:";
+      if (hflags & kVSelfLoop) m += " self-loop";
+      if (hflags & kVUnsorted) m += " row not strictly ascending";
+      if (hflags & kVAsymmetric) m += " missing reverse edge";
+      set_error(m);
+      rc = RBFS_E_INVAL;
+      goto fail;
+    }
+  }
+  g->max_degree = (int64_t)hstats[0];
+  g->n_plus = (int64_t)hstats[1];
+fail:
+  if (d_flags) (void)hipFree(d_flags);
+  if (d_stats) (void)hipFree(d_stats);
+  return rc;
+}
+
+}  // namespace rbfs
+
+using rbfs::Graph;
+using rbfs::set_error;
+
+extern "C" {
+
+const char* rbfs_last_error(void) { return rbfs::t_last_error.c_str(); }
+
+int rbfs_device_info(rbfs_device_info_t* out) {
+  if (!out) {
+    set_error("rbfs_device_info: out is NULL");
+    return RBFS_E_INVAL;
+  }
+  int rc = rbfs::device_ok();
+  if (rc) return rc;
+  int dev = 0;
+  hipDeviceProp_t p;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) {
+    set_error("hipGetDeviceProperties failed");
+    return RBFS_E_DEVICE;
+  }
+  memset(out, 0, sizeof(*out));
+  out->device = dev;
+  out->compute_units = p.multiProcessorCount;
+  out->wavefront_size = p.warpSize;
+  out->clock_khz = p.clockRate;
+  out->global_mem_bytes = (int64_t)p.totalGlobalMem;
+  out->l2_bytes = p.l2CacheSize;
+  strncpy(out->arch, p.gcnArchName, sizeof(out->arch) - 1);
+  return RBFS_OK;
+}
+
+int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const int32_t* cols,
+                      uint32_t flags, void* stream_, rbfs_graph_t** out) {
+  if (!out) {
+    set_error("rbfs_graph_create: out is NULL");
+    return RBFS_E_INVAL;
+  }
+  *out = nullptr;
+  if (n < 0 || n >= 0x7FFFFFFFll || nnz < 0) {
+    set_error("rbfs_graph_create: n must be in [0, 2^31-1) and nnz >= 0");
+    return RBFS_E_RANGE;
+  }
+  if (!row_offsets || (nnz > 0 && !cols)) {
+    set_error("rbfs_graph_create: NULL row_offsets or cols");
+    return RBFS_E_INVAL;
+  }
+  if (flags & ~(RBFS_HOST_PTRS | RBFS_VALIDATE)) {
+    set_error("rbfs_graph_create: unknown flags");
+    return RBFS_E_INVAL;
+  }
+  if (flags & RBFS_HOST_PTRS) {
+    if (row_offsets[0] != 0 || row_offsets[n] != nnz) {
+      set_error("rbfs_graph_create: row_offsets[0] != 0 or row_offsets[n] != nnz");
+      return RBFS_E_INVAL;
+    }
+  }
+  int rc = rbfs::device_ok();
+  if (rc) return rc;
+  hipStream_t stream = (hipStream_t)stream_;
+  rbfs_graph_t* h = new rbfs_graph_t();
+  Graph* g = &h->g;
+  hipDeviceProp_t p;
+  const hipMemcpyKind kind =
+      (flags & RBFS_HOST_PTRS) ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice;
+  int rate = 0;
+  API_CHECK(hipGetDevice(&g->device));
+  API_CHECK(hipGetDeviceProperties(&p, g->device));
+  g->compute_units = p.multiProcessorCount;
+  if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
+      rate > 0)
+    g->wall_rate_khz = rate;
+  g->n = n;
+  g->nnz = nnz;
+  g->n_sweep = n;
+  API_CHECK(hipMalloc(&g->off, sizeof(int64_t) * (size_t)(n + 1)));
+  API_CHECK(hipMalloc(&g->cols, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+  g->bytes = sizeof(int64_t) * (size_t)(n + 1) + sizeof(int32_t) * (size_t)nnz;
+  API_CHECK(hipMemcpyAsync(g->off, row_offsets, sizeof(int64_t) * (size_t)(n + 1), kind, stream));
+  if (nnz > 0)
+    API_CHECK(hipMemcpyAsync(g->cols, cols, sizeof(int32_t) * (size_t)nnz, kind, stream));
+  rc = rbfs::graph_setup(g, flags, stream);
+  if (rc) goto fail;
+  *out = h;
+  return RBFS_OK;
+fail:
+  if (g->off) (void)hipFree(g->off);
+  if (g->cols) (void)hipFree(g->cols);
+  delete h;
+  return rc ? rc : RBFS_E_DEVICE;
+}
+
+int rbfs_graph_destroy(rbfs_graph_t* h) {
+  if (!h) return RBFS_OK;
+  Graph* g = &h->g;
+  (void)hipSetDevice(g->device);
+  rbfs::free_bfs_work(g);
+  rbfs::free_ms_work(g);
+  g->scratch.release();
+  g->timing.destroy();
+  if (g->off) (void)hipFree(g->off);
+  if (g->cols) (void)hipFree(g->cols);
+  if (g->perm) (void)hipFree(g->perm);
+  if (g->iperm) (void)hipFree(g->iperm);
+  delete h;
+  return RBFS_OK;
+}
+
+int rbfs_graph_info(const rbfs_graph_t* h, rbfs_graph_info_t* out) {
+  if (!h || !out) {
+    set_error("rbfs_graph_info: NULL argument");
+    return RBFS_E_INVAL;
+  }
+  const Graph* g = &h->g;
+  memset(out, 0, sizeof(*out));
+  out->n = g->n;
+  out->nnz = g->nnz;
+  out->n_plus = g->n_plus;
+  out->reordered = g->reordered;
+  out->device = g->device;
+  out->max_degree = g->max_degree;
+  out->device_bytes = (int64_t)g->bytes;
+  return RBFS_OK;
+}
+
+int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream_, float* ms_out) {
+  if (!h) {
+    set_error("rbfs_rcm_reorder: NULL graph");
+    return RBFS_E_INVAL;
+  }
+  Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  int rc = 0;
+  if (!g->reordered) {
+    if (g->n == 0) {
+      set_error("rbfs_rcm_reorder: empty graph");
+      return RBFS_E_INVAL;
+    }
+    rc = rbfs::rcm_reorder_impl(g, stream, ms_out);
+    if (rc) return rc;
+  } else if (ms_out) {
+    *ms_out = 0.f;
+  }
+  if (perm_out) {
+    API_CHECK(hipMemcpyAsync(perm_out, g->perm, sizeof(int32_t) * (size_t)g->n,
+                             hipMemcpyDeviceToDevice, stream));
+    API_CHECK(hipStreamSynchronize(stream));
+  }
+  return RBFS_OK;
+fail:
+  return rc;
+}
+
+int rbfs_graph_iperm(const rbfs_graph_t* h, int32_t* iperm_out, void* stream_) {
+  if (!h || !iperm_out) {
+    set_error("rbfs_graph_iperm: NULL argument");
+    return RBFS_E_INVAL;
+  }
+  const Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  int rc = 0;
+  if (!g->reordered) {
+    std::string msg = "rbfs_graph_iperm: graph not reordered";
+    set_error(msg);
+    return RBFS_E_STATE;
+  }
+  API_CHECK(hipMemcpyAsync(iperm_out, g->iperm, sizeof(int32_t) * (size_t)g->n,
+                           hipMemcpyDeviceToDevice, stream));
+  API_CHECK(hipStreamSynchronize(stream));
+  return RBFS_OK;
+fail:
+  return rc;
+}
+
+static int parse_opts(const rbfs_opts_t* o, int* mode, int* alpha, int* beta, int* out_space) {
+  *mode = RBFS_DIR_HEURISTIC;
+  *alpha = 14;
+  *beta = 24;
+  *out_space = RBFS_OUT_ORIGINAL;
+  if (!o) return 0;
+  if (o->direction < RBFS_DIR_HEURISTIC || o->direction > RBFS_DIR_LEARNED ||
+      o->alpha <= 0 || o->beta <= 0 ||
+      (o->output_space != RBFS_OUT_ORIGINAL && o->output_space != RBFS_OUT_INTERNAL)) {
+    set_error("invalid rbfs_opts_t");
+    return RBFS_E_INVAL;
+  }
+  *mode = o->direction;
+  *alpha = o->alpha;
+  *beta = o->beta;
+  *out_space = o->output_space;
+  return 0;
+}
+
+int rbfs_bfs(rbfs_graph_t* h, int32_t root, int32_t* depth, int32_t* parent,
+             const rbfs_opts_t* opts, void* stream_, rbfs_stats_t* stats) {
+  if (!h || !depth || !parent) {
+    set_error("rbfs_bfs: NULL argument");
+    return RBFS_E_INVAL;
+  }
+  Graph* g = &h->g;
+  if (root < 0 || root >= g->n) {
+    set_error("rbfs_bfs: root out of range");
+    return RBFS_E_RANGE;
+  }
+  int mode, alpha, beta, out_space;
+  int rc = parse_opts(opts, &mode, &alpha, &beta, &out_space);
+  if (rc) return rc;
+  if (mode == RBFS_DIR_LEARNED) {
+    set_error("rbfs_bfs: learned direction needs weights (rbfs_switch_load)");
+    return RBFS_E_UNSUPPORTED;
+  }
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  return rbfs::bfs_impl(g, root, depth, parent, mode, alpha, beta,
+                        opts ? opts->schedule : nullptr, opts ? opts->schedule_len : 0,
+                        out_space, opts ? opts->flags : 0, (hipStream_t)stream_, stats);
+}
+
+int rbfs_graph_timings(rbfs_graph_t* h, float* kernel_ms, float* total_ms, int32_t cap,
+                       int32_t* count, void* stream_) {
+  if (!h || !count || cap < 0 || (cap > 0 && (!kernel_ms || !total_ms))) {
+    set_error("rbfs_graph_timings: bad arguments");
+    return RBFS_E_INVAL;
+  }
+  Graph* g = &h->g;
+  int rc = 0;
+  const int nrec = g->timing.count;
+  const int nout = nrec < cap ? nrec : cap;
+  API_CHECK(hipStreamSynchronize((hipStream_t)stream_));
+  for (int i = 0; i < nout; ++i) {
+    API_CHECK(hipEventElapsedTime(&kernel_ms[i], g->timing.ev[i][0], g->timing.ev[i][1]));
+    API_CHECK(hipEventElapsedTime(&total_ms[i], g->timing.ev[i][0], g->timing.ev[i][2]));
+  }
+  *count = nout;
+  g->timing.count = 0;
+  return RBFS_OK;
+fail:
+  g->timing.count = 0;
+  return rc;
+}
+
+int rbfs_graph_check(rbfs_graph_t* h, void* stream_) {
+  if (!h) {
+    set_error("rbfs_graph_check: NULL graph");
+    return RBFS_E_INVAL;
+  }
+  return rbfs::bfs_check_status(&h->g, (hipStream_t)stream_);
+}
+
+}  // extern "C"

@@ -1,0 +1,86 @@
+// Edge-balanced frontier expansion.
+//
+// A frontier is a list of vertices q[0..nq) with the exclusive prefix sum of
+// their degrees qe[0..nq] (qe[nq] = E).  The E adjacency entries of the
+// frontier, taken in list order, are cut into chunks of kChunkEdges; chunk c
+// starts at entry c * kChunkEdges, and chunk_pos[c] is the list position
+// whose row holds that entry.  A workgroup stages the list positions a chunk
+// touches (at most kChunkEdges + 1) in LDS and each thread finds the position
+// of its entry by binary search there, so every thread handles the same
+// number of entries whatever the degree skew, and consecutive threads read
+// consecutive column entries.  This is the GPU counterpart of the paper's
+// even split of each frontier vertex's neighbours over the threads (top-down
+// load balancing, Algorithm 4 and Eq. 3).
+#pragma once
+#include "common.cuh"
+#include "graph.h"
+
+namespace rbfs {
+
+// Marks the chunks whose first entry lies in [base, base + deg) as starting at
+// list position pos.
+__device__ __forceinline__ void mark_chunks(int32_t* chunk_pos, int64_t chunk_cap, int64_t base,
+                                            int64_t deg, int32_t pos) {
+  const int64_t c0 = (base + kChunkEdges - 1) / kChunkEdges;
+  const int64_t c1 = (base + deg + kChunkEdges - 1) / kChunkEdges;
+  for (int64_t c = c0; c < c1 && c < chunk_cap; ++c) chunk_pos[c] = pos;
+}
+
+struct ChunkLds {
+  int64_t qe[kChunkEdges + 2];
+  int64_t rowoff[kChunkEdges + 2];
+  int32_t u[kChunkEdges + 2];
+  int32_t k;
+};
+
+// Processes chunk c.  f(active, u, w) is called by every thread of the block
+// in lock-step rounds of kBlock entries (inactive threads get active = false),
+// so f may use wave-wide operations.  Returns false if the chunk touched more
+// list positions than fit in LDS (corrupt input).
+template <class F>
+__device__ __forceinline__ bool expand_chunk(ChunkLds& s, int64_t c, int64_t E, const int32_t* q,
+                                             const int64_t* qe, int64_t nq,
+                                             const int32_t* chunk_pos, int64_t nchunks,
+                                             const int64_t* off, const int32_t* cols, F&& f) {
+  const int64_t e0 = c * kChunkEdges;
+  const int64_t e1 = (e0 + kChunkEdges < E) ? e0 + kChunkEdges : E;
+  if (threadIdx.x == 0) {
+    const int64_t p0 = chunk_pos[c];
+    const int64_t p1 = (c + 1 < nchunks) ? (int64_t)chunk_pos[c + 1] : nq - 1;
+    int64_t k = p1 - p0 + 1;
+    const bool bad = p0 < 0 || p1 >= nq || k < 1 || k > kChunkEdges + 2;
+    s.k = bad ? -1 : (int32_t)k;
+    s.u[kChunkEdges + 1] = (int32_t)p0;
+  }
+  __syncthreads();
+  const int32_t k = s.k;
+  if (k < 0) return false;
+  const int64_t p0 = s.u[kChunkEdges + 1];
+  __syncthreads();
+  for (int i = threadIdx.x; i < k; i += kBlock) {
+    const int32_t u = q[p0 + i];
+    s.qe[i] = qe[p0 + i];
+    s.u[i] = u;
+    s.rowoff[i] = off[u];
+  }
+  __syncthreads();
+  for (int64_t base = e0; base < e1; base += kBlock) {
+    const int64_t e = base + threadIdx.x;
+    const bool active = e < e1;
+    int32_t u = 0, w = 0;
+    if (active) {
+      int lo = 0, hi = k - 1;  // last i with qe[i] <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.qe[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      u = s.u[lo];
+      w = cols[s.rowoff[lo] + (e - s.qe[lo])];
+    }
+    f(active, u, w);
+  }
+  __syncthreads();
+  return true;
+}
+
+}  // namespace rbfs

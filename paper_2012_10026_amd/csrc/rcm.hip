@@ -1,0 +1,516 @@
+// Reverse Cuthill-McKee relabelling on the GPU (Algorithm 3, section 3.2),
+// equal to the sequential algorithm label for label.
+//
+// Sequential Algorithm 3 labels vertices in queue order: a component starts
+// at its unvisited vertex of least (degree, id) and every processed vertex
+// appends its unvisited neighbours in increasing (degree, id) order.  Since a
+// whole BFS level is labelled before any vertex of it is processed, a vertex
+// w of level L+1 is appended by its level-L neighbour with the smallest
+// label, and level L+1 is ordered by (that label, degree(w), id(w)).
+// Components are explored in increasing order of their start key and each
+// occupies one contiguous label range.  The GPU pass therefore:
+//   1. ranks V+ by (degree, id) (radix sort of degree << b | id);
+//   2. finds connected components by union-find in rank space, always
+//      linking the larger root under the smaller, so each root is the
+//      component's minimum-rank vertex, i.e. its start;
+//   3. gives each component the label base = number of vertices in
+//      components with a smaller start rank (scan of component sizes);
+//   4. runs Cuthill-McKee level by level for all components at once: every
+//      unlabelled neighbour w of the current level takes the minimum label of
+//      its level neighbours (atomicMin), the new level is sorted by
+//      (that label, rank(w)), and labels are handed out per component in that
+//      order;
+//   5. reverses the labels over V+, appends the isolated vertices in
+//      increasing id, and rebuilds the CSR in the new labels with every row
+//      ascending (one sort of (new row, new column) keys).
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "common.cuh"
+#include "expand.cuh"
+#include "graph.h"
+#include "prim.h"
+
+namespace rbfs {
+namespace {
+
+constexpr uint32_t kUnset = 0xFFFFFFFFu;
+
+int grid_for(int64_t work) {
+  int64_t b = ceil_div(work, kBlock);
+  if (b < 1) b = 1;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (int)b;
+}
+
+#define GRID_STRIDE(i, n) \
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
+       i += (int64_t)gridDim.x * blockDim.x)
+
+__global__ void deg_kernel(const int64_t* off, int64_t n, int32_t* deg, int32_t* nz,
+                           unsigned long long* maxdeg) {
+  GRID_STRIDE(v, n) {
+    const int64_t d = off[v + 1] - off[v];
+    deg[v] = (int32_t)d;
+    nz[v] = d > 0 ? 1 : 0;
+    if (d > 0) atomicMax(maxdeg, (unsigned long long)d);
+  }
+}
+
+__global__ void deg_keys_kernel(const int32_t* deg, const int64_t* pos_nz, int64_t n, int bv,
+                                uint64_t* keys) {
+  GRID_STRIDE(v, n) {
+    if (deg[v] > 0) keys[pos_nz[v]] = ((uint64_t)deg[v] << bv) | (uint64_t)v;
+  }
+}
+
+__global__ void vplus_kernel(const uint64_t* keys, int64_t nplus, int bv, int32_t* vplus,
+                             int32_t* rank, int32_t* ccp) {
+  const uint64_t mask = (1ull << bv) - 1ull;
+  GRID_STRIDE(k, nplus) {
+    const int32_t v = (int32_t)(keys[k] & mask);
+    vplus[k] = v;
+    rank[v] = (int32_t)k;
+    ccp[k] = (int32_t)k;
+  }
+}
+
+// Union-find with the larger root linked under the smaller root (hooking as
+// in ECL-CC, Jaiganesh and Burtscher, HPDC 2018).  Parent pointers only ever
+// decrease, so racy reads are safe.
+__device__ __forceinline__ int32_t uf_find(int32_t* p, int32_t x) {
+  int32_t cur = __hip_atomic_load(&p[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (cur != x) {
+    int32_t prev = x;
+    int32_t next;
+    while (cur > (next = __hip_atomic_load(&p[cur], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT))) {
+      __hip_atomic_store(&p[prev], next, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      prev = cur;
+      cur = next;
+    }
+  }
+  return cur;
+}
+
+__device__ __forceinline__ void uf_union(int32_t* p, int32_t a, int32_t b) {
+  int32_t ra = uf_find(p, a);
+  int32_t rb = uf_find(p, b);
+  while (ra != rb) {
+    if (ra < rb) {
+      const int32_t old = atomicCAS(&p[rb], rb, ra);
+      if (old == rb) break;
+      rb = old;
+    } else {
+      const int32_t old = atomicCAS(&p[ra], ra, rb);
+      if (old == ra) break;
+      ra = old;
+    }
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void cc_union_kernel(const int64_t* off, const int32_t* cols,
+                                                          int64_t n, const int32_t* rank,
+                                                          int32_t* ccp) {
+  const int64_t nwords = ceil_div(n, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nwords;
+       word += wstride) {
+    word_edges(off, cols, n, word, [&](int64_t v, int32_t w, int64_t) {
+      if (v < w) uf_union(ccp, rank[v], rank[w]);
+    });
+  }
+}
+
+__global__ void cc_compress_kernel(int32_t* ccp, int64_t nplus, int32_t* csize) {
+  GRID_STRIDE(k, nplus) {
+    int32_t x = (int32_t)k;
+    int32_t p = ccp[x];
+    while (p != x) {
+      x = p;
+      p = ccp[x];
+    }
+    ccp[k] = p;
+    atomicAdd(&csize[p], 1);
+  }
+}
+
+__global__ void cm_roots_kernel(const int32_t* ccp, const int64_t* cbase, const int32_t* vplus,
+                                int64_t nplus, int32_t* label, int32_t* nextfree,
+                                int32_t* front, int32_t* front_count) {
+  GRID_STRIDE(k, nplus) {
+    if (ccp[k] == (int32_t)k) {
+      const int32_t v = vplus[k];
+      label[v] = (int32_t)cbase[k];
+      nextfree[k] = (int32_t)cbase[k] + 1;
+      const int pos = atomicAdd(front_count, 1);
+      front[pos] = v;
+    }
+  }
+}
+
+__global__ void gather_deg_kernel(const int32_t* front, int64_t nf, const int32_t* deg,
+                                  int32_t* out) {
+  GRID_STRIDE(i, nf) { out[i] = deg[front[i]]; }
+}
+
+__global__ void mark_kernel(const int64_t* qe, int64_t nq, int32_t* chunk_pos, int64_t cap) {
+  GRID_STRIDE(i, nq) { mark_chunks(chunk_pos, cap, qe[i], qe[i + 1] - qe[i], (int32_t)i); }
+}
+
+// CM expansion of one level: every unlabelled neighbour w takes the minimum
+// label of its frontier neighbours; the first to touch w appends it.
+__global__ __launch_bounds__(kBlock) void cm_expand_kernel(
+    const int32_t* front, const int64_t* qe, int64_t nq, int64_t E, const int32_t* chunk_pos,
+    int64_t nchunks, const int64_t* off, const int32_t* cols, const int32_t* label,
+    uint32_t* plabel, int32_t* next, int32_t* next_count, int64_t next_cap, int* status) {
+  __shared__ ChunkLds s;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const bool ok = expand_chunk(s, c, E, front, qe, nq, chunk_pos, nchunks, off, cols,
+                                 [&](bool active, int32_t u, int32_t w) {
+      bool first = false;
+      if (active && label[w] < 0) {
+        const uint32_t old = atomicMin(&plabel[w], (uint32_t)label[u]);
+        first = (old == kUnset);
+      }
+      const uint64_t m = ballot(first);
+      if (m) {
+        const int leader = ffs64(m);
+        int base = 0;
+        if (lane_id() == leader) base = atomicAdd(next_count, popc64(m));
+        base = shfl(base, leader);
+        const int64_t pos = (int64_t)base + popc64(m & lanemask_lt());
+        if (first) {
+          if (pos < next_cap) next[pos] = w; else atomicOr(status, kStatusOverflow);
+        }
+      }
+    });
+    if (!ok) {
+      if (threadIdx.x == 0) atomicOr(status, kStatusBadInput);
+      return;
+    }
+  }
+}
+
+__global__ void cm_keys_kernel(const int32_t* next, int64_t m, const uint32_t* plabel,
+                               const int32_t* rank, int br, uint64_t* keys) {
+  GRID_STRIDE(i, m) {
+    const int32_t w = next[i];
+    keys[i] = ((uint64_t)plabel[w] << br) | (uint64_t)rank[w];
+  }
+}
+
+__global__ void cm_heads_kernel(const uint64_t* keys, int64_t m, int br, const int32_t* ccp,
+                                int32_t* segstart) {
+  const uint64_t mask = (1ull << br) - 1ull;
+  GRID_STRIDE(i, m) {
+    const int32_t c = ccp[keys[i] & mask];
+    if (i == 0 || ccp[keys[i - 1] & mask] != c) segstart[c] = (int32_t)i;
+  }
+}
+
+__global__ void cm_assign_kernel(const uint64_t* keys, int64_t m, int br, const int32_t* ccp,
+                                 const int32_t* vplus, const int32_t* segstart,
+                                 const int32_t* nextfree, int32_t* label, int32_t* front) {
+  const uint64_t mask = (1ull << br) - 1ull;
+  GRID_STRIDE(i, m) {
+    const int32_t r = (int32_t)(keys[i] & mask);
+    const int32_t c = ccp[r];
+    const int32_t w = vplus[r];
+    const int32_t s = segstart[c];
+    label[w] = nextfree[c] + (int32_t)(i - s);
+    front[i] = w;
+  }
+}
+
+// Separate launch: every thread of a segment must have read nextfree[c]
+// before the segment's last element advances it.
+__global__ void cm_advance_kernel(const uint64_t* keys, int64_t m, int br, const int32_t* ccp,
+                                  const int32_t* segstart, int32_t* nextfree) {
+  const uint64_t mask = (1ull << br) - 1ull;
+  GRID_STRIDE(i, m) {
+    const int32_t c = ccp[keys[i] & mask];
+    if (i == m - 1 || ccp[keys[i + 1] & mask] != c) nextfree[c] += (int32_t)(i - segstart[c] + 1);
+  }
+}
+
+__global__ void perm_kernel(const int32_t* deg, const int32_t* label, const int64_t* pos_nz,
+                            int64_t n, int64_t nplus, int32_t* perm, int32_t* iperm,
+                            int* status) {
+  GRID_STRIDE(v, n) {
+    int64_t p;
+    if (deg[v] > 0) {
+      const int32_t l = label[v];
+      if (l < 0 || l >= nplus) atomicOr(status, kStatusBadInput);
+      p = nplus - 1 - l;
+    } else {
+      p = nplus + (v - pos_nz[v]);
+    }
+    perm[v] = (int32_t)p;
+    if (p >= 0 && p < n) iperm[p] = (int32_t)v;
+  }
+}
+
+__global__ void newdeg_kernel(const int32_t* iperm, const int32_t* deg, int64_t n,
+                              int32_t* newdeg) {
+  GRID_STRIDE(i, n) { newdeg[i] = deg[iperm[i]]; }
+}
+
+__global__ __launch_bounds__(kBlock) void relabel_keys_kernel(const int64_t* off,
+                                                              const int32_t* cols, int64_t n,
+                                                              const int32_t* perm, int bn,
+                                                              uint64_t* keys) {
+  const int64_t nwords = ceil_div(n, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nwords;
+       word += wstride) {
+    word_edges(off, cols, n, word, [&](int64_t v, int32_t w, int64_t e) {
+      keys[e] = ((uint64_t)perm[v] << bn) | (uint64_t)perm[w];
+    });
+  }
+}
+
+__global__ void keys_to_cols_kernel(const uint64_t* keys, int64_t nnz, int bn, int32_t* cols) {
+  const uint64_t mask = (1ull << bn) - 1ull;
+  GRID_STRIDE(i, nnz) { cols[i] = (int32_t)(keys[i] & mask); }
+}
+
+// Device buffers owned for the duration of one pass.
+struct Bufs {
+  std::vector<void*> ptrs;
+  ~Bufs() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+  template <class T>
+  hipError_t alloc(T** out, int64_t count) {
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+    if (e != hipSuccess) return e;
+    ptrs.push_back(p);
+    *out = (T*)p;
+    return hipSuccess;
+  }
+  void forget(void* p) {
+    for (auto& q : ptrs)
+      if (q == p) q = nullptr;
+  }
+};
+
+}  // namespace
+
+#define RCM_CHECK(x)                                                            \
+  do {                                                                          \
+    hipError_t e_ = (x);                                                        \
+    if (e_ != hipSuccess) {                                                     \
+      set_error(std::string("rcm_reorder: ") + #x + ": " + hipGetErrorString(e_)); \
+      return e_ == hipErrorOutOfMemory ? -3 : -4;                                \
+    }                                                                           \
+  } while (0)
+
+int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
+  const int64_t n = g->n, nnz = g->nnz;
+  hipEvent_t e0, e1;
+  RCM_CHECK(hipEventCreate(&e0));
+  RCM_CHECK(hipEventCreate(&e1));
+  RCM_CHECK(hipEventRecord(e0, stream));
+  Bufs B;
+  int32_t *deg, *nz, *vplus, *rank, *ccp, *csize, *label, *nextfree, *front, *next, *segstart,
+      *counts, *tmpdeg, *chunk_pos, *perm, *iperm, *newdeg, *newcols;
+  int64_t *pos_nz, *cbase, *qe, *newoff;
+  uint32_t* plabel;
+  unsigned long long* d_max;
+  int* d_status;
+  uint64_t *keys, *keys2;
+  RCM_CHECK(B.alloc(&deg, n));
+  RCM_CHECK(B.alloc(&nz, n));
+  RCM_CHECK(B.alloc(&pos_nz, n + 1));
+  RCM_CHECK(B.alloc(&d_max, 1));
+  RCM_CHECK(B.alloc(&d_status, 1));
+  RCM_CHECK(B.alloc(&counts, 2));
+  RCM_CHECK(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), stream));
+  RCM_CHECK(hipMemsetAsync(d_status, 0, sizeof(int), stream));
+  hipLaunchKernelGGL(deg_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n, deg, nz,
+                     d_max);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(scan_exclusive_i32(nz, pos_nz, n, g->scratch, stream));
+  int64_t nplus = 0;
+  unsigned long long maxdeg = 0;
+  RCM_CHECK(hipMemcpyAsync(&nplus, pos_nz + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipMemcpyAsync(&maxdeg, d_max, sizeof(maxdeg), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipStreamSynchronize(stream));
+
+  // 1. V+ ranked by (degree, id)
+  const int bv = bits_for(n);
+  const int bdeg = bits_for((int64_t)maxdeg + 1);
+  RCM_CHECK(B.alloc(&keys, nplus > nnz ? nplus : nnz));
+  RCM_CHECK(B.alloc(&keys2, nplus > nnz ? nplus : nnz));
+  RCM_CHECK(B.alloc(&vplus, nplus));
+  RCM_CHECK(B.alloc(&rank, n));
+  RCM_CHECK(B.alloc(&ccp, nplus));
+  hipLaunchKernelGGL(deg_keys_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, deg, pos_nz, n,
+                     bv, keys);
+  RCM_CHECK(hipGetLastError());
+  {
+    uint64_t* k1 = keys;
+    uint64_t* k2 = keys2;
+    RCM_CHECK(radix_sort_u64(&k1, &k2, nplus, 0, bv + bdeg, g->scratch, stream));
+    hipLaunchKernelGGL(vplus_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, k1, nplus,
+                       bv, vplus, rank, ccp);
+    RCM_CHECK(hipGetLastError());
+  }
+
+  // 2. components (root = minimum rank) and 3. label bases
+  const int64_t nwords = ceil_div(n, kWave);
+  const int wgrid = (int)(ceil_div(nwords, kWavesPerBlock) < (1 << 18)
+                              ? ceil_div(nwords, kWavesPerBlock) : (1 << 18));
+  hipLaunchKernelGGL(cc_union_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, g->cols, n,
+                     rank, ccp);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(B.alloc(&csize, nplus));
+  RCM_CHECK(B.alloc(&cbase, nplus + 1));
+  RCM_CHECK(hipMemsetAsync(csize, 0, sizeof(int32_t) * (nplus > 0 ? nplus : 1), stream));
+  hipLaunchKernelGGL(cc_compress_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp,
+                     nplus, csize);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(scan_exclusive_i32(csize, cbase, nplus, g->scratch, stream));
+
+  // 4. level-synchronous Cuthill-McKee over all components
+  RCM_CHECK(B.alloc(&label, n));
+  RCM_CHECK(B.alloc(&plabel, n));
+  RCM_CHECK(B.alloc(&nextfree, nplus));
+  RCM_CHECK(B.alloc(&front, nplus));
+  RCM_CHECK(B.alloc(&next, nplus));
+  RCM_CHECK(B.alloc(&segstart, nplus));
+  RCM_CHECK(B.alloc(&tmpdeg, nplus));
+  RCM_CHECK(B.alloc(&qe, nplus + 1));
+  const int64_t chunk_cap = ceil_div(nnz, kChunkEdges) + 2;
+  RCM_CHECK(B.alloc(&chunk_pos, chunk_cap));
+  RCM_CHECK(hipMemsetAsync(label, 0xFF, sizeof(int32_t) * (size_t)n, stream));
+  RCM_CHECK(hipMemsetAsync(plabel, 0xFF, sizeof(uint32_t) * (size_t)n, stream));
+  RCM_CHECK(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2, stream));
+  hipLaunchKernelGGL(cm_roots_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp, cbase,
+                     vplus, nplus, label, nextfree, front, counts);
+  RCM_CHECK(hipGetLastError());
+  int32_t nf = 0;
+  RCM_CHECK(hipMemcpyAsync(&nf, counts, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipStreamSynchronize(stream));
+  const int br = bits_for(nplus);
+  int64_t labelled = nf;
+  int status = 0;
+  while (nf > 0) {
+    hipLaunchKernelGGL(gather_deg_kernel, dim3(grid_for(nf)), dim3(kBlock), 0, stream, front,
+                       (int64_t)nf, deg, tmpdeg);
+    RCM_CHECK(hipGetLastError());
+    RCM_CHECK(scan_exclusive_i32(tmpdeg, qe, nf, g->scratch, stream));
+    hipLaunchKernelGGL(mark_kernel, dim3(grid_for(nf)), dim3(kBlock), 0, stream, qe, (int64_t)nf,
+                       chunk_pos, chunk_cap);
+    RCM_CHECK(hipGetLastError());
+    int64_t E = 0;
+    RCM_CHECK(hipMemcpyAsync(&E, qe + nf, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+    RCM_CHECK(hipMemsetAsync(counts + 1, 0, sizeof(int32_t), stream));
+    RCM_CHECK(hipStreamSynchronize(stream));
+    const int64_t nchunks = ceil_div(E, kChunkEdges);
+    if (nchunks > 0) {
+      const int64_t gx = nchunks < 65536 ? nchunks : 65536;
+      hipLaunchKernelGGL(cm_expand_kernel, dim3((unsigned)gx), dim3(kBlock), 0, stream, front, qe,
+                         (int64_t)nf, E, chunk_pos, nchunks, g->off, g->cols, label, plabel, next,
+                         counts + 1, nplus, d_status);
+      RCM_CHECK(hipGetLastError());
+    }
+    int32_t m = 0;
+    RCM_CHECK(hipMemcpyAsync(&m, counts + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
+    RCM_CHECK(hipStreamSynchronize(stream));
+    if (status != 0 || m < 0 || m > nplus - labelled) {
+      set_error("rcm_reorder: inconsistent level expansion (corrupt or non-canonical CSR?)");
+      return -1;
+    }
+    if (m > 0) {
+      hipLaunchKernelGGL(cm_keys_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, next,
+                         (int64_t)m, plabel, rank, br, keys);
+      RCM_CHECK(hipGetLastError());
+      uint64_t* k1 = keys;
+      uint64_t* k2 = keys2;
+      RCM_CHECK(radix_sort_u64(&k1, &k2, m, 0, 2 * br, g->scratch, stream));
+      hipLaunchKernelGGL(cm_heads_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
+                         (int64_t)m, br, ccp, segstart);
+      RCM_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(cm_assign_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
+                         (int64_t)m, br, ccp, vplus, segstart, nextfree, label, front);
+      RCM_CHECK(hipGetLastError());
+      hipLaunchKernelGGL(cm_advance_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
+                         (int64_t)m, br, ccp, segstart, nextfree);
+      RCM_CHECK(hipGetLastError());
+    }
+    labelled += m;
+    nf = m;
+  }
+  RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipStreamSynchronize(stream));
+  if (status != 0 || labelled != nplus) {
+    set_error("rcm_reorder: inconsistent labelling (corrupt or non-canonical CSR?)");
+    return -1;
+  }
+
+  // 5. reversal, isolated vertices, relabelled CSR
+  RCM_CHECK(B.alloc(&perm, n));
+  RCM_CHECK(B.alloc(&iperm, n));
+  hipLaunchKernelGGL(perm_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, deg, label, pos_nz,
+                     n, nplus, perm, iperm, d_status);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(B.alloc(&newdeg, n));
+  RCM_CHECK(B.alloc(&newoff, n + 1));
+  hipLaunchKernelGGL(newdeg_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, iperm, deg, n,
+                     newdeg);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(scan_exclusive_i32(newdeg, newoff, n, g->scratch, stream));
+  // free what is no longer needed before the big sort
+  (void)hipStreamSynchronize(stream);
+  const int bn = bits_for(n);
+  hipLaunchKernelGGL(relabel_keys_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, g->cols,
+                     n, perm, bn, keys);
+  RCM_CHECK(hipGetLastError());
+  uint64_t* k1 = keys;
+  uint64_t* k2 = keys2;
+  RCM_CHECK(radix_sort_u64(&k1, &k2, nnz, 0, 2 * bn, g->scratch, stream));
+  RCM_CHECK(B.alloc(&newcols, nnz));
+  hipLaunchKernelGGL(keys_to_cols_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, k1, nnz,
+                     bn, newcols);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipEventRecord(e1, stream));
+  RCM_CHECK(hipStreamSynchronize(stream));
+  if (status != 0) {
+    set_error("rcm_reorder: inconsistent labelling (corrupt or non-canonical CSR?)");
+    return -1;
+  }
+  float ms = 0.f;
+  RCM_CHECK(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (ms_out) *ms_out = ms;
+
+  // install: the handle takes ownership of the new CSR and the permutation
+  (void)hipFree(g->off);
+  (void)hipFree(g->cols);
+  g->off = newoff;
+  g->cols = newcols;
+  g->perm = perm;
+  g->iperm = iperm;
+  B.forget(newoff);
+  B.forget(newcols);
+  B.forget(perm);
+  B.forget(iperm);
+  g->n_plus = nplus;
+  g->n_sweep = nplus;
+  g->reordered = 1;
+  g->bytes += sizeof(int32_t) * 2 * (size_t)n;
+  free_bfs_work(g);
+  free_ms_work(g);
+  g->scratch.release();
+  return 0;
+}
+
+}  // namespace rbfs

@@ -1,0 +1,257 @@
+"""GPU parity: RCM permutation and single-root BFS through the C ABI against
+the CPU oracle, bit for bit."""
+import random
+
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_10026_amd as rb
+    return rb
+
+
+def csr_of(n, edges):
+    src = np.array([a for a, b in edges], np.int32)
+    dst = np.array([b for a, b in edges], np.int32)
+    return oracle.canonical_csr(n, src, dst)
+
+
+def small_graphs():
+    """Edge cases: paths, stars, cycles, cliques, many small components with
+    equal-degree ties, isolated vertices, random graphs."""
+    gs = []
+    gs.append(("path", csr_of(6, [(i, i + 1) for i in range(5)])))
+    gs.append(("star", csr_of(9, [(0, i) for i in range(1, 9)])))
+    gs.append(("cycle", csr_of(10, [(i, (i + 1) % 10) for i in range(10)])))
+    gs.append(("clique", csr_of(7, [(a, b) for a in range(7) for b in range(a + 1, 7)])))
+    gs.append(("pairs_iso", csr_of(20, [(2 * i, 2 * i + 1) for i in range(7)])))
+    gs.append(("mixed", csr_of(7, [(1, 4), (4, 6), (6, 1), (6, 2), (0, 5)])))
+    rng = random.Random(5)
+    for t in range(6):
+        n = rng.randint(20, 300)
+        p = rng.choice([0.005, 0.01, 0.03, 0.1])
+        edges = [(u, v) for u in range(n) for v in range(u + 1, n) if rng.random() < p]
+        gs.append(("er%d" % t, csr_of(n + rng.randint(0, 5), edges)))
+    # long path: many levels
+    gs.append(("longpath", csr_of(3000, [(i, i + 1) for i in range(2999)])))
+    # a hub larger than a wave and a chunk
+    hub = [(0, i) for i in range(1, 5000)] + [(i, i + 1) for i in range(1, 4999, 2)]
+    gs.append(("hub", csr_of(5001, hub)))
+    return gs
+
+
+SMALL = small_graphs()
+
+
+def kron(scale, seed=1016):
+    return graphgen.kronecker_csr(scale, 16, seed)
+
+
+@pytest.mark.parametrize("name,g", SMALL, ids=[s[0] for s in SMALL])
+def test_rcm_small(rb, name, g):
+    off, cols = g
+    G = rb.Graph(off, cols, validate=True)
+    perm, ms = G.rcm_reorder()
+    perm_o, iperm_o, nplus = oracle.rcm(off, cols)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+    assert np.array_equal(G.iperm().cpu().numpy(), iperm_o)
+    assert G.info()["n_plus"] == nplus
+
+
+@pytest.mark.parametrize("scale,seed", [(8, 1), (12, 2), (16, 1016)])
+def test_rcm_kronecker(rb, scale, seed):
+    off, cols = kron(scale, seed)
+    G = rb.Graph(off, cols)
+    perm, ms = G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+
+
+def test_rcm_chung_lu(rb):
+    off, cols = graphgen.chung_lu_csr(30000, 1500, seed=3, max_deg=3000.0, mean_deg=12.0)
+    G = rb.Graph(off, cols)
+    perm, _ = G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+
+
+MODES = ["heuristic", "td", "bu", "random"]
+
+
+def opts_for(rb, mode, rng, **kw):
+    if mode == "heuristic":
+        return rb.make_opts(rb.DIR_HEURISTIC, **kw)
+    if mode == "td":
+        return rb.make_opts(rb.DIR_TD_ONLY, **kw)
+    if mode == "bu":
+        return rb.make_opts(rb.DIR_BU_ONLY, **kw)
+    sched = [0] + [rng.randint(0, 1) for _ in range(40)]
+    return rb.make_opts(rb.DIR_SCHEDULE, schedule=sched, **kw)
+
+
+def check_bfs(rb, G, off, cols, roots, ell, modes=MODES, seed=0):
+    rng = random.Random(seed)
+    for root in roots:
+        d_o, p_o, _ = oracle.bfs(off, cols, root, ell)
+        for mode in modes:
+            d, p = G.bfs(root, opts=opts_for(rb, mode, rng))
+            assert np.array_equal(d.cpu().numpy(), d_o), (root, mode)
+            assert np.array_equal(p.cpu().numpy(), p_o), (root, mode)
+
+
+@pytest.mark.parametrize("name,g", SMALL, ids=[s[0] for s in SMALL])
+def test_bfs_small_unreordered(rb, name, g):
+    off, cols = g
+    G = rb.Graph(off, cols)
+    n = off.shape[0] - 1
+    roots = sorted(set([0, n - 1, n // 2]))
+    check_bfs(rb, G, off, cols, roots, None)
+
+
+@pytest.mark.parametrize("name,g", SMALL, ids=[s[0] for s in SMALL])
+def test_bfs_small_rcm(rb, name, g):
+    off, cols = g
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    n = off.shape[0] - 1
+    roots = sorted(set([0, n - 1, n // 2]))
+    check_bfs(rb, G, off, cols, roots, perm_o)
+
+
+@pytest.mark.parametrize("scale", [10, 14, 16])
+def test_bfs_kronecker_rcm(rb, scale):
+    off, cols = kron(scale)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    roots = graphgen.sample_roots(off, 8, 7)
+    check_bfs(rb, G, off, cols, roots, perm_o, seed=scale)
+
+
+def test_bfs_kronecker_unreordered(rb):
+    off, cols = kron(14, 3)
+    G = rb.Graph(off, cols)
+    roots = graphgen.sample_roots(off, 4, 7)
+    check_bfs(rb, G, off, cols, roots, None)
+
+
+def test_bfs_internal_output(rb):
+    off, cols = kron(12, 4)
+    G = rb.Graph(off, cols)
+    perm_t, _ = G.rcm_reorder()
+    perm = perm_t.cpu().numpy()
+    iperm = G.iperm().cpu().numpy()
+    root = graphgen.sample_roots(off, 1, 7)[0]
+    d_o, p_o, _ = oracle.bfs(off, cols, root, perm)
+    d, p = G.bfs(root, opts=rb.make_opts(output_space=rb.OUT_INTERNAL))
+    d, p = d.cpu().numpy(), p.cpu().numpy()
+    # internal index i holds vertex iperm[i]; parents are internal labels
+    assert np.array_equal(d[perm], d_o)
+    exp = np.where(p_o >= 0, perm[np.maximum(p_o, 0)], -1)
+    assert np.array_equal(p[perm], exp)
+
+
+def test_isolated_root(rb):
+    off, cols = csr_of(8, [(0, 1), (1, 2), (4, 5)])
+    for reorder in (False, True):
+        G = rb.Graph(off, cols)
+        if reorder:
+            G.rcm_reorder()
+        for root in (3, 6, 7):
+            d, p = G.bfs(root)
+            d, p = d.cpu().numpy(), p.cpu().numpy()
+            exp_d = -np.ones(8, np.int32)
+            exp_d[root] = 0
+            exp_p = -np.ones(8, np.int32)
+            exp_p[root] = root
+            assert np.array_equal(d, exp_d) and np.array_equal(p, exp_p)
+
+
+def test_stats_match_oracle_schedule(rb):
+    """Per-level counters and the heuristic directions equal the oracle's
+    replay of the alpha/beta rule."""
+    off, cols = kron(14, 9)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    perm_o, _, nplus = oracle.rcm(off, cols)
+    for root in graphgen.sample_roots(off, 4, 7):
+        for alpha, beta in [(14, 24), (64, 8), (2, 2)]:
+            d, p, st = G.bfs(root, opts=rb.make_opts(alpha=alpha, beta=beta), stats=True)
+            d_o, _, nlev = oracle.bfs(off, cols, root, perm_o)
+            c = oracle.level_counters(off, cols, d_o, perm_o, nplus)
+            sched = oracle.heuristic_schedule(c["nf"], c["mf"], c["mu"], nplus, alpha, beta)
+            assert st["levels"] == nlev
+            assert st["dir"] == sched.tolist()
+            assert st["nf"] == c["nf"].tolist()
+            assert st["mf"] == c["mf"].tolist()
+            assert st["mu"] == c["mu"].tolist()
+            assert st["reached"] == int((d_o >= 0).sum())
+            assert st["component_edges"] == oracle.component_edges(off, d_o)
+            # bottom-up levels read exactly the oracle's count of examined entries
+            for lv in range(nlev):
+                if st["dir"][lv] == 1:
+                    assert st["edges"][lv] == c["ebu"][lv]
+                else:
+                    assert st["edges"][lv] == c["mf"][lv]
+
+
+def test_repeatable(rb):
+    off, cols = kron(15, 5)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    root = graphgen.sample_roots(off, 1, 7)[0]
+    d0, p0 = G.bfs(root)
+    d0, p0 = d0.clone(), p0.clone()
+    for _ in range(20):
+        d, p = G.bfs(root)
+        assert torch.equal(d, d0) and torch.equal(p, p0)
+    G.check()
+
+
+def test_graph_create_rejects_bad_csr(rb):
+    off = np.array([0, 1, 2], np.int64)
+    cols = np.array([1, 1], np.int32)  # self loop at vertex 1
+    with pytest.raises(rb.RbfsError):
+        rb.Graph(off, cols, validate=True)
+    off = np.array([0, 2, 1], np.int64)  # non-monotone
+    with pytest.raises(rb.RbfsError):
+        rb.Graph(off, np.array([1, 0], np.int32))
+    off = np.array([0, 1, 2], np.int64)
+    with pytest.raises(rb.RbfsError):
+        rb.Graph(off, np.array([5, 0], np.int32))  # column out of range
+    off = np.array([0, 1, 1], np.int64)  # asymmetric
+    with pytest.raises(rb.RbfsError):
+        rb.Graph(off, np.array([1], np.int32), validate=True)
+
+
+def test_root_out_of_range(rb):
+    off, cols = csr_of(4, [(0, 1)])
+    G = rb.Graph(off, cols)
+    with pytest.raises(rb.RbfsError):
+        G.bfs(4)
+    with pytest.raises(rb.RbfsError):
+        G.bfs(-1)
+
+
+def test_device_generator_matches_host(rb):
+    off_h, cols_h = graphgen.kronecker_csr(14, 16, 33)
+    off_d, cols_d = graphgen.kronecker_csr_device(14, 16, 33)
+    assert np.array_equal(off_d.cpu().numpy(), off_h)
+    assert np.array_equal(cols_d.cpu().numpy(), cols_h)
+    off_h, cols_h = graphgen.chung_lu_csr(20000, 1000, seed=4, max_deg=2000.0, mean_deg=10.0)
+    off_d, cols_d = graphgen.chung_lu_csr_device(20000, 1000, seed=4, max_deg=2000.0,
+                                                 mean_deg=10.0)
+    assert np.array_equal(off_d.cpu().numpy(), off_h)
+    assert np.array_equal(cols_d.cpu().numpy(), cols_h)
