@@ -107,6 +107,7 @@ typedef struct rbfs_stats {
   int64_t mf[RBFS_STATS_MAX_LEVELS];         /* degree sum over F_d */
   int64_t mu[RBFS_STATS_MAX_LEVELS];         /* degree sum of unreached after F_d */
   int64_t edges[RBFS_STATS_MAX_LEVELS];      /* adjacency entries read at level d */
+  float level_us[RBFS_STATS_MAX_LEVELS];     /* device wall-clock time of level d */
   int64_t reached;                           /* vertices with depth >= 0 */
   int64_t component_edges;                   /* undirected edges among reached */
   float ms_kernel;                           /* search kernel time */

@@ -43,7 +43,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int32), ("status", ctypes.c_int32),
                 ("dir", ctypes.c_int8 * L), ("nf", ctypes.c_int64 * L),
                 ("mf", ctypes.c_int64 * L), ("mu", ctypes.c_int64 * L),
-                ("edges", ctypes.c_int64 * L), ("reached", ctypes.c_int64),
+                ("edges", ctypes.c_int64 * L), ("level_us", ctypes.c_float * L),
+                ("reached", ctypes.c_int64),
                 ("component_edges", ctypes.c_int64), ("ms_kernel", ctypes.c_float),
                 ("ms_total", ctypes.c_float)]
 
@@ -52,6 +53,7 @@ class Stats(ctypes.Structure):
         return {"levels": self.levels, "status": self.status,
                 "dir": list(self.dir[:n]), "nf": list(self.nf[:n]), "mf": list(self.mf[:n]),
                 "mu": list(self.mu[:n]), "edges": list(self.edges[:n]),
+                "level_us": list(self.level_us[:n]),
                 "reached": self.reached, "component_edges": self.component_edges,
                 "ms_kernel": self.ms_kernel, "ms_total": self.ms_total}
 

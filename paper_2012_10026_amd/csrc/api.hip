@@ -398,7 +398,8 @@ int rbfs_bfs(rbfs_graph_t* h, int32_t root, int32_t* depth, int32_t* parent,
   }
   return rbfs::bfs_impl(g, root, depth, parent, mode, alpha, beta,
                         opts ? opts->schedule : nullptr, opts ? opts->schedule_len : 0,
-                        out_space, opts ? opts->flags : 0, (hipStream_t)stream_, stats);
+                        out_space, opts ? opts->flags : 0, opts ? opts->tune_profile : 0,
+                        (hipStream_t)stream_, stats);
 }
 
 int rbfs_graph_timings(rbfs_graph_t* h, float* kernel_ms, float* total_ms, int32_t cap,

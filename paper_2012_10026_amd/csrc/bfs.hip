@@ -4,30 +4,39 @@
 //
 // Labels are the graph's internal labels; the swept set is [0, n_sweep)
 // (the non-isolated prefix after RCM).  parent(v) is the smallest-label
-// neighbour one level up; both step kinds reach exactly that value:
-//   top-down (Algorithm 1 / 4): for each frontier vertex u and neighbour w
-//     not visited before this level, depth[w] is claimed with a CAS
-//     (-1 -> d+1; the winner appends w to the next queue) and parent[w] is
-//     lowered with atomicMin(u), so the minimum over all frontier neighbours
-//     remains whatever the order;
-//   bottom-up (Algorithm 2 lines 15-21 / Algorithm 5): each unvisited v scans
-//     its row in increasing label order and stops at the first neighbour
-//     that was visited at the start of the level.  For an unvisited v every
-//     visited neighbour is in the current frontier, so that first hit is the
-//     smallest-label frontier neighbour.
-// The visited set is a bitmap.  Bottom-up reads the level-start bitmap and
-// writes the next one (each 64-vertex word is owned by one wave, found bits
-// come from one ballot: no atomics, the GPU form of the paper's cache-line
-// blocks and of its visited |= next update outside the loop).  Top-down
-// reads the bitmap to skip visited vertices and ORs the new vertices in after
-// the level.
+// neighbour one level up, reached the same way by both step kinds: a scan of
+// v's row in increasing label order that stops at the first neighbour in the
+// current frontier F_d (any visited neighbour of a vertex first reached at
+// level d+1 lies in F_d), or the minimum over all its frontier neighbours:
+//   top-down (Algorithms 1 and 4): frontier edges (u, w) are spread evenly
+//     over the GPU; w not yet visited is claimed with one CAS on depth
+//     (-1 -> d+1; the winner appends w) and every frontier edge into w
+//     lowers parent[w] with atomicMin(u).  (Scanning w's row for the first
+//     frontier neighbour instead would read nearly whole rows here: after
+//     RCM the hubs that make up the early frontiers carry the highest
+//     labels.);
+//   bottom-up (Algorithm 2 lines 15-21, Algorithm 5): every unvisited v scans
+//     its own row; one wave owns a 64-vertex word, the found bits come from
+//     one ballot and are stored without atomics (the GPU form of the paper's
+//     cache-line blocks).
 //
-// Queues carry, besides the vertex, the exclusive prefix of degrees, which
-// the appending wave obtains from one packed 64-bit atomic
-// (count << eb | edges).  That prefix drives the edge-balanced top-down
-// expansion of the next level without a separate scan.
-// Bottom-up work is cut into edge-balanced ranges of words and handed out
-// with an atomic counter (the fetch_add work stealing of Algorithm 5).
+// Visited state: `vis` (reached before level d) plus three rotating frontier
+// bitmaps: front[d % 3] = F_d, front[(d+1) % 3] receives F_{d+1}, and
+// front[(d+2) % 3] (holding the dead F_{d-1}) is cleared for the next level.
+// "Visited at the start of level d" is vis | F_d, so folding F_d into vis can
+// happen during level d itself (the paper's visited |= next outside the
+// loop), and every level needs exactly one grid barrier.
+//
+// Every workgroup keeps the level state (level, direction, |F|, degree sums)
+// in registers and takes the direction decision itself from the one packed
+// counter it reads after the barrier, so nothing runs serially inside the
+// barrier.  Queue appends are staged per wave in LDS and published with one
+// packed 64-bit atomic (count << eb | degree sum) per batch; the returned
+// base gives both the queue position and the exclusive degree prefix that
+// drives the edge-balanced top-down expansion of the next level.  Bottom-up
+// work is cut into edge-balanced ranges of words handed out by fetch-add
+// counters (the work stealing of Algorithm 5), one counter per group of
+// workgroups (blockIdx mod 8) with stealing across groups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -41,25 +50,25 @@
 
 namespace rbfs {
 
-struct BfsCtl {
+struct alignas(128) BfsCtl {
   GridBarrier bar;
-  int level;
-  int dir;
-  int done;
-  int pad0;
-  unsigned long long qpack[2];
-  long long nf, mf, mu, nf_prev;
-  unsigned long long work;
-  unsigned long long edges_level;
+  alignas(128) unsigned long long qpack[3][16];     // [rotation][0], own line each
+  alignas(128) unsigned long long work[3][8][16];   // BU range counters per group
+  alignas(128) unsigned long long edges[3][16];     // entries read this level
+  int levels;
+  int pad;
   long long reached, deg_reached;
   signed char hdir[RBFS_STATS_MAX_LEVELS];
   long long hnf[RBFS_STATS_MAX_LEVELS];
   long long hmf[RBFS_STATS_MAX_LEVELS];
   long long hmu[RBFS_STATS_MAX_LEVELS];
   long long hedges[RBFS_STATS_MAX_LEVELS];
+  unsigned long long hts[RBFS_STATS_MAX_LEVELS + 1];
 };
 
 namespace {
+
+constexpr int kStage = 256;  // staged appends per wave
 
 struct BfsParams {
   const int64_t* off;
@@ -70,7 +79,8 @@ struct BfsParams {
   int64_t deg_total;     // degree sum over the swept set
   int32_t* depth;
   uint32_t* parent;
-  uint64_t* vis[2];
+  uint64_t* vis;
+  uint64_t* front[3];
   int32_t* qv[2];
   int64_t* qe[2];
   int32_t* chunk[2];
@@ -88,31 +98,70 @@ struct BfsParams {
   BfsCtl* ctl;
 };
 
-__device__ __forceinline__ void wave_append(bool take, int32_t v, int64_t deg,
-                                            unsigned long long* qpack, int eb, int32_t* qv,
-                                            int64_t* qe, int32_t* chunk, int64_t chunk_cap,
-                                            int64_t qcap, int* status) {
+struct StageLds {
+  int32_t v[kWavesPerBlock][kStage];
+  int32_t d[kWavesPerBlock][kStage];
+  int32_t cnt[kWavesPerBlock];
+};
+
+// Publishes this wave's staged vertices to the next queue.
+__device__ __forceinline__ void flush_stage(StageLds& st, const BfsParams& P, int nq_idx,
+                                            unsigned long long* qpack) {
+  const int wv = wave_id(), l = lane_id();
+  const int cnt = st.cnt[wv];
+  if (cnt == 0) return;
+  int64_t total = 0;
+  for (int j0 = 0; j0 < cnt; j0 += kWave) {
+    const int j = j0 + l;
+    total += (j < cnt) ? (int64_t)st.d[wv][j] : 0;
+  }
+  total = wave_sum(total);
+  unsigned long long old = 0;
+  if (l == 0)
+    old = atomicAdd(qpack, ((unsigned long long)cnt << P.eb) + (unsigned long long)total);
+  old = shfl(old, 0);
+  const int64_t pos0 = (int64_t)(old >> P.eb);
+  int64_t ebase = (int64_t)(old & ((1ull << P.eb) - 1ull));
+  if (pos0 + cnt > P.n_sweep) {
+    if (l == 0) atomicOr(&P.ctl->bar.status, kStatusOverflow);
+  } else {
+    for (int j0 = 0; j0 < cnt; j0 += kWave) {
+      const int j = j0 + l;
+      const bool act = j < cnt;
+      const int64_t d = act ? (int64_t)st.d[wv][j] : 0;
+      const int64_t inc = wave_inclusive_sum(d);
+      if (act) {
+        const int64_t pos = pos0 + j;
+        const int64_t base = ebase + inc - d;
+        P.qv[nq_idx][pos] = st.v[wv][j];
+        P.qe[nq_idx][pos] = base;
+        mark_chunks(P.chunk[nq_idx], P.chunk_cap, base, d, (int32_t)pos);
+      }
+      ebase += shfl(inc, kWave - 1);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (l == 0) st.cnt[wv] = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Stages the vertices of the lanes with take = true; flushes when full.
+__device__ __forceinline__ void stage(StageLds& st, bool take, int32_t v, int64_t deg,
+                                      const BfsParams& P, int nq_idx,
+                                      unsigned long long* qpack) {
   const uint64_t m = ballot(take);
   if (m == 0) return;
-  const int64_t d = take ? deg : 0;
-  const int64_t inc = wave_inclusive_sum(d);
-  const int64_t tot = shfl(inc, kWave - 1);
-  const int leader = ffs64(m);
-  unsigned long long old = 0;
-  if (lane_id() == leader)
-    old = atomicAdd(qpack, ((unsigned long long)popc64(m) << eb) + (unsigned long long)tot);
-  old = shfl(old, leader);
+  const int wv = wave_id();
+  const int base = st.cnt[wv];
+  __builtin_amdgcn_wave_barrier();
   if (take) {
-    const int64_t pos = (int64_t)(old >> eb) + popc64(m & lanemask_lt());
-    const int64_t base = (int64_t)(old & ((1ull << eb) - 1ull)) + inc - d;
-    if (pos >= qcap) {
-      atomicOr(status, kStatusOverflow);
-      return;
-    }
-    qv[pos] = v;
-    qe[pos] = base;
-    mark_chunks(chunk, chunk_cap, base, deg, (int32_t)pos);
+    const int pos = base + popc64(m & lanemask_lt());
+    st.v[wv][pos] = v;
+    st.d[wv][pos] = (int32_t)deg;
   }
+  if (lane_id() == 0) st.cnt[wv] = base + popc64(m);
+  __builtin_amdgcn_wave_barrier();
+  if (base + popc64(m) > kStage - kWave) flush_stage(st, P, nq_idx, qpack);
 }
 
 __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf, long long mu,
@@ -122,20 +171,179 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
   return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
 }
 
-// Runs on the last workgroup to reach the end-of-level barrier.
-__device__ void decide(const BfsParams& P, int out_buf) {
-  if (threadIdx.x != 0) return;
-  BfsCtl* c = P.ctl;
-  const unsigned long long pk = c->qpack[out_buf];
-  const long long nf_new = (long long)(pk >> P.eb);
-  const long long mf_new = (long long)(pk & ((1ull << P.eb) - 1ull));
-  const int L = c->level;
-  if (L < RBFS_STATS_MAX_LEVELS) c->hedges[L] = (long long)c->edges_level;
-  const long long mu_new = c->mu - mf_new;
-  int nd = c->dir;
-  if (nf_new == 0) {
-    c->done = 1;
-  } else {
+__global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
+  __shared__ ChunkLds s_chunk;
+  __shared__ StageLds s_st;
+  BfsCtl* ctl = P.ctl;
+  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * kBlock;
+  const int32_t root = P.perm ? P.perm[P.root_orig] : P.root_orig;
+  const bool root_in = root < P.n_sweep;
+  const int64_t W = ceil_div(P.n_sweep, kWave);
+  const uint64_t emask = (1ull << P.eb) - 1ull;
+  const int l = lane_id();
+  if (threadIdx.x < kWavesPerBlock) s_st.cnt[threadIdx.x] = 0;
+
+  // ---- initialisation
+  if (P.init) {
+    for (int64_t i = gtid; i < P.n_init; i += gsz) {
+      P.depth[i] = (i == root) ? 0 : -1;
+      P.parent[i] = (i == root) ? (uint32_t)root : kNoParent;
+    }
+  }
+  for (int64_t w = gtid; w < W; w += gsz) {
+    P.vis[w] = 0ull;
+    P.front[0][w] = (root_in && w == (root >> 6)) ? (1ull << (root & 63)) : 0ull;
+    P.front[1][w] = 0ull;
+  }
+  const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
+  if (gtid == 0) {
+    if (!P.init && root_in) {
+      P.depth[root] = 0;
+      P.parent[root] = (uint32_t)root;
+    }
+    for (int r = 0; r < 2; ++r) {
+      ctl->qpack[r][0] = 0ull;
+      ctl->edges[r][0] = 0ull;
+      for (int g = 0; g < 8; ++g) ctl->work[r][g][0] = 0ull;
+    }
+    ctl->qpack[0][0] = root_in ? ((1ull << P.eb) | (unsigned long long)dr) : 0ull;
+    ctl->hdir[0] = 0;
+    ctl->hnf[0] = 1;
+    ctl->hmf[0] = dr;
+    ctl->hmu[0] = P.deg_total - dr;
+    ctl->hts[0] = (unsigned long long)wall_clock64();
+    if (root_in) {
+      P.qv[0][0] = root;
+      P.qe[0][0] = 0;
+      mark_chunks(P.chunk[0], P.chunk_cap, 0, dr, 0);
+    }
+  }
+  __syncthreads();
+  if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+  // level state, identical in every workgroup
+  int L = 0;
+  int dir = 0;
+  long long nf = root_in ? 1 : 0, mf = dr, mu = P.deg_total - dr;
+  long long reached = 1, deg_reached = dr;
+  while (nf > 0) {
+    const int c3 = L % 3, n3 = (L + 1) % 3, z3 = (L + 2) % 3;
+    const int qc = L & 1, qn = qc ^ 1;
+    const uint64_t* fcur = P.front[c3];
+    uint64_t* fnext = P.front[n3];
+    unsigned long long* qpack = &ctl->qpack[n3][0];
+    int64_t examined = 0;
+    // clear what level L+1 will fill
+    for (int64_t w = gtid; w < W; w += gsz) P.front[z3][w] = 0ull;
+    if (gtid == 0) {
+      ctl->qpack[z3][0] = 0ull;
+      ctl->edges[z3][0] = 0ull;
+      for (int g = 0; g < 8; ++g) ctl->work[z3][g][0] = 0ull;
+    }
+    if (dir == 0) {
+      // ---- top-down
+      if (nf * 8 < W) {
+        for (int64_t i = gtid; i < nf; i += gsz) {
+          const int32_t u = P.qv[qc][i];
+          atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
+        }
+      } else {
+        for (int64_t w = gtid; w < W; w += gsz) P.vis[w] |= fcur[w];
+      }
+      const int64_t E = mf;
+      const int64_t nchunks = ceil_div(E, kChunkEdges);
+      for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const bool ok = expand_chunk(s_chunk, c, E, P.qv[qc], P.qe[qc], nf, P.chunk[qc],
+                                     nchunks, P.off, P.cols,
+                                     [&](bool active, int32_t u, int32_t w) {
+          bool claim = false;
+          int64_t dw = 0;
+          if (active) {
+            const uint64_t word = P.vis[w >> 6] | fcur[w >> 6];
+            if (!((word >> (w & 63)) & 1ull) && P.depth[w] == -1) {
+              claim = atomicCAS(&P.depth[w], -1, L + 1) == -1;
+              if (claim) {
+                dw = P.off[w + 1] - P.off[w];
+                atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+              }
+            }
+            // w is unvisited at level start: depth[w] is now L+1, u is a
+            // candidate parent (a stale read can only be larger)
+            if (!((word >> (w & 63)) & 1ull) && P.parent[w] > (uint32_t)u)
+              atomicMin(&P.parent[w], (uint32_t)u);
+          }
+          stage(s_st, claim, w, dw, P, qn, qpack);
+        });
+        if (!ok) {
+          if (threadIdx.x == 0) atomicOr(&ctl->bar.status, kStatusBadInput);
+          break;
+        }
+      }
+      flush_stage(s_st, P, qn, qpack);
+      if (gtid == 0) examined = E;
+    } else {
+      // ---- bottom-up over edge-balanced word ranges
+      const int g0 = blockIdx.x & 7;
+      for (int t = 0; t < 8; ++t) {
+        const int g = (g0 + t) & 7;
+        const int64_t lo = (int64_t)P.n_part * g / 8, hi = (int64_t)P.n_part * (g + 1) / 8;
+        for (;;) {
+          unsigned long long p = 0;
+          if (l == 0) {
+            // look before taking: exhausted groups cost a load, not an atomic
+            p = __hip_atomic_load(&ctl->work[c3][g][0], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            if (lo + (int64_t)p < hi)
+              p = __hip_atomic_fetch_add(&ctl->work[c3][g][0], 1ull, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+          }
+          p = shfl(p, 0);
+          if (lo + (int64_t)p >= hi) break;
+          const int64_t part = lo + (int64_t)p;
+          const int64_t k0 = P.bu_part[part], k1 = P.bu_part[part + 1];
+          for (int64_t k = k0; k < k1; ++k) {
+            const uint64_t vk = P.vis[k], fk = fcur[k];
+            const int64_t v = k * kWave + l;
+            const bool unvis = (v < P.n_sweep) && !(((vk | fk) >> l) & 1ull);
+            if (l == 0) P.vis[k] = vk | fk;
+            if (ballot(unvis) == 0) {
+              if (l == 0) fnext[k] = 0ull;
+              continue;
+            }
+            int64_t b = 0, e = 0;
+            if (unvis) {
+              b = P.off[v];
+              e = P.off[v + 1];
+            }
+            bool found;
+            int32_t par;
+            wave_first_hit(unvis, b, e, P.cols, fcur, found, par, examined);
+            const uint64_t fm = ballot(found);
+            if (l == 0) fnext[k] = fm;
+            if (found) {
+              P.depth[v] = L + 1;
+              P.parent[v] = (uint32_t)par;
+            }
+            stage(s_st, found, (int32_t)v, e - b, P, qn, qpack);
+          }
+        }
+      }
+      flush_stage(s_st, P, qn, qpack);
+    }
+    const int64_t ex = wave_sum(examined);
+    if (l == 0 && ex)
+      __hip_atomic_fetch_add(&ctl->edges[c3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+    // ---- next level: every workgroup decides the same way
+    const unsigned long long pk =
+        __hip_atomic_load(&ctl->qpack[n3][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long nf_new = (long long)(pk >> P.eb);
+    const long long mf_new = (long long)(pk & emask);
+    const long long mu_new = mu - mf_new;
+    int nd = dir;
     switch (P.mode) {
       case RBFS_DIR_TD_ONLY: nd = 0; break;
       case RBFS_DIR_BU_ONLY: nd = 1; break;
@@ -146,223 +354,30 @@ __device__ void decide(const BfsParams& P, int out_buf) {
         break;
       }
       default:
-        nd = heuristic_dir(c->dir, nf_new, mf_new, mu_new, c->nf, P.n_sweep, P.alpha, P.beta);
+        nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
     }
-    if (L + 1 < RBFS_STATS_MAX_LEVELS) {
-      c->hdir[L + 1] = (signed char)nd;
-      c->hnf[L + 1] = nf_new;
-      c->hmf[L + 1] = mf_new;
-      c->hmu[L + 1] = mu_new;
+    if (gtid == 0 && L < RBFS_STATS_MAX_LEVELS) {
+      ctl->hedges[L] = (long long)ctl->edges[c3][0];
+      ctl->hts[L + 1] = (unsigned long long)wall_clock64();
+      if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
+        ctl->hdir[L + 1] = (signed char)nd;
+        ctl->hnf[L + 1] = nf_new;
+        ctl->hmf[L + 1] = mf_new;
+        ctl->hmu[L + 1] = mu_new;
+      }
     }
+    nf = nf_new;
+    mf = mf_new;
+    mu = mu_new;
+    dir = nd;
+    reached += nf_new;
+    deg_reached += mf_new;
+    ++L;
   }
-  c->nf_prev = c->nf;
-  c->nf = nf_new;
-  c->mf = mf_new;
-  c->mu = mu_new;
-  c->dir = nd;
-  c->level = L + 1;
-  c->reached += nf_new;
-  c->deg_reached += mf_new;
-  c->qpack[out_buf ^ 1] = 0ull;  // the consumed queue is the next output
-  c->work = 0ull;
-  c->edges_level = 0ull;
-}
-
-__global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
-  __shared__ ChunkLds s_chunk;
-  BfsCtl* ctl = P.ctl;
-  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * kBlock;
-  const int32_t root = P.perm ? P.perm[P.root_orig] : P.root_orig;
-  const bool root_in = root < P.n_sweep;
-  const int64_t W = ceil_div(P.n_sweep, kWave);
-  const uint64_t emask = (1ull << P.eb) - 1ull;
-
-  // ---- initialisation
-  if (P.init) {
-    for (int64_t i = gtid; i < P.n_init; i += gsz) {
-      P.depth[i] = (i == root) ? 0 : -1;
-      P.parent[i] = (i == root) ? (uint32_t)root : kNoParent;
-    }
-  }
-  for (int64_t w = gtid; w < W; w += gsz)
-    P.vis[0][w] = (root_in && w == (root >> 6)) ? (1ull << (root & 63)) : 0ull;
   if (gtid == 0) {
-    const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
-    if (!P.init && root_in) {
-      P.depth[root] = 0;
-      P.parent[root] = (uint32_t)root;
-    }
-    ctl->level = 0;
-    ctl->dir = 0;
-    ctl->done = root_in ? 0 : 1;
-    ctl->qpack[0] = root_in ? ((1ull << P.eb) | (unsigned long long)dr) : 0ull;
-    ctl->qpack[1] = 0ull;
-    ctl->nf = root_in ? 1 : 0;
-    ctl->mf = dr;
-    ctl->mu = P.deg_total - dr;
-    ctl->nf_prev = 0;
-    ctl->work = 0ull;
-    ctl->edges_level = 0ull;
-    ctl->reached = 1;
-    ctl->deg_reached = dr;
-    ctl->hdir[0] = 0;
-    ctl->hnf[0] = ctl->nf;
-    ctl->hmf[0] = dr;
-    ctl->hmu[0] = ctl->mu;
-    if (root_in) {
-      P.qv[0][0] = root;
-      P.qe[0][0] = 0;
-      mark_chunks(P.chunk[0], P.chunk_cap, 0, dr, 0);
-    }
-  }
-  if (!grid_barrier(&ctl->bar, P.timeout_ticks, [] {})) return;
-
-  int cur = 0;  // queue buffer holding the current frontier
-  int vc = 0;   // bitmap holding the level-start visited set
-  for (;;) {
-    const int done = ld_relaxed(&ctl->done);
-    if (done) break;
-    const int L = ld_relaxed(&ctl->level);
-    const int dir = ld_relaxed(&ctl->dir);
-    const int nb = cur ^ 1;
-    const uint64_t* vis = P.vis[vc];
-    if (dir == 0) {
-      // ---- top-down step over frontier edges, chunk by chunk
-      const unsigned long long pk = __hip_atomic_load(&ctl->qpack[cur], __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-      const int64_t nq = (int64_t)(pk >> P.eb);
-      const int64_t E = (int64_t)(pk & emask);
-      const int64_t nchunks = ceil_div(E, kChunkEdges);
-      for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const bool ok = expand_chunk(s_chunk, c, E, P.qv[cur], P.qe[cur], nq, P.chunk[cur],
-                                     nchunks, P.off, P.cols,
-                                     [&](bool active, int32_t u, int32_t w) {
-          bool win = false;
-          int64_t dw = 0;
-          if (active && !test_bit(vis, (uint32_t)w)) {
-            int dcur = P.depth[w];
-            if (dcur == -1) {
-              const int old = atomicCAS(&P.depth[w], -1, L + 1);
-              win = (old == -1);
-            }
-            if (P.parent[w] > (uint32_t)u) atomicMin(&P.parent[w], (uint32_t)u);
-            if (win) dw = P.off[w + 1] - P.off[w];
-          }
-          wave_append(win, w, dw, &ctl->qpack[nb], P.eb, P.qv[nb], P.qe[nb], P.chunk[nb],
-                      P.chunk_cap, P.n_sweep, &ctl->bar.status);
-        });
-        if (!ok) {
-          if (threadIdx.x == 0) atomicOr(&ctl->bar.status, kStatusBadInput);
-          break;
-        }
-      }
-      if (threadIdx.x == 0 && blockIdx.x == 0) {
-        __hip_atomic_fetch_add(&ctl->edges_level, (unsigned long long)E, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      }
-      if (!grid_barrier(&ctl->bar, P.timeout_ticks, [&] { decide(P, nb); })) return;
-      // new vertices join the visited bitmap
-      int64_t nn = (int64_t)(__hip_atomic_load(&ctl->qpack[nb], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT) >> P.eb);
-      if (nn > P.n_sweep) nn = P.n_sweep;
-      uint64_t* visw = P.vis[vc];
-      for (int64_t i = gtid; i < nn; i += gsz) {
-        const int32_t w = P.qv[nb][i];
-        atomicOr((unsigned long long*)&visw[w >> 6], 1ull << (w & 63));
-      }
-      if (!grid_barrier(&ctl->bar, P.timeout_ticks, [] {})) return;
-    } else {
-      // ---- bottom-up step over the swept words, edge-balanced ranges
-      uint64_t* visn = P.vis[vc ^ 1];
-      const int l = lane_id();
-      int64_t examined = 0;
-      for (;;) {
-        unsigned long long p = 0;
-        if (l == 0)
-          p = __hip_atomic_fetch_add(&ctl->work, 1ull, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_AGENT);
-        p = shfl(p, 0);
-        if ((int64_t)p >= P.n_part) break;
-        const int64_t k0 = P.bu_part[p], k1 = P.bu_part[p + 1];
-        for (int64_t k = k0; k < k1; ++k) {
-          const uint64_t curw = vis[k];
-          const int64_t v = k * kWave + l;
-          const bool valid = v < P.n_sweep;
-          const bool unvis = valid && !((curw >> l) & 1ull);
-          if (ballot(unvis) == 0) {
-            if (l == 0) visn[k] = curw;
-            continue;
-          }
-          int64_t b = 0, e = 0;
-          if (unvis) {
-            b = P.off[v];
-            e = P.off[v + 1];
-          }
-          const bool hub = unvis && (e - b) > kLaneRow;
-          bool found = false;
-          int32_t par = 0;
-          if (unvis && !hub) {
-            for (int64_t j = b; j < e; ++j) {
-              const int32_t w = P.cols[j];
-              if (test_bit(vis, (uint32_t)w)) {
-                found = true;
-                par = w;
-                examined += j - b + 1;
-                break;
-              }
-            }
-            if (!found) examined += e - b;
-          }
-          uint64_t hubs = ballot(hub);
-          while (hubs) {
-            const int h = ffs64(hubs);
-            hubs &= hubs - 1;
-            const int64_t hb = shfl(b, h), he = shfl(e, h);
-            bool hf = false;
-            int32_t hp = 0;
-            int64_t scanned = he - hb;
-            for (int64_t j0 = hb; j0 < he; j0 += kWave) {
-              const int64_t j = j0 + l;
-              int32_t w = 0;
-              bool hit = false;
-              if (j < he) {
-                w = P.cols[j];
-                hit = test_bit(vis, (uint32_t)w);
-              }
-              const uint64_t hm = ballot(hit);
-              if (hm) {
-                const int first = ffs64(hm);
-                hp = shfl(w, first);
-                hf = true;
-                scanned = j0 - hb + first + 1;
-                break;
-              }
-            }
-            if (l == h) {
-              found = hf;
-              par = hp;
-            }
-            if (l == 0) examined += scanned;
-          }
-          const uint64_t fm = ballot(found);
-          if (l == 0) visn[k] = curw | fm;
-          if (found) {
-            P.depth[v] = L + 1;
-            P.parent[v] = (uint32_t)par;
-          }
-          wave_append(found, (int32_t)v, e - b, &ctl->qpack[nb], P.eb, P.qv[nb], P.qe[nb],
-                      P.chunk[nb], P.chunk_cap, P.n_sweep, &ctl->bar.status);
-        }
-      }
-      const int64_t ex = wave_sum(examined);
-      if (l == 0 && ex)
-        __hip_atomic_fetch_add(&ctl->edges_level, (unsigned long long)ex, __ATOMIC_RELAXED,
-                               __HIP_MEMORY_SCOPE_AGENT);
-      if (!grid_barrier(&ctl->bar, P.timeout_ticks, [&] { decide(P, nb); })) return;
-      vc ^= 1;
-    }
-    cur = nb;
+    ctl->levels = root_in ? L : 1;
+    ctl->reached = reached;
+    ctl->deg_reached = deg_reached;
   }
 }
 
@@ -393,11 +408,9 @@ __global__ void translate_kernel(int64_t n, const int32_t* perm, const int32_t* 
 }
 
 __global__ void reset_ctl_kernel(BfsCtl* c) {
-  if (threadIdx.x == 0) {
-    c->bar.count = 0;
-    c->bar.gen = 0;
-    c->bar.status = 0;
-  }
+  int* p = (int*)&c->bar;
+  for (int i = threadIdx.x; i < (int)(sizeof(GridBarrier) / sizeof(int)); i += blockDim.x)
+    p[i] = 0;
 }
 
 // Edge-balanced word ranges over the swept set for the bottom-up step.
@@ -418,14 +431,13 @@ __global__ void bu_part_kernel(const int64_t* off, int64_t n_sweep, int64_t targ
   }
 }
 
-
 }  // namespace
 
 void free_bfs_work(Graph* g) {
   BfsWork* w = g->bfs;
   if (!w) return;
-  void* ps[] = {w->depth, w->parent, w->vis[0], w->vis[1], w->qv[0], w->qv[1], w->qe[0],
-                w->qe[1], w->chunk[0], w->chunk[1], w->bu_part, w->ctl};
+  void* ps[] = {w->depth, w->parent, w->vis, w->front, w->qv[0], w->qv[1],
+                w->qe[0], w->qe[1], w->chunk[0], w->chunk[1], w->bu_part, w->ctl};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -444,28 +456,13 @@ void free_bfs_work(Graph* g) {
     }                                                                           \
   } while (0)
 
-static int ensure_bfs_work(Graph* g, hipStream_t stream) {
-  if (g->bfs) return 0;
-  BfsWork* w = new BfsWork();
-  g->bfs = w;
-  const int64_t ns = g->n_sweep > 0 ? g->n_sweep : 1;
-  const int64_t W = ceil_div(ns, kWave);
-  w->n_sweep = g->n_sweep;
-  BFS_CHECK(hipMalloc(&w->depth, sizeof(int32_t) * ns));
-  BFS_CHECK(hipMalloc(&w->parent, sizeof(uint32_t) * ns));
-  for (int i = 0; i < 2; ++i) {
-    BFS_CHECK(hipMalloc(&w->vis[i], sizeof(uint64_t) * W));
-    BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * ns));
-    BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * ns));
-  }
-  w->chunk_cap = ceil_div(g->nnz, kChunkEdges) + 2;
-  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * w->chunk_cap));
-  BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
-  BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
-  // bottom-up ranges: about 64K adjacency entries each, at most 256 words each
-  const int64_t nnz_sweep = g->nnz;  // isolated vertices contribute no entries
-  const int64_t target = std::max<int64_t>(4096, nnz_sweep / 16384 + 1);
-  const int64_t nparts_e = std::max<int64_t>(1, ceil_div(nnz_sweep, target));
+// Edge-balanced bottom-up ranges: about nnz / nparts_want adjacency entries
+// each, at most W / nparts_want words each.
+static int build_bu_parts(Graph* g, BfsWork* w, int64_t nparts_want, hipStream_t stream) {
+  const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
+  const int64_t target = std::max<int64_t>(2048, g->nnz / std::max<int64_t>(1, nparts_want) + 1);
+  const int64_t nparts_e = std::max<int64_t>(1, ceil_div(g->nnz, target));
+  const int64_t max_words = std::max<int64_t>(64, W / std::max<int64_t>(1, nparts_want) + 1);
   int32_t* d_b = nullptr;
   BFS_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
   hipLaunchKernelGGL(bu_part_kernel, dim3((unsigned)ceil_div(nparts_e + 1, 256)), dim3(256), 0,
@@ -480,36 +477,63 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   parts.push_back(0);
   for (int64_t p = 1; p <= nparts_e; ++p) {
     int32_t a = parts.back(), b = std::max(hb[p], a);
-    while (b - a > 256) {
-      a += 256;
+    while (b - a > max_words) {
+      a += (int32_t)max_words;
       parts.push_back(a);
     }
     if (b > parts.back()) parts.push_back(b);
   }
   if (parts.back() != (int32_t)W) parts.push_back((int32_t)W);
   w->n_part = (int32_t)parts.size() - 1;
+  if (w->bu_part) (void)hipFree(w->bu_part);
+  w->bu_part = nullptr;
   BFS_CHECK(hipMalloc(&w->bu_part, sizeof(int32_t) * parts.size()));
   BFS_CHECK(hipMemcpyAsync(w->bu_part, parts.data(), sizeof(int32_t) * parts.size(),
                            hipMemcpyHostToDevice, stream));
+  BFS_CHECK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+static int ensure_bfs_work(Graph* g, hipStream_t stream) {
+  if (g->bfs) return 0;
+  BfsWork* w = new BfsWork();
+  g->bfs = w;
+  const int64_t ns = g->n_sweep > 0 ? g->n_sweep : 1;
+  const int64_t W = ceil_div(ns, kWave);
+  w->n_sweep = g->n_sweep;
+  BFS_CHECK(hipMalloc(&w->depth, sizeof(int32_t) * ns));
+  BFS_CHECK(hipMalloc(&w->parent, sizeof(uint32_t) * ns));
+  BFS_CHECK(hipMalloc(&w->vis, sizeof(uint64_t) * W));
+  BFS_CHECK(hipMalloc(&w->front, sizeof(uint64_t) * 3 * W));
+  for (int i = 0; i < 2; ++i) {
+    BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * ns));
+    BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * ns));
+  }
+  w->chunk_cap = ceil_div(g->nnz, kChunkEdges) + 2;
+  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * w->chunk_cap));
+  BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
+  BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
   int per_cu = 0;
   BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel, kBlock,
                                                           0));
   if (per_cu < 1) per_cu = 1;
-  if (per_cu > 4) per_cu = 4;
-  w->grid = per_cu * g->compute_units;
+  w->max_per_cu = per_cu;
+  w->grid = std::min(per_cu, 2) * g->compute_units;
+  int rc = build_bu_parts(g, w, 4 * (int64_t)w->grid * kWavesPerBlock, stream);
+  if (rc) return rc;
   BFS_CHECK(hipEventCreate(&w->ev0));
   BFS_CHECK(hipEventCreate(&w->ev1));
   BFS_CHECK(hipEventCreate(&w->ev2));
   BFS_CHECK(hipStreamSynchronize(stream));
   w->clean = false;
   g->bytes += (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * (size_t)ns +
-              sizeof(uint64_t) * 2 * W + sizeof(int32_t) * 2 * w->chunk_cap;
+              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * w->chunk_cap;
   return 0;
 }
 
 int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, int alpha,
              int beta, const int8_t* sched, int sched_len, int out_space, int flags,
-             hipStream_t stream, void* stats_v) {
+             int tune_profile, hipStream_t stream, void* stats_v) {
   rbfs_stats_t* stats = (rbfs_stats_t*)stats_v;
   int rc = ensure_bfs_work(g, stream);
   if (rc) return rc;
@@ -517,7 +541,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   const bool translate = g->reordered && out_space == RBFS_OUT_ORIGINAL;
   const int bits_n = bits_for(g->n_sweep + 2);
   const int eb = 64 - bits_n;
-  if (eb < 40 && (g->nnz >> eb) != 0) {
+  if (((uint64_t)g->nnz >> eb) != 0) {
     set_error("bfs: graph too large for the packed queue counter");
     return RBFS_E_UNSUPPORTED;
   }
@@ -538,8 +562,10 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     P.init = 1;
     P.n_init = g->n;
   }
+  const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
+  P.vis = w->vis;
+  for (int i = 0; i < 3; ++i) P.front[i] = w->front + (size_t)i * W;
   for (int i = 0; i < 2; ++i) {
-    P.vis[i] = w->vis[i];
     P.qv[i] = w->qv[i];
     P.qe[i] = w->qe[i];
     P.chunk[i] = w->chunk[i];
@@ -568,9 +594,11 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   if (flags & RBFS_OPT_TIMING) BFS_CHECK(g->timing.next(&tev));
   if (tev) BFS_CHECK(hipEventRecord(tev[0], stream));
   BFS_CHECK(hipEventRecord(w->ev0, stream));
-  hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(64), 0, stream, w->ctl);
+  hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(256), 0, stream, w->ctl);
   BFS_CHECK(hipGetLastError());
-  hipLaunchKernelGGL(bfs_persistent_kernel, dim3(w->grid), dim3(kBlock), 0, stream, P);
+  int grid = w->grid;
+  if (tune_profile > 0) grid = std::min(tune_profile, w->max_per_cu) * g->compute_units;
+  hipLaunchKernelGGL(bfs_persistent_kernel, dim3(grid), dim3(kBlock), 0, stream, P);
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
@@ -584,27 +612,35 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipEventRecord(w->ev2, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[2], stream));
   if (stats) {
-    BfsCtl h;
-    BFS_CHECK(hipMemcpyAsync(&h, w->ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, stream));
-    BFS_CHECK(hipStreamSynchronize(stream));
-    memset(stats, 0, sizeof(*stats));
-    stats->levels = h.level;
-    stats->status = h.bar.status;
-    const int nl = std::min(h.level, RBFS_STATS_MAX_LEVELS);
-    for (int i = 0; i < nl; ++i) {
-      stats->dir[i] = h.hdir[i];
-      stats->nf[i] = h.hnf[i];
-      stats->mf[i] = h.hmf[i];
-      stats->mu[i] = h.hmu[i];
-      stats->edges[i] = h.hedges[i];
+    BfsCtl* h = new BfsCtl;
+    hipError_t e = hipMemcpyAsync(h, w->ctl, sizeof(BfsCtl), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+      delete h;
+      BFS_CHECK(e);
     }
-    stats->reached = h.reached;
-    stats->component_edges = h.deg_reached / 2;
+    memset(stats, 0, sizeof(*stats));
+    stats->levels = h->levels;
+    stats->status = h->bar.status;
+    const int nl = std::min(h->levels, RBFS_STATS_MAX_LEVELS);
+    for (int i = 0; i < nl; ++i) {
+      stats->dir[i] = h->hdir[i];
+      stats->nf[i] = h->hnf[i];
+      stats->mf[i] = h->hmf[i];
+      stats->mu[i] = h->hmu[i];
+      stats->edges[i] = h->hedges[i];
+      stats->level_us[i] = (float)((double)(h->hts[i + 1] - h->hts[i]) * 1000.0 /
+                                   (double)g->wall_rate_khz);
+    }
+    stats->reached = h->reached;
+    stats->component_edges = h->deg_reached / 2;
+    const int st = h->bar.status;
+    delete h;
     BFS_CHECK(hipEventElapsedTime(&stats->ms_kernel, w->ev0, w->ev1));
     BFS_CHECK(hipEventElapsedTime(&stats->ms_total, w->ev0, w->ev2));
-    if (h.bar.status != 0) {
+    if (st != 0) {
       w->clean = false;
-      set_error("bfs: device status " + std::to_string(h.bar.status));
+      set_error("bfs: device status " + std::to_string(st));
       return RBFS_E_DEVICE;
     }
   }

@@ -72,51 +72,63 @@ __device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
 // ---------------------------------------------------------------------------
 // Grid barrier for a persistent kernel whose whole grid is resident.
 //
-// Arrival counter plus generation number.  The last workgroup to arrive runs
-// `last_fn` (with every workgroup's writes visible), resets the counter and
-// bumps the generation, which releases the others.  A waiter gives up after
-// `timeout_ticks` of the constant-rate wall clock, or as soon as the status
-// word is non-zero, so the kernel always terminates; the status word then
-// carries kStatusTimeout and the caller reports an error.
+// Arrival is counted in two stages: workgroups b with the same b mod 8 share
+// a counter (each on its own 128-byte line, so arrivals proceed on eight
+// addresses in parallel instead of serialising on one), and the last arrival
+// of each group bumps the top counter; the last of those bumps the
+// generation, which releases everyone.  Each workgroup publishes its writes
+// with one agent-scope release fence before arriving and takes one acquire
+// fence after the release (polling itself is relaxed: an acquire per poll
+// would invalidate the XCD's L2 while others still work).  A waiter gives up
+// after `timeout_ticks` of the constant-rate wall clock, or as soon as the
+// status word is non-zero, so the kernel always terminates; the status word
+// then carries kStatusTimeout and the caller reports an error.
 struct GridBarrier {
-  unsigned count;
+  unsigned group[8][32];
+  unsigned top;
+  unsigned pad0[31];
   unsigned gen;
+  unsigned pad1[31];
   int status;
-  unsigned pad;
+  int pad2[31];
 };
 
-template <class F>
-__device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint64_t timeout_ticks, F&& last_fn) {
-  __shared__ unsigned s_last;
-  __shared__ unsigned s_gen;
+__device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks) {
   __syncthreads();
   if (threadIdx.x == 0) {
-    s_gen = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned gen0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");  // publish this workgroup's writes
-    unsigned old = __hip_atomic_fetch_add(&b->count, 1u, __ATOMIC_ACQ_REL,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    s_last = (old == gridDim.x - 1) ? 1u : 0u;
-    if (s_last) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
-  __syncthreads();
-  if (s_last) {
-    last_fn();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      __hip_atomic_store(&b->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned G = gridDim.x;
+    const unsigned g = blockIdx.x & 7u;
+    const unsigned ng = G < 8u ? G : 8u;
+    const unsigned gsize = (G - g + 7u) / 8u;
+    bool last = false;
+    const unsigned old = __hip_atomic_fetch_add(&b->group[g][0], 1u, __ATOMIC_RELAXED,
+                                                __HIP_MEMORY_SCOPE_AGENT);
+    if (old == gsize - 1u) {
+      (void)__hip_atomic_exchange(&b->group[g][0], 0u, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // reset lands before top
+      const unsigned o2 = __hip_atomic_fetch_add(&b->top, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+      last = (o2 == ng - 1u);
     }
-  } else if (threadIdx.x == 0) {
-    const uint64_t t0 = wall_clock64();
-    while (__hip_atomic_load(&b->gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == s_gen) {
-      if (__hip_atomic_load(&b->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
-      if (wall_clock64() - t0 > timeout_ticks) {
-        __hip_atomic_fetch_or(&b->status, kStatusTimeout, __ATOMIC_RELAXED,
-                              __HIP_MEMORY_SCOPE_AGENT);
-        break;
+    if (last) {
+      (void)__hip_atomic_exchange(&b->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const uint64_t t0 = wall_clock64();
+      while (__hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == gen0) {
+        if (__hip_atomic_load(&b->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+          break;
+        if ((uint64_t)wall_clock64() - t0 > timeout_ticks) {
+          __hip_atomic_fetch_or(&b->status, kStatusTimeout, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      __builtin_amdgcn_s_sleep(2);
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
@@ -125,11 +137,71 @@ __device__ __forceinline__ bool grid_barrier(GridBarrier* b, uint64_t timeout_ti
 }
 
 // ---------------------------------------------------------------------------
+// First hit: each active lane holds a vertex whose row is cols[b, e); it
+// finds the first entry w (in row order, i.e. increasing label) with bit w
+// set in `bits`.  Rows of at most kLaneRow entries are scanned by their own
+// lane; longer rows by the whole wave, 64 entries per step, where the lowest
+// hitting lane is the first hit.  `examined` (per lane, summed later) counts
+// the entries read up to and including the hit.  All lanes must call.
+constexpr int kLaneRow = 32;
+
+__device__ __forceinline__ void wave_first_hit(bool active, int64_t b, int64_t e,
+                                               const int32_t* cols, const uint64_t* bits,
+                                               bool& found, int32_t& par, int64_t& examined) {
+  const int l = lane_id();
+  found = false;
+  par = 0;
+  const bool hub = active && (e - b) > kLaneRow;
+  if (active && !hub) {
+    int64_t j = b;
+    for (; j < e; ++j) {
+      const int32_t w = cols[j];
+      if (test_bit(bits, (uint32_t)w)) {
+        found = true;
+        par = w;
+        break;
+      }
+    }
+    examined += found ? (j - b + 1) : (e - b);
+  }
+  uint64_t hubs = ballot(hub);
+  while (hubs) {
+    const int h = ffs64(hubs);
+    hubs &= hubs - 1;
+    const int64_t hb = shfl(b, h), he = shfl(e, h);
+    bool hf = false;
+    int32_t hp = 0;
+    int64_t scanned = he - hb;
+    for (int64_t j0 = hb; j0 < he; j0 += kWave) {
+      const int64_t j = j0 + l;
+      int32_t w = 0;
+      bool hit = false;
+      if (j < he) {
+        w = cols[j];
+        hit = test_bit(bits, (uint32_t)w);
+      }
+      const uint64_t hm = ballot(hit);
+      if (hm) {
+        const int first = ffs64(hm);
+        hp = shfl(w, first);
+        hf = true;
+        scanned = j0 - hb + first + 1;
+        break;
+      }
+    }
+    if (l == h) {
+      found = hf;
+      par = hp;
+    }
+    if (l == 0) examined += scanned;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Edge walk over the rows of one 64-vertex word [64 k, 64 k + 64): rows of at
 // most kLaneRow entries are walked by their own lane, longer rows by the whole
 // wave (64 consecutive entries per step, coalesced).  f(v, w, e) is called
 // once per adjacency entry e = (v, w).  All lanes of the wave must call it.
-constexpr int kLaneRow = 32;
 
 template <class F>
 __device__ __forceinline__ void word_edges(const int64_t* off, const int32_t* cols, int64_t n,

@@ -21,7 +21,8 @@ struct BfsWork {
   int64_t n_sweep = 0;
   int32_t* depth = nullptr;     // internal depth (translate mode)
   uint32_t* parent = nullptr;   // internal parent (translate mode)
-  uint64_t* vis[2] = {nullptr, nullptr};
+  uint64_t* vis = nullptr;      // reached before the current level
+  uint64_t* front = nullptr;    // three rotating frontier bitmaps
   int32_t* qv[2] = {nullptr, nullptr};
   int64_t* qe[2] = {nullptr, nullptr};
   int32_t* chunk[2] = {nullptr, nullptr};
@@ -31,6 +32,7 @@ struct BfsWork {
   BfsCtl* ctl = nullptr;
   bool clean = false;           // depth/parent hold -1 everywhere
   int grid = 0;                 // persistent grid size
+  int max_per_cu = 1;           // resident workgroups per CU (occupancy)
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 
@@ -83,7 +85,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out);
 int validate_csr_impl(Graph* g, hipStream_t stream);
 int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, int alpha,
              int beta, const int8_t* sched, int sched_len, int out_space, int flags,
-             hipStream_t stream, void* stats);
+             int tune_profile, hipStream_t stream, void* stats);
 int bfs_batch_impl(Graph* g, const int32_t* roots, int32_t k, int32_t* depth, int32_t* parent,
                    int mode, int alpha, int beta, int out_space, int flags,
                    hipStream_t stream, void* stats);
