@@ -297,16 +297,22 @@ class MultiGraph:
         except Exception:
             pass
 
-    def bfs(self, roots, opts=None, stats=False):
+    def out_size(self, k):
+        return sum(k * g.n for g in self.graphs)
+
+    def bfs(self, roots, opts=None, stats=False, depth=None, parent=None):
         """roots: list (per graph) of k root lists.  Returns a list of
-        (depth, parent) views, each (k, n_g)."""
+        (depth, parent) views, each (k, n_g).  Passing the same output
+        buffers again replays the captured search."""
         import torch
         k = len(roots[0])
         flat = [int(r) for rs in roots for r in rs]
         r = (ctypes.c_int32 * len(flat))(*flat)
-        total = sum(k * g.n for g in self.graphs)
-        depth = torch.empty(total, dtype=torch.int32, device=self.device)
-        parent = torch.empty(total, dtype=torch.int32, device=self.device)
+        total = self.out_size(k)
+        if depth is None:
+            depth = torch.empty(total, dtype=torch.int32, device=self.device)
+        if parent is None:
+            parent = torch.empty(total, dtype=torch.int32, device=self.device)
         st = Stats() if stats else None
         _check(lib().rbfs_bfs_multi(self._h, r, k, _dptr(depth), _dptr(parent),
                                     ctypes.byref(opts) if opts is not None else None,

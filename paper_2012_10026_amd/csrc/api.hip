@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/rbfs.h"
 #include "common.cuh"
@@ -11,6 +12,20 @@
 
 struct rbfs_graph {
   rbfs::Graph g;
+};
+
+struct rbfs_multi {
+  rbfs::MsEngine eng;
+  std::vector<rbfs::Graph*> gs;
+  std::vector<int64_t> ubase;      // first union ID of each graph
+  std::vector<int64_t> out_off;    // per-k output offset factor (sum of n before)
+  int device = 0;
+  // shape of the captured search
+  int cap_k = 0, cap_mode = -1, cap_alpha = 0, cap_beta = 0;
+  int32_t* cap_depth = nullptr;
+  int32_t* cap_parent = nullptr;
+  hipStream_t cap_stream = nullptr;
+  hipStream_t own_stream = nullptr;  // used when the caller passes the NULL stream
 };
 
 namespace rbfs {
@@ -423,6 +438,218 @@ int rbfs_graph_timings(rbfs_graph_t* h, float* kernel_ms, float* total_ms, int32
 fail:
   g->timing.count = 0;
   return rc;
+}
+
+int rbfs_bfs_batch(rbfs_graph_t* h, const int32_t* roots, int32_t k, int32_t* depth,
+                   int32_t* parent, const rbfs_opts_t* opts, void* stream_, rbfs_stats_t* stats) {
+  if (!h || !roots || !depth || !parent || k < 1) {
+    set_error("rbfs_bfs_batch: NULL argument or k < 1");
+    return RBFS_E_INVAL;
+  }
+  Graph* g = &h->g;
+  for (int32_t j = 0; j < k; ++j) {
+    if (roots[j] < 0 || roots[j] >= g->n) {
+      set_error("rbfs_bfs_batch: root out of range");
+      return RBFS_E_RANGE;
+    }
+  }
+  int mode, alpha, beta, out_space;
+  int rc = parse_opts(opts, &mode, &alpha, &beta, &out_space);
+  if (rc) return rc;
+  if (mode == RBFS_DIR_SCHEDULE || mode == RBFS_DIR_LEARNED) {
+    set_error("rbfs_bfs_batch: direction mode not supported for batches");
+    return RBFS_E_UNSUPPORTED;
+  }
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  return rbfs::bfs_batch_impl(g, roots, k, depth, parent, mode, alpha, beta, out_space,
+                              opts ? opts->flags : 0, (hipStream_t)stream_, stats);
+}
+
+int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream_,
+                      rbfs_multi_t** out) {
+  if (!graphs || !out || count < 1) {
+    set_error("rbfs_multi_create: NULL argument or count < 1");
+    return RBFS_E_INVAL;
+  }
+  *out = nullptr;
+  for (int32_t i = 0; i < count; ++i) {
+    if (!graphs[i]) {
+      set_error("rbfs_multi_create: NULL graph");
+      return RBFS_E_INVAL;
+    }
+    if (graphs[i]->g.device != graphs[0]->g.device ||
+        graphs[i]->g.reordered != graphs[0]->g.reordered) {
+      set_error("rbfs_multi_create: graphs differ in device or RCM state");
+      return RBFS_E_STATE;
+    }
+  }
+  if (hipSetDevice(graphs[0]->g.device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  rbfs_multi_t* m = new rbfs_multi_t();
+  m->device = graphs[0]->g.device;
+  int64_t ub = 0, ob = 0;
+  for (int32_t i = 0; i < count; ++i) {
+    Graph* g = &graphs[i]->g;
+    m->gs.push_back(g);
+    m->ubase.push_back(ub);
+    m->out_off.push_back(ob);
+    ub += g->n_sweep;
+    ob += g->n;
+  }
+  if (ub >= 0x7FFFFFFFll) {
+    delete m;
+    set_error("rbfs_multi_create: union too large");
+    return RBFS_E_RANGE;
+  }
+  m->eng.ngraphs = count;
+  std::vector<const Graph*> cg(m->gs.begin(), m->gs.end());
+  int rc = rbfs::ms_build_union(&m->eng, cg.data(), count, stream);
+  if (!rc) rc = rbfs::ms_engine_setup(&m->eng, graphs[0]->g.compute_units,
+                                      graphs[0]->g.wall_rate_khz, stream);
+  if (!rc && hipStreamCreateWithFlags(&m->own_stream, hipStreamNonBlocking) != hipSuccess) {
+    set_error("rbfs_multi_create: stream creation failed");
+    rc = RBFS_E_DEVICE;
+  }
+  if (rc) {
+    rbfs::ms_engine_free(&m->eng);
+    delete m;
+    return rc;
+  }
+  *out = m;
+  return RBFS_OK;
+}
+
+int rbfs_multi_destroy(rbfs_multi_t* m) {
+  if (!m) return RBFS_OK;
+  (void)hipSetDevice(m->device);
+  rbfs::ms_engine_free(&m->eng);
+  if (m->own_stream) (void)hipStreamDestroy(m->own_stream);
+  delete m;
+  return RBFS_OK;
+}
+
+// Enqueues the whole multi-graph search: roots upload, root mapping, the
+// persistent search kernel and one output transpose per graph.
+static int multi_enqueue(rbfs_multi_t* m, int32_t k, int32_t* depth, int32_t* parent, int mode,
+                         int alpha, int beta, hipStream_t stream) {
+  rbfs::MsEngine* e = &m->eng;
+  const int G = (int)m->gs.size();
+  int32_t* orig_dev = e->roots_dev + 64 * G;
+  hipError_t he = hipMemcpyAsync(orig_dev, e->roots_host, sizeof(int32_t) * 64 * G,
+                                 hipMemcpyHostToDevice, stream);
+  if (he != hipSuccess) {
+    set_error(std::string("rbfs_bfs_multi: roots upload: ") + hipGetErrorString(he));
+    return RBFS_E_DEVICE;
+  }
+  for (int i = 0; i < G; ++i) {
+    Graph* g = m->gs[i];
+    int rc = rbfs::ms_enqueue_roots(orig_dev + 64 * i, k, g->reordered ? g->perm : nullptr,
+                                    g->n_sweep, m->ubase[i], e->roots_dev + k * i, stream);
+    if (rc) return rc;
+  }
+  int rc = rbfs::ms_enqueue_search(e, k, k * G, mode, alpha, beta, stream);
+  if (rc) return rc;
+  for (int i = 0; i < G; ++i) {
+    Graph* g = m->gs[i];
+    rc = rbfs::ms_enqueue_translate(e, g->n, g->reordered ? g->perm : nullptr, g->n_sweep,
+                                    m->ubase[i], k, orig_dev + 64 * i,
+                                    depth + (int64_t)k * m->out_off[i],
+                                    parent + (int64_t)k * m->out_off[i], stream);
+    if (rc) return rc;
+  }
+  return 0;
+}
+
+int rbfs_bfs_multi(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t* depth,
+                   int32_t* parent, const rbfs_opts_t* opts, void* stream_, rbfs_stats_t* stats) {
+  if (!m || !roots || !depth || !parent || k < 1 || k > 64) {
+    set_error("rbfs_bfs_multi: NULL argument or k outside [1, 64]");
+    return RBFS_E_INVAL;
+  }
+  const int G = (int)m->gs.size();
+  for (int i = 0; i < G; ++i)
+    for (int32_t j = 0; j < k; ++j) {
+      const int32_t r = roots[(int64_t)i * k + j];
+      if (r < 0 || r >= m->gs[i]->n) {
+        set_error("rbfs_bfs_multi: root out of range");
+        return RBFS_E_RANGE;
+      }
+    }
+  int mode, alpha, beta, out_space;
+  int rc = parse_opts(opts, &mode, &alpha, &beta, &out_space);
+  if (rc) return rc;
+  if (out_space != RBFS_OUT_ORIGINAL || mode == RBFS_DIR_SCHEDULE || mode == RBFS_DIR_LEARNED) {
+    set_error("rbfs_bfs_multi: unsupported options");
+    return RBFS_E_UNSUPPORTED;
+  }
+  if (hipSetDevice(m->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  // stream capture is not possible on the legacy NULL stream: run on an own
+  // stream then (the call synchronises before returning either way)
+  hipStream_t stream = (hipStream_t)stream_;
+  if (!stream) {
+    if (hipStreamSynchronize(nullptr) != hipSuccess) {
+      set_error("rbfs_bfs_multi: stream error");
+      return RBFS_E_DEVICE;
+    }
+    stream = m->own_stream;
+  }
+  rbfs::MsEngine* e = &m->eng;
+  // the pinned roots buffer is read by the (possibly captured) upload: make
+  // sure the previous search has consumed it
+  if (hipStreamSynchronize(stream) != hipSuccess) {
+    set_error("rbfs_bfs_multi: stream error");
+    return RBFS_E_DEVICE;
+  }
+  for (int i = 0; i < G; ++i)
+    for (int32_t j = 0; j < k; ++j) e->roots_host[64 * i + j] = roots[(int64_t)i * k + j];
+  const bool same = e->gexec && m->cap_k == k && m->cap_depth == depth &&
+                    m->cap_parent == parent && m->cap_mode == mode && m->cap_alpha == alpha &&
+                    m->cap_beta == beta && m->cap_stream == stream;
+  if (!same) {
+    if (e->gexec) (void)hipGraphExecDestroy(e->gexec);
+    e->gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipError_t he = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    if (he != hipSuccess) {
+      set_error(std::string("rbfs_bfs_multi: begin capture: ") + hipGetErrorString(he));
+      return RBFS_E_DEVICE;
+    }
+    rc = multi_enqueue(m, k, depth, parent, mode, alpha, beta, stream);
+    he = hipStreamEndCapture(stream, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (he == hipSuccess) he = hipGraphInstantiate(&e->gexec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (he != hipSuccess) {
+      e->gexec = nullptr;
+      set_error(std::string("rbfs_bfs_multi: capture: ") + hipGetErrorString(he));
+      return RBFS_E_DEVICE;
+    }
+    m->cap_k = k;
+    m->cap_depth = depth;
+    m->cap_parent = parent;
+    m->cap_mode = mode;
+    m->cap_alpha = alpha;
+    m->cap_beta = beta;
+    m->cap_stream = stream;
+  }
+  hipError_t he = hipGraphLaunch(e->gexec, stream);
+  if (he != hipSuccess) {
+    set_error(std::string("rbfs_bfs_multi: launch: ") + hipGetErrorString(he));
+    return RBFS_E_DEVICE;
+  }
+  return rbfs::ms_read_stats(e, stream, stats);
 }
 
 int rbfs_graph_check(rbfs_graph_t* h, void* stream_) {

@@ -77,8 +77,9 @@ struct BfsParams {
   int64_t n_sweep;
   int64_t n_init;        // entries of depth/parent initialised by the kernel
   int64_t deg_total;     // degree sum over the swept set
-  int32_t* depth;
-  uint32_t* parent;
+  int32_t* depth;        // element v at depth[v * ds]
+  uint32_t* parent;      // element v at parent[v * ds]
+  int64_t ds;            // 1: separate arrays; 2: interleaved (depth, parent) pairs
   uint64_t* vis;
   uint64_t* front[3];
   int32_t* qv[2];
@@ -98,14 +99,35 @@ struct BfsParams {
   BfsCtl* ctl;
 };
 
+template <int WAVES>
 struct StageLds {
-  int32_t v[kWavesPerBlock][kStage];
-  int32_t d[kWavesPerBlock][kStage];
-  int32_t cnt[kWavesPerBlock];
+  int32_t v[WAVES][kStage];
+  int32_t d[WAVES][kStage];
+  int32_t cnt[WAVES];
+  uint64_t found[WAVES][kWave];  // bottom-up: found bits of the batch's words
 };
 
+// Position of the n-th set bit (n < popcount(m)).
+__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1ull);
+    const int c = popc64(low);
+    if (n >= c) {
+      n -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
 // Publishes this wave's staged vertices to the next queue.
-__device__ __forceinline__ void flush_stage(StageLds& st, const BfsParams& P, int nq_idx,
+template <class ST>
+__device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_idx,
                                             unsigned long long* qpack) {
   const int wv = wave_id(), l = lane_id();
   const int cnt = st.cnt[wv];
@@ -146,7 +168,8 @@ __device__ __forceinline__ void flush_stage(StageLds& st, const BfsParams& P, in
 }
 
 // Stages the vertices of the lanes with take = true; flushes when full.
-__device__ __forceinline__ void stage(StageLds& st, bool take, int32_t v, int64_t deg,
+template <class ST>
+__device__ __forceinline__ void stage(ST& st, bool take, int32_t v, int64_t deg,
                                       const BfsParams& P, int nq_idx,
                                       unsigned long long* qpack) {
   const uint64_t m = ballot(take);
@@ -171,24 +194,26 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
   return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
 }
 
-__global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
+template <int BLOCK>
+__global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
+  constexpr int WAVES = BLOCK / kWave;
   __shared__ ChunkLds s_chunk;
-  __shared__ StageLds s_st;
+  __shared__ StageLds<WAVES> s_st;
   BfsCtl* ctl = P.ctl;
-  const int64_t gtid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int64_t gsz = (int64_t)gridDim.x * kBlock;
+  const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * BLOCK;
   const int32_t root = P.perm ? P.perm[P.root_orig] : P.root_orig;
   const bool root_in = root < P.n_sweep;
   const int64_t W = ceil_div(P.n_sweep, kWave);
   const uint64_t emask = (1ull << P.eb) - 1ull;
   const int l = lane_id();
-  if (threadIdx.x < kWavesPerBlock) s_st.cnt[threadIdx.x] = 0;
+  if (threadIdx.x < WAVES) s_st.cnt[threadIdx.x] = 0;
 
   // ---- initialisation
   if (P.init) {
     for (int64_t i = gtid; i < P.n_init; i += gsz) {
-      P.depth[i] = (i == root) ? 0 : -1;
-      P.parent[i] = (i == root) ? (uint32_t)root : kNoParent;
+      P.depth[i * P.ds] = (i == root) ? 0 : -1;
+      P.parent[i * P.ds] = (i == root) ? (uint32_t)root : kNoParent;
     }
   }
   for (int64_t w = gtid; w < W; w += gsz) {
@@ -199,8 +224,8 @@ __global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
   const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
   if (gtid == 0) {
     if (!P.init && root_in) {
-      P.depth[root] = 0;
-      P.parent[root] = (uint32_t)root;
+      P.depth[root * P.ds] = 0;
+      P.parent[root * P.ds] = (uint32_t)root;
     }
     for (int r = 0; r < 2; ++r) {
       ctl->qpack[r][0] = 0ull;
@@ -254,15 +279,15 @@ __global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
       const int64_t E = mf;
       const int64_t nchunks = ceil_div(E, kChunkEdges);
       for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const bool ok = expand_chunk(s_chunk, c, E, P.qv[qc], P.qe[qc], nf, P.chunk[qc],
+        const bool ok = expand_chunk<BLOCK>(s_chunk, c, E, P.qv[qc], P.qe[qc], nf, P.chunk[qc],
                                      nchunks, P.off, P.cols,
                                      [&](bool active, int32_t u, int32_t w) {
           bool claim = false;
           int64_t dw = 0;
           if (active) {
             const uint64_t word = P.vis[w >> 6] | fcur[w >> 6];
-            if (!((word >> (w & 63)) & 1ull) && P.depth[w] == -1) {
-              claim = atomicCAS(&P.depth[w], -1, L + 1) == -1;
+            if (!((word >> (w & 63)) & 1ull) && P.depth[w * P.ds] == -1) {
+              claim = atomicCAS(&P.depth[w * P.ds], -1, L + 1) == -1;
               if (claim) {
                 dw = P.off[w + 1] - P.off[w];
                 atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
@@ -270,8 +295,8 @@ __global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
             }
             // w is unvisited at level start: depth[w] is now L+1, u is a
             // candidate parent (a stale read can only be larger)
-            if (!((word >> (w & 63)) & 1ull) && P.parent[w] > (uint32_t)u)
-              atomicMin(&P.parent[w], (uint32_t)u);
+            if (!((word >> (w & 63)) & 1ull) && P.parent[w * P.ds] > (uint32_t)u)
+              atomicMin(&P.parent[w * P.ds], (uint32_t)u);
           }
           stage(s_st, claim, w, dw, P, qn, qpack);
         });
@@ -302,30 +327,56 @@ __global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
           if (lo + (int64_t)p >= hi) break;
           const int64_t part = lo + (int64_t)p;
           const int64_t k0 = P.bu_part[part], k1 = P.bu_part[part + 1];
-          for (int64_t k = k0; k < k1; ++k) {
-            const uint64_t vk = P.vis[k], fk = fcur[k];
-            const int64_t v = k * kWave + l;
-            const bool unvis = (v < P.n_sweep) && !(((vk | fk) >> l) & 1ull);
-            if (l == 0) P.vis[k] = vk | fk;
-            if (ballot(unvis) == 0) {
-              if (l == 0) fnext[k] = 0ull;
-              continue;
+          // batches of 64 words: lane j loads word j (coalesced); the
+          // unvisited vertices of the batch are then handed to the lanes
+          // densely, 64 at a time, whatever their spread over the words
+          const int wv = wave_id();
+          for (int64_t kb = k0; kb < k1; kb += kWave) {
+            const int64_t kw = kb + l;
+            uint64_t um = 0;
+            if (kw < k1) {
+              const uint64_t vk = P.vis[kw], fk = fcur[kw];
+              P.vis[kw] = vk | fk;
+              const int64_t v0 = kw * kWave;
+              const uint64_t valid = (v0 + kWave <= P.n_sweep)
+                                         ? ~0ull
+                                         : ((1ull << (P.n_sweep - v0)) - 1ull);
+              um = ~(vk | fk) & valid;
             }
-            int64_t b = 0, e = 0;
-            if (unvis) {
-              b = P.off[v];
-              e = P.off[v + 1];
+            const int cnt = popc64(um);
+            const int inc = (int)wave_inclusive_sum(cnt);
+            const int total = shfl(inc, kWave - 1);
+            s_st.found[wv][l] = 0ull;
+            __builtin_amdgcn_wave_barrier();
+            for (int t0 = 0; t0 < total; t0 += kWave) {
+              const int t = t0 + l;
+              const bool act = t < total;
+              int j = 0;  // first lane (word) whose inclusive count exceeds t
+#pragma unroll
+              for (int sft = 32; sft >= 1; sft >>= 1) {
+                const int probe = shfl(inc, j + sft - 1);
+                if (probe <= t) j += sft;
+              }
+              const int excl = shfl(inc - cnt, j);
+              const uint64_t mj = shfl(um, j);
+              int64_t v = 0, b = 0, e = 0;
+              if (act) {
+                v = (kb + j) * kWave + nth_set_bit(mj, t - excl);
+                b = P.off[v];
+                e = P.off[v + 1];
+              }
+              bool found;
+              int32_t par;
+              wave_first_hit(act, b, e, P.cols, fcur, found, par, examined);
+              if (found) {
+                atomicOr((unsigned long long*)&s_st.found[wv][j], 1ull << (v & 63));
+                P.depth[v * P.ds] = L + 1;
+                P.parent[v * P.ds] = (uint32_t)par;
+              }
+              stage(s_st, found, (int32_t)v, e - b, P, qn, qpack);
             }
-            bool found;
-            int32_t par;
-            wave_first_hit(unvis, b, e, P.cols, fcur, found, par, examined);
-            const uint64_t fm = ballot(found);
-            if (l == 0) fnext[k] = fm;
-            if (found) {
-              P.depth[v] = L + 1;
-              P.parent[v] = (uint32_t)par;
-            }
-            stage(s_st, found, (int32_t)v, e - b, P, qn, qpack);
+            __builtin_amdgcn_wave_barrier();
+            if (kw < k1) fnext[kw] = s_st.found[wv][l];
           }
         }
       }
@@ -381,23 +432,24 @@ __global__ __launch_bounds__(kBlock) void bfs_persistent_kernel(BfsParams P) {
   }
 }
 
-// Output in original IDs.  The internal arrays are read once and reset to
-// their initial values, so the next search needs no initialisation pass.
+// Output in original IDs from the interleaved internal (depth, parent)
+// pairs: one 8-byte gather per vertex.  Pairs that were reached are reset to
+// (-1, none), so the next search needs no initialisation pass.
 __global__ void translate_kernel(int64_t n, const int32_t* perm, const int32_t* iperm,
-                                 int64_t n_sweep, int32_t* depth_i, uint32_t* parent_i,
-                                 int32_t* depth_o, int32_t* parent_o, int32_t root_orig) {
+                                 int64_t n_sweep, int2* dp, int32_t* depth_o, int32_t* parent_o,
+                                 int32_t root_orig) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t i = perm[v];
     int32_t d = -1, p = -1;
     if (i < n_sweep) {
-      d = depth_i[i];
-      const uint32_t pi = parent_i[i];
+      const int2 x = dp[i];
+      d = x.x;
       if (d >= 0) {
-        depth_i[i] = -1;
-        parent_i[i] = kNoParent;
+        dp[i] = make_int2(-1, -1);
+        const uint32_t pi = (uint32_t)x.y;
+        p = (pi >= (uint64_t)n_sweep) ? -1 : iperm[pi];
       }
-      p = (pi >= (uint64_t)n_sweep) ? -1 : iperm[pi];
     } else if (v == root_orig) {
       d = 0;
       p = root_orig;
@@ -436,7 +488,7 @@ __global__ void bu_part_kernel(const int64_t* off, int64_t n_sweep, int64_t targ
 void free_bfs_work(Graph* g) {
   BfsWork* w = g->bfs;
   if (!w) return;
-  void* ps[] = {w->depth, w->parent, w->vis, w->front, w->qv[0], w->qv[1],
+  void* ps[] = {w->dp, w->vis, w->front, w->qv[0], w->qv[1],
                 w->qe[0], w->qe[1], w->chunk[0], w->chunk[1], w->bu_part, w->ctl};
   for (void* p : ps)
     if (p) (void)hipFree(p);
@@ -462,7 +514,7 @@ static int build_bu_parts(Graph* g, BfsWork* w, int64_t nparts_want, hipStream_t
   const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
   const int64_t target = std::max<int64_t>(2048, g->nnz / std::max<int64_t>(1, nparts_want) + 1);
   const int64_t nparts_e = std::max<int64_t>(1, ceil_div(g->nnz, target));
-  const int64_t max_words = std::max<int64_t>(64, W / std::max<int64_t>(1, nparts_want) + 1);
+  const int64_t max_words = std::max<int64_t>(kWave, W / std::max<int64_t>(1, nparts_want) + 1);
   int32_t* d_b = nullptr;
   BFS_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
   hipLaunchKernelGGL(bu_part_kernel, dim3((unsigned)ceil_div(nparts_e + 1, 256)), dim3(256), 0,
@@ -501,8 +553,7 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   const int64_t ns = g->n_sweep > 0 ? g->n_sweep : 1;
   const int64_t W = ceil_div(ns, kWave);
   w->n_sweep = g->n_sweep;
-  BFS_CHECK(hipMalloc(&w->depth, sizeof(int32_t) * ns));
-  BFS_CHECK(hipMalloc(&w->parent, sizeof(uint32_t) * ns));
+  BFS_CHECK(hipMalloc(&w->dp, sizeof(int2) * ns));
   BFS_CHECK(hipMalloc(&w->vis, sizeof(uint64_t) * W));
   BFS_CHECK(hipMalloc(&w->front, sizeof(uint64_t) * 3 * W));
   for (int i = 0; i < 2; ++i) {
@@ -514,12 +565,15 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
   int per_cu = 0;
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel, kBlock,
-                                                          0));
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel<1024>,
+                                                          1024, 0));
   if (per_cu < 1) per_cu = 1;
   w->max_per_cu = per_cu;
-  w->grid = std::min(per_cu, 2) * g->compute_units;
-  int rc = build_bu_parts(g, w, 4 * (int64_t)w->grid * kWavesPerBlock, stream);
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel<256>,
+                                                          256, 0));
+  w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
+  w->grid = g->compute_units;
+  int rc = build_bu_parts(g, w, 2 * (int64_t)w->grid * 16, stream);
   if (rc) return rc;
   BFS_CHECK(hipEventCreate(&w->ev0));
   BFS_CHECK(hipEventCreate(&w->ev1));
@@ -552,13 +606,15 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.n_sweep = g->n_sweep;
   P.deg_total = g->nnz;
   if (translate) {
-    P.depth = w->depth;
-    P.parent = w->parent;
+    P.depth = (int32_t*)w->dp;
+    P.parent = (uint32_t*)w->dp + 1;
+    P.ds = 2;
     P.init = w->clean ? 0 : 1;
     P.n_init = g->n_sweep;
   } else {
     P.depth = depth;
     P.parent = (uint32_t*)parent;
+    P.ds = 1;
     P.init = 1;
     P.n_init = g->n;
   }
@@ -596,16 +652,26 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipEventRecord(w->ev0, stream));
   hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(256), 0, stream, w->ctl);
   BFS_CHECK(hipGetLastError());
-  int grid = w->grid;
-  if (tune_profile > 0) grid = std::min(tune_profile, w->max_per_cu) * g->compute_units;
-  hipLaunchKernelGGL(bfs_persistent_kernel, dim3(grid), dim3(kBlock), 0, stream, P);
+  // launch shape: profile 0 = 1024-thread workgroups, one per CU; profiles
+  // 1..4 = 256-thread workgroups, that many per CU; 5..6 = 1024-thread, 1..2
+  // per CU (for tuning)
+  if (tune_profile >= 1 && tune_profile <= 4) {
+    const int per = std::min(tune_profile, w->max_per_cu_256);
+    hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(per * g->compute_units), dim3(256), 0,
+                       stream, P);
+  } else {
+    int per = 1;
+    if (tune_profile == 6) per = std::min(2, w->max_per_cu);
+    hipLaunchKernelGGL(bfs_persistent_kernel<1024>, dim3(per * g->compute_units), dim3(1024), 0,
+                       stream, P);
+  }
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
   if (translate) {
     const int64_t blocks = std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20);
     hipLaunchKernelGGL(translate_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       g->perm, g->iperm, g->n_sweep, w->depth, w->parent, depth, parent, root);
+                       g->perm, g->iperm, g->n_sweep, w->dp, depth, parent, root);
     BFS_CHECK(hipGetLastError());
     w->clean = true;
   }

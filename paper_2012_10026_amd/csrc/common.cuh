@@ -153,16 +153,25 @@ __device__ __forceinline__ void wave_first_hit(bool active, int64_t b, int64_t e
   par = 0;
   const bool hub = active && (e - b) > kLaneRow;
   if (active && !hub) {
-    int64_t j = b;
-    for (; j < e; ++j) {
-      const int32_t w = cols[j];
-      if (test_bit(bits, (uint32_t)w)) {
-        found = true;
-        par = w;
-        break;
-      }
+    // four entries per step: the loads of a step are independent, so one
+    // memory round trip covers four candidates
+    int64_t hitj = e;
+    for (int64_t j = b; j < e && hitj == e; j += 4) {
+      int32_t w[4];
+      bool h[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[q] = (j + q < e) ? cols[j + q] : 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) h[q] = (j + q < e) && test_bit(bits, (uint32_t)w[q]);
+#pragma unroll
+      for (int q = 3; q >= 0; --q)
+        if (h[q]) {
+          hitj = j + q;
+          par = w[q];
+        }
     }
-    examined += found ? (j - b + 1) : (e - b);
+    found = hitj < e;
+    examined += found ? (hitj - b + 1) : (e - b);
   }
   uint64_t hubs = ballot(hub);
   while (hubs) {

@@ -34,10 +34,10 @@ struct ChunkLds {
 };
 
 // Processes chunk c.  f(active, u, w) is called by every thread of the block
-// in lock-step rounds of kBlock entries (inactive threads get active = false),
+// in lock-step rounds of BLOCK entries (inactive threads get active = false),
 // so f may use wave-wide operations.  Returns false if the chunk touched more
 // list positions than fit in LDS (corrupt input).
-template <class F>
+template <int BLOCK, class F>
 __device__ __forceinline__ bool expand_chunk(ChunkLds& s, int64_t c, int64_t E, const int32_t* q,
                                              const int64_t* qe, int64_t nq,
                                              const int32_t* chunk_pos, int64_t nchunks,
@@ -57,14 +57,14 @@ __device__ __forceinline__ bool expand_chunk(ChunkLds& s, int64_t c, int64_t E, 
   if (k < 0) return false;
   const int64_t p0 = s.u[kChunkEdges + 1];
   __syncthreads();
-  for (int i = threadIdx.x; i < k; i += kBlock) {
+  for (int i = threadIdx.x; i < k; i += BLOCK) {
     const int32_t u = q[p0 + i];
     s.qe[i] = qe[p0 + i];
     s.u[i] = u;
     s.rowoff[i] = off[u];
   }
   __syncthreads();
-  for (int64_t base = e0; base < e1; base += kBlock) {
+  for (int64_t base = e0; base < e1; base += BLOCK) {
     const int64_t e = base + threadIdx.x;
     const bool active = e < e1;
     int32_t u = 0, w = 0;

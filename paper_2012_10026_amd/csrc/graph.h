@@ -15,12 +15,12 @@ constexpr int kChunkEdges = 1024;
 
 struct BfsCtl;
 struct MsCtl;
+struct Graph;
 
 // Workspace of the single-root search (sized for n_sweep vertices).
 struct BfsWork {
   int64_t n_sweep = 0;
-  int32_t* depth = nullptr;     // internal depth (translate mode)
-  uint32_t* parent = nullptr;   // internal parent (translate mode)
+  int2* dp = nullptr;           // internal (depth, parent) pairs (translate mode)
   uint64_t* vis = nullptr;      // reached before the current level
   uint64_t* front = nullptr;    // three rotating frontier bitmaps
   int32_t* qv[2] = {nullptr, nullptr};
@@ -32,21 +32,54 @@ struct BfsWork {
   BfsCtl* ctl = nullptr;
   bool clean = false;           // depth/parent hold -1 everywhere
   int grid = 0;                 // persistent grid size
-  int max_per_cu = 1;           // resident workgroups per CU (occupancy)
+  int max_per_cu = 1;           // resident 1024-thread workgroups per CU
+  int max_per_cu_256 = 1;       // resident 256-thread workgroups per CU
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
 };
 
-// Workspace of the 64-root bit-parallel search.
-struct MsWork {
+// Bit-parallel multi-root search engine over one "union" graph: a single
+// graph (off/cols/oid point at the graph's arrays) or a packed disjoint union
+// of several graphs (uoff/ucols/uoid owned here).
+struct MsEngine {
+  const int64_t* off = nullptr;
+  const int32_t* cols = nullptr;
+  const int32_t* oid = nullptr;   // internal -> original ID, null = identity
+  int64_t* uoff = nullptr;        // owned union CSR (multi-graph)
+  int32_t* ucols = nullptr;
+  int32_t* uoid = nullptr;
   int64_t n_sweep = 0;
-  uint64_t* seen = nullptr;
-  uint64_t* front[2] = {nullptr, nullptr};
-  int32_t* dep = nullptr;       // [n_sweep][64] internal, vertex-major
-  int32_t* par = nullptr;       // [n_sweep][64]
+  int64_t nnz = 0;
+  uint64_t* vis = nullptr;
+  uint64_t* front = nullptr;      // 3 x n_sweep words
+  int32_t* dep = nullptr;         // [n_sweep][64]
+  int32_t* par = nullptr;         // [n_sweep][64]
+  int32_t* qv[2] = {nullptr, nullptr};
+  int64_t* qe[2] = {nullptr, nullptr};
+  int32_t* chunk[2] = {nullptr, nullptr};
+  int64_t chunk_cap = 0;
+  int32_t* bu_part = nullptr;
+  int32_t n_part = 0;
   MsCtl* ctl = nullptr;
-  int32_t* roots_dev = nullptr; // 64 internal roots
+  int ngraphs = 1;
+  int32_t* roots_dev = nullptr;   // 64 union IDs per graph, then 64 original IDs per graph
+  int32_t* roots_host = nullptr;  // pinned staging for the original IDs (64 per graph)
   int grid = 0;
+  int64_t wall_rate_khz = 100000;
+  hipGraphExec_t gexec = nullptr; // captured multi-graph search
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
+
+int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipStream_t stream);
+void ms_engine_free(MsEngine* m);
+int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alpha, int beta,
+                      hipStream_t stream);
+int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
+                         int64_t ubase, int32_t k, const int32_t* roots_orig_dev,
+                         int32_t* out_dep, int32_t* out_par, hipStream_t stream);
+int ms_enqueue_roots(const int32_t* roots_orig_dev, int32_t k, const int32_t* perm,
+                     int64_t n_sweep, int64_t ubase, int32_t* roots_union, hipStream_t stream);
+int ms_read_stats(MsEngine* m, hipStream_t stream, void* stats);
+int ms_build_union(MsEngine* m, const struct Graph* const* gs, int count, hipStream_t stream);
 
 // Ring of event triples (start, after search kernel, end) for timed calls.
 struct TimingRing {
@@ -70,7 +103,7 @@ struct Graph {
   int32_t* perm = nullptr;   // original -> internal (after RCM)
   int32_t* iperm = nullptr;  // internal -> original
   BfsWork* bfs = nullptr;
-  MsWork* ms = nullptr;
+  MsEngine* ms = nullptr;
   Scratch scratch;
   TimingRing timing;
   int compute_units = 0;

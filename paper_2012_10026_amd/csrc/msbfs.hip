@@ -1,11 +1,878 @@
-// placeholder, replaced by the bit-parallel search
-#include "graph.h"
+// Batched BFS: up to 64 roots searched together, one bit per root in a
+// 64-bit word per vertex (multi-source BFS), as one persistent kernel.
+//
+// Row j of the result equals the single-root search from root j: depth is
+// the hop distance and the parent of v for root j is the smallest-label
+// neighbour of v one level closer to root j.  For a vertex v still missing
+// root j at level d, every neighbour that has bit j in the frontier F_d is at
+// distance d from root j, so scanning v's row in increasing label order and
+// taking, for each missing bit, the first neighbour whose frontier word has
+// it gives exactly those parents.  Both step kinds use that scan:
+//   bottom-up: every vertex with missing bits scans its row until all of
+//     them are found (Algorithm 2's bottom-up loop, per bit);
+//   top-down: frontier vertices push their bits to their neighbours with
+//     atomicOr; after a barrier, the vertices that received bits scan their
+//     rows for the parents of those bits.
+// Visited words, three rotating frontier word arrays, the per-wave staged
+// frontier queue with degree prefix (edge-balanced top-down expansion) and
+// the hierarchical grid barrier follow the single-root kernel.
+//
+// The kernel runs over a "union" graph: the graph itself for a batch, or the
+// disjoint union of several graphs (each keeps its own labels, offset by the
+// vertex counts of the graphs before it), where root j of every graph uses
+// bit j; components never touch, so the bits never mix.
+//
+// Per-(vertex, root) results are written vertex-major ([v][64], int32),
+// parents already converted to original IDs (one lookup per distinct hit),
+// then transposed to the caller's root-major original-ID layout by a
+// gather over original IDs; the transpose resets the internal rows it reads.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
 #include "../../include/rbfs.h"
+#include "common.cuh"
+#include "expand.cuh"
+#include "graph.h"
+
 namespace rbfs {
-void free_ms_work(Graph* g) { (void)g; }
-int bfs_batch_impl(Graph*, const int32_t*, int32_t, int32_t*, int32_t*, int, int, int, int,
-                   hipStream_t, void*) {
-  set_error("bfs_batch: not built");
-  return RBFS_E_UNSUPPORTED;
+
+struct alignas(128) MsCtl {
+  GridBarrier bar;
+  alignas(128) unsigned long long qpack[3][16];
+  alignas(128) unsigned long long work[3][8][16];
+  alignas(128) unsigned long long done_deg[3][16];  // degree of vertices completed
+  alignas(128) unsigned long long edges[3][16];
+  int levels;
+  int pad;
+  signed char hdir[RBFS_STATS_MAX_LEVELS];
+  long long hnf[RBFS_STATS_MAX_LEVELS];
+  long long hmf[RBFS_STATS_MAX_LEVELS];
+  long long hmu[RBFS_STATS_MAX_LEVELS];
+  long long hedges[RBFS_STATS_MAX_LEVELS];
+  unsigned long long hts[RBFS_STATS_MAX_LEVELS + 1];
+};
+
+namespace {
+
+constexpr int kMsStage = 256;
+constexpr int kMsBlock = 1024;
+constexpr int kMsWaves = kMsBlock / kWave;
+
+struct MsParams {
+  const int64_t* off;
+  const int32_t* cols;
+  int64_t n_sweep;
+  int64_t deg_total;
+  const int32_t* oid;      // internal -> original ID (null: identity)
+  uint64_t* vis;
+  uint64_t* front[3];
+  int32_t* dep;            // [n_sweep][64]
+  int32_t* par;            // [n_sweep][64]
+  int32_t* qv[2];
+  int64_t* qe[2];
+  int32_t* chunk[2];
+  int64_t chunk_cap;
+  const int32_t* bu_part;
+  int32_t n_part;
+  const int32_t* roots;    // nroots internal (union) IDs, -1 when not swept;
+                           // entry i is root (i mod k) of its graph (bit i mod k)
+  int32_t nroots;
+  int32_t k;
+  uint64_t amask;
+  int32_t mode, alpha, beta;
+  int32_t eb;
+  uint64_t timeout_ticks;
+  MsCtl* ctl;
+};
+
+struct MsStage {
+  int32_t v[kMsWaves][kMsStage];
+  int32_t d[kMsWaves][kMsStage];
+  int32_t cnt[kMsWaves];
+};
+
+__device__ __forceinline__ int32_t orig_id(const MsParams& P, int32_t x) {
+  return P.oid ? P.oid[x] : x;
 }
+
+__device__ __forceinline__ void ms_flush(MsStage& st, const MsParams& P, int nq_idx,
+                                         unsigned long long* qpack) {
+  const int wv = wave_id(), l = lane_id();
+  const int cnt = st.cnt[wv];
+  if (cnt == 0) return;
+  int64_t total = 0;
+  for (int j0 = 0; j0 < cnt; j0 += kWave) {
+    const int j = j0 + l;
+    total += (j < cnt) ? (int64_t)st.d[wv][j] : 0;
+  }
+  total = wave_sum(total);
+  unsigned long long old = 0;
+  if (l == 0)
+    old = atomicAdd(qpack, ((unsigned long long)cnt << P.eb) + (unsigned long long)total);
+  old = shfl(old, 0);
+  const int64_t pos0 = (int64_t)(old >> P.eb);
+  int64_t ebase = (int64_t)(old & ((1ull << P.eb) - 1ull));
+  if (pos0 + cnt > P.n_sweep) {
+    if (l == 0) atomicOr(&P.ctl->bar.status, kStatusOverflow);
+  } else {
+    for (int j0 = 0; j0 < cnt; j0 += kWave) {
+      const int j = j0 + l;
+      const bool act = j < cnt;
+      const int64_t d = act ? (int64_t)st.d[wv][j] : 0;
+      const int64_t inc = wave_inclusive_sum(d);
+      if (act) {
+        const int64_t pos = pos0 + j;
+        const int64_t base = ebase + inc - d;
+        P.qv[nq_idx][pos] = st.v[wv][j];
+        P.qe[nq_idx][pos] = base;
+        mark_chunks(P.chunk[nq_idx], P.chunk_cap, base, d, (int32_t)pos);
+      }
+      ebase += shfl(inc, kWave - 1);
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (l == 0) st.cnt[wv] = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ void ms_stage(MsStage& st, bool take, int32_t v, int64_t deg,
+                                         const MsParams& P, int nq_idx,
+                                         unsigned long long* qpack) {
+  const uint64_t m = ballot(take);
+  if (m == 0) return;
+  const int wv = wave_id();
+  const int base = st.cnt[wv];
+  __builtin_amdgcn_wave_barrier();
+  if (take) {
+    const int pos = base + popc64(m & lanemask_lt());
+    st.v[wv][pos] = v;
+    st.d[wv][pos] = (int32_t)deg;
+  }
+  if (lane_id() == 0) st.cnt[wv] = base + popc64(m);
+  __builtin_amdgcn_wave_barrier();
+  if (base + popc64(m) > kMsStage - kWave) ms_flush(st, P, nq_idx, qpack);
+}
+
+// Records level d+1 and parent `x` for every root bit in `bits` of vertex v.
+__device__ __forceinline__ void ms_record(const MsParams& P, int64_t v, uint64_t bits,
+                                          int32_t x, int d1) {
+  const int32_t ox = orig_id(P, x);
+  int32_t* dr = P.dep + v * 64;
+  int32_t* pr = P.par + v * 64;
+  while (bits) {
+    const int j = ffs64(bits);
+    bits &= bits - 1;
+    dr[j] = d1;
+    pr[j] = ox;
+  }
+}
+
+__device__ __forceinline__ uint64_t wave_or(uint64_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x |= __shfl_xor(x, off, kWave);
+  return x;
+}
+
+__device__ __forceinline__ uint64_t wave_exclusive_or(uint64_t x) {
+  const int l = lane_id();
+  uint64_t inc = x;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const uint64_t t = __shfl_up(inc, off, kWave);
+    if (l >= off) inc |= t;
+  }
+  const uint64_t ex = __shfl_up(inc, 1, kWave);
+  return l == 0 ? 0ull : ex;
+}
+
+// Each active lane holds vertex v (row cols[b, e)) missing root bits `miss`;
+// it scans the row in increasing label order and records, for every missing
+// bit, the first neighbour whose frontier word carries it.  Returns the bits
+// found.  Long rows are scanned by the whole wave, 64 entries per step; the
+// first lane holding a bit (exclusive OR-scan) owns it.  All lanes call.
+__device__ __forceinline__ uint64_t ms_pull(const MsParams& P, bool active, int64_t v,
+                                            int64_t b, int64_t e, uint64_t miss,
+                                            const uint64_t* fcur, int d1, int64_t& examined) {
+  const int l = lane_id();
+  uint64_t found = 0;
+  const bool hub = active && (e - b) > kLaneRow;
+  if (active && !hub && miss) {
+    int64_t j = b;
+    for (; j < e && miss; ++j) {
+      const int32_t x = P.cols[j];
+      const uint64_t hb = fcur[x] & miss;
+      if (hb) {
+        ms_record(P, v, hb, x, d1);
+        miss &= ~hb;
+        found |= hb;
+      }
+    }
+    examined += j - b;
+  }
+  uint64_t hubs = ballot(hub && miss != 0);
+  while (hubs) {
+    const int h = ffs64(hubs);
+    hubs &= hubs - 1;
+    const int64_t hv = shfl(v, h);
+    const int64_t hb0 = shfl(b, h), he = shfl(e, h);
+    uint64_t hmiss = shfl(miss, h);
+    uint64_t hfound = 0;
+    int64_t scanned = 0;
+    for (int64_t j0 = hb0; j0 < he && hmiss; j0 += kWave) {
+      const int64_t j = j0 + l;
+      int32_t x = 0;
+      uint64_t hb = 0;
+      if (j < he) {
+        x = P.cols[j];
+        hb = fcur[x] & hmiss;
+      }
+      const uint64_t mine = hb & ~wave_exclusive_or(hb);
+      if (mine) ms_record(P, hv, mine, x, d1);
+      const uint64_t all = wave_or(hb);
+      hmiss &= ~all;
+      hfound |= all;
+      scanned += (j0 + kWave < he ? kWave : he - j0);
+    }
+    if (l == h) found |= hfound;
+    if (l == 0) examined += scanned;
+  }
+  return found;
+}
+
+__device__ __forceinline__ int ms_heuristic(int dir, long long nf, long long mf, long long mu,
+                                            long long nf_prev, long long n, int alpha,
+                                            int beta) {
+  if (dir == 0) return (mf * (long long)alpha > mu) ? 1 : 0;
+  return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
+}
+
+__global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
+  __shared__ ChunkLds s_chunk;
+  __shared__ MsStage s_st;
+  MsCtl* ctl = P.ctl;
+  const int64_t gtid = (int64_t)blockIdx.x * kMsBlock + threadIdx.x;
+  const int64_t gsz = (int64_t)gridDim.x * kMsBlock;
+  const uint64_t emask = (1ull << P.eb) - 1ull;
+  const int l = lane_id();
+  if (threadIdx.x < kMsWaves) s_st.cnt[threadIdx.x] = 0;
+
+  for (int64_t i = gtid; i < P.n_sweep; i += gsz) {
+    P.vis[i] = 0ull;
+    P.front[0][i] = 0ull;
+    P.front[1][i] = 0ull;
+  }
+  if (gtid == 0) {
+    for (int r = 0; r < 2; ++r) {
+      ctl->qpack[r][0] = 0ull;
+      ctl->edges[r][0] = 0ull;
+      ctl->done_deg[r][0] = 0ull;
+      for (int g = 0; g < 8; ++g) ctl->work[r][g][0] = 0ull;
+    }
+    ctl->hts[0] = (unsigned long long)wall_clock64();
+  }
+  __syncthreads();
+  if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+  // roots: level 0 frontier (one wave; duplicate roots share a vertex)
+  if (blockIdx.x == 0 && threadIdx.x < kWave) {
+    for (int i0 = 0; i0 < P.nroots; i0 += kWave) {
+      const int i = i0 + l;
+      int32_t r = -1;
+      bool first = false;
+      int64_t dg = 0;
+      if (i < P.nroots) {
+        r = P.roots[i];
+        const int j = i % P.k;
+        if (r >= 0) {
+          const unsigned long long old =
+              atomicOr((unsigned long long*)&P.front[0][r], 1ull << j);
+          first = (old == 0ull);
+          P.dep[(int64_t)r * 64 + j] = 0;
+          P.par[(int64_t)r * 64 + j] = orig_id(P, r);
+          dg = P.off[r + 1] - P.off[r];
+        }
+      }
+      ms_stage(s_st, first, r, dg, P, 0, &ctl->qpack[0][0]);
+    }
+    ms_flush(s_st, P, 0, &ctl->qpack[0][0]);
+  }
+  if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+  long long nf, mf, mu;
+  {
+    const unsigned long long pk =
+        __hip_atomic_load(&ctl->qpack[0][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    nf = (long long)(pk >> P.eb);
+    mf = (long long)(pk & emask);
+    mu = P.deg_total;
+  }
+  if (gtid == 0) {
+    ctl->hdir[0] = 0;
+    ctl->hnf[0] = nf;
+    ctl->hmf[0] = mf;
+    ctl->hmu[0] = mu;
+  }
+  int L = 0, dir = 0;
+  while (nf > 0) {
+    const int c3 = L % 3, n3 = (L + 1) % 3, z3 = (L + 2) % 3;
+    const int qc = L & 1, qn = qc ^ 1;
+    const uint64_t* fcur = P.front[c3];
+    uint64_t* fnext = P.front[n3];
+    unsigned long long* qpack = &ctl->qpack[n3][0];
+    int64_t examined = 0, done = 0;
+    for (int64_t i = gtid; i < P.n_sweep; i += gsz) P.front[z3][i] = 0ull;
+    if (gtid == 0) {
+      ctl->qpack[z3][0] = 0ull;
+      ctl->edges[z3][0] = 0ull;
+      ctl->done_deg[z3][0] = 0ull;
+      for (int g = 0; g < 8; ++g) ctl->work[z3][g][0] = 0ull;
+    }
+    if (dir == 0) {
+      // ---- top-down push
+      for (int64_t i = gtid; i < nf; i += gsz) {
+        const int32_t u = P.qv[qc][i];
+        P.vis[u] |= fcur[u];
+      }
+      const int64_t E = mf;
+      const int64_t nchunks = ceil_div(E, kChunkEdges);
+      for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+        const bool ok = expand_chunk<kMsBlock>(s_chunk, c, E, P.qv[qc], P.qe[qc], nf,
+                                               P.chunk[qc], nchunks, P.off, P.cols,
+                                               [&](bool active, int32_t u, int32_t w) {
+          bool first = false;
+          int64_t dw = 0;
+          if (active) {
+            const uint64_t cand = fcur[u] & P.amask & ~(P.vis[w] | fcur[w]);
+            if (cand & ~fnext[w]) {
+              const unsigned long long old = atomicOr((unsigned long long*)&fnext[w], cand);
+              if (old == 0ull) {
+                first = true;
+                dw = P.off[w + 1] - P.off[w];
+              }
+            }
+          }
+          ms_stage(s_st, first, w, dw, P, qn, qpack);
+        });
+        if (!ok) {
+          if (threadIdx.x == 0) atomicOr(&ctl->bar.status, kStatusBadInput);
+          break;
+        }
+      }
+      ms_flush(s_st, P, qn, qpack);
+      if (gtid == 0) examined = E;
+      if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+      // parents of the bits pushed this level
+      const int64_t nn = (int64_t)(__hip_atomic_load(qpack, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT) >> P.eb);
+      const int64_t wgl = (int64_t)blockIdx.x * kMsWaves + wave_id();
+      for (int64_t i0 = wgl * kWave; i0 < nn; i0 += (int64_t)gridDim.x * kMsBlock) {
+        const int64_t i = i0 + l;
+        const bool act = i < nn;
+        int64_t w = 0, b = 0, e = 0;
+        uint64_t bits = 0;
+        if (act) {
+          w = P.qv[qn][i];
+          bits = fnext[w];
+          b = P.off[w];
+          e = P.off[w + 1];
+        }
+        int64_t ex2 = 0;
+        (void)ms_pull(P, act, w, b, e, bits, fcur, L + 1, ex2);
+        if (act && (((P.vis[w] | fcur[w] | bits) & P.amask) == P.amask)) done += e - b;
+      }
+    } else {
+      // ---- bottom-up pull over edge-balanced vertex ranges
+      const int g0 = blockIdx.x & 7;
+      for (int t = 0; t < 8; ++t) {
+        const int g = (g0 + t) & 7;
+        const int64_t lo = (int64_t)P.n_part * g / 8, hi = (int64_t)P.n_part * (g + 1) / 8;
+        for (;;) {
+          unsigned long long p = 0;
+          if (l == 0) {
+            p = __hip_atomic_load(&ctl->work[c3][g][0], __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+            if (lo + (int64_t)p < hi)
+              p = __hip_atomic_fetch_add(&ctl->work[c3][g][0], 1ull, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+          }
+          p = shfl(p, 0);
+          if (lo + (int64_t)p >= hi) break;
+          const int64_t part = lo + (int64_t)p;
+          const int64_t v0 = (int64_t)P.bu_part[part] * kWave;
+          const int64_t v1 = std::min<int64_t>((int64_t)P.bu_part[part + 1] * kWave, P.n_sweep);
+          for (int64_t vb = v0; vb < v1; vb += kWave) {
+            const int64_t v = vb + l;
+            const bool inr = v < v1;
+            uint64_t miss = 0;
+            int64_t b = 0, e = 0;
+            if (inr) {
+              const uint64_t vv = P.vis[v], fv = fcur[v];
+              P.vis[v] = vv | fv;
+              miss = P.amask & ~(vv | fv);
+              if (miss) {
+                b = P.off[v];
+                e = P.off[v + 1];
+              }
+            }
+            const uint64_t found = ms_pull(P, inr && miss != 0, v, b, e, miss, fcur, L + 1,
+                                           examined);
+            if (found) {
+              fnext[v] = found;
+              if ((miss & ~found) == 0ull) done += e - b;
+            }
+            ms_stage(s_st, found != 0ull, (int32_t)v, e - b, P, qn, qpack);
+          }
+        }
+      }
+      ms_flush(s_st, P, qn, qpack);
+    }
+    const int64_t ex = wave_sum(examined), dn = wave_sum(done);
+    if (l == 0 && ex)
+      __hip_atomic_fetch_add(&ctl->edges[c3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (l == 0 && dn)
+      __hip_atomic_fetch_add(&ctl->done_deg[c3][0], (unsigned long long)dn, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+    if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+    const unsigned long long pk =
+        __hip_atomic_load(&ctl->qpack[n3][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const long long nf_new = (long long)(pk >> P.eb);
+    const long long mf_new = (long long)(pk & emask);
+    const long long mu_new =
+        mu - (long long)__hip_atomic_load(&ctl->done_deg[c3][0], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+    int nd = dir;
+    if (P.mode == RBFS_DIR_TD_ONLY) nd = 0;
+    else if (P.mode == RBFS_DIR_BU_ONLY) nd = 1;
+    else nd = ms_heuristic(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
+    if (gtid == 0 && L < RBFS_STATS_MAX_LEVELS) {
+      ctl->hedges[L] = (long long)ctl->edges[c3][0];
+      ctl->hts[L + 1] = (unsigned long long)wall_clock64();
+      if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
+        ctl->hdir[L + 1] = (signed char)nd;
+        ctl->hnf[L + 1] = nf_new;
+        ctl->hmf[L + 1] = mf_new;
+        ctl->hmu[L + 1] = mu_new;
+      }
+    }
+    nf = nf_new;
+    mf = mf_new;
+    mu = mu_new;
+    dir = nd;
+    ++L;
+  }
+  if (gtid == 0) ctl->levels = L;
+}
+
+__global__ void ms_fill_kernel(int32_t* a, int64_t n, int32_t val) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = val;
+}
+
+__global__ void ms_reset_ctl_kernel(MsCtl* c) {
+  int* p = (int*)&c->bar;
+  for (int i = threadIdx.x; i < (int)(sizeof(GridBarrier) / sizeof(int)); i += blockDim.x)
+    p[i] = 0;
+}
+
+// Root-major output of one graph: out[j][v] for j < k and original IDs v of
+// the graph.  Vertex v's internal (union) row is gathered (256 contiguous
+// bytes per array) and reset to -1.  Isolated vertices get -1; isolated
+// roots are fixed up by ms_roots_fixup_kernel.
+__global__ void ms_translate_kernel(int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
+                                    int64_t ubase, int32_t k, int32_t* dep, int32_t* par,
+                                    int32_t* out_dep, int32_t* out_par) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_g;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = perm ? perm[v] : v;
+    if (i < n_sweep_g) {
+      int4* dr = (int4*)(dep + (ubase + i) * 64);
+      int4* pr = (int4*)(par + (ubase + i) * 64);
+      const int4 m1 = make_int4(-1, -1, -1, -1);
+      for (int q = 0; q < (k + 3) / 4; ++q) {
+        const int4 a = dr[q], b = pr[q];
+        const int j = 4 * q;
+        out_dep[(int64_t)j * n_g + v] = a.x;
+        out_par[(int64_t)j * n_g + v] = b.x;
+        if (j + 1 < k) {
+          out_dep[(int64_t)(j + 1) * n_g + v] = a.y;
+          out_par[(int64_t)(j + 1) * n_g + v] = b.y;
+        }
+        if (j + 2 < k) {
+          out_dep[(int64_t)(j + 2) * n_g + v] = a.z;
+          out_par[(int64_t)(j + 2) * n_g + v] = b.z;
+        }
+        if (j + 3 < k) {
+          out_dep[(int64_t)(j + 3) * n_g + v] = a.w;
+          out_par[(int64_t)(j + 3) * n_g + v] = b.w;
+        }
+        dr[q] = m1;
+        pr[q] = m1;
+      }
+    } else {
+      for (int j = 0; j < k; ++j) {
+        out_dep[(int64_t)j * n_g + v] = -1;
+        out_par[(int64_t)j * n_g + v] = -1;
+      }
+    }
+  }
+}
+
+__global__ void ms_roots_kernel(const int32_t* roots_orig, int32_t k, const int32_t* perm,
+                                int64_t n_sweep, int64_t ubase, int32_t* roots_union) {
+  const int j = threadIdx.x;
+  if (j >= k) return;
+  const int32_t r = roots_orig[j];
+  const int64_t i = perm ? perm[r] : r;
+  roots_union[j] = (i < n_sweep) ? (int32_t)(ubase + i) : -1;
+}
+
+__global__ void ms_roots_fixup_kernel(int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
+                                      const int32_t* roots_orig, int32_t k, int32_t* out_dep,
+                                      int32_t* out_par) {
+  const int j = threadIdx.x;
+  if (j >= k) return;
+  const int32_t r = roots_orig[j];
+  const int64_t i = perm ? perm[r] : r;
+  if (i >= n_sweep_g) {
+    out_dep[(int64_t)j * n_g + r] = 0;
+    out_par[(int64_t)j * n_g + r] = r;
+  }
+}
+
+// union construction: shifted copies of one graph's internal CSR
+__global__ void union_off_kernel(const int64_t* off, int64_t n_sweep, int64_t ubase,
+                                 int64_t ebase, int64_t* uoff) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= n_sweep;
+       i += (int64_t)gridDim.x * blockDim.x)
+    uoff[ubase + i] = ebase + off[i];
+}
+
+__global__ void union_cols_kernel(const int32_t* cols, int64_t nnz, int64_t ubase,
+                                  int64_t ebase, int32_t* ucols) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
+       e += (int64_t)gridDim.x * blockDim.x)
+    ucols[ebase + e] = (int32_t)(ubase + cols[e]);
+}
+
+__global__ void union_oid_kernel(const int32_t* iperm, int64_t n_sweep, int64_t ubase,
+                                 int32_t* uoid) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_sweep;
+       i += (int64_t)gridDim.x * blockDim.x)
+    uoid[ubase + i] = iperm ? iperm[i] : (int32_t)i;
+}
+
+__global__ void ms_part_kernel(const int64_t* off, int64_t n_sweep, int64_t target,
+                               int64_t nparts, int32_t* bounds) {
+  const int64_t W = ceil_div(n_sweep, kWave);
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nparts;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t want = p * target;
+    int64_t lo = 0, hi = n_sweep;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (off[mid] < want) lo = mid + 1; else hi = mid;
+    }
+    int64_t w = ceil_div(lo, kWave);
+    if (p == nparts || w > W) w = W;
+    bounds[p] = (int32_t)w;
+  }
+}
+
+int grid_blocks(int64_t work) {
+  int64_t b = ceil_div(work, 256);
+  if (b < 1) b = 1;
+  if (b > (1 << 20)) b = 1 << 20;
+  return (int)b;
+}
+
+}  // namespace
+
+#define MS_CHECK(x)                                                             \
+  do {                                                                          \
+    hipError_t e_ = (x);                                                        \
+    if (e_ != hipSuccess) {                                                     \
+      set_error(std::string("bfs_batch: ") + #x + ": " + hipGetErrorString(e_)); \
+      return e_ == hipErrorOutOfMemory ? RBFS_E_NOMEM : RBFS_E_DEVICE;          \
+    }                                                                           \
+  } while (0)
+
+void ms_engine_free(MsEngine* m) {
+  if (!m) return;
+  void* ps[] = {m->uoff, m->ucols, m->uoid, m->vis, m->front, m->dep, m->par, m->qv[0],
+                m->qv[1], m->qe[0], m->qe[1], m->chunk[0], m->chunk[1], m->bu_part, m->ctl,
+                m->roots_dev};
+  for (void* p : ps)
+    if (p) (void)hipFree(p);
+  m->uoff = nullptr;
+  m->ucols = nullptr;
+  m->uoid = nullptr;
+  m->vis = m->front = nullptr;
+  m->dep = m->par = nullptr;
+  m->qv[0] = m->qv[1] = m->chunk[0] = m->chunk[1] = m->bu_part = nullptr;
+  m->qe[0] = m->qe[1] = nullptr;
+  m->ctl = nullptr;
+  m->roots_dev = nullptr;
+  if (m->roots_host) (void)hipHostFree(m->roots_host);
+  m->roots_host = nullptr;
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  m->gexec = nullptr;
+  if (m->ev0) (void)hipEventDestroy(m->ev0);
+  if (m->ev1) (void)hipEventDestroy(m->ev1);
+  m->ev0 = m->ev1 = nullptr;
+}
+
+void free_ms_work(Graph* g) {
+  if (!g->ms) return;
+  ms_engine_free(g->ms);
+  delete g->ms;
+  g->ms = nullptr;
+}
+
+// Sets up the engine's work buffers for an already described union graph
+// (off, cols, oid, n_sweep, nnz filled in).
+int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipStream_t stream) {
+  const int64_t ns = m->n_sweep > 0 ? m->n_sweep : 1;
+  MS_CHECK(hipMalloc(&m->vis, sizeof(uint64_t) * ns));
+  MS_CHECK(hipMalloc(&m->front, sizeof(uint64_t) * 3 * ns));
+  MS_CHECK(hipMalloc(&m->dep, sizeof(int32_t) * 64 * ns));
+  MS_CHECK(hipMalloc(&m->par, sizeof(int32_t) * 64 * ns));
+  for (int i = 0; i < 2; ++i) {
+    MS_CHECK(hipMalloc(&m->qv[i], sizeof(int32_t) * ns));
+    MS_CHECK(hipMalloc(&m->qe[i], sizeof(int64_t) * ns));
+  }
+  m->chunk_cap = ceil_div(m->nnz, kChunkEdges) + 2;
+  for (int i = 0; i < 2; ++i) MS_CHECK(hipMalloc(&m->chunk[i], sizeof(int32_t) * m->chunk_cap));
+  MS_CHECK(hipMalloc(&m->ctl, sizeof(MsCtl)));
+  MS_CHECK(hipMemsetAsync(m->ctl, 0, sizeof(MsCtl), stream));
+  MS_CHECK(hipMalloc(&m->roots_dev, sizeof(int32_t) * 64 * 2 * m->ngraphs));
+  MS_CHECK(hipHostMalloc(&m->roots_host, sizeof(int32_t) * 64 * (1 + m->ngraphs)));
+  hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->dep,
+                     64 * ns, -1);
+  hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->par,
+                     64 * ns, -1);
+  MS_CHECK(hipGetLastError());
+  // edge-balanced vertex ranges (in 64-vertex units) for the bottom-up pull
+  int per_cu = 0;
+  MS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msbfs_kernel, kMsBlock, 0));
+  if (per_cu < 1) per_cu = 1;
+  m->grid = compute_units;
+  const int64_t W = ceil_div(ns, kWave);
+  const int64_t want = 2 * (int64_t)m->grid * kMsWaves;
+  const int64_t target = std::max<int64_t>(2048, m->nnz / want + 1);
+  const int64_t nparts_e = std::max<int64_t>(1, ceil_div(m->nnz, target));
+  const int64_t max_words = std::max<int64_t>(1, W / want + 1);
+  int32_t* d_b = nullptr;
+  MS_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
+  hipLaunchKernelGGL(ms_part_kernel, dim3(grid_blocks(nparts_e + 1)), dim3(256), 0, stream,
+                     m->uoff ? m->uoff : m->off, m->n_sweep, target, nparts_e, d_b);
+  MS_CHECK(hipGetLastError());
+  std::vector<int32_t> hb(nparts_e + 1);
+  MS_CHECK(hipMemcpyAsync(hb.data(), d_b, sizeof(int32_t) * (nparts_e + 1),
+                          hipMemcpyDeviceToHost, stream));
+  MS_CHECK(hipStreamSynchronize(stream));
+  (void)hipFree(d_b);
+  std::vector<int32_t> parts{0};
+  for (int64_t p = 1; p <= nparts_e; ++p) {
+    int32_t a = parts.back(), b = std::max(hb[p], a);
+    while (b - a > max_words) {
+      a += (int32_t)max_words;
+      parts.push_back(a);
+    }
+    if (b > parts.back()) parts.push_back(b);
+  }
+  if (parts.back() != (int32_t)W) parts.push_back((int32_t)W);
+  m->n_part = (int32_t)parts.size() - 1;
+  MS_CHECK(hipMalloc(&m->bu_part, sizeof(int32_t) * parts.size()));
+  MS_CHECK(hipMemcpyAsync(m->bu_part, parts.data(), sizeof(int32_t) * parts.size(),
+                          hipMemcpyHostToDevice, stream));
+  MS_CHECK(hipEventCreate(&m->ev0));
+  MS_CHECK(hipEventCreate(&m->ev1));
+  MS_CHECK(hipStreamSynchronize(stream));
+  m->wall_rate_khz = wall_rate_khz;
+  return 0;
+}
+
+// Enqueues one search of up to 64 roots (internal union IDs already in
+// m->roots_dev): control reset + persistent kernel.
+int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alpha, int beta,
+                      hipStream_t stream) {
+  const int bits_n = bits_for(m->n_sweep + 2);
+  const int eb = 64 - bits_n;
+  if (((uint64_t)m->nnz >> eb) != 0) {
+    set_error("bfs_batch: graph too large for the packed queue counter");
+    return RBFS_E_UNSUPPORTED;
+  }
+  MsParams P{};
+  P.off = m->uoff ? m->uoff : m->off;
+  P.cols = m->ucols ? m->ucols : m->cols;
+  P.n_sweep = m->n_sweep;
+  P.deg_total = m->nnz;
+  P.oid = m->uoid ? m->uoid : m->oid;
+  P.vis = m->vis;
+  for (int i = 0; i < 3; ++i) P.front[i] = m->front + (size_t)i * (m->n_sweep > 0 ? m->n_sweep : 1);
+  P.dep = m->dep;
+  P.par = m->par;
+  for (int i = 0; i < 2; ++i) {
+    P.qv[i] = m->qv[i];
+    P.qe[i] = m->qe[i];
+    P.chunk[i] = m->chunk[i];
+  }
+  P.chunk_cap = m->chunk_cap;
+  P.bu_part = m->bu_part;
+  P.n_part = m->n_part;
+  P.roots = m->roots_dev;
+  P.nroots = nroots;
+  P.k = k;
+  P.amask = (k >= 64) ? ~0ull : ((1ull << k) - 1ull);
+  P.mode = mode;
+  P.alpha = alpha;
+  P.beta = beta;
+  P.eb = eb;
+  P.timeout_ticks = (uint64_t)m->wall_rate_khz * 1000ull * 4ull;
+  P.ctl = m->ctl;
+  hipLaunchKernelGGL(ms_reset_ctl_kernel, dim3(1), dim3(256), 0, stream, m->ctl);
+  MS_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(msbfs_kernel, dim3(m->grid), dim3(kMsBlock), 0, stream, P);
+  MS_CHECK(hipGetLastError());
+  return 0;
+}
+
+int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
+                         int64_t ubase, int32_t k, const int32_t* roots_orig_dev,
+                         int32_t* out_dep, int32_t* out_par, hipStream_t stream) {
+  hipLaunchKernelGGL(ms_translate_kernel, dim3(grid_blocks(n_g)), dim3(256), 0, stream, n_g,
+                     perm, n_sweep_g, ubase, k, m->dep, m->par, out_dep, out_par);
+  MS_CHECK(hipGetLastError());
+  hipLaunchKernelGGL(ms_roots_fixup_kernel, dim3(1), dim3(64), 0, stream, n_g, perm, n_sweep_g,
+                     roots_orig_dev, k, out_dep, out_par);
+  MS_CHECK(hipGetLastError());
+  return 0;
+}
+
+int ms_read_stats(MsEngine* m, hipStream_t stream, void* stats_v) {
+  rbfs_stats_t* stats = (rbfs_stats_t*)stats_v;
+  MsCtl* h = new MsCtl;
+  hipError_t e = hipMemcpyAsync(h, m->ctl, sizeof(MsCtl), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    delete h;
+    MS_CHECK(e);
+  }
+  const int st = h->bar.status;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->levels = h->levels;
+    stats->status = st;
+    const int nl = std::min(h->levels, RBFS_STATS_MAX_LEVELS);
+    for (int i = 0; i < nl; ++i) {
+      stats->dir[i] = h->hdir[i];
+      stats->nf[i] = h->hnf[i];
+      stats->mf[i] = h->hmf[i];
+      stats->mu[i] = h->hmu[i];
+      stats->edges[i] = h->hedges[i];
+      stats->level_us[i] = (float)((double)(h->hts[i + 1] - h->hts[i]) * 1000.0 /
+                                   (double)m->wall_rate_khz);
+    }
+  }
+  delete h;
+  if (st != 0) {
+    set_error("bfs_batch: device status " + std::to_string(st));
+    return RBFS_E_DEVICE;
+  }
+  return 0;
+}
+
+static int ensure_ms(Graph* g, hipStream_t stream) {
+  if (g->ms) return 0;
+  MsEngine* m = new MsEngine();
+  g->ms = m;
+  m->off = g->off;
+  m->cols = g->cols;
+  m->oid = g->reordered ? g->iperm : nullptr;
+  m->n_sweep = g->n_sweep;
+  m->nnz = g->nnz;
+  int rc = ms_engine_setup(m, g->compute_units, g->wall_rate_khz, stream);
+  if (rc) return rc;
+  g->bytes += sizeof(int32_t) * 128 * (size_t)(g->n_sweep > 0 ? g->n_sweep : 1);
+  return 0;
+}
+
+
+int ms_enqueue_roots(const int32_t* roots_orig_dev, int32_t k, const int32_t* perm,
+                     int64_t n_sweep, int64_t ubase, int32_t* roots_union, hipStream_t stream) {
+  hipLaunchKernelGGL(ms_roots_kernel, dim3(1), dim3(64), 0, stream, roots_orig_dev, k, perm,
+                     n_sweep, ubase, roots_union);
+  MS_CHECK(hipGetLastError());
+  return 0;
+}
+
+// Packs the internal CSRs of the graphs into one union CSR: graph g's swept
+// vertices occupy [ubase_g, ubase_g + n_sweep_g).
+int ms_build_union(MsEngine* m, const Graph* const* gs, int count, hipStream_t stream) {
+  int64_t ntot = 0, etot = 0;
+  for (int i = 0; i < count; ++i) {
+    ntot += gs[i]->n_sweep;
+    etot += gs[i]->nnz;
+  }
+  m->n_sweep = ntot;
+  m->nnz = etot;
+  MS_CHECK(hipMalloc(&m->uoff, sizeof(int64_t) * (ntot + 1)));
+  MS_CHECK(hipMalloc(&m->ucols, sizeof(int32_t) * (etot > 0 ? etot : 1)));
+  MS_CHECK(hipMalloc(&m->uoid, sizeof(int32_t) * (ntot > 0 ? ntot : 1)));
+  int64_t ub = 0, eb = 0;
+  for (int i = 0; i < count; ++i) {
+    const Graph* g = gs[i];
+    hipLaunchKernelGGL(union_off_kernel, dim3(grid_blocks(g->n_sweep + 1)), dim3(256), 0, stream,
+                       g->off, g->n_sweep, ub, eb, m->uoff);
+    if (g->nnz > 0)
+      hipLaunchKernelGGL(union_cols_kernel, dim3(grid_blocks(g->nnz)), dim3(256), 0, stream,
+                         g->cols, g->nnz, ub, eb, m->ucols);
+    hipLaunchKernelGGL(union_oid_kernel, dim3(grid_blocks(g->n_sweep)), dim3(256), 0, stream,
+                       g->reordered ? g->iperm : nullptr, g->n_sweep, ub, m->uoid);
+    MS_CHECK(hipGetLastError());
+    ub += g->n_sweep;
+    eb += g->nnz;
+  }
+  MS_CHECK(hipStreamSynchronize(stream));
+  return 0;
+}
+
+int bfs_batch_impl(Graph* g, const int32_t* roots, int32_t k, int32_t* depth, int32_t* parent,
+                   int mode, int alpha, int beta, int out_space, int flags, hipStream_t stream,
+                   void* stats) {
+  (void)flags;
+  if (out_space != RBFS_OUT_ORIGINAL) {
+    set_error("bfs_batch: only original-ID output is supported");
+    return RBFS_E_UNSUPPORTED;
+  }
+  int rc = ensure_ms(g, stream);
+  if (rc) return rc;
+  MsEngine* m = g->ms;
+  int32_t* roots_orig_dev = m->roots_dev + 64 * m->ngraphs;
+  for (int32_t j0 = 0; j0 < k; j0 += 64) {
+    const int32_t kk = std::min<int32_t>(64, k - j0);
+    memcpy(m->roots_host, roots + j0, sizeof(int32_t) * kk);
+    hipError_t e = hipMemcpyAsync(roots_orig_dev, m->roots_host, sizeof(int32_t) * kk,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // host buffer reused next pass
+    MS_CHECK(e);
+    rc = ms_enqueue_roots(roots_orig_dev, kk, g->reordered ? g->perm : nullptr, g->n_sweep, 0,
+                          m->roots_dev, stream);
+    if (!rc) rc = ms_enqueue_search(m, kk, kk, mode, alpha, beta, stream);
+    if (!rc)
+      rc = ms_enqueue_translate(m, g->n, g->reordered ? g->perm : nullptr, g->n_sweep, 0, kk,
+                                roots_orig_dev, depth + (int64_t)j0 * g->n,
+                                parent + (int64_t)j0 * g->n, stream);
+    if (!rc && (stats || j0 + 64 < k)) rc = ms_read_stats(m, stream, stats);
+    if (rc) return rc;
+  }
+  return ms_read_stats(m, stream, stats);
+}
+
 }  // namespace rbfs

@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void cm_expand_kernel(
     uint32_t* plabel, int32_t* next, int32_t* next_count, int64_t next_cap, int* status) {
   __shared__ ChunkLds s;
   for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const bool ok = expand_chunk(s, c, E, front, qe, nq, chunk_pos, nchunks, off, cols,
+    const bool ok = expand_chunk<kBlock>(s, c, E, front, qe, nq, chunk_pos, nchunks, off, cols,
                                  [&](bool active, int32_t u, int32_t w) {
       bool first = false;
       if (active && label[w] < 0) {
