@@ -103,6 +103,8 @@ typedef struct rbfs_stats {
   int32_t levels;                            /* number of levels expanded */
   int32_t status;                            /* device status word, 0 = ok */
   int8_t dir[RBFS_STATS_MAX_LEVELS];         /* 0 = TD, 1 = BU */
+  int8_t fallback[RBFS_STATS_MAX_LEVELS];    /* learned mode: 1 if the alpha/beta rule
+                                                decided (features out of range) */
   int64_t nf[RBFS_STATS_MAX_LEVELS];         /* |F_d| */
   int64_t mf[RBFS_STATS_MAX_LEVELS];         /* degree sum over F_d */
   int64_t mu[RBFS_STATS_MAX_LEVELS];         /* degree sum of unreached after F_d */
@@ -218,6 +220,54 @@ int rbfs_multi_destroy(rbfs_multi_t* m);
  * is replayed on later calls with the same k. */
 int rbfs_bfs_multi(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t* depth,
                    int32_t* parent, const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
+
+/* ---- learned direction switch ------------------------------------------
+ * Not in the paper: the alpha/beta rule of Algorithm 2 (section 2.1,
+ * "Parameter Tuning") is replaced by a small network that predicts, from 8
+ * per-level features, ln(microseconds) of the next level in each direction
+ * (output 0 top-down, 1 bottom-up); the cheaper one is taken, an exact tie
+ * keeps the current direction, and inputs outside the training range fall
+ * back to the alpha/beta rule.
+ *
+ * Network: x[8] -> ReLU(W1 x + b1)[32] -> ReLU(W2 h1 + b2)[32] -> W3 h2 + b3
+ * [2], fp32.  Parameters (1410 floats) in the order W1[32][8] (row = output
+ * unit), b1[32], W2[32][32], b2[32], W3[2][32], b3[2].  A switch blob adds
+ * fmin[8], fmax[8] (training feature range) and the largest training level:
+ * 1427 floats.  Features: log2(1+n_f)/log2(n), log2(1+m_f)/log2(nnz),
+ * log2(1+m_u)/log2(nnz), n_u/n, clamp(log2((1+m_f)/(1+m_u))/16, -2, 2),
+ * level/32, current direction, clamp(log2((1+n_f)/(1+n_f_prev))/8, -2, 2),
+ * with n the swept vertex count and n_u the swept vertices not yet reached.
+ * All buffers of these calls are host memory. */
+
+/* Loads the switch blob (1427 floats) for the current device; later
+ * searches with RBFS_DIR_LEARNED use it.  Process-wide. */
+int rbfs_switch_load(const float* blob, int32_t n);
+
+/* Training samples: for each root, searches with every level top-down and
+ * with every level after the first bottom-up, `reps` times each (the level
+ * state does not depend on the directions taken, so level d of both runs
+ * starts from the same frontier); the median device time of level d in each
+ * is that direction's cost.  Rows of 11 floats: features[8], ln(us TD),
+ * ln(us BU), level.  Writes at most `cap` rows; *count receives the number. */
+int rbfs_collect_level_samples(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
+                               int32_t alpha, int32_t beta, float* out, int32_t cap,
+                               int32_t* count, void* stream);
+
+/* Training on the GPU: samples[n][10] (features[8], targets[2]); w_init[1410];
+ * order[epochs][n]: the sample order of each epoch (batches are consecutive
+ * runs of `batch` entries, the last one possibly shorter).  Loss: mean over
+ * the batch of half the squared error; Adam (beta1 0.9, beta2 0.999, eps
+ * 1e-8, learning rate lr).  Gradients are summed in a fixed order, so the
+ * result is bit-reproducible.  w_out[1410]; loss_curve[epochs] (nullable):
+ * mean loss of each epoch. */
+int rbfs_mlp_train(const float* samples, int32_t n, const float* w_init, const int32_t* order,
+                   int32_t epochs, int32_t batch, float lr, float* w_out, float* loss_curve,
+                   void* stream);
+
+/* Test hooks: forward pass (x[n][8] -> y[n][2]) with the kernel the search
+ * uses, and the gradient of the batch loss over all n samples. */
+int rbfs_mlp_forward(const float* w, const float* x, int32_t n, float* y);
+int rbfs_mlp_grad(const float* w, const float* samples, int32_t n, float* grad, float* loss);
 
 #ifdef __cplusplus
 }

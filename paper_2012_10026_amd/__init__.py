@@ -23,6 +23,7 @@ DIR_HEURISTIC, DIR_TD_ONLY, DIR_BU_ONLY, DIR_SCHEDULE, DIR_LEARNED = 0, 1, 2, 3,
 OUT_ORIGINAL, OUT_INTERNAL = 0, 1
 STATS_MAX_LEVELS = 64
 MLP_PARAMS = 8 * 32 + 32 + 32 * 32 + 32 + 32 * 2 + 2
+SWITCH_BLOB = MLP_PARAMS + 8 + 8 + 1
 
 
 class RbfsError(RuntimeError):
@@ -41,7 +42,8 @@ class Opts(ctypes.Structure):
 class Stats(ctypes.Structure):
     L = STATS_MAX_LEVELS
     _fields_ = [("levels", ctypes.c_int32), ("status", ctypes.c_int32),
-                ("dir", ctypes.c_int8 * L), ("nf", ctypes.c_int64 * L),
+                ("dir", ctypes.c_int8 * L), ("fallback", ctypes.c_int8 * L),
+                ("nf", ctypes.c_int64 * L),
                 ("mf", ctypes.c_int64 * L), ("mu", ctypes.c_int64 * L),
                 ("edges", ctypes.c_int64 * L), ("level_us", ctypes.c_float * L),
                 ("reached", ctypes.c_int64),
@@ -51,7 +53,8 @@ class Stats(ctypes.Structure):
     def as_dict(self):
         n = min(self.levels, STATS_MAX_LEVELS)
         return {"levels": self.levels, "status": self.status,
-                "dir": list(self.dir[:n]), "nf": list(self.nf[:n]), "mf": list(self.mf[:n]),
+                "dir": list(self.dir[:n]), "fallback": list(self.fallback[:n]),
+                "nf": list(self.nf[:n]), "mf": list(self.mf[:n]),
                 "mu": list(self.mu[:n]), "edges": list(self.edges[:n]),
                 "level_us": list(self.level_us[:n]),
                 "reached": self.reached, "component_edges": self.component_edges,
@@ -91,6 +94,13 @@ SIGNATURES = {
     "rbfs_multi_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "rbfs_multi_destroy": (ctypes.c_int, [_P]),
     "rbfs_bfs_multi": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "rbfs_switch_load": (ctypes.c_int, [_P, _I32]),
+    "rbfs_collect_level_samples": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32,
+                                                  _P, _P]),
+    "rbfs_mlp_train": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P,
+                                      _P]),
+    "rbfs_mlp_forward": (ctypes.c_int, [_P, _P, _I32, _P]),
+    "rbfs_mlp_grad": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
 }
 
 _lib = None
@@ -326,3 +336,71 @@ class MultiGraph:
         if stats:
             return out, st.as_dict()
         return out
+
+
+# ----------------------------------------------------------------------------
+# learned direction switch
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def mlp_forward(w, x):
+    w = np.ascontiguousarray(w, np.float32)
+    x = np.ascontiguousarray(x, np.float32)
+    n = x.shape[0]
+    y = np.empty((n, 2), np.float32)
+    _check(lib().rbfs_mlp_forward(_fptr(w), _fptr(x), n, _fptr(y)))
+    return y
+
+
+def mlp_grad(w, samples):
+    w = np.ascontiguousarray(w, np.float32)
+    samples = np.ascontiguousarray(samples, np.float32)
+    g = np.empty(MLP_PARAMS, np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(lib().rbfs_mlp_grad(_fptr(w), _fptr(samples), samples.shape[0], _fptr(g),
+                               ctypes.byref(loss)))
+    return g, loss.value
+
+
+def mlp_train(samples, w_init, order, batch=256, lr=1e-3):
+    """order: (epochs, n) int32.  Returns (weights, loss curve)."""
+    samples = np.ascontiguousarray(samples, np.float32)
+    w_init = np.ascontiguousarray(w_init, np.float32)
+    order = np.ascontiguousarray(order, np.int32)
+    epochs, n = order.shape
+    w = np.empty(MLP_PARAMS, np.float32)
+    curve = np.empty(epochs, np.float32)
+    _check(lib().rbfs_mlp_train(_fptr(samples), n, _fptr(w_init), _fptr(order), epochs, batch,
+                                ctypes.c_float(lr), _fptr(w), _fptr(curve),
+                                _stream_ptr()))
+    return w, curve
+
+
+def switch_load(blob):
+    blob = np.ascontiguousarray(blob, np.float32)
+    assert blob.shape == (SWITCH_BLOB,)
+    _check(lib().rbfs_switch_load(_fptr(blob), SWITCH_BLOB))
+
+
+def collect_level_samples(graph, roots, reps=3, alpha=14, beta=24, cap=4096):
+    """Rows of 11 floats: features[8], ln us top-down, ln us bottom-up, level."""
+    r = (ctypes.c_int32 * len(roots))(*[int(x) for x in roots])
+    out = np.empty((cap, 11), np.float32)
+    cnt = ctypes.c_int32(0)
+    _check(lib().rbfs_collect_level_samples(graph.handle, r, len(roots), reps, alpha, beta,
+                                            _fptr(out), cap, ctypes.byref(cnt),
+                                            _stream_ptr(graph.device)))
+    return out[:cnt.value].copy()
+
+
+def make_switch_blob(w, features):
+    """Weights plus the training feature range and the largest level."""
+    features = np.asarray(features, np.float32)
+    blob = np.zeros(SWITCH_BLOB, np.float32)
+    blob[:MLP_PARAMS] = w
+    blob[MLP_PARAMS:MLP_PARAMS + 8] = features[:, :8].min(axis=0)
+    blob[MLP_PARAMS + 8:MLP_PARAMS + 16] = features[:, :8].max(axis=0)
+    blob[MLP_PARAMS + 16] = features[:, 10].max() if features.shape[1] > 10 else 64
+    return blob

@@ -3,12 +3,14 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
 #include "../../include/rbfs.h"
 #include "common.cuh"
 #include "graph.h"
+#include "switch.h"
 
 struct rbfs_graph {
   rbfs::Graph g;
@@ -403,10 +405,6 @@ int rbfs_bfs(rbfs_graph_t* h, int32_t root, int32_t* depth, int32_t* parent,
   int mode, alpha, beta, out_space;
   int rc = parse_opts(opts, &mode, &alpha, &beta, &out_space);
   if (rc) return rc;
-  if (mode == RBFS_DIR_LEARNED) {
-    set_error("rbfs_bfs: learned direction needs weights (rbfs_switch_load)");
-    return RBFS_E_UNSUPPORTED;
-  }
   if (hipSetDevice(g->device) != hipSuccess) {
     set_error("hipSetDevice failed");
     return RBFS_E_DEVICE;
@@ -650,6 +648,71 @@ int rbfs_bfs_multi(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t* de
     return RBFS_E_DEVICE;
   }
   return rbfs::ms_read_stats(e, stream, stats);
+}
+
+int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k, int32_t reps,
+                               int32_t alpha, int32_t beta, float* out, int32_t cap,
+                               int32_t* count, void* stream_) {
+  if (!h || !roots || !out || !count || k < 1 || reps < 1 || cap < 0 || alpha <= 0 ||
+      beta <= 0) {
+    set_error("rbfs_collect_level_samples: bad arguments");
+    return RBFS_E_INVAL;
+  }
+  Graph* g = &h->g;
+  for (int32_t j = 0; j < k; ++j)
+    if (roots[j] < 0 || roots[j] >= g->n) {
+      set_error("rbfs_collect_level_samples: root out of range");
+      return RBFS_E_RANGE;
+    }
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  hipStream_t stream = (hipStream_t)stream_;
+  int rc = 0;
+  int32_t *dd = nullptr, *dp = nullptr;
+  int32_t cnt = 0;
+  rbfs_stats_t sh, st;
+  std::vector<std::vector<float>> ttd, tbu;
+  API_CHECK(hipMalloc(&dd, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+  API_CHECK(hipMalloc(&dp, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+  for (int32_t j = 0; j < k && cnt < cap; ++j) {
+    rc = rbfs::bfs_impl(g, roots[j], dd, dp, RBFS_DIR_HEURISTIC, alpha, beta, nullptr, 0,
+                        RBFS_OUT_INTERNAL, 0, 0, stream, &sh);
+    if (rc) goto fail;
+    const int D = std::min(sh.levels, RBFS_STATS_MAX_LEVELS);
+    ttd.assign(D, std::vector<float>());
+    tbu.assign(D, std::vector<float>());
+    for (int32_t r = 0; r < reps; ++r) {
+      for (int mode : {RBFS_DIR_TD_ONLY, RBFS_DIR_BU_ONLY}) {
+        rc = rbfs::bfs_impl(g, roots[j], dd, dp, mode, alpha, beta, nullptr, 0,
+                            RBFS_OUT_INTERNAL, 0, 0, stream, &st);
+        if (rc) goto fail;
+        for (int d = 0; d < D && d < st.levels; ++d)
+          (mode == RBFS_DIR_TD_ONLY ? ttd : tbu)[d].push_back(st.level_us[d]);
+      }
+    }
+    long long reached = 1;
+    for (int d = 1; d < D && cnt < cap; ++d) {
+      reached += sh.nf[d];
+      if (ttd[d].empty() || tbu[d].empty()) continue;
+      std::sort(ttd[d].begin(), ttd[d].end());
+      std::sort(tbu[d].begin(), tbu[d].end());
+      const float a = ttd[d][ttd[d].size() / 2], b = tbu[d][tbu[d].size() / 2];
+      float* row = out + (int64_t)cnt * 11;
+      rbfs::switch_features(row, sh.nf[d], sh.mf[d], sh.mu[d], g->n_sweep - reached,
+                            sh.nf[d - 1], d, sh.dir[d - 1], g->n_sweep, g->nnz);
+      row[8] = logf(std::max(a, 0.1f));
+      row[9] = logf(std::max(b, 0.1f));
+      row[10] = (float)d;
+      ++cnt;
+    }
+  }
+  *count = cnt;
+fail:
+  if (dd) (void)hipFree(dd);
+  if (dp) (void)hipFree(dp);
+  return rc;
 }
 
 int rbfs_graph_check(rbfs_graph_t* h, void* stream_) {

@@ -47,8 +47,12 @@
 #include "common.cuh"
 #include "expand.cuh"
 #include "graph.h"
+#include "mlp_dev.cuh"
+#include "switch.h"
 
 namespace rbfs {
+
+const float* switch_blob_device(int device);
 
 struct alignas(128) BfsCtl {
   GridBarrier bar;
@@ -59,6 +63,7 @@ struct alignas(128) BfsCtl {
   int pad;
   long long reached, deg_reached;
   signed char hdir[RBFS_STATS_MAX_LEVELS];
+  signed char hood[RBFS_STATS_MAX_LEVELS];
   long long hnf[RBFS_STATS_MAX_LEVELS];
   long long hmf[RBFS_STATS_MAX_LEVELS];
   long long hmu[RBFS_STATS_MAX_LEVELS];
@@ -96,6 +101,7 @@ struct BfsParams {
   int8_t sched[RBFS_STATS_MAX_LEVELS];
   int32_t eb;
   uint64_t timeout_ticks;
+  const float* sw;       // learned-switch blob (RBFS_DIR_LEARNED)
   BfsCtl* ctl;
 };
 
@@ -234,6 +240,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     }
     ctl->qpack[0][0] = root_in ? ((1ull << P.eb) | (unsigned long long)dr) : 0ull;
     ctl->hdir[0] = 0;
+    ctl->hood[0] = 0;
     ctl->hnf[0] = 1;
     ctl->hmf[0] = dr;
     ctl->hmu[0] = P.deg_total - dr;
@@ -395,6 +402,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     const long long mf_new = (long long)(pk & emask);
     const long long mu_new = mu - mf_new;
     int nd = dir;
+    bool ood = false;
     switch (P.mode) {
       case RBFS_DIR_TD_ONLY: nd = 0; break;
       case RBFS_DIR_BU_ONLY: nd = 1; break;
@@ -402,6 +410,28 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         int i = L + 1;
         if (i >= P.sched_len) i = P.sched_len - 1;
         nd = P.sched[i] ? 1 : 0;
+        break;
+      }
+      case RBFS_DIR_LEARNED: {
+        // every workgroup evaluates the network on identical inputs with the
+        // same fixed-order arithmetic, so all take the same decision
+        __shared__ int s_dec;
+        float f[kMlpIn];
+        switch_features(f, nf_new, mf_new, mu_new, P.n_sweep - (reached + nf_new), nf, L + 1,
+                        dir, P.n_sweep, P.deg_total);
+        ood = switch_ood(P.sw, f, L + 1);
+        if (ood) {
+          nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
+        } else {
+          if (threadIdx.x < kWave) {
+            float y0, y1;
+            mlp_forward_wave(P.sw, f, y0, y1);
+            if (threadIdx.x == 0) s_dec = (y1 < y0) ? 1 : ((y0 < y1) ? 0 : dir);
+          }
+          __syncthreads();
+          nd = s_dec;
+          __syncthreads();
+        }
         break;
       }
       default:
@@ -412,6 +442,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       ctl->hts[L + 1] = (unsigned long long)wall_clock64();
       if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
         ctl->hdir[L + 1] = (signed char)nd;
+        ctl->hood[L + 1] = ood ? 1 : 0;
         ctl->hnf[L + 1] = nf_new;
         ctl->hmf[L + 1] = mf_new;
         ctl->hmu[L + 1] = mu_new;
@@ -645,6 +676,13 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.eb = eb;
   P.timeout_ticks = (uint64_t)g->wall_rate_khz * 1000ull * 4ull;  // 4 s
   P.ctl = w->ctl;
+  if (mode == RBFS_DIR_LEARNED) {
+    P.sw = switch_blob_device(g->device);
+    if (!P.sw) {
+      set_error("bfs: learned direction needs weights (rbfs_switch_load)");
+      return RBFS_E_STATE;
+    }
+  }
 
   hipEvent_t* tev = nullptr;
   if (flags & RBFS_OPT_TIMING) BFS_CHECK(g->timing.next(&tev));
@@ -691,6 +729,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     const int nl = std::min(h->levels, RBFS_STATS_MAX_LEVELS);
     for (int i = 0; i < nl; ++i) {
       stats->dir[i] = h->hdir[i];
+      stats->fallback[i] = h->hood[i];
       stats->nf[i] = h->hnf[i];
       stats->mf[i] = h->hmf[i];
       stats->mu[i] = h->hmu[i];

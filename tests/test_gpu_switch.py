@@ -1,0 +1,150 @@
+"""GPU tests of the learned direction switch: forward, gradient and training
+kernels against the fp64 oracle, reproducibility, BFS results in learned
+mode (bit-exact whatever the network decides), and the gain over the
+alpha/beta rule on a held-out graph."""
+import numpy as np
+import pytest
+
+import graphgen
+import oracle
+from oracle import mlp
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def rb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2012_10026_amd as rb
+    return rb
+
+
+def rand_samples(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(0, 1, size=(n, 8))
+    T = np.stack([3 + X[:, 0] - 2 * X[:, 3], 2 + X[:, 1] * X[:, 2]], axis=1)
+    return np.hstack([X, T]).astype(np.float32)
+
+
+def test_forward_matches_oracle(rb):
+    w = mlp.init_weights(1).astype(np.float32)
+    X = rand_samples(300, 2)[:, :8]
+    y = rb.mlp_forward(w, X)
+    y_o, _ = mlp.forward(w.astype(np.float64), X.astype(np.float64))
+    assert np.allclose(y, y_o, rtol=1e-5, atol=1e-6)
+
+
+def test_gradient_matches_oracle(rb):
+    w = mlp.init_weights(3).astype(np.float32)
+    S = rand_samples(200, 4)
+    g, loss = rb.mlp_grad(w, S)
+    loss_o, g_o = mlp.loss_and_grad(w.astype(np.float64), S.astype(np.float64))
+    assert abs(loss - loss_o) <= 1e-5 * abs(loss_o)
+    scale = np.abs(g_o).max()
+    assert np.max(np.abs(g - g_o)) <= 1e-4 * scale
+
+
+def test_training_matches_oracle_and_is_reproducible(rb):
+    S = rand_samples(700, 5)
+    w0 = mlp.init_weights(7).astype(np.float32)
+    order = mlp.epoch_orders(700, 3, 11)
+    w1, c1 = rb.mlp_train(S, w0, order, batch=256, lr=1e-3)
+    w2, c2 = rb.mlp_train(S, w0, order, batch=256, lr=1e-3)
+    assert np.array_equal(w1, w2) and np.array_equal(c1, c2)  # bit-reproducible
+    w_o, c_o = mlp.train(S.astype(np.float64), w0.astype(np.float64), order, batch=256,
+                         lr=1e-3)
+    assert np.max(np.abs(w1 - w_o)) <= 1e-4 * np.abs(w_o).max()
+    assert np.allclose(c1, c_o, rtol=1e-4)
+
+
+def test_training_reduces_loss(rb):
+    S = rand_samples(1024, 8)
+    order = mlp.epoch_orders(1024, 60, 3)
+    w, curve = rb.mlp_train(S, mlp.init_weights(2).astype(np.float32), order, batch=128,
+                            lr=3e-3)
+    assert curve[-1] < 0.1 * curve[0]
+
+
+def _kron_graph(rb, scale, seed):
+    off, cols = graphgen.kronecker_csr(scale, 16, seed)
+    G = rb.Graph(off, cols)
+    perm, _ = G.rcm_reorder()
+    return off, cols, G, perm.cpu().numpy()
+
+
+def test_learned_mode_results_are_exact(rb):
+    """Whatever the network decides, depth and parent equal the oracle's."""
+    off, cols, G, perm = _kron_graph(rb, 13, 21)
+    roots = graphgen.sample_roots(off, 4, 7)
+    samples = rb.collect_level_samples(G, roots[:2], reps=1)
+    assert samples.shape[0] > 0
+    for seed in (0, 1, 2):
+        w = mlp.init_weights(seed).astype(np.float32)
+        blob = rb.make_switch_blob(w, samples)
+        blob[mlp.NPARAMS:mlp.NPARAMS + 8] = -10.0   # accept every input: the
+        blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16] = 10.0  # random net decides all
+        blob[mlp.NPARAMS + 16] = 64
+        rb.switch_load(blob)
+        for r in roots:
+            d, p, st = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
+            d_o, p_o, _ = oracle.bfs(off, cols, r, perm)
+            assert np.array_equal(d.cpu().numpy(), d_o)
+            assert np.array_equal(p.cpu().numpy(), p_o)
+            assert sum(st["fallback"]) == 0
+
+
+def test_out_of_range_falls_back_to_heuristic(rb):
+    off, cols, G, perm = _kron_graph(rb, 12, 5)
+    root = graphgen.sample_roots(off, 1, 7)[0]
+    blob = np.zeros(rb.SWITCH_BLOB, np.float32)  # empty feature range: always OOD
+    blob[mlp.NPARAMS + 16] = 64
+    rb.switch_load(blob)
+    _, _, st_l = G.bfs(root, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
+    _, _, st_h = G.bfs(root, opts=rb.make_opts(rb.DIR_HEURISTIC), stats=True)
+    assert st_l["dir"] == st_h["dir"]
+    assert all(x == 1 for x in st_l["fallback"][1:])
+
+
+def modeled_cost(samples_by_level, dirs):
+    """Sum over levels >= 1 of the measured time of the chosen direction."""
+    total = 0.0
+    for lv, d in enumerate(dirs):
+        if lv in samples_by_level:
+            total += np.exp(samples_by_level[lv][8 + d])
+    return total
+
+
+def test_learned_switch_gain_on_held_out_graph(rb):
+    """Train on per-level timings of scale 14-16 graphs; on a held-out scale
+    16 graph the learned schedule's measured per-level cost is compared with
+    the alpha/beta schedule's and with the best possible per-level choice."""
+    train_rows = []
+    for scale, seed in [(14, 1), (15, 2), (16, 3), (16, 4)]:
+        off, cols, G, _ = _kron_graph(rb, scale, seed)
+        roots = graphgen.sample_roots(off, 8, 100 + seed)
+        train_rows.append(rb.collect_level_samples(G, roots, reps=3))
+    rows = np.vstack(train_rows)
+    S = rows[:, :10]
+    order = mlp.epoch_orders(S.shape[0], 300, 1)
+    w, curve = rb.mlp_train(S, mlp.init_weights(0).astype(np.float32), order, batch=64,
+                            lr=3e-3)
+    assert curve[-1] < curve[0]
+    rb.switch_load(rb.make_switch_blob(w, rows))
+    off, cols, G, perm = _kron_graph(rb, 16, 99)
+    roots = graphgen.sample_roots(off, 8, 5)
+    cost_l = cost_h = cost_best = 0.0
+    for r in roots:
+        s = rb.collect_level_samples(G, [r], reps=3)
+        by_level = {int(row[10]): row for row in s}
+        _, _, st_l = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
+        _, _, st_h = G.bfs(r, stats=True)
+        cost_l += modeled_cost(by_level, st_l["dir"])
+        cost_h += modeled_cost(by_level, st_h["dir"])
+        cost_best += sum(np.exp(min(row[8], row[9])) for row in s)
+    print("learned %.1f us, alpha/beta %.1f us, per-level best %.1f us"
+          % (cost_l, cost_h, cost_best))
+    assert cost_l <= 1.10 * cost_h
+    assert cost_best <= cost_l + 1e-3
