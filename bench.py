@@ -3,14 +3,16 @@ direction-optimizing BFS on one MI355X, Kronecker scale 26 by default.
 
 One step = 64 single-root searches (plain alpha = 14 / beta = 24 heuristic,
 outputs in original IDs), inputs resident in HBM.  RCM is timed once,
-separately.  Prints one JSON line.
+separately.  Also measured on the same graph and roots: the learned direction
+switch (trained here on per-level timings of scale 18-24 graphs) and the
+64-root bit-parallel batch; and the 32-graph multi-graph batch.  Prints one
+JSON line.
 """
 import argparse
 import json
 import math
 import os
 import platform
-import subprocess
 import sys
 import time
 
@@ -18,6 +20,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 def host_cpu():
@@ -57,16 +63,14 @@ def bfs_alg_bytes(st, n_sweep):
 def cpu_baseline(off_dev, cols_dev, roots, budget_s=30.0):
     """The oracle's BFS (single thread, original labels) on a bounded sample
     of the roots of the same graph."""
-    import numpy as np
     import oracle
     off = off_dev.cpu().numpy()
     cols = cols_dev.cpu().numpy()
     t_all, edges_all, used = 0.0, 0, []
     for r in roots:
         t0 = time.perf_counter()
-        depth, parent, _ = oracle.bfs(off, cols, r)
-        dt = time.perf_counter() - t0
-        t_all += dt
+        depth, _, _ = oracle.bfs(off, cols, r)
+        t_all += time.perf_counter() - t0
         edges_all += oracle.component_edges(off, depth)
         used.append(r)
         if t_all > budget_s * 0.5:
@@ -75,6 +79,137 @@ def cpu_baseline(off_dev, cols_dev, roots, budget_s=30.0):
     return {"value": edges_all / t_all / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": "oracle BFS (single thread, original labels) from %d of the roots on the "
                       "same graph, %.1f s" % (len(used), t_all)}
+
+
+def time_roots(G, roots, depth, parent, opts, steps):
+    """Per-root event times (ms, mean over steps) on the current stream, and
+    the wall time of all steps."""
+    import torch
+    stream = torch.cuda.current_stream()
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in roots] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        for i, r in enumerate(roots):
+            evs[s][i][0].record(stream)
+            G.bfs(r, depth, parent, opts=opts)
+            evs[s][i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_root = [sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(steps)) / steps
+                for i in range(len(roots))]
+    return per_root, wall
+
+
+def hmean_gteps(m_c, per_root_ms):
+    teps = [m / (t * 1e-3) for m, t in zip(m_c, per_root_ms)]
+    return len(teps) / sum(1.0 / x for x in teps) / 1e9
+
+
+def train_switch(rb, graphgen):
+    """Per-level both-direction timings on Kronecker graphs of scales 18, 20,
+    22, 24 (4 graphs each, 8 roots each), then GPU training; returns the
+    switch blob and a summary."""
+    import numpy as np
+    import torch
+    rows = []
+    t0 = time.perf_counter()
+    for s in (18, 20, 22, 24):
+        for j in range(4):
+            off, cols = graphgen.kronecker_csr_device(s, 16, 2000 + 10 * s + j)
+            roots = graphgen.sample_roots_device(off, 8, 7)
+            G = rb.Graph(off, cols)
+            del off, cols
+            G.rcm_reorder(want_perm=False)
+            rows.append(rb.collect_level_samples(G, roots, reps=3))
+            G.close()
+            torch.cuda.empty_cache()
+    rows = np.vstack(rows)
+    t_collect = time.perf_counter() - t0
+    order = graphgen.epoch_orders(rows.shape[0], 300, 1)
+    t0 = time.perf_counter()
+    w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
+                            batch=64, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    log("# switch: %d samples (%.1f s), trained %.2f s, loss %.3f -> %.3f"
+        % (rows.shape[0], t_collect, t_train, curve[0], curve[-1]))
+    return rb.make_switch_blob(w, rows), {"samples": int(rows.shape[0]),
+                                          "train_graphs": "kronecker scales 18,20,22,24 x 4",
+                                          "collect_s": t_collect, "train_s": t_train,
+                                          "loss_first": float(curve[0]),
+                                          "loss_last": float(curve[-1])}
+
+
+def schedule_costs(rb, G, roots, learned_opts, plain_opts):
+    """Measured per-level cost of the alpha/beta and learned schedules and of
+    the best per-level choice (from both-direction level timings)."""
+    tot = {"alpha_beta_us": 0.0, "learned_us": 0.0, "best_us": 0.0}
+    agree_l = agree_h = nlev = 0
+    for r in roots:
+        rows = rb.collect_level_samples(G, [r], reps=3)
+        by = {int(x[10]): x for x in rows}
+        _, _, sl = G.bfs(r, opts=learned_opts, stats=True)
+        _, _, sh = G.bfs(r, opts=plain_opts, stats=True)
+        for lv, x in by.items():
+            best = 0 if x[8] <= x[9] else 1
+            tot["best_us"] += math.exp(min(x[8], x[9]))
+            if lv < len(sl["dir"]):
+                tot["learned_us"] += math.exp(x[8 + sl["dir"][lv]])
+                agree_l += int(sl["dir"][lv] == best)
+            if lv < len(sh["dir"]):
+                tot["alpha_beta_us"] += math.exp(x[8 + sh["dir"][lv]])
+                agree_h += int(sh["dir"][lv] == best)
+            nlev += 1
+    tot["learned_regret"] = tot["learned_us"] / tot["best_us"] - 1.0
+    tot["alpha_beta_regret"] = tot["alpha_beta_us"] / tot["best_us"] - 1.0
+    tot["learned_best_choice_frac"] = agree_l / max(1, nlev)
+    tot["alpha_beta_best_choice_frac"] = agree_h / max(1, nlev)
+    tot["roots"] = len(roots)
+    return tot
+
+
+def multi_batch(rb, graphgen, steps):
+    """32 Kronecker graphs of scales 12 + (g mod 9), 16 roots each, searched in
+    one captured launch, against the 512 single-root searches."""
+    import torch
+    Gs, roots, m_c = [], [], 0
+    for g in range(32):
+        s = 12 + (g % 9)
+        off, cols = graphgen.kronecker_csr_device(s, 16, 3000 + g)
+        rs = graphgen.sample_roots_device(off, 16, 7)
+        G = rb.Graph(off, cols)
+        G.rcm_reorder(want_perm=False)
+        Gs.append(G)
+        roots.append(rs)
+    M = rb.MultiGraph(Gs)
+    tot = M.out_size(16)
+    depth = torch.empty(tot, dtype=torch.int32, device="cuda")
+    parent = torch.empty(tot, dtype=torch.int32, device="cuda")
+    single_ms = 0.0
+    for G, rs in zip(Gs, roots):
+        d = torch.empty(G.n, dtype=torch.int32, device="cuda")
+        p = torch.empty(G.n, dtype=torch.int32, device="cuda")
+        for r in rs:
+            _, _, st = G.bfs(r, d, p, stats=True)
+            m_c += st["component_edges"]
+        per_root, _ = time_roots(G, rs, d, p, rb.make_opts(), steps)
+        single_ms += sum(per_root)
+    M.bfs(roots, depth=depth, parent=parent)  # capture
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        M.bfs(roots, depth=depth, parent=parent)  # replay
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    log("# multi: 32 graphs x 16 roots: %.2f ms batched vs %.2f ms single-root" % (ms, single_ms))
+    return {"value": m_c / (ms * 1e-3) / 1e9, "unit": "GTEPS (aggregate)",
+            "ms_per_batch": ms, "single_root_ms_sum": single_ms,
+            "single_root_gteps": m_c / (single_ms * 1e-3) / 1e9,
+            "vs_single_root": single_ms / ms, "graphs": 32, "roots_per_graph": 16,
+            "scales": "12..20"}
 
 
 def main():
@@ -90,6 +225,9 @@ def main():
     ap.add_argument("--alpha", type=int, default=14)
     ap.add_argument("--beta", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -108,9 +246,8 @@ def main():
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     roots = graphgen.sample_roots_device(off, args.roots, args.root_seed)
-    print("# generated scale %d: n=%d nnz=%d in %.1fs" % (args.scale, off.numel() - 1,
-                                                          cols.numel(), t_gen),
-          file=sys.stderr, flush=True)
+    log("# generated scale %d: n=%d nnz=%d in %.1fs" % (args.scale, off.numel() - 1,
+                                                        cols.numel(), t_gen))
     G = rb.Graph(off, cols)
     keep_host = not args.no_cpu
     if not keep_host:
@@ -118,9 +255,10 @@ def main():
         torch.cuda.empty_cache()
     _, rcm_ms = G.rcm_reorder(want_perm=False)
     info = G.info()
-    print("# rcm %.1f ms, n_plus=%d" % (rcm_ms, info["n_plus"]), file=sys.stderr, flush=True)
+    log("# rcm %.1f ms, n_plus=%d" % (rcm_ms, info["n_plus"]))
 
     n = info["n"]
+    nroot = len(roots)
     depth = torch.empty(n, dtype=torch.int32, device="cuda")
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     plain = rb.make_opts(alpha=args.alpha, beta=args.beta)
@@ -137,40 +275,23 @@ def main():
     G.check()
     G.timings()  # clear
 
-    stream = torch.cuda.current_stream()
-    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-            for _ in roots] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t_wall0 = time.perf_counter()
-    for s in range(args.steps):
-        for i, r in enumerate(roots):
-            evs[s][i][0].record(stream)
-            G.bfs(r, depth, parent, opts=timed)
-            evs[s][i][1].record(stream)
-    torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t_wall0
+    per_root_ms, t_wall = time_roots(G, roots, depth, parent, timed, args.steps)
     G.check()
     kernel_ms, total_ms = G.timings()
 
-    per_root_ms = [sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps))
-                   / args.steps for i in range(len(roots))]
     m_c = [st["component_edges"] for st in stats]
-    teps = [m / (t * 1e-3) for m, t in zip(m_c, per_root_ms)]
-    hmean = len(teps) / sum(1.0 / x for x in teps)
+    hmean = hmean_gteps(m_c, per_root_ms)
     ms_per_step = t_wall * 1e3 / args.steps
-
     n_sweep = info["n_plus"]
     alg = [bfs_alg_bytes(st, n_sweep) for st in stats]
-    nroot = len(roots)
     k_avg_ms = sum(kernel_ms) / max(1, len(kernel_ms))
     bytes_avg = sum(alg[i % nroot] for i in range(len(kernel_ms))) / max(1, len(kernel_ms))
     achieved = bytes_avg / (k_avg_ms * 1e-3) / 1e9
-    internal_teps = [m / (k * 1e-3) for m, k in zip(m_c * args.steps, kernel_ms)]
-    hmean_internal = len(internal_teps) / sum(1.0 / x for x in internal_teps)
+    hmean_internal = hmean_gteps(m_c * args.steps, kernel_ms)
 
     out = {
         "metric": "GTEPS (harmonic mean, 64 roots) Kronecker scale %d" % args.scale,
-        "value": hmean / 1e9,
+        "value": hmean,
         "unit": "GTEPS",
         "n_gpus": 1,
         "steps": args.steps,
@@ -193,11 +314,50 @@ def main():
                      "alg_bytes_avg": bytes_avg},
         "rcm_ms": rcm_ms,
         "gen_s": t_gen,
-        "gteps_search_kernel_only": hmean_internal / 1e9,
+        "gteps_search_kernel_only": hmean_internal,
         "translate_ms_avg": (sum(total_ms) - sum(kernel_ms)) / max(1, len(kernel_ms)),
         "levels_avg": sum(st["levels"] for st in stats) / nroot,
         "device": dev,
     }
+
+    if not args.no_batch:
+        # 64 roots bit-parallel on the same graph, one call
+        dB = torch.empty((nroot, n), dtype=torch.int32, device="cuda")
+        pB = torch.empty((nroot, n), dtype=torch.int32, device="cuda")
+        G.bfs_batch(roots, dB, pB)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            G.bfs_batch(roots, dB, pB)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / args.steps
+        d_last, p_last = G.bfs(roots[-1], depth, parent)
+        ok = bool(torch.equal(dB[nroot - 1], d_last) and torch.equal(pB[nroot - 1], p_last))
+        out["batched"] = {"value": sum(m_c) / (ms_b * 1e-3) / 1e9,
+                          "unit": "GTEPS (aggregate, 64 roots bit-parallel, one launch)",
+                          "ms_per_batch": ms_b, "vs_plain": sum(per_root_ms) / ms_b,
+                          "last_row_equals_single_root": ok}
+        log("# batched: %.2f ms for 64 roots (%.1f GTEPS aggregate)"
+            % (ms_b, out["batched"]["value"]))
+        del dB, pB
+        torch.cuda.empty_cache()
+    if not args.no_learned:
+        blob, info_sw = train_switch(rb, graphgen)
+        rb.switch_load(blob)
+        learned = rb.make_opts(rb.DIR_LEARNED, alpha=args.alpha, beta=args.beta)
+        for r in roots[:4]:
+            G.bfs(r, depth, parent, opts=learned)
+        per_root_l, _ = time_roots(G, roots, depth, parent, learned, args.steps)
+        gl = hmean_gteps(m_c, per_root_l)
+        out["learned"] = {"value": gl, "unit": "GTEPS", "vs_plain": gl / hmean,
+                          "training": info_sw,
+                          "schedule_costs_8_roots": schedule_costs(rb, G, roots[:8], learned,
+                                                                   plain)}
+        log("# learned: %.1f GTEPS (plain %.1f)" % (gl, hmean))
+    if not args.no_multi:
+        out["multi"] = multi_batch(rb, graphgen, args.steps)
     if keep_host:
         out["cpu_baseline"] = cpu_baseline(off, cols, roots, args.cpu_budget)
         model, ncpu = host_cpu()

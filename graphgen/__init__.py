@@ -239,3 +239,25 @@ def sample_roots_device(off_dev, k, seed, distinct=True):
             seen.add(v)
             roots.append(int(v))
     return roots
+
+
+# ----------------------------------------------------------------------------
+# seeded draws for training the direction-switch network (initial weights and
+# per-epoch sample orders); passed to both the GPU trainer and its reference
+
+MLP_LAYERS = [((32, 8), 8), ((32,), 8), ((32, 32), 32), ((32,), 32), ((2, 32), 32), ((2,), 32)]
+
+
+def mlp_init_weights(seed):
+    """1410 values, layer by layer (W1, b1, W2, b2, W3, b3), each uniform in
+    +-1/sqrt(fan_in) of its layer."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1.0 / np.sqrt(fan), 1.0 / np.sqrt(fan), size=shape).ravel()
+             for shape, fan in MLP_LAYERS]
+    return np.concatenate(parts)
+
+
+def epoch_orders(n, epochs, seed):
+    """Seeded per-epoch permutations of n samples, shape (epochs, n)."""
+    rng = np.random.default_rng(seed)
+    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)

@@ -35,17 +35,6 @@ def pack(parts):
     return np.concatenate([np.asarray(parts[name], np.float64).ravel() for name, _ in SIZES])
 
 
-def init_weights(seed):
-    """Uniform in +-1/sqrt(fan_in) per layer (weights and biases)."""
-    rng = np.random.default_rng(seed)
-    parts = {}
-    for name, shape in SIZES:
-        fan_in = NIN if name in ("W1", "b1") else NHID
-        bound = 1.0 / np.sqrt(fan_in)
-        parts[name] = rng.uniform(-bound, bound, size=shape)
-    return pack(parts)
-
-
 def forward(w, X):
     p = unpack(w)
     X = np.asarray(X, np.float64)
@@ -105,9 +94,3 @@ def train(samples, w0, order, batch=256, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
             w = w - lr * mh / (np.sqrt(vh) + eps)
         curve.append(total / n)
     return w, np.array(curve)
-
-
-def epoch_orders(n, epochs, seed):
-    """Seeded per-epoch permutations of the n samples (passed to the GPU)."""
-    rng = np.random.default_rng(seed)
-    return np.stack([rng.permutation(n) for _ in range(epochs)]).astype(np.int32)

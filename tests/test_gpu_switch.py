@@ -30,7 +30,7 @@ def rand_samples(n, seed):
 
 
 def test_forward_matches_oracle(rb):
-    w = mlp.init_weights(1).astype(np.float32)
+    w = graphgen.mlp_init_weights(1).astype(np.float32)
     X = rand_samples(300, 2)[:, :8]
     y = rb.mlp_forward(w, X)
     y_o, _ = mlp.forward(w.astype(np.float64), X.astype(np.float64))
@@ -38,7 +38,7 @@ def test_forward_matches_oracle(rb):
 
 
 def test_gradient_matches_oracle(rb):
-    w = mlp.init_weights(3).astype(np.float32)
+    w = graphgen.mlp_init_weights(3).astype(np.float32)
     S = rand_samples(200, 4)
     g, loss = rb.mlp_grad(w, S)
     loss_o, g_o = mlp.loss_and_grad(w.astype(np.float64), S.astype(np.float64))
@@ -49,8 +49,8 @@ def test_gradient_matches_oracle(rb):
 
 def test_training_matches_oracle_and_is_reproducible(rb):
     S = rand_samples(700, 5)
-    w0 = mlp.init_weights(7).astype(np.float32)
-    order = mlp.epoch_orders(700, 3, 11)
+    w0 = graphgen.mlp_init_weights(7).astype(np.float32)
+    order = graphgen.epoch_orders(700, 3, 11)
     w1, c1 = rb.mlp_train(S, w0, order, batch=256, lr=1e-3)
     w2, c2 = rb.mlp_train(S, w0, order, batch=256, lr=1e-3)
     assert np.array_equal(w1, w2) and np.array_equal(c1, c2)  # bit-reproducible
@@ -62,8 +62,8 @@ def test_training_matches_oracle_and_is_reproducible(rb):
 
 def test_training_reduces_loss(rb):
     S = rand_samples(1024, 8)
-    order = mlp.epoch_orders(1024, 60, 3)
-    w, curve = rb.mlp_train(S, mlp.init_weights(2).astype(np.float32), order, batch=128,
+    order = graphgen.epoch_orders(1024, 60, 3)
+    w, curve = rb.mlp_train(S, graphgen.mlp_init_weights(2).astype(np.float32), order, batch=128,
                             lr=3e-3)
     assert curve[-1] < 0.1 * curve[0]
 
@@ -82,7 +82,7 @@ def test_learned_mode_results_are_exact(rb):
     samples = rb.collect_level_samples(G, roots[:2], reps=1)
     assert samples.shape[0] > 0
     for seed in (0, 1, 2):
-        w = mlp.init_weights(seed).astype(np.float32)
+        w = graphgen.mlp_init_weights(seed).astype(np.float32)
         blob = rb.make_switch_blob(w, samples)
         blob[mlp.NPARAMS:mlp.NPARAMS + 8] = -10.0   # accept every input: the
         blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16] = 10.0  # random net decides all
@@ -128,8 +128,8 @@ def test_learned_switch_gain_on_held_out_graph(rb):
         train_rows.append(rb.collect_level_samples(G, roots, reps=3))
     rows = np.vstack(train_rows)
     S = rows[:, :10]
-    order = mlp.epoch_orders(S.shape[0], 300, 1)
-    w, curve = rb.mlp_train(S, mlp.init_weights(0).astype(np.float32), order, batch=64,
+    order = graphgen.epoch_orders(S.shape[0], 300, 1)
+    w, curve = rb.mlp_train(S, graphgen.mlp_init_weights(0).astype(np.float32), order, batch=64,
                             lr=3e-3)
     assert curve[-1] < curve[0]
     rb.switch_load(rb.make_switch_blob(w, rows))

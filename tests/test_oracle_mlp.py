@@ -3,6 +3,8 @@ closed forms, and a known property of Adam's first step."""
 import numpy as np
 import pytest
 
+import graphgen
+
 from oracle import mlp
 
 
@@ -15,7 +17,7 @@ def rand_samples(n, seed):
 
 @pytest.mark.parametrize("seed", range(4))
 def test_gradient_finite_differences(seed):
-    w = mlp.init_weights(seed)
+    w = graphgen.mlp_init_weights(seed)
     S = rand_samples(37, seed + 10)
     loss, g = mlp.loss_and_grad(w, S)
     h = 1e-6
@@ -28,7 +30,7 @@ def test_gradient_finite_differences(seed):
 
 
 def test_closed_form_zero_output_layer():
-    w = mlp.init_weights(3)
+    w = graphgen.mlp_init_weights(3)
     p = mlp.unpack(w)
     p["W3"][:] = 0.0
     w = mlp.pack(p)
@@ -56,7 +58,7 @@ def test_linear_regime_matches_least_squares_gradient():
 
 
 def test_adam_first_step_moves_by_lr_sign():
-    w0 = mlp.init_weights(5)
+    w0 = graphgen.mlp_init_weights(5)
     S = rand_samples(64, 6)
     order = np.arange(64)[None, :]
     w1, _ = mlp.train(S, w0, order, batch=64, lr=1e-3)
@@ -70,6 +72,6 @@ def test_training_reduces_loss_on_learnable_target():
     X = rng.uniform(0, 1, size=(512, 8))
     T = np.stack([X[:, 0] * 2 + X[:, 1], 1 - X[:, 2]], axis=1)
     S = np.hstack([X, T])
-    order = mlp.epoch_orders(512, 30, 9)
-    w, curve = mlp.train(S, mlp.init_weights(1), order, batch=64, lr=3e-3)
+    order = graphgen.epoch_orders(512, 30, 9)
+    w, curve = mlp.train(S, graphgen.mlp_init_weights(1), order, batch=64, lr=3e-3)
     assert curve[-1] < 0.2 * curve[0]
