@@ -60,6 +60,26 @@ def bfs_alg_bytes(st, n_sweep):
     return total
 
 
+def measured_traffic():
+    """Per-launch bytes of the search kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic_bfs_persistent_kernel.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        h = hashlib.sha1()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != rec["source_sha1"]:
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def cpu_baseline(off_dev, cols_dev, roots, budget_s=30.0):
     """The oracle's BFS (single thread, original labels) on a bounded sample
     of the roots of the same graph."""
@@ -229,6 +249,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
+                    help="also run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported" % args.gpus,
@@ -309,7 +331,8 @@ def main():
                                   args.beta),
                    "n": n, "nnz": info["nnz"], "n_plus": n_sweep},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic(),
                      "kernel": "bfs_persistent_kernel", "kernel_avg_ms": k_avg_ms,
                      "alg_bytes_avg": bytes_avg},
         "rcm_ms": rcm_ms,
@@ -358,6 +381,15 @@ def main():
         log("# learned: %.1f GTEPS (plain %.1f)" % (gl, hmean))
     if not args.no_multi:
         out["multi"] = multi_batch(rb, graphgen, args.steps)
+    if args.copy_calibration_gib > 0:
+        nb = int(args.copy_calibration_gib * (1 << 30))
+        a = torch.ones(nb, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = nb
+        del a, b
     if keep_host:
         out["cpu_baseline"] = cpu_baseline(off, cols, roots, args.cpu_budget)
         model, ncpu = host_cpu()

@@ -124,16 +124,32 @@ __global__ __launch_bounds__(kBlock) void cc_union_kernel(const int64_t* off, co
   }
 }
 
+// Final root of every rank and the component sizes.  One component usually
+// holds almost every vertex, so the size counts are aggregated per wave
+// (lanes with the wave's first root add with one atomic) instead of one
+// same-address atomic per vertex.
 __global__ void cc_compress_kernel(int32_t* ccp, int64_t nplus, int32_t* csize) {
-  GRID_STRIDE(k, nplus) {
-    int32_t x = (int32_t)k;
-    int32_t p = ccp[x];
-    while (p != x) {
-      x = p;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < nplus; k0 += stride) {
+    const int64_t k = k0 + threadIdx.x;
+    const bool act = k < nplus;
+    int32_t p = -1;
+    if (act) {
+      int32_t x = (int32_t)k;
       p = ccp[x];
+      while (p != x) {
+        x = p;
+        p = ccp[x];
+      }
+      ccp[k] = p;
     }
-    ccp[k] = p;
-    atomicAdd(&csize[p], 1);
+    const uint64_t am = ballot(act);
+    if (am == 0) continue;
+    const int32_t p0 = shfl(p, ffs64(am));
+    const bool same = act && p == p0;
+    const uint64_t sm = ballot(same);
+    if (lane_id() == ffs64(sm)) atomicAdd(&csize[p0], popc64(sm));
+    if (act && !same) atomicAdd(&csize[p], 1);
   }
 }
 
@@ -172,8 +188,13 @@ __global__ __launch_bounds__(kBlock) void cm_expand_kernel(
                                  [&](bool active, int32_t u, int32_t w) {
       bool first = false;
       if (active && label[w] < 0) {
-        const uint32_t old = atomicMin(&plabel[w], (uint32_t)label[u]);
-        first = (old == kUnset);
+        // a stale read can only be larger: skip the atomic when w already
+        // holds a label no larger than u's (then w was touched before)
+        const uint32_t lu = (uint32_t)label[u];
+        if (plabel[w] > lu) {
+          const uint32_t old = atomicMin(&plabel[w], lu);
+          first = (old == kUnset);
+        }
       }
       const uint64_t m = ballot(first);
       if (m) {
