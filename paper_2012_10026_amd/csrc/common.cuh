@@ -139,19 +139,20 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks
 // ---------------------------------------------------------------------------
 // First hit: each active lane holds a vertex whose row is cols[b, e); it
 // finds the first entry w (in row order, i.e. increasing label) with bit w
-// set in `bits`.  Rows of at most kLaneRow entries are scanned by their own
+// set in `bits`.  Rows of at most `lane_row` entries are scanned by their own
 // lane; longer rows by the whole wave, 64 entries per step, where the lowest
 // hitting lane is the first hit.  `examined` (per lane, summed later) counts
 // the entries read up to and including the hit.  All lanes must call.
-constexpr int kLaneRow = 32;
+constexpr int kLaneRow = 32;  // default lane/wave split
 
 __device__ __forceinline__ void wave_first_hit(bool active, int64_t b, int64_t e,
                                                const int32_t* cols, const uint64_t* bits,
-                                               bool& found, int32_t& par, int64_t& examined) {
+                                               bool& found, int32_t& par, int64_t& examined,
+                                               int lane_row = kLaneRow) {
   const int l = lane_id();
   found = false;
   par = 0;
-  const bool hub = active && (e - b) > kLaneRow;
+  const bool hub = active && (e - b) > lane_row;
   if (active && !hub) {
     // four entries per step: the loads of a step are independent, so one
     // memory round trip covers four candidates

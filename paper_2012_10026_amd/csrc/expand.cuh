@@ -2,13 +2,13 @@
 //
 // A frontier is a list of vertices q[0..nq) with the exclusive prefix sum of
 // their degrees qe[0..nq] (qe[nq] = E).  The E adjacency entries of the
-// frontier, taken in list order, are cut into chunks of kChunkEdges; chunk c
-// starts at entry c * kChunkEdges, and chunk_pos[c] is the list position
-// whose row holds that entry.  A workgroup stages the list positions a chunk
-// touches (at most kChunkEdges + 1) in LDS and each thread finds the position
-// of its entry by binary search there, so every thread handles the same
-// number of entries whatever the degree skew, and consecutive threads read
-// consecutive column entries.  This is the GPU counterpart of the paper's
+// frontier, taken in list order, are cut into chunks of 2^cshift entries
+// (at most kChunkEdges); chunk c starts at entry c << cshift, and
+// chunk_pos[c] is the list position whose row holds that entry.  A
+// workgroup stages the list positions a chunk touches in LDS and each thread
+// finds the position of its entry by binary search there, so every thread
+// handles the same number of entries whatever the degree skew, and
+// consecutive threads read consecutive column entries.  This is the GPU counterpart of the paper's
 // even split of each frontier vertex's neighbours over the threads (top-down
 // load balancing, Algorithm 4 and Eq. 3).
 #pragma once
@@ -20,9 +20,11 @@ namespace rbfs {
 // Marks the chunks whose first entry lies in [base, base + deg) as starting at
 // list position pos.
 __device__ __forceinline__ void mark_chunks(int32_t* chunk_pos, int64_t chunk_cap, int64_t base,
-                                            int64_t deg, int32_t pos) {
-  const int64_t c0 = (base + kChunkEdges - 1) / kChunkEdges;
-  const int64_t c1 = (base + deg + kChunkEdges - 1) / kChunkEdges;
+                                            int64_t deg, int32_t pos,
+                                            int cshift = kChunkShift) {
+  const int64_t cm = ((int64_t)1 << cshift) - 1;
+  const int64_t c0 = (base + cm) >> cshift;
+  const int64_t c1 = (base + deg + cm) >> cshift;
   for (int64_t c = c0; c < c1 && c < chunk_cap; ++c) chunk_pos[c] = pos;
 }
 
@@ -41,14 +43,17 @@ template <int BLOCK, class F>
 __device__ __forceinline__ bool expand_chunk(ChunkLds& s, int64_t c, int64_t E, const int32_t* q,
                                              const int64_t* qe, int64_t nq,
                                              const int32_t* chunk_pos, int64_t nchunks,
-                                             const int64_t* off, const int32_t* cols, F&& f) {
-  const int64_t e0 = c * kChunkEdges;
-  const int64_t e1 = (e0 + kChunkEdges < E) ? e0 + kChunkEdges : E;
+                                             const int64_t* off, const int32_t* cols, F&& f,
+                                             int cshift = kChunkShift) {
+  const int64_t ch = (int64_t)1 << cshift;
+  const int64_t e0 = c << cshift;
+  const int64_t e1 = (e0 + ch < E) ? e0 + ch : E;
   if (threadIdx.x == 0) {
     const int64_t p0 = chunk_pos[c];
     const int64_t p1 = (c + 1 < nchunks) ? (int64_t)chunk_pos[c + 1] : nq - 1;
     int64_t k = p1 - p0 + 1;
-    const bool bad = p0 < 0 || p1 >= nq || k < 1 || k > kChunkEdges + 2;
+    const bool bad = p0 < 0 || p1 >= nq || k < 1 || k > kChunkEdges + 1 ||
+                     cshift > kChunkShift;
     s.k = bad ? -1 : (int32_t)k;
     s.u[kChunkEdges + 1] = (int32_t)p0;
   }

@@ -11,7 +11,9 @@
 namespace rbfs {
 
 // Edges per chunk of the edge-balanced frontier expansion.
-constexpr int kChunkEdges = 1024;
+constexpr int kChunkShift = 10;
+constexpr int kChunkEdges = 1 << kChunkShift;  // largest top-down chunk
+constexpr int kMinChunkShift = 8;
 
 struct BfsCtl;
 struct MsCtl;
