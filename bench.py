@@ -5,8 +5,10 @@ One step = 64 single-root searches (plain alpha = 14 / beta = 24 heuristic,
 outputs in original IDs), inputs resident in HBM.  RCM is timed once,
 separately.  Also measured on the same graph and roots: the learned direction
 switch (trained here on per-level timings of scale 18-24 graphs) and the
-64-root bit-parallel batch; and the 32-graph multi-graph batch.  Prints one
-JSON line.
+64-root bit-parallel batch; and the 32-graph multi-graph batch.  Launch
+parameters come from the autotuner's JSON cache (tuned on other roots of the
+same graphs; a missing entry is tuned in the run, --retune forces it,
+--no-tune uses the built-in defaults).  Prints one JSON line.
 """
 import argparse
 import json
@@ -20,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+DEFAULT_TUNING_CACHE = os.path.join(ROOT, "paper_2012_10026_amd", "tuning", "mi355x.json")
 
 
 def log(msg):
@@ -189,20 +192,43 @@ def schedule_costs(rb, G, roots, learned_opts, plain_opts):
     return tot
 
 
-def multi_batch(rb, graphgen, steps):
+def tuned_leg(rb, target, roots, cache, graph_class, kind, retune, opts=None, reps=2):
+    """Autotuned parameters for one leg: from the cache, or tuned now (and
+    stored).  Returns a report dict."""
+    from paper_2012_10026_amd import autotune
+    t_t = time.perf_counter()
+    best, recs = rb.tune_cached(target, roots, cache, graph_class, kind=kind, reps=reps,
+                                opts=opts, retune=retune)
+    key = autotune.tuning_key(rb.device_info()["arch"], graph_class,
+                              autotune.target_size(target), kind)
+    e = cache.entries.get(key, {})
+    rep = {"tuning": best, "key": key, "source": "tuned now" if recs else "cache",
+           "default_ms": e.get("default_ms"), "tuned_ms": e.get("ms"),
+           "seconds": time.perf_counter() - t_t}
+    if recs:
+        rep["candidates"] = len(recs)
+    log("# tuning %s (%s): %s" % (key, rep["source"], best))
+    return rep
+
+
+def multi_batch(rb, graphgen, steps, cache=None, retune=False):
     """32 Kronecker graphs of scales 12 + (g mod 9), 16 roots each, searched in
     one captured launch, against the 512 single-root searches."""
     import torch
-    Gs, roots, m_c = [], [], 0
+    Gs, roots, troots, m_c = [], [], [], 0
     for g in range(32):
         s = 12 + (g % 9)
         off, cols = graphgen.kronecker_csr_device(s, 16, 3000 + g)
         rs = graphgen.sample_roots_device(off, 16, 7)
+        troots.append(graphgen.sample_roots_device(off, 16, 1007))  # autotuner's sample
         G = rb.Graph(off, cols)
         G.rcm_reorder(want_perm=False)
         Gs.append(G)
         roots.append(rs)
     M = rb.MultiGraph(Gs)
+    tuned = None
+    if cache is not None:
+        tuned = tuned_leg(rb, M, troots, cache, "kronecker-multi32", rb.TUNE_BATCH, retune)
     tot = M.out_size(16)
     depth = torch.empty(tot, dtype=torch.int32, device="cuda")
     parent = torch.empty(tot, dtype=torch.int32, device="cuda")
@@ -229,7 +255,7 @@ def multi_batch(rb, graphgen, steps):
             "ms_per_batch": ms, "single_root_ms_sum": single_ms,
             "single_root_gteps": m_c / (single_ms * 1e-3) / 1e9,
             "vs_single_root": single_ms / ms, "graphs": 32, "roots_per_graph": 16,
-            "scales": "12..20"}
+            "scales": "12..20", "tuning": tuned}
 
 
 def main():
@@ -248,6 +274,13 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="time the built-in launch parameters instead of autotuned ones")
+    ap.add_argument("--retune", action="store_true",
+                    help="run the autotuner even where the cache has an entry, and store it")
+    ap.add_argument("--tuning-cache", default=DEFAULT_TUNING_CACHE,
+                    help="JSON file of autotuned parameters (read, and written on a miss)")
+    ap.add_argument("--tune-roots", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (profiler calibration)")
@@ -268,6 +301,8 @@ def main():
     torch.cuda.synchronize()
     t_gen = time.perf_counter() - t0
     roots = graphgen.sample_roots_device(off, args.roots, args.root_seed)
+    # the autotuner samples its own roots (another seed) from the same graph
+    tune_roots = graphgen.sample_roots_device(off, 64, args.root_seed + 1000)
     log("# generated scale %d: n=%d nnz=%d in %.1fs" % (args.scale, off.numel() - 1,
                                                         cols.numel(), t_gen))
     G = rb.Graph(off, cols)
@@ -285,6 +320,12 @@ def main():
     parent = torch.empty(n, dtype=torch.int32, device="cuda")
     plain = rb.make_opts(alpha=args.alpha, beta=args.beta)
     timed = rb.make_opts(alpha=args.alpha, beta=args.beta, timing=True)
+
+    tuning = {}
+    cache = None if args.no_tune else rb.TuningCache(args.tuning_cache)
+    if cache is not None:
+        tuning["single"] = tuned_leg(rb, G, tune_roots[:args.tune_roots], cache, "kronecker",
+                                     rb.TUNE_SINGLE, args.retune, opts=plain)
 
     # untimed pass: per-root counters (deterministic) for TEPS and the bytes model
     stats = []
@@ -345,6 +386,10 @@ def main():
 
     if not args.no_batch:
         # 64 roots bit-parallel on the same graph, one call
+        if cache is not None:
+            tuning["batch"] = tuned_leg(rb, G, tune_roots, cache, "kronecker", rb.TUNE_BATCH,
+                                        args.retune, reps=1)
+            torch.cuda.empty_cache()
         dB = torch.empty((nroot, n), dtype=torch.int32, device="cuda")
         pB = torch.empty((nroot, n), dtype=torch.int32, device="cuda")
         G.bfs_batch(roots, dB, pB)
@@ -380,7 +425,9 @@ def main():
                                                                    plain)}
         log("# learned: %.1f GTEPS (plain %.1f)" % (gl, hmean))
     if not args.no_multi:
-        out["multi"] = multi_batch(rb, graphgen, args.steps)
+        out["multi"] = multi_batch(rb, graphgen, args.steps, cache, args.retune)
+    if tuning:
+        out["tuning"] = tuning
     if args.copy_calibration_gib > 0:
         nb = int(args.copy_calibration_gib * (1 << 30))
         a = torch.ones(nb, dtype=torch.uint8, device="cuda")

@@ -88,8 +88,11 @@ typedef struct rbfs_opts {
                               d; levels past schedule_len repeat the last entry;
                               level 0 is always top-down */
   int32_t schedule_len;
-  int32_t tune_profile;    /* 0 = default launch shape, else an autotuned
-                              profile id (rbfs_tune) */
+  int32_t tune_profile;    /* 0 = the graph's tuning (rbfs_graph_set_tuning,
+                              rbfs_tune; built-in defaults until then);
+                              1..4 = 256-thread workgroups, that many per
+                              compute unit; 5, 6 = 1024-thread workgroups,
+                              1 or 2 per compute unit (single-root only) */
   int32_t flags;           /* RBFS_OPT_* */
 } rbfs_opts_t;
 
@@ -220,6 +223,78 @@ int rbfs_multi_destroy(rbfs_multi_t* m);
  * is replayed on later calls with the same k. */
 int rbfs_bfs_multi(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t* depth,
                    int32_t* parent, const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
+
+/* ---- autotuner ----------------------------------------------------------
+ * Launch shape and work-split parameters of the searches.  They decide only
+ * how the work of a level is spread over the GPU: every setting gives the
+ * same depth and parent arrays, bit for bit.  The autotuner (not in the
+ * paper; its counterpart there is the grid search over the partition factor
+ * lambda of Algorithm 5 in "Parameter Tuning") times settings on sample roots
+ * and keeps the fastest whose outputs equal those of the built-in defaults. */
+typedef struct rbfs_tuning {
+  int32_t block;     /* threads per search workgroup: 256 or 1024 (batched
+                        searches: 1024 only) */
+  int32_t per_cu;    /* search workgroups per compute unit, 1..4; clamped to
+                        what can be resident at once */
+  int32_t lane_row;  /* bottom-up: rows of at most lane_row entries are scanned
+                        by one lane each, longer rows by a whole wave; 1..4096 */
+  int32_t bu_grain;  /* bottom-up: edge-balanced work ranges per search
+                        workgroup (taken by work stealing); 1..1024 */
+  int32_t td_chunk;  /* top-down: adjacency entries per load-balancing chunk:
+                        256, 512 or 1024 (single-root only) */
+  int32_t reset;     /* single-root with original-ID outputs: 1 = the output
+                        translation clears the internal entries it reads
+                        (scattered writes), 0 = the next search
+                        re-initialises them in one coalesced pass */
+} rbfs_tuning_t;
+
+#define RBFS_TUNE_SINGLE 0 /* rbfs_bfs */
+#define RBFS_TUNE_BATCH 1  /* rbfs_bfs_batch */
+
+typedef struct rbfs_tune_record {
+  rbfs_tuning_t tuning;
+  float ms;            /* mean device time of one call (rbfs_bfs: one root;
+                          batch and multi: one call over all roots) */
+  int32_t mismatches;  /* output entries that differ from the reference */
+} rbfs_tune_record_t;
+
+/* Fills *t with the built-in defaults of `kind`. */
+int rbfs_tuning_default(int32_t kind, rbfs_tuning_t* t);
+
+/* Sets or reads the parameters later calls of `kind` use on this graph.
+ * Values outside the documented ranges return RBFS_E_INVAL; per_cu is
+ * clamped.  Setting synchronises `stream` when the bottom-up ranges have to
+ * be rebuilt. */
+int rbfs_graph_set_tuning(rbfs_graph_t* g, int32_t kind, const rbfs_tuning_t* t, void* stream);
+int rbfs_graph_get_tuning(const rbfs_graph_t* g, int32_t kind, rbfs_tuning_t* t);
+
+/* Autotuner.  roots: host int32[k] original IDs (RBFS_TUNE_SINGLE: 1 <= k <=
+ * 64, each root searched in turn; RBFS_TUNE_BATCH: 1 <= k <= 64, one batch).
+ * opts (nullable) gives direction and output space; timing flags and
+ * tune_profile are ignored.  The reference outputs come from the built-in
+ * defaults.  Each candidate runs once per root (compared entry by entry with
+ * the reference) and then `reps` timed times.  The search is coordinate
+ * descent over launch shape, lane_row, bu_grain, td_chunk and reset, starting
+ * from the defaults; a change is kept when it is at least 1 % faster.  The
+ * winner is set on the graph and copied to *best (nullable); records[cap]
+ * (nullable) receives every candidate timed, *count (nullable) their number.
+ * A candidate whose outputs differ is never chosen and makes the call return
+ * RBFS_E_DEVICE after it finishes (its record shows the mismatches).
+ * Device memory: 8 * k * n bytes for the reference and 8 * n (single) or
+ * 8 * k * n (batch) for the candidate outputs, freed before returning.
+ * Synchronises `stream`. */
+int rbfs_tune(rbfs_graph_t* g, int32_t kind, const int32_t* roots, int32_t k, int32_t reps,
+              const rbfs_opts_t* opts, rbfs_tuning_t* best, rbfs_tune_record_t* records,
+              int32_t cap, int32_t* count, void* stream);
+
+/* The same for a multi-graph batch (kind RBFS_TUNE_BATCH parameters; roots
+ * as in rbfs_bfs_multi).  Changing the parameters re-captures the search on
+ * the next call.  Device memory: twice the output size of rbfs_bfs_multi. */
+int rbfs_multi_set_tuning(rbfs_multi_t* m, const rbfs_tuning_t* t, void* stream);
+int rbfs_multi_get_tuning(const rbfs_multi_t* m, rbfs_tuning_t* t);
+int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t reps,
+                    rbfs_tuning_t* best, rbfs_tune_record_t* records, int32_t cap,
+                    int32_t* count, void* stream);
 
 /* ---- learned direction switch ------------------------------------------
  * Not in the paper: the alpha/beta rule of Algorithm 2 (section 2.1,

@@ -67,6 +67,28 @@ class GraphInfo(ctypes.Structure):
                 ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
 
 
+TUNE_SINGLE, TUNE_BATCH = 0, 1
+TUNING_FIELDS = ("block", "per_cu", "lane_row", "bu_grain", "td_chunk", "reset")
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int32) for f in TUNING_FIELDS]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f in TUNING_FIELDS}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for f in TUNING_FIELDS:
+            setattr(t, f, int(d[f]))
+        return t
+
+
+class TuneRecord(ctypes.Structure):
+    _fields_ = [("tuning", Tuning), ("ms", ctypes.c_float), ("mismatches", ctypes.c_int32)]
+
+
 class DeviceInfo(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("compute_units", ctypes.c_int32),
                 ("wavefront_size", ctypes.c_int32), ("clock_khz", ctypes.c_int32),
@@ -101,6 +123,13 @@ SIGNATURES = {
                                       _P]),
     "rbfs_mlp_forward": (ctypes.c_int, [_P, _P, _I32, _P]),
     "rbfs_mlp_grad": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "rbfs_tuning_default": (ctypes.c_int, [_I32, _P]),
+    "rbfs_graph_set_tuning": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "rbfs_graph_get_tuning": (ctypes.c_int, [_P, _I32, _P]),
+    "rbfs_tune": (ctypes.c_int, [_P, _I32, _P, _I32, _I32, _P, _P, _P, _I32, _P, _P]),
+    "rbfs_multi_set_tuning": (ctypes.c_int, [_P, _P, _P]),
+    "rbfs_multi_get_tuning": (ctypes.c_int, [_P, _P]),
+    "rbfs_multi_tune": (ctypes.c_int, [_P, _P, _I32, _I32, _P, _P, _I32, _P, _P]),
 }
 
 _lib = None
@@ -147,6 +176,21 @@ def device_info():
 
 
 OPT_TIMING = 1
+
+
+def default_tuning(kind=TUNE_SINGLE):
+    t = Tuning()
+    _check(lib().rbfs_tuning_default(kind, ctypes.byref(t)))
+    return t.as_dict()
+
+
+def _as_tuning(t):
+    return t if isinstance(t, Tuning) else Tuning.from_dict(t)
+
+
+def _records(recs, cnt):
+    return [dict(r.tuning.as_dict(), ms=float(r.ms), mismatches=int(r.mismatches))
+            for r in recs[:cnt]]
 
 
 def make_opts(direction=DIR_HEURISTIC, alpha=14, beta=24, output_space=OUT_ORIGINAL,
@@ -275,6 +319,31 @@ class Graph:
     def check(self):
         _check(lib().rbfs_graph_check(self._h, _stream_ptr(self.device)))
 
+    def set_tuning(self, tuning, kind=TUNE_SINGLE):
+        t = _as_tuning(tuning)
+        _check(lib().rbfs_graph_set_tuning(self._h, kind, ctypes.byref(t),
+                                           _stream_ptr(self.device)))
+
+    def get_tuning(self, kind=TUNE_SINGLE):
+        t = Tuning()
+        _check(lib().rbfs_graph_get_tuning(self._h, kind, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tune(self, roots, kind=TUNE_SINGLE, reps=2, opts=None, cap=256):
+        """Autotune the launch shape and work split on these roots (original
+        IDs, at most 64).  Returns (best tuning dict, list of timed
+        candidates); the best is set on the graph."""
+        k = len(roots)
+        r = (ctypes.c_int32 * k)(*[int(x) for x in roots])
+        best = Tuning()
+        recs = (TuneRecord * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().rbfs_tune(self._h, kind, r, k, reps,
+                               ctypes.byref(opts) if opts is not None else None,
+                               ctypes.byref(best), recs, cap, ctypes.byref(cnt),
+                               _stream_ptr(self.device)))
+        return best.as_dict(), _records(recs, cnt.value)
+
     def timings(self, cap=1024):
         """(kernel_ms, total_ms) lists of the calls made with timing=True."""
         k = (ctypes.c_float * cap)()
@@ -309,6 +378,28 @@ class MultiGraph:
 
     def out_size(self, k):
         return sum(k * g.n for g in self.graphs)
+
+    def set_tuning(self, tuning):
+        t = _as_tuning(tuning)
+        _check(lib().rbfs_multi_set_tuning(self._h, ctypes.byref(t), _stream_ptr(self.device)))
+
+    def get_tuning(self):
+        t = Tuning()
+        _check(lib().rbfs_multi_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def tune(self, roots, reps=2, cap=256):
+        """Autotune the batch parameters; roots as for bfs().  Returns (best
+        tuning dict, list of timed candidates); the best is set."""
+        k = len(roots[0])
+        flat = [int(r) for rs in roots for r in rs]
+        r = (ctypes.c_int32 * len(flat))(*flat)
+        best = Tuning()
+        recs = (TuneRecord * cap)()
+        cnt = ctypes.c_int32(0)
+        _check(lib().rbfs_multi_tune(self._h, r, k, reps, ctypes.byref(best), recs, cap,
+                                     ctypes.byref(cnt), _stream_ptr(self.device)))
+        return best.as_dict(), _records(recs, cnt.value)
 
     def bfs(self, roots, opts=None, stats=False, depth=None, parent=None):
         """roots: list (per graph) of k root lists.  Returns a list of
@@ -404,3 +495,6 @@ def make_switch_blob(w, features):
     blob[MLP_PARAMS + 8:MLP_PARAMS + 16] = features[:, :8].max(axis=0)
     blob[MLP_PARAMS + 16] = features[:, 10].max() if features.shape[1] > 10 else 64
     return blob
+
+
+from .autotune import TuningCache, tuning_key, tune_cached  # noqa: E402,F401

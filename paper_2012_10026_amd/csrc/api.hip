@@ -12,23 +12,7 @@
 #include "graph.h"
 #include "switch.h"
 
-struct rbfs_graph {
-  rbfs::Graph g;
-};
-
-struct rbfs_multi {
-  rbfs::MsEngine eng;
-  std::vector<rbfs::Graph*> gs;
-  std::vector<int64_t> ubase;      // first union ID of each graph
-  std::vector<int64_t> out_off;    // per-k output offset factor (sum of n before)
-  int device = 0;
-  // shape of the captured search
-  int cap_k = 0, cap_mode = -1, cap_alpha = 0, cap_beta = 0;
-  int32_t* cap_depth = nullptr;
-  int32_t* cap_parent = nullptr;
-  hipStream_t cap_stream = nullptr;
-  hipStream_t own_stream = nullptr;  // used when the caller passes the NULL stream
-};
+#include "handles.h"
 
 namespace rbfs {
 
@@ -263,6 +247,8 @@ int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const 
   API_CHECK(hipGetDevice(&g->device));
   API_CHECK(hipGetDeviceProperties(&p, g->device));
   g->compute_units = p.multiProcessorCount;
+  g->tune_single = rbfs::default_tuning(RBFS_TUNE_SINGLE);
+  g->tune_batch = rbfs::default_tuning(RBFS_TUNE_BATCH);
   if (hipDeviceGetAttribute(&rate, hipDeviceAttributeWallClockRate, g->device) == hipSuccess &&
       rate > 0)
     g->wall_rate_khz = rate;

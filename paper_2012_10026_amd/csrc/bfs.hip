@@ -100,6 +100,8 @@ struct BfsParams {
   int32_t sched_len;
   int8_t sched[RBFS_STATS_MAX_LEVELS];
   int32_t eb;
+  int32_t lane_row;      // bottom-up lane/wave split
+  int32_t cshift;        // log2 of the top-down chunk length
   uint64_t timeout_ticks;
   const float* sw;       // learned-switch blob (RBFS_DIR_LEARNED)
   BfsCtl* ctl;
@@ -163,7 +165,7 @@ __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_i
         const int64_t base = ebase + inc - d;
         P.qv[nq_idx][pos] = st.v[wv][j];
         P.qe[nq_idx][pos] = base;
-        mark_chunks(P.chunk[nq_idx], P.chunk_cap, base, d, (int32_t)pos);
+        mark_chunks(P.chunk[nq_idx], P.chunk_cap, base, d, (int32_t)pos, P.cshift);
       }
       ebase += shfl(inc, kWave - 1);
     }
@@ -248,7 +250,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     if (root_in) {
       P.qv[0][0] = root;
       P.qe[0][0] = 0;
-      mark_chunks(P.chunk[0], P.chunk_cap, 0, dr, 0);
+      mark_chunks(P.chunk[0], P.chunk_cap, 0, dr, 0, P.cshift);
     }
   }
   __syncthreads();
@@ -284,7 +286,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         for (int64_t w = gtid; w < W; w += gsz) P.vis[w] |= fcur[w];
       }
       const int64_t E = mf;
-      const int64_t nchunks = ceil_div(E, kChunkEdges);
+      const int64_t nchunks = ceil_div(E, (int64_t)1 << P.cshift);
       for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         const bool ok = expand_chunk<BLOCK>(s_chunk, c, E, P.qv[qc], P.qe[qc], nf, P.chunk[qc],
                                      nchunks, P.off, P.cols,
@@ -306,7 +308,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
               atomicMin(&P.parent[w * P.ds], (uint32_t)u);
           }
           stage(s_st, claim, w, dw, P, qn, qpack);
-        });
+        }, P.cshift);
         if (!ok) {
           if (threadIdx.x == 0) atomicOr(&ctl->bar.status, kStatusBadInput);
           break;
@@ -374,7 +376,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
               }
               bool found;
               int32_t par;
-              wave_first_hit(act, b, e, P.cols, fcur, found, par, examined);
+              wave_first_hit(act, b, e, P.cols, fcur, found, par, examined, P.lane_row);
               if (found) {
                 atomicOr((unsigned long long*)&s_st.found[wv][j], 1ull << (v & 63));
                 P.depth[v * P.ds] = L + 1;
@@ -464,11 +466,12 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
 }
 
 // Output in original IDs from the interleaved internal (depth, parent)
-// pairs: one 8-byte gather per vertex.  Pairs that were reached are reset to
-// (-1, none), so the next search needs no initialisation pass.
+// pairs: one 8-byte gather per vertex.  With `reset`, pairs that were reached
+// are set back to (-1, none), so the next search needs no initialisation
+// pass (scattered 8-byte writes instead of one coalesced pass).
 __global__ void translate_kernel(int64_t n, const int32_t* perm, const int32_t* iperm,
                                  int64_t n_sweep, int2* dp, int32_t* depth_o, int32_t* parent_o,
-                                 int32_t root_orig) {
+                                 int32_t root_orig, int reset) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int32_t i = perm[v];
@@ -477,7 +480,7 @@ __global__ void translate_kernel(int64_t n, const int32_t* perm, const int32_t* 
       const int2 x = dp[i];
       d = x.x;
       if (d >= 0) {
-        dp[i] = make_int2(-1, -1);
+        if (reset) dp[i] = make_int2(-1, -1);
         const uint32_t pi = (uint32_t)x.y;
         p = (pi >= (uint64_t)n_sweep) ? -1 : iperm[pi];
       }
@@ -494,24 +497,6 @@ __global__ void reset_ctl_kernel(BfsCtl* c) {
   int* p = (int*)&c->bar;
   for (int i = threadIdx.x; i < (int)(sizeof(GridBarrier) / sizeof(int)); i += blockDim.x)
     p[i] = 0;
-}
-
-// Edge-balanced word ranges over the swept set for the bottom-up step.
-__global__ void bu_part_kernel(const int64_t* off, int64_t n_sweep, int64_t target,
-                               int64_t nparts, int32_t* bounds) {
-  const int64_t W = ceil_div(n_sweep, kWave);
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nparts;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t want = p * target;
-    int64_t lo = 0, hi = n_sweep;  // first vertex with off[v] >= want
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (off[mid] < want) lo = mid + 1; else hi = mid;
-    }
-    int64_t w = ceil_div(lo, kWave);
-    if (p == nparts || w > W) w = W;
-    bounds[p] = (int32_t)w;
-  }
 }
 
 }  // namespace
@@ -539,44 +524,6 @@ void free_bfs_work(Graph* g) {
     }                                                                           \
   } while (0)
 
-// Edge-balanced bottom-up ranges: about nnz / nparts_want adjacency entries
-// each, at most W / nparts_want words each.
-static int build_bu_parts(Graph* g, BfsWork* w, int64_t nparts_want, hipStream_t stream) {
-  const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
-  const int64_t target = std::max<int64_t>(2048, g->nnz / std::max<int64_t>(1, nparts_want) + 1);
-  const int64_t nparts_e = std::max<int64_t>(1, ceil_div(g->nnz, target));
-  const int64_t max_words = std::max<int64_t>(kWave, W / std::max<int64_t>(1, nparts_want) + 1);
-  int32_t* d_b = nullptr;
-  BFS_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
-  hipLaunchKernelGGL(bu_part_kernel, dim3((unsigned)ceil_div(nparts_e + 1, 256)), dim3(256), 0,
-                     stream, g->off, g->n_sweep, target, nparts_e, d_b);
-  BFS_CHECK(hipGetLastError());
-  std::vector<int32_t> hb(nparts_e + 1);
-  BFS_CHECK(hipMemcpyAsync(hb.data(), d_b, sizeof(int32_t) * (nparts_e + 1),
-                           hipMemcpyDeviceToHost, stream));
-  BFS_CHECK(hipStreamSynchronize(stream));
-  (void)hipFree(d_b);
-  std::vector<int32_t> parts;
-  parts.push_back(0);
-  for (int64_t p = 1; p <= nparts_e; ++p) {
-    int32_t a = parts.back(), b = std::max(hb[p], a);
-    while (b - a > max_words) {
-      a += (int32_t)max_words;
-      parts.push_back(a);
-    }
-    if (b > parts.back()) parts.push_back(b);
-  }
-  if (parts.back() != (int32_t)W) parts.push_back((int32_t)W);
-  w->n_part = (int32_t)parts.size() - 1;
-  if (w->bu_part) (void)hipFree(w->bu_part);
-  w->bu_part = nullptr;
-  BFS_CHECK(hipMalloc(&w->bu_part, sizeof(int32_t) * parts.size()));
-  BFS_CHECK(hipMemcpyAsync(w->bu_part, parts.data(), sizeof(int32_t) * parts.size(),
-                           hipMemcpyHostToDevice, stream));
-  BFS_CHECK(hipStreamSynchronize(stream));
-  return 0;
-}
-
 static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   if (g->bfs) return 0;
   BfsWork* w = new BfsWork();
@@ -591,7 +538,7 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
     BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * ns));
     BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * ns));
   }
-  w->chunk_cap = ceil_div(g->nnz, kChunkEdges) + 2;
+  w->chunk_cap = ceil_div(g->nnz, (int64_t)1 << kMinChunkShift) + 2;
   for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * w->chunk_cap));
   BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
@@ -604,8 +551,6 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
                                                           256, 0));
   w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
   w->grid = g->compute_units;
-  int rc = build_bu_parts(g, w, 2 * (int64_t)w->grid * 16, stream);
-  if (rc) return rc;
   BFS_CHECK(hipEventCreate(&w->ev0));
   BFS_CHECK(hipEventCreate(&w->ev1));
   BFS_CHECK(hipEventCreate(&w->ev2));
@@ -616,13 +561,48 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   return 0;
 }
 
+// Launch shape of the graph's single-root tuning, clamped to residency.
+static void tuned_shape(const Graph* g, const BfsWork* w, int* block, int* grid) {
+  const rbfs_tuning_t& t = g->tune_single;
+  *block = t.block == 256 ? 256 : 1024;
+  const int cap = *block == 256 ? w->max_per_cu_256 : w->max_per_cu;
+  const int per = std::max(1, std::min(t.per_cu, cap));
+  *grid = per * g->compute_units;
+}
+
+// (Re)builds the bottom-up ranges for the graph's tuning: bu_grain ranges
+// per workgroup of the tuned grid.  Synchronises `stream` when it builds.
+static int ensure_bfs_parts(Graph* g, hipStream_t stream) {
+  BfsWork* w = g->bfs;
+  int block, grid;
+  tuned_shape(g, w, &block, &grid);
+  const int grain = g->tune_single.bu_grain;
+  if (w->bu_part && w->part_grain == grain && w->part_grid == grid) return 0;
+  if (w->bu_part) (void)hipFree(w->bu_part);
+  w->bu_part = nullptr;
+  w->n_part = 0;
+  int rc = build_edge_ranges(g->off, g->n_sweep, g->nnz, (int64_t)grain * grid, kWave,
+                             &w->bu_part, &w->n_part, stream);
+  if (rc) return rc;
+  w->part_grain = grain;
+  w->part_grid = grid;
+  return 0;
+}
+
+int bfs_apply_tuning(Graph* g, hipStream_t stream) {
+  if (!g->bfs) return 0;  // applied when the workspace is made
+  return ensure_bfs_parts(g, stream);
+}
+
 int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, int alpha,
              int beta, const int8_t* sched, int sched_len, int out_space, int flags,
              int tune_profile, hipStream_t stream, void* stats_v) {
   rbfs_stats_t* stats = (rbfs_stats_t*)stats_v;
   int rc = ensure_bfs_work(g, stream);
+  if (!rc) rc = ensure_bfs_parts(g, stream);
   if (rc) return rc;
   BfsWork* w = g->bfs;
+  const rbfs_tuning_t& tun = g->tune_single;
   const bool translate = g->reordered && out_space == RBFS_OUT_ORIGINAL;
   const int bits_n = bits_for(g->n_sweep + 2);
   const int eb = 64 - bits_n;
@@ -674,6 +654,8 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     for (int i = 0; i < P.sched_len; ++i) P.sched[i] = sched[i];
   }
   P.eb = eb;
+  P.lane_row = tun.lane_row;
+  P.cshift = bits_for(tun.td_chunk);
   P.timeout_ticks = (uint64_t)g->wall_rate_khz * 1000ull * 4ull;  // 4 s
   P.ctl = w->ctl;
   if (mode == RBFS_DIR_LEARNED) {
@@ -690,28 +672,31 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipEventRecord(w->ev0, stream));
   hipLaunchKernelGGL(reset_ctl_kernel, dim3(1), dim3(256), 0, stream, w->ctl);
   BFS_CHECK(hipGetLastError());
-  // launch shape: profile 0 = 1024-thread workgroups, one per CU; profiles
-  // 1..4 = 256-thread workgroups, that many per CU; 5..6 = 1024-thread, 1..2
-  // per CU (for tuning)
+  // launch shape: the graph's tuning, or a fixed profile (1..4: 256-thread
+  // workgroups, that many per CU; 5, 6: 1024-thread, 1 or 2 per CU)
+  int block, grid;
+  tuned_shape(g, w, &block, &grid);
   if (tune_profile >= 1 && tune_profile <= 4) {
-    const int per = std::min(tune_profile, w->max_per_cu_256);
-    hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(per * g->compute_units), dim3(256), 0,
-                       stream, P);
-  } else {
-    int per = 1;
-    if (tune_profile == 6) per = std::min(2, w->max_per_cu);
-    hipLaunchKernelGGL(bfs_persistent_kernel<1024>, dim3(per * g->compute_units), dim3(1024), 0,
-                       stream, P);
+    block = 256;
+    grid = std::min(tune_profile, w->max_per_cu_256) * g->compute_units;
+  } else if (tune_profile == 5 || tune_profile == 6) {
+    block = 1024;
+    grid = std::min(tune_profile - 4, w->max_per_cu) * g->compute_units;
   }
+  if (block == 256)
+    hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(grid), dim3(256), 0, stream, P);
+  else
+    hipLaunchKernelGGL(bfs_persistent_kernel<1024>, dim3(grid), dim3(1024), 0, stream, P);
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
   if (translate) {
     const int64_t blocks = std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20);
     hipLaunchKernelGGL(translate_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       g->perm, g->iperm, g->n_sweep, w->dp, depth, parent, root);
+                       g->perm, g->iperm, g->n_sweep, w->dp, depth, parent, root,
+                       tun.reset ? 1 : 0);
     BFS_CHECK(hipGetLastError());
-    w->clean = true;
+    w->clean = tun.reset != 0;
   }
   BFS_CHECK(hipEventRecord(w->ev2, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[2], stream));

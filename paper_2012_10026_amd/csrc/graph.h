@@ -6,6 +6,7 @@
 
 #include <string>
 
+#include "../../include/rbfs.h"
 #include "prim.h"
 
 namespace rbfs {
@@ -13,7 +14,18 @@ namespace rbfs {
 // Edges per chunk of the edge-balanced frontier expansion.
 constexpr int kChunkShift = 10;
 constexpr int kChunkEdges = 1 << kChunkShift;  // largest top-down chunk
-constexpr int kMinChunkShift = 8;
+constexpr int kMinChunkShift = 8;               // smallest (tunable)
+
+// Built-in defaults of the tunable parameters and their check.
+rbfs_tuning_t default_tuning(int kind);
+bool tuning_valid(int kind, const rbfs_tuning_t& t, std::string* why);
+
+// Edge-balanced ranges of 64-vertex words over [0, n_sweep): about
+// nnz / nparts_want adjacency entries and at most
+// max(min_words, W / nparts_want + 1) words each (W = number of words).
+// Allocates *bounds (n_part + 1 entries, device); synchronises `stream`.
+int build_edge_ranges(const int64_t* off, int64_t n_sweep, int64_t nnz, int64_t nparts_want,
+                      int64_t min_words, int32_t** bounds, int32_t* n_part, hipStream_t stream);
 
 struct BfsCtl;
 struct MsCtl;
@@ -31,6 +43,8 @@ struct BfsWork {
   int64_t chunk_cap = 0;
   int32_t* bu_part = nullptr;
   int32_t n_part = 0;
+  int32_t part_grain = 0;       // bu_grain the ranges were built for
+  int32_t part_grid = 0;        // grid size the ranges were built for
   BfsCtl* ctl = nullptr;
   bool clean = false;           // depth/parent hold -1 everywhere
   int grid = 0;                 // persistent grid size
@@ -63,6 +77,9 @@ struct MsEngine {
   int32_t n_part = 0;
   MsCtl* ctl = nullptr;
   int ngraphs = 1;
+  rbfs_tuning_t tune{};           // parameters in use (kind RBFS_TUNE_BATCH)
+  int max_per_cu = 1;             // resident search workgroups per CU
+  int compute_units = 0;
   int32_t* roots_dev = nullptr;   // 64 union IDs per graph, then 64 original IDs per graph
   int32_t* roots_host = nullptr;  // pinned staging for the original IDs (64 per graph)
   int grid = 0;
@@ -72,6 +89,9 @@ struct MsEngine {
 };
 
 int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipStream_t stream);
+// Applies batch parameters (rebuilds the bottom-up ranges when the grain or
+// grid changes and drops a captured search).
+int ms_apply_tuning(MsEngine* m, const rbfs_tuning_t& t, hipStream_t stream);
 void ms_engine_free(MsEngine* m);
 int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alpha, int beta,
                       hipStream_t stream);
@@ -106,6 +126,8 @@ struct Graph {
   int32_t* iperm = nullptr;  // internal -> original
   BfsWork* bfs = nullptr;
   MsEngine* ms = nullptr;
+  rbfs_tuning_t tune_single{};  // parameters of rbfs_bfs
+  rbfs_tuning_t tune_batch{};   // parameters of rbfs_bfs_batch
   Scratch scratch;
   TimingRing timing;
   int compute_units = 0;
@@ -124,6 +146,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
 int bfs_batch_impl(Graph* g, const int32_t* roots, int32_t k, int32_t* depth, int32_t* parent,
                    int mode, int alpha, int beta, int out_space, int flags,
                    hipStream_t stream, void* stats);
+int bfs_apply_tuning(Graph* g, hipStream_t stream);
 void free_bfs_work(Graph* g);
 void free_ms_work(Graph* g);
 

@@ -84,6 +84,7 @@ struct MsParams {
   uint64_t amask;
   int32_t mode, alpha, beta;
   int32_t eb;
+  int32_t lane_row;      // rows longer than this are scanned by a whole wave
   uint64_t timeout_ticks;
   MsCtl* ctl;
 };
@@ -198,7 +199,7 @@ __device__ __forceinline__ uint64_t ms_pull(const MsParams& P, bool active, int6
                                             const uint64_t* fcur, int d1, int64_t& examined) {
   const int l = lane_id();
   uint64_t found = 0;
-  const bool hub = active && (e - b) > kLaneRow;
+  const bool hub = active && (e - b) > P.lane_row;
   if (active && !hub && miss) {
     int64_t j = b;
     for (; j < e && miss; ++j) {
@@ -567,23 +568,6 @@ __global__ void union_oid_kernel(const int32_t* iperm, int64_t n_sweep, int64_t 
     uoid[ubase + i] = iperm ? iperm[i] : (int32_t)i;
 }
 
-__global__ void ms_part_kernel(const int64_t* off, int64_t n_sweep, int64_t target,
-                               int64_t nparts, int32_t* bounds) {
-  const int64_t W = ceil_div(n_sweep, kWave);
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p <= nparts;
-       p += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t want = p * target;
-    int64_t lo = 0, hi = n_sweep;
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (off[mid] < want) lo = mid + 1; else hi = mid;
-    }
-    int64_t w = ceil_div(lo, kWave);
-    if (p == nparts || w > W) w = W;
-    bounds[p] = (int32_t)w;
-  }
-}
-
 int grid_blocks(int64_t work) {
   int64_t b = ceil_div(work, 256);
   if (b < 1) b = 1;
@@ -657,44 +641,33 @@ int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipSt
   hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->par,
                      64 * ns, -1);
   MS_CHECK(hipGetLastError());
-  // edge-balanced vertex ranges (in 64-vertex units) for the bottom-up pull
   int per_cu = 0;
   MS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msbfs_kernel, kMsBlock, 0));
-  if (per_cu < 1) per_cu = 1;
-  m->grid = compute_units;
-  const int64_t W = ceil_div(ns, kWave);
-  const int64_t want = 2 * (int64_t)m->grid * kMsWaves;
-  const int64_t target = std::max<int64_t>(2048, m->nnz / want + 1);
-  const int64_t nparts_e = std::max<int64_t>(1, ceil_div(m->nnz, target));
-  const int64_t max_words = std::max<int64_t>(1, W / want + 1);
-  int32_t* d_b = nullptr;
-  MS_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
-  hipLaunchKernelGGL(ms_part_kernel, dim3(grid_blocks(nparts_e + 1)), dim3(256), 0, stream,
-                     m->uoff ? m->uoff : m->off, m->n_sweep, target, nparts_e, d_b);
-  MS_CHECK(hipGetLastError());
-  std::vector<int32_t> hb(nparts_e + 1);
-  MS_CHECK(hipMemcpyAsync(hb.data(), d_b, sizeof(int32_t) * (nparts_e + 1),
-                          hipMemcpyDeviceToHost, stream));
-  MS_CHECK(hipStreamSynchronize(stream));
-  (void)hipFree(d_b);
-  std::vector<int32_t> parts{0};
-  for (int64_t p = 1; p <= nparts_e; ++p) {
-    int32_t a = parts.back(), b = std::max(hb[p], a);
-    while (b - a > max_words) {
-      a += (int32_t)max_words;
-      parts.push_back(a);
-    }
-    if (b > parts.back()) parts.push_back(b);
-  }
-  if (parts.back() != (int32_t)W) parts.push_back((int32_t)W);
-  m->n_part = (int32_t)parts.size() - 1;
-  MS_CHECK(hipMalloc(&m->bu_part, sizeof(int32_t) * parts.size()));
-  MS_CHECK(hipMemcpyAsync(m->bu_part, parts.data(), sizeof(int32_t) * parts.size(),
-                          hipMemcpyHostToDevice, stream));
+  m->max_per_cu = per_cu < 1 ? 1 : per_cu;
+  m->compute_units = compute_units;
   MS_CHECK(hipEventCreate(&m->ev0));
   MS_CHECK(hipEventCreate(&m->ev1));
   MS_CHECK(hipStreamSynchronize(stream));
   m->wall_rate_khz = wall_rate_khz;
+  return ms_apply_tuning(m, default_tuning(RBFS_TUNE_BATCH), stream);
+}
+
+int ms_apply_tuning(MsEngine* m, const rbfs_tuning_t& t, hipStream_t stream) {
+  const int per = std::max(1, std::min(t.per_cu, m->max_per_cu));
+  const int grid = per * m->compute_units;
+  if (!m->bu_part || t.bu_grain != m->tune.bu_grain || grid != m->grid) {
+    // edge-balanced vertex ranges (in 64-vertex units) for the bottom-up pull
+    if (m->bu_part) (void)hipFree(m->bu_part);
+    m->bu_part = nullptr;
+    m->n_part = 0;
+    int rc = build_edge_ranges(m->uoff ? m->uoff : m->off, m->n_sweep, m->nnz,
+                               (int64_t)t.bu_grain * grid, 1, &m->bu_part, &m->n_part, stream);
+    if (rc) return rc;
+  }
+  m->grid = grid;
+  m->tune = t;
+  if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
+  m->gexec = nullptr;
   return 0;
 }
 
@@ -734,6 +707,7 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
   P.alpha = alpha;
   P.beta = beta;
   P.eb = eb;
+  P.lane_row = m->tune.lane_row;
   P.timeout_ticks = (uint64_t)m->wall_rate_khz * 1000ull * 4ull;
   P.ctl = m->ctl;
   hipLaunchKernelGGL(ms_reset_ctl_kernel, dim3(1), dim3(256), 0, stream, m->ctl);
@@ -798,6 +772,7 @@ static int ensure_ms(Graph* g, hipStream_t stream) {
   m->n_sweep = g->n_sweep;
   m->nnz = g->nnz;
   int rc = ms_engine_setup(m, g->compute_units, g->wall_rate_khz, stream);
+  if (!rc) rc = ms_apply_tuning(m, g->tune_batch, stream);
   if (rc) return rc;
   g->bytes += sizeof(int32_t) * 128 * (size_t)(g->n_sweep > 0 ? g->n_sweep : 1);
   return 0;
