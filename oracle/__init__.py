@@ -39,7 +39,7 @@ def lib():
         L.orc_bfs.argtypes = [c.c_int64, P, P, c.c_int32, P, P, P]
         L.orc_level_counters.restype = None
         L.orc_level_counters.argtypes = [c.c_int64, P, P, P, c.c_int64, P, c.c_int32,
-                                         P, P, P, P, P]
+                                         P, P, P, P, P, P]
         L.orc_heuristic_schedule.restype = None
         L.orc_heuristic_schedule.argtypes = [c.c_int32, P, P, P, c.c_int64, c.c_int64,
                                              c.c_int64, P]
@@ -105,17 +105,17 @@ def bfs(off, cols, root, ell=None):
 
 
 def level_counters(off, cols, depth, ell=None, n_sweep=None):
-    """Dict of per-level arrays nf, mf, nu, mu, ebu (see oracle.c)."""
+    """Dict of per-level arrays nf, mf, nu, mu, ebu, ebc (see oracle.c)."""
     off, cols, n = _csr(off, cols)
     ell = _opt_i32(ell)
     depth = np.ascontiguousarray(depth, np.int32)
     nlev = int(depth.max()) + 1 if depth.size else 0
     if n_sweep is None:
         n_sweep = n
-    out = {k: np.zeros(max(1, nlev), np.int64) for k in ("nf", "mf", "nu", "mu", "ebu")}
+    out = {k: np.zeros(max(1, nlev), np.int64) for k in ("nf", "mf", "nu", "mu", "ebu", "ebc")}
     lib().orc_level_counters(n, _p(off), _p(cols), _p(ell), int(n_sweep), _p(depth), nlev,
                              _p(out["nf"]), _p(out["mf"]), _p(out["nu"]), _p(out["mu"]),
-                             _p(out["ebu"]))
+                             _p(out["ebu"]), _p(out["ebc"]))
     return {k: v[:nlev] for k, v in out.items()}
 
 

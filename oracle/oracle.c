@@ -216,13 +216,17 @@ int32_t orc_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root
  *            scanned in increasing label order and stops at the first
  *            neighbour in F_d: 1 + (number of neighbours of smaller label
  *            than that neighbour), or deg(v) when there is none.
+ *   ebc[d] = the part of ebu[d] spent on vertices of the root's component
+ *            (those reached later, depth > d): a bottom-up pass needs to
+ *            sweep only that component, since a vertex of another one has
+ *            no neighbour in F_d and is never reached.
  * The swept set is the first n_sweep vertices in label order (the
  * non-isolated prefix after RCM, or every vertex without it). */
 void orc_level_counters(int64_t n, const int64_t* off, const int32_t* cols, const int32_t* ell,
                         int64_t n_sweep, const int32_t* depth, int32_t nlev, int64_t* nf,
-                        int64_t* mf, int64_t* nu, int64_t* mu, int64_t* ebu) {
+                        int64_t* mf, int64_t* nu, int64_t* mu, int64_t* ebu, int64_t* ebc) {
   for (int32_t d = 0; d < nlev; ++d) {
-    nf[d] = mf[d] = nu[d] = mu[d] = ebu[d] = 0;
+    nf[d] = mf[d] = nu[d] = mu[d] = ebu[d] = ebc[d] = 0;
   }
   for (int64_t v = 0; v < n; ++v) {
     int64_t lab = ell ? ell[v] : v;
@@ -244,17 +248,18 @@ void orc_level_counters(int64_t n, const int64_t* off, const int32_t* cols, cons
         int64_t lw = ell ? ell[w] : w;
         if (depth[w] == d && lw < first) first = lw;
       }
-      if (first == INT64_MAX) {
-        ebu[d] += deg;
-      } else {
+      int64_t work = deg;
+      if (first != INT64_MAX) {
         int64_t smaller = 0;
         for (int64_t e = off[v]; e < off[v + 1]; ++e) {
           int32_t w = cols[e];
           int64_t lw = ell ? ell[w] : w;
           if (lw < first) smaller++;
         }
-        ebu[d] += 1 + smaller;
+        work = 1 + smaller;
       }
+      ebu[d] += work;
+      if (dv >= 0) ebc[d] += work;
     }
   }
 }

@@ -284,6 +284,7 @@ int rbfs_graph_destroy(rbfs_graph_t* h) {
   if (g->cols) (void)hipFree(g->cols);
   if (g->perm) (void)hipFree(g->perm);
   if (g->iperm) (void)hipFree(g->iperm);
+  if (g->comp_bounds) (void)hipFree(g->comp_bounds);
   delete h;
   return RBFS_OK;
 }

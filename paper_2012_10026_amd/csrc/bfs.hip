@@ -7,18 +7,21 @@
 // neighbour one level up, reached the same way by both step kinds: a scan of
 // v's row in increasing label order that stops at the first neighbour in the
 // current frontier F_d (any visited neighbour of a vertex first reached at
-// level d+1 lies in F_d), or the minimum over all its frontier neighbours:
+// level d+1 lies in F_d), or the minimum over all its frontier neighbours.
+// Depth and parent of a vertex are one 64-bit word, depth in the high half
+// (unreached = all ones), so that ordering the words orders by depth first:
 //   top-down (Algorithms 1 and 4): frontier edges (u, w) are spread evenly
-//     over the GPU; w not yet visited is claimed with one CAS on depth
-//     (-1 -> d+1; the winner appends w) and every frontier edge into w
-//     lowers parent[w] with atomicMin(u).  (Scanning w's row for the first
+//     over the GPU; every edge into a w unvisited at level start proposes
+//     (d+1, u) with one 64-bit atomicMin: the smallest proposal, i.e. the
+//     smallest-label parent, stays, and the one proposal that finds w
+//     unreached claims w and appends it.  (Scanning w's row for the first
 //     frontier neighbour instead would read nearly whole rows here: after
 //     RCM the hubs that make up the early frontiers carry the highest
 //     labels.);
-//   bottom-up (Algorithm 2 lines 15-21, Algorithm 5): every unvisited v scans
-//     its own row; one wave owns a 64-vertex word, the found bits come from
-//     one ballot and are stored without atomics (the GPU form of the paper's
-//     cache-line blocks).
+//   bottom-up (the bottom-up step of Algorithm 2, Algorithm 5): every
+//     unvisited v scans its own row; one wave owns a 64-vertex word, the
+//     found bits come from one ballot and are stored without atomics (the GPU
+//     form of the paper's cache-line blocks).
 //
 // Visited state: `vis` (reached before level d) plus three rotating frontier
 // bitmaps: front[d % 3] = F_d, front[(d+1) % 3] receives F_{d+1}, and
@@ -34,9 +37,9 @@
 // packed 64-bit atomic (count << eb | degree sum) per batch; the returned
 // base gives both the queue position and the exclusive degree prefix that
 // drives the edge-balanced top-down expansion of the next level.  Bottom-up
-// work is cut into edge-balanced ranges of words handed out by fetch-add
-// counters (the work stealing of Algorithm 5), one counter per group of
-// workgroups (blockIdx mod 8) with stealing across groups.
+// work is cut into edge-balanced ranges of words; each workgroup owns a share
+// behind its own counter and steals from the fullest others when done (the
+// work stealing of Algorithm 5).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,10 +60,11 @@ const float* switch_blob_device(int device);
 struct alignas(128) BfsCtl {
   GridBarrier bar;
   alignas(128) unsigned long long qpack[3][16];     // [rotation][0], own line each
-  alignas(128) unsigned long long work[3][8][16];   // BU range counters per group
   alignas(128) unsigned long long edges[3][16];     // entries read this level
+  alignas(128) unsigned long long vlcnt[3][16];     // vertices appended to the list
   int levels;
   int pad;
+  int sweep_lo, sweep_hi;  // bottom-up sweep: the root's component
   long long reached, deg_reached;
   signed char hdir[RBFS_STATS_MAX_LEVELS];
   signed char hood[RBFS_STATS_MAX_LEVELS];
@@ -74,17 +78,19 @@ struct alignas(128) BfsCtl {
 namespace {
 
 constexpr int kStage = 256;  // staged appends per wave
+constexpr int kListRange = 64;  // list vertices per bottom-up work range
+constexpr int kScanStep = 8;    // row entries a lane tests per step
+constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
 
 struct BfsParams {
   const int64_t* off;
   const int32_t* cols;
   const int32_t* perm;   // original -> internal, null when not reordered
   int64_t n_sweep;
-  int64_t n_init;        // entries of depth/parent initialised by the kernel
   int64_t deg_total;     // degree sum over the swept set
-  int32_t* depth;        // element v at depth[v * ds]
-  uint32_t* parent;      // element v at parent[v * ds]
-  int64_t ds;            // 1: separate arrays; 2: interleaved (depth, parent) pairs
+  uint64_t* dp;          // packed (depth << 32 | parent) per swept vertex
+  const int32_t* comp_bounds;  // component intervals (null: one interval)
+  int64_t n_comp;
   uint64_t* vis;
   uint64_t* front[3];
   int32_t* qv[2];
@@ -93,6 +99,9 @@ struct BfsParams {
   int64_t chunk_cap;
   const int32_t* bu_part;
   int32_t n_part;
+  unsigned long long* wctr;  // BU range counters: 3 slots of wstride, 16 per workgroup
+  int64_t wstride;
+  int32_t* vl[2];            // vertex lists: unvisited vertices left by a bottom-up level
   int32_t root_orig;
   int32_t init;
   int32_t mode;
@@ -113,25 +122,9 @@ struct StageLds {
   int32_t d[WAVES][kStage];
   int32_t cnt[WAVES];
   uint64_t found[WAVES][kWave];  // bottom-up: found bits of the batch's words
+  int32_t lv[WAVES][kStage];     // bottom-up: vertices left for the next list
+  int32_t lcnt[WAVES];
 };
-
-// Position of the n-th set bit (n < popcount(m)).
-__device__ __forceinline__ int nth_set_bit(uint64_t m, int n) {
-  int pos = 0;
-#pragma unroll
-  for (int w = 32; w >= 1; w >>= 1) {
-    const uint64_t low = m & ((1ull << w) - 1ull);
-    const int c = popc64(low);
-    if (n >= c) {
-      n -= c;
-      m >>= w;
-      pos += w;
-    } else {
-      m = low;
-    }
-  }
-  return pos;
-}
 
 // Publishes this wave's staged vertices to the next queue.
 template <class ST>
@@ -195,6 +188,139 @@ __device__ __forceinline__ void stage(ST& st, bool take, int32_t v, int64_t deg,
   if (base + popc64(m) > kStage - kWave) flush_stage(st, P, nq_idx, qpack);
 }
 
+// Publishes this wave's staged list vertices (appended at *count).
+template <class ST>
+__device__ __forceinline__ void flush_list(ST& st, int32_t* out, unsigned long long* count,
+                                           int64_t cap, BfsCtl* ctl) {
+  const int wv = wave_id(), l = lane_id();
+  const int cnt = st.lcnt[wv];
+  if (cnt == 0) return;
+  unsigned long long base = 0;
+  if (l == 0)
+    base = __hip_atomic_fetch_add(count, (unsigned long long)cnt, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  base = shfl(base, 0);
+  if ((int64_t)base + cnt > cap) {
+    if (l == 0) atomicOr(&ctl->bar.status, kStatusOverflow);
+  } else {
+    for (int j = l; j < cnt; j += kWave) out[base + j] = st.lv[wv][j];
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (l == 0) st.lcnt[wv] = 0;
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Stages the vertices of the lanes with take = true for the next list.
+template <class ST>
+__device__ __forceinline__ void stage_list(ST& st, bool take, int32_t v, int32_t* out,
+                                           unsigned long long* count, int64_t cap,
+                                           BfsCtl* ctl) {
+  const uint64_t m = ballot(take);
+  if (m == 0) return;
+  const int wv = wave_id();
+  const int base = st.lcnt[wv];
+  __builtin_amdgcn_wave_barrier();
+  if (take) st.lv[wv][base + popc64(m & lanemask_lt())] = v;
+  if (lane_id() == 0) st.lcnt[wv] = base + popc64(m);
+  __builtin_amdgcn_wave_barrier();
+  if (base + popc64(m) > kStage - kWave) flush_list(st, out, count, cap, ctl);
+}
+
+// Sets bit v of `words` for the lanes with take = true: one atomic per
+// distinct word among them.
+__device__ __forceinline__ void wave_set_bits(uint64_t* words, bool take, int64_t v) {
+  uint64_t pend = ballot(take);
+  while (pend) {
+    const int lead = ffs64(pend);
+    const int64_t wl = shfl(v >> 6, lead);
+    const bool mine = take && (v >> 6) == wl;
+    const uint64_t bits = wave_or64(mine ? (1ull << (v & 63)) : 0ull);
+    if (lane_id() == lead) atomicOr((unsigned long long*)&words[wl], bits);
+    pend &= ~ballot(mine);
+  }
+}
+
+// Lane-refilled first-hit scans.  `total` candidates are handed to the lanes
+// in order, and a lane that finishes its candidate takes the next one at
+// once, so a long row keeps only its own lane busy instead of stalling the
+// other 63.  Each lane also holds the candidate after its current one with
+// its row bounds already loaded, so taking it over costs no extra memory
+// round trip.  Each row gets the same ascending first-hit scan: kScanStep
+// entries per step (their loads are independent, so one pair of memory round
+// trips covers them all), rows longer than lane_row by the whole wave in one
+// go.  cand(t)
+// gives candidate t's vertex (t < 0: none), or -1 to skip it; it is called
+// by all lanes.  done(fin, found, v, par, deg) is called by all lanes after
+// every step; fin marks the lanes that finished a candidate in it.
+template <class Cand, class Done>
+__device__ __forceinline__ void refill_scan(int total, const int64_t* off, const int32_t* cols,
+                                            const uint64_t* bits, int lane_row,
+                                            int64_t& examined, Cand&& cand, Done&& done) {
+  int next = 0;  // next candidate to hand out (same in every lane)
+  bool busy = false, queued = false;
+  int64_t v = 0, b = 0, j = 0, e = 0;  // current candidate
+  int64_t vq = 0, bq = 0, eq = 0;      // queued candidate, bounds loaded
+  for (;;) {
+    // take over the queued candidate
+    bool fresh = false;
+    if (!busy && queued) {
+      v = vq;
+      b = bq;
+      e = eq;
+      j = b;
+      busy = true;
+      queued = false;
+      fresh = true;
+    }
+    // queue the next one (its bounds arrive while this step runs)
+    const uint64_t want = ballot(!queued);
+    if (want != 0ull && next < total) {
+      const int t = next + popc64(want & lanemask_lt());
+      const int64_t c = cand((!queued && t < total) ? t : -1);
+      next += popc64(want);
+      if (c >= 0) {
+        vq = c;
+        bq = off[c];
+        eq = off[c + 1];
+        queued = true;
+      }
+    }
+    const bool hub = fresh && (e - b) > lane_row;
+    bool found = false;
+    int32_t par = 0;
+    wave_hub_first_hit(hub, b, e, cols, bits, found, par, examined);
+    bool fin = hub;
+    if (busy && !hub) {
+      int32_t w[kScanStep];
+      bool h[kScanStep];
+#pragma unroll
+      for (int q = 0; q < kScanStep; ++q) w[q] = (j + q < e) ? cols[j + q] : 0;
+#pragma unroll
+      for (int q = 0; q < kScanStep; ++q)
+        h[q] = (j + q < e) && test_bit(bits, (uint32_t)w[q]);
+      int hq = kScanStep;
+#pragma unroll
+      for (int q = kScanStep - 1; q >= 0; --q)
+        if (h[q]) {
+          hq = q;
+          par = w[q];
+        }
+      if (hq < kScanStep) {
+        found = true;
+        fin = true;
+        examined += hq + 1;
+      } else {
+        examined += (e - j < kScanStep) ? (e - j) : kScanStep;
+        j += kScanStep;
+        fin = j >= e;
+      }
+    }
+    done(fin, found, v, par, e - b);
+    if (fin) busy = false;
+    if (next >= total && ballot(busy || queued) == 0ull) break;
+  }
+}
+
 __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf, long long mu,
                                              long long nf_prev, long long n, int alpha,
                                              int beta) {
@@ -215,14 +341,15 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   const int64_t W = ceil_div(P.n_sweep, kWave);
   const uint64_t emask = (1ull << P.eb) - 1ull;
   const int l = lane_id();
-  if (threadIdx.x < WAVES) s_st.cnt[threadIdx.x] = 0;
+  if (threadIdx.x < WAVES) {
+    s_st.cnt[threadIdx.x] = 0;
+    s_st.lcnt[threadIdx.x] = 0;
+  }
 
   // ---- initialisation
   if (P.init) {
-    for (int64_t i = gtid; i < P.n_init; i += gsz) {
-      P.depth[i * P.ds] = (i == root) ? 0 : -1;
-      P.parent[i * P.ds] = (i == root) ? (uint32_t)root : kNoParent;
-    }
+    for (int64_t i = gtid; i < P.n_sweep; i += gsz)
+      P.dp[i] = (i == root) ? (uint64_t)(uint32_t)root : kUnreached;
   }
   for (int64_t w = gtid; w < W; w += gsz) {
     P.vis[w] = 0ull;
@@ -231,14 +358,11 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   }
   const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
   if (gtid == 0) {
-    if (!P.init && root_in) {
-      P.depth[root * P.ds] = 0;
-      P.parent[root * P.ds] = (uint32_t)root;
-    }
+    if (!P.init && root_in) P.dp[root] = (uint64_t)(uint32_t)root;
     for (int r = 0; r < 2; ++r) {
       ctl->qpack[r][0] = 0ull;
       ctl->edges[r][0] = 0ull;
-      for (int g = 0; g < 8; ++g) ctl->work[r][g][0] = 0ull;
+      ctl->vlcnt[r][0] = 0ull;
     }
     ctl->qpack[0][0] = root_in ? ((1ull << P.eb) | (unsigned long long)dr) : 0ull;
     ctl->hdir[0] = 0;
@@ -247,20 +371,49 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     ctl->hmf[0] = dr;
     ctl->hmu[0] = P.deg_total - dr;
     ctl->hts[0] = (unsigned long long)wall_clock64();
+    // the root's component [lo, hi): nothing outside it can be reached, so
+    // the bottom-up sweep skips it (small components would otherwise be
+    // rescanned in full at every bottom-up level)
+    int64_t clo = 0, chi = P.n_sweep;
+    if (P.comp_bounds && root_in) {
+      int64_t a = 0, b = P.n_comp;  // last j with bounds[j] <= root
+      while (b - a > 1) {
+        const int64_t mid = (a + b) >> 1;
+        if (P.comp_bounds[mid] <= root) a = mid; else b = mid;
+      }
+      clo = P.comp_bounds[a];
+      chi = P.comp_bounds[a + 1];
+    }
+    ctl->sweep_lo = (int)clo;
+    ctl->sweep_hi = (int)chi;
     if (root_in) {
       P.qv[0][0] = root;
       P.qe[0][0] = 0;
       mark_chunks(P.chunk[0], P.chunk_cap, 0, dr, 0, P.cshift);
     }
   }
+  if (threadIdx.x == 0)
+    for (int r = 0; r < 3; ++r) P.wctr[r * P.wstride + blockIdx.x * 16] = 0ull;
   __syncthreads();
   if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
+
+  // bottom-up word range: the words of the root's component
+  const int sweep_lo = __hip_atomic_load(&ctl->sweep_lo, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  const int sweep_hi = __hip_atomic_load(&ctl->sweep_hi, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
+  const int64_t kw_lo = sweep_lo >> 6, kw_hi = ceil_div(sweep_hi, kWave);
 
   // level state, identical in every workgroup
   int L = 0;
   int dir = 0;
   long long nf = root_in ? 1 : 0, mf = dr, mu = P.deg_total - dr;
   long long reached = 1, deg_reached = dr;
+  // vertex list of the last bottom-up level: vl[lsrc][0, lcount) holds the
+  // vertices of the root's component it left unvisited, a superset of the
+  // unvisited ones (top-down levels only shrink that set); -1 = none yet
+  int lsrc = -1;
+  long long lcount = 0;
   while (nf > 0) {
     const int c3 = L % 3, n3 = (L + 1) % 3, z3 = (L + 2) % 3;
     const int qc = L & 1, qn = qc ^ 1;
@@ -273,8 +426,9 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     if (gtid == 0) {
       ctl->qpack[z3][0] = 0ull;
       ctl->edges[z3][0] = 0ull;
-      for (int g = 0; g < 8; ++g) ctl->work[z3][g][0] = 0ull;
+      ctl->vlcnt[z3][0] = 0ull;
     }
+    if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
     if (dir == 0) {
       // ---- top-down
       if (nf * 8 < W) {
@@ -295,17 +449,21 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           int64_t dw = 0;
           if (active) {
             const uint64_t word = P.vis[w >> 6] | fcur[w >> 6];
-            if (!((word >> (w & 63)) & 1ull) && P.depth[w * P.ds] == -1) {
-              claim = atomicCAS(&P.depth[w * P.ds], -1, L + 1) == -1;
-              if (claim) {
-                dw = P.off[w + 1] - P.off[w];
-                atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+            if (!((word >> (w & 63)) & 1ull)) {
+              // w is unvisited at level start: propose (L+1, u).  The
+              // smallest proposal stays, so the parent is the smallest
+              // label; only the first proposal finds w unreached and claims
+              // it.  A stale read can only be larger than the stored value.
+              const uint64_t prop = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)u;
+              if (P.dp[w] > prop) {
+                claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
+                        kUnreached;
+                if (claim) {
+                  dw = P.off[w + 1] - P.off[w];
+                  atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+                }
               }
             }
-            // w is unvisited at level start: depth[w] is now L+1, u is a
-            // candidate parent (a stale read can only be larger)
-            if (!((word >> (w & 63)) & 1ull) && P.parent[w * P.ds] > (uint32_t)u)
-              atomicMin(&P.parent[w * P.ds], (uint32_t)u);
           }
           stage(s_st, claim, w, dw, P, qn, qpack);
         }, P.cshift);
@@ -317,78 +475,107 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       flush_stage(s_st, P, qn, qpack);
       if (gtid == 0) examined = E;
     } else {
-      // ---- bottom-up over edge-balanced word ranges
-      const int g0 = blockIdx.x & 7;
-      for (int t = 0; t < 8; ++t) {
-        const int g = (g0 + t) & 7;
-        const int64_t lo = (int64_t)P.n_part * g / 8, hi = (int64_t)P.n_part * (g + 1) / 8;
-        for (;;) {
-          unsigned long long p = 0;
-          if (l == 0) {
-            // look before taking: exhausted groups cost a load, not an atomic
-            p = __hip_atomic_load(&ctl->work[c3][g][0], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            if (lo + (int64_t)p < hi)
-              p = __hip_atomic_fetch_add(&ctl->work[c3][g][0], 1ull, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
+      // ---- bottom-up.  The first bottom-up level sweeps the component's
+      // words in edge-balanced ranges; later ones walk only the vertex list
+      // the previous one left (the paper's shrinking of the bottom-up
+      // ranges), in ranges of kListRange vertices.  Rows are scanned with
+      // lane refill.  The vertices a level leaves unvisited form the next
+      // list.
+      const bool listed = lsrc >= 0;
+      const int32_t* vl_in = listed ? P.vl[lsrc] : nullptr;
+      int32_t* vl_out = P.vl[listed ? (lsrc ^ 1) : 0];
+      unsigned long long* vlcnt = &ctl->vlcnt[n3][0];
+      if (listed) {
+        // fold F_d into vis here: the list walk visits no words
+        if (nf * 8 < W) {
+          for (int64_t i = gtid; i < nf; i += gsz) {
+            const int32_t u = P.qv[qc][i];
+            atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
           }
-          p = shfl(p, 0);
-          if (lo + (int64_t)p >= hi) break;
-          const int64_t part = lo + (int64_t)p;
-          const int64_t k0 = P.bu_part[part], k1 = P.bu_part[part + 1];
-          // batches of 64 words: lane j loads word j (coalesced); the
-          // unvisited vertices of the batch are then handed to the lanes
-          // densely, 64 at a time, whatever their spread over the words
-          const int wv = wave_id();
-          for (int64_t kb = k0; kb < k1; kb += kWave) {
-            const int64_t kw = kb + l;
-            uint64_t um = 0;
-            if (kw < k1) {
-              const uint64_t vk = P.vis[kw], fk = fcur[kw];
-              P.vis[kw] = vk | fk;
-              const int64_t v0 = kw * kWave;
-              const uint64_t valid = (v0 + kWave <= P.n_sweep)
-                                         ? ~0ull
-                                         : ((1ull << (P.n_sweep - v0)) - 1ull);
-              um = ~(vk | fk) & valid;
-            }
-            const int cnt = popc64(um);
-            const int inc = (int)wave_inclusive_sum(cnt);
-            const int total = shfl(inc, kWave - 1);
-            s_st.found[wv][l] = 0ull;
-            __builtin_amdgcn_wave_barrier();
-            for (int t0 = 0; t0 < total; t0 += kWave) {
-              const int t = t0 + l;
-              const bool act = t < total;
-              int j = 0;  // first lane (word) whose inclusive count exceeds t
-#pragma unroll
-              for (int sft = 32; sft >= 1; sft >>= 1) {
-                const int probe = shfl(inc, j + sft - 1);
-                if (probe <= t) j += sft;
-              }
-              const int excl = shfl(inc - cnt, j);
-              const uint64_t mj = shfl(um, j);
-              int64_t v = 0, b = 0, e = 0;
-              if (act) {
-                v = (kb + j) * kWave + nth_set_bit(mj, t - excl);
-                b = P.off[v];
-                e = P.off[v + 1];
-              }
-              bool found;
-              int32_t par;
-              wave_first_hit(act, b, e, P.cols, fcur, found, par, examined, P.lane_row);
-              if (found) {
-                atomicOr((unsigned long long*)&s_st.found[wv][j], 1ull << (v & 63));
-                P.depth[v * P.ds] = L + 1;
-                P.parent[v * P.ds] = (uint32_t)par;
-              }
-              stage(s_st, found, (int32_t)v, e - b, P, qn, qpack);
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (kw < k1) fnext[kw] = s_st.found[wv][l];
-          }
+        } else {
+          for (int64_t w = kw_lo + gtid; w < kw_hi; w += gsz) P.vis[w] |= fcur[w];
         }
       }
+      const int64_t nranges = listed ? ceil_div(lcount, kListRange) : P.n_part;
+      const int wv = wave_id();
+      RangeCursor cur;
+      for (;;) {
+        const int64_t part = next_range(P.wctr + c3 * P.wstride, nranges, cur);
+        if (part < 0) break;
+        if (listed) {
+          const int64_t i0 = part * kListRange;
+          const int total = (int)std::min<int64_t>(kListRange, lcount - i0);
+          refill_scan(
+              total, P.off, P.cols, fcur, P.lane_row, examined,
+              [&](int t) -> int64_t {
+                if (t < 0) return -1;
+                const int32_t u = vl_in[i0 + t];
+                // reached since the list was made (by a top-down level)
+                const uint64_t word = P.vis[u >> 6] | fcur[u >> 6];
+                return ((word >> (u & 63)) & 1ull) ? -1 : (int64_t)u;
+              },
+              [&](bool fin, bool found, int64_t v, int32_t par, int64_t deg) {
+                if (found) P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
+                wave_set_bits(fnext, found, v);
+                stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.n_sweep, ctl);
+              });
+          continue;
+        }
+        const int64_t k0 = std::max<int64_t>(P.bu_part[part], kw_lo);
+        const int64_t k1 = std::min<int64_t>(P.bu_part[part + 1], kw_hi);
+        // batches of 64 words: lane j loads word j (coalesced); the
+        // unvisited vertices of the batch are handed to the lanes in order
+        for (int64_t kb = k0; kb < k1; kb += kWave) {
+          const int64_t kw = kb + l;
+          uint64_t um = 0;
+          if (kw < k1) {
+            const uint64_t vk = P.vis[kw], fk = fcur[kw];
+            P.vis[kw] = vk | fk;
+            const int64_t v0 = kw * kWave;
+            // vertices of this word inside [sweep_lo, sweep_hi)
+            const uint64_t below = (v0 + kWave <= sweep_hi) ? ~0ull
+                                   : ((1ull << (sweep_hi - v0)) - 1ull);
+            const uint64_t above = (v0 >= sweep_lo) ? ~0ull : (~0ull << (sweep_lo - v0));
+            um = ~(vk | fk) & below & above;
+          }
+          const int cnt = popc64(um);
+          const int inc = (int)wave_inclusive_sum(cnt);
+          const int total = shfl(inc, kWave - 1);
+          s_st.found[wv][l] = 0ull;
+          __builtin_amdgcn_wave_barrier();
+          refill_scan(
+              total, P.off, P.cols, fcur, P.lane_row, examined,
+              [&](int t) -> int64_t {
+                // the word holding the t-th unvisited vertex of the batch:
+                // the first lane whose inclusive count exceeds t
+                const int tt = t < 0 ? 0 : t;
+                int jw = 0;
+#pragma unroll
+                for (int sft = 32; sft >= 1; sft >>= 1) {
+                  const int probe = shfl(inc, jw + sft - 1);
+                  if (probe <= tt) jw += sft;
+                }
+                const int excl = shfl(inc - cnt, jw);
+                const uint64_t mj = shfl(um, jw);
+                if (t < 0) return -1;
+                return (kb + jw) * kWave + nth_set_bit64(mj, tt - excl);
+              },
+              [&](bool fin, bool found, int64_t v, int32_t par, int64_t deg) {
+                if (found) {
+                  atomicOr((unsigned long long*)&s_st.found[wv][(v >> 6) - kb],
+                           1ull << (v & 63));
+                  P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
+                }
+                stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.n_sweep, ctl);
+              });
+          __builtin_amdgcn_wave_barrier();
+          const uint64_t fw = s_st.found[wv][l];
+          if (kw < k1 && fw) fnext[kw] = fw;
+        }
+      }
+      flush_list(s_st, vl_out, vlcnt, P.n_sweep, ctl);
       flush_stage(s_st, P, qn, qpack);
     }
     const int64_t ex = wave_sum(examined);
@@ -450,6 +637,11 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         ctl->hmu[L + 1] = mu_new;
       }
     }
+    if (dir == 1) {
+      lsrc = (lsrc >= 0) ? (lsrc ^ 1) : 0;
+      lcount = (long long)__hip_atomic_load(&ctl->vlcnt[n3][0], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+    }
     nf = nf_new;
     mf = mf_new;
     mu = mu_new;
@@ -465,28 +657,32 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   }
 }
 
-// Output in original IDs from the interleaved internal (depth, parent)
-// pairs: one 8-byte gather per vertex.  With `reset`, pairs that were reached
-// are set back to (-1, none), so the next search needs no initialisation
-// pass (scattered 8-byte writes instead of one coalesced pass).
-__global__ void translate_kernel(int64_t n, const int32_t* perm, const int32_t* iperm,
-                                 int64_t n_sweep, int2* dp, int32_t* depth_o, int32_t* parent_o,
-                                 int32_t root_orig, int reset) {
+// Outputs from the packed internal pairs.  Output index v is an original ID
+// when perm is given (one 8-byte gather per vertex, parents mapped back
+// through iperm), else an internal label.  Indices past the swept set are
+// unreached, except an isolated root.  With `reset`, reached pairs are set
+// back to unreached, so the next search needs no initialisation pass
+// (scattered 8-byte writes instead of one coalesced pass).
+__global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* iperm,
+                              const int32_t* perm_root, int64_t n_sweep, uint64_t* dp,
+                              int32_t* depth_o, int32_t* parent_o, int32_t root_orig,
+                              int reset) {
+  const int32_t root_out = (perm || !perm_root) ? root_orig : perm_root[root_orig];
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    const int32_t i = perm[v];
+    const int64_t i = perm ? perm[v] : v;
     int32_t d = -1, p = -1;
     if (i < n_sweep) {
-      const int2 x = dp[i];
-      d = x.x;
-      if (d >= 0) {
-        if (reset) dp[i] = make_int2(-1, -1);
-        const uint32_t pi = (uint32_t)x.y;
-        p = (pi >= (uint64_t)n_sweep) ? -1 : iperm[pi];
+      const uint64_t x = dp[i];
+      if (x != kUnreached) {
+        if (reset) dp[i] = kUnreached;
+        d = (int32_t)(x >> 32);
+        const uint32_t pi = (uint32_t)x;
+        p = (pi >= (uint64_t)n_sweep) ? -1 : (iperm ? iperm[pi] : (int32_t)pi);
       }
-    } else if (v == root_orig) {
+    } else if (v == root_out) {
       d = 0;
-      p = root_orig;
+      p = root_out;
     }
     depth_o[v] = d;
     parent_o[v] = p;
@@ -504,8 +700,8 @@ __global__ void reset_ctl_kernel(BfsCtl* c) {
 void free_bfs_work(Graph* g) {
   BfsWork* w = g->bfs;
   if (!w) return;
-  void* ps[] = {w->dp, w->vis, w->front, w->qv[0], w->qv[1],
-                w->qe[0], w->qe[1], w->chunk[0], w->chunk[1], w->bu_part, w->ctl};
+  void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
+                w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1]};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -531,9 +727,10 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   const int64_t ns = g->n_sweep > 0 ? g->n_sweep : 1;
   const int64_t W = ceil_div(ns, kWave);
   w->n_sweep = g->n_sweep;
-  BFS_CHECK(hipMalloc(&w->dp, sizeof(int2) * ns));
+  BFS_CHECK(hipMalloc(&w->dp, sizeof(uint64_t) * ns));
   BFS_CHECK(hipMalloc(&w->vis, sizeof(uint64_t) * W));
   BFS_CHECK(hipMalloc(&w->front, sizeof(uint64_t) * 3 * W));
+  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->vl[i], sizeof(int32_t) * ns));
   for (int i = 0; i < 2; ++i) {
     BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * ns));
     BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * ns));
@@ -551,13 +748,15 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
                                                           256, 0));
   w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
   w->grid = g->compute_units;
+  w->max_grid = 4 * g->compute_units;  // per_cu is at most 4
+  BFS_CHECK(hipMalloc(&w->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)w->max_grid));
   BFS_CHECK(hipEventCreate(&w->ev0));
   BFS_CHECK(hipEventCreate(&w->ev1));
   BFS_CHECK(hipEventCreate(&w->ev2));
   BFS_CHECK(hipStreamSynchronize(stream));
   w->clean = false;
   g->bytes += (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * (size_t)ns +
-              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * w->chunk_cap;
+              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * (ns + w->chunk_cap);
   return 0;
 }
 
@@ -616,19 +815,10 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.perm = g->reordered ? g->perm : nullptr;
   P.n_sweep = g->n_sweep;
   P.deg_total = g->nnz;
-  if (translate) {
-    P.depth = (int32_t*)w->dp;
-    P.parent = (uint32_t*)w->dp + 1;
-    P.ds = 2;
-    P.init = w->clean ? 0 : 1;
-    P.n_init = g->n_sweep;
-  } else {
-    P.depth = depth;
-    P.parent = (uint32_t*)parent;
-    P.ds = 1;
-    P.init = 1;
-    P.n_init = g->n;
-  }
+  P.dp = w->dp;
+  P.comp_bounds = g->reordered ? g->comp_bounds : nullptr;
+  P.n_comp = g->n_comp;
+  P.init = w->clean ? 0 : 1;
   const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
   P.vis = w->vis;
   for (int i = 0; i < 3; ++i) P.front[i] = w->front + (size_t)i * W;
@@ -640,6 +830,10 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.chunk_cap = w->chunk_cap;
   P.bu_part = w->bu_part;
   P.n_part = w->n_part;
+  P.wctr = w->wctr;
+  P.wstride = 16 * (int64_t)w->max_grid;
+  P.vl[0] = w->vl[0];
+  P.vl[1] = w->vl[1];
   P.root_orig = root;
   P.mode = mode;
   P.alpha = alpha;
@@ -683,6 +877,10 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     block = 1024;
     grid = std::min(tune_profile - 4, w->max_per_cu) * g->compute_units;
   }
+  if (grid < 1 || grid > w->max_grid) {  // the range counters hold max_grid workgroups
+    set_error("bfs: launch grid outside the workspace");
+    return RBFS_E_STATE;
+  }
   if (block == 256)
     hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(grid), dim3(256), 0, stream, P);
   else
@@ -690,10 +888,11 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
-  if (translate) {
-    const int64_t blocks = std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20);
-    hipLaunchKernelGGL(translate_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       g->perm, g->iperm, g->n_sweep, w->dp, depth, parent, root,
+  {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));
+    hipLaunchKernelGGL(output_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
+                       translate ? g->perm : nullptr, translate ? g->iperm : nullptr,
+                       g->reordered ? g->perm : nullptr, g->n_sweep, w->dp, depth, parent, root,
                        tun.reset ? 1 : 0);
     BFS_CHECK(hipGetLastError());
     w->clean = tun.reset != 0;

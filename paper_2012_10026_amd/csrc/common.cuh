@@ -30,6 +30,24 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
 
 __device__ __forceinline__ int popc64(uint64_t x) { return __popcll(x); }
 
+// Position of the n-th set bit of m (0-based, n < popcount(m)).
+__device__ __forceinline__ int nth_set_bit64(uint64_t m, int n) {
+  int pos = 0;
+#pragma unroll
+  for (int w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1ull);
+    const int c = popc64(low);
+    if (n >= c) {
+      n -= c;
+      m >>= w;
+      pos += w;
+    } else {
+      m = low;
+    }
+  }
+  return pos;
+}
+
 // index of the lowest set bit; x != 0
 __device__ __forceinline__ int ffs64(uint64_t x) { return __ffsll((unsigned long long)x) - 1; }
 
@@ -55,6 +73,12 @@ __device__ __forceinline__ int64_t wave_sum(int64_t v) {
   return v;
 }
 
+__device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) x |= __shfl_xor(x, off, kWave);
+  return x;
+}
+
 __device__ __forceinline__ bool test_bit(const uint64_t* bits, uint32_t v) {
   return (bits[v >> 6] >> (v & 63)) & 1ull;
 }
@@ -76,13 +100,20 @@ __device__ __forceinline__ unsigned ld_relaxed(const unsigned* p) {
 // a counter (each on its own 128-byte line, so arrivals proceed on eight
 // addresses in parallel instead of serialising on one), and the last arrival
 // of each group bumps the top counter; the last of those bumps the
-// generation, which releases everyone.  Each workgroup publishes its writes
-// with one agent-scope release fence before arriving and takes one acquire
-// fence after the release (polling itself is relaxed: an acquire per poll
-// would invalidate the XCD's L2 while others still work).  A waiter gives up
-// after `timeout_ticks` of the constant-rate wall clock, or as soon as the
-// status word is non-zero, so the kernel always terminates; the status word
-// then carries kStatusTimeout and the caller reports an error.
+// generation, which releases everyone.  The counters are never reset: no
+// workgroup passes barrier k before every arrival at k has been counted, so
+// each group counter advances by exactly its group size per barrier and the
+// last arrival is the one that makes it a multiple of that size (the same
+// for the top counter).  A reset would have to be ordered before the
+// releasing increment at agent scope; without one, a fast workgroup's
+// arrival at the next barrier could be wiped out by a late reset.  Each
+// workgroup publishes its writes with one agent-scope release fence before
+// arriving and takes one acquire fence after the release (polling itself is
+// relaxed: an acquire per poll would invalidate the XCD's L2 while others
+// still work).  A waiter gives up after `timeout_ticks` of the constant-rate
+// wall clock, or as soon as the status word is non-zero, so the kernel always
+// terminates; the status word then carries kStatusTimeout and the caller
+// reports an error.  The counters start at zero for each launch.
 struct GridBarrier {
   unsigned group[8][32];
   unsigned top;
@@ -105,17 +136,12 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks
     bool last = false;
     const unsigned old = __hip_atomic_fetch_add(&b->group[g][0], 1u, __ATOMIC_RELAXED,
                                                 __HIP_MEMORY_SCOPE_AGENT);
-    if (old == gsize - 1u) {
-      (void)__hip_atomic_exchange(&b->group[g][0], 0u, __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");  // reset lands before top
+    if ((old + 1u) % gsize == 0u) {
       const unsigned o2 = __hip_atomic_fetch_add(&b->top, 1u, __ATOMIC_RELAXED,
                                                  __HIP_MEMORY_SCOPE_AGENT);
-      last = (o2 == ng - 1u);
+      last = ((o2 + 1u) % ng == 0u);
     }
     if (last) {
-      (void)__hip_atomic_exchange(&b->top, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
       __hip_atomic_fetch_add(&b->gen, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
       const uint64_t t0 = wall_clock64();
@@ -137,43 +163,110 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks
 }
 
 // ---------------------------------------------------------------------------
-// First hit: each active lane holds a vertex whose row is cols[b, e); it
-// finds the first entry w (in row order, i.e. increasing label) with bit w
-// set in `bits`.  Rows of at most `lane_row` entries are scanned by their own
-// lane; longer rows by the whole wave, 64 entries per step, where the lowest
-// hitting lane is the first hit.  `examined` (per lane, summed later) counts
-// the entries read up to and including the hit.  All lanes must call.
-constexpr int kLaneRow = 32;  // default lane/wave split
+// Work ranges of one level, taken by whole waves.  The n ranges are cut into
+// G regions (G = grid size); workgroup g owns region r(g) behind its own
+// counter ctrs[16 * r] (one 128-byte line each), so only its own waves
+// contend on it.  The 32 workgroups that share an XCD (workgroups are
+// dispatched round-robin over the 8 XCDs) own adjacent regions, so an XCD
+// works on one contiguous stretch of labels and its L2 sees their locality.
+// A wave whose workgroup has drained its region steals: its lanes read up to
+// 64 other counters per round trip, and it takes a range from a victim
+// picked at random among those with at least two ranges left (the last one
+// stays with its owner, so idle waves do not all queue on one counter).  It
+// gives up after a few failed attempts; every range is still taken, since
+// each workgroup drains its own region.  A counter is read before it is
+// incremented, so a drained one costs a load and no atomic.
 
-__device__ __forceinline__ void wave_first_hit(bool active, int64_t b, int64_t e,
-                                               const int32_t* cols, const uint64_t* bits,
-                                               bool& found, int32_t& par, int64_t& examined,
-                                               int lane_row = kLaneRow) {
-  const int l = lane_id();
-  found = false;
-  par = 0;
-  const bool hub = active && (e - b) > lane_row;
-  if (active && !hub) {
-    // four entries per step: the loads of a step are independent, so one
-    // memory round trip covers four candidates
-    int64_t hitj = e;
-    for (int64_t j = b; j < e && hitj == e; j += 4) {
-      int32_t w[4];
-      bool h[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) w[q] = (j + q < e) ? cols[j + q] : 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) h[q] = (j + q < e) && test_bit(bits, (uint32_t)w[q]);
-#pragma unroll
-      for (int q = 3; q >= 0; --q)
-        if (h[q]) {
-          hitj = j + q;
-          par = w[q];
-        }
+struct RangeCursor {
+  int victim = -1;  // region stolen from last (-1: none)
+  int fails = 0;    // failed steal attempts
+  bool own_done = false;
+};
+
+__device__ __forceinline__ int region_of(int g, int G) {
+  return (G % 8 == 0) ? (g % 8) * (G / 8) + g / 8 : g;
+}
+
+// Claims the next range of region r if at least min_left are left there.
+// Only the value returned by this wave's own fetch-add is a claim.
+__device__ __forceinline__ bool take_range(unsigned long long* ctrs, int64_t n, int G, int r,
+                                           int64_t min_left, int64_t* out) {
+  const int64_t lo = n * r / G, hi = n * (r + 1) / G;
+  int64_t got = -1;
+  if (lane_id() == 0) {
+    unsigned long long* ctr = ctrs + (size_t)r * 16;
+    const unsigned long long p =
+        __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (hi - lo - (int64_t)p >= min_left) {
+      const unsigned long long q =
+          __hip_atomic_fetch_add(ctr, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lo + (int64_t)q < hi) got = lo + (int64_t)q;
     }
-    found = hitj < e;
-    examined += found ? (hitj - b + 1) : (e - b);
   }
+  got = shfl(got, 0);
+  *out = got;
+  return got >= 0;
+}
+
+// Next range for the calling wave (same value in every lane), or -1.
+__device__ __forceinline__ int64_t next_range(unsigned long long* ctrs, int64_t n,
+                                              RangeCursor& c) {
+  constexpr int kMaxFails = 3;
+  const int G = (int)gridDim.x;
+  const int own = region_of((int)blockIdx.x, G);
+  int64_t r;
+  if (!c.own_done) {
+    if (take_range(ctrs, n, G, own, 1, &r)) return r;
+    c.own_done = true;
+  }
+  if (c.victim >= 0) {
+    if (take_range(ctrs, n, G, c.victim, 2, &r)) return r;
+    c.victim = -1;
+  }
+  const int l = lane_id();
+  // per-wave pseudo-random choices
+  uint32_t h = (uint32_t)(blockIdx.x * 64 + wave_id()) * 2654435761u + 0x9e3779b9u;
+  while (c.fails < kMaxFails) {
+    const int rounds = (G - 1 + kWave - 1) / kWave;
+    int victim = -1;
+    h = h * 1664525u + 1013904223u;
+    for (int q = 0; q < rounds && victim < 0; ++q) {
+      const int k = 1 + ((int)((h >> 8) % (uint32_t)rounds) + q) % rounds * kWave + l;
+      bool cand = false;
+      int v = 0;
+      if (k < G) {
+        v = (own + k) % G;
+        const int64_t lo = n * v / G, hi = n * (v + 1) / G;
+        const unsigned long long p = __hip_atomic_load(ctrs + (size_t)v * 16, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        cand = hi - lo - (int64_t)p >= 2;
+      }
+      const uint64_t who = ballot(cand);
+      if (who) {
+        const int pick = nth_set_bit64(who, (int)((h >> 16) % (uint32_t)popc64(who)));
+        victim = shfl(v, pick);
+      }
+    }
+    if (victim < 0) return -1;  // nobody has ranges to spare
+    if (take_range(ctrs, n, G, victim, 2, &r)) {
+      c.victim = victim;
+      return r;
+    }
+    ++c.fails;
+  }
+  return -1;
+}
+
+// The lanes with hub = true hold long rows cols[b, e); each is scanned by
+// the whole wave, 64 entries per step, where the lowest hitting lane gives
+// the first hit (in row order).  Sets found / par on the hub lanes; adds the
+// entries read (up to and including the hit) to lane 0's `examined`.  All
+// lanes must call.
+__device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t e,
+                                                   const int32_t* cols, const uint64_t* bits,
+                                                   bool& found, int32_t& par,
+                                                   int64_t& examined) {
+  const int l = lane_id();
   uint64_t hubs = ballot(hub);
   while (hubs) {
     const int h = ffs64(hubs);
@@ -206,6 +299,10 @@ __device__ __forceinline__ void wave_first_hit(bool active, int64_t b, int64_t e
     if (l == 0) examined += scanned;
   }
 }
+
+// Rows of at most kLaneRow entries are scanned by one lane by default,
+// longer rows by a whole wave (wave_hub_first_hit); the split is tunable.
+constexpr int kLaneRow = 32;
 
 // ---------------------------------------------------------------------------
 // Edge walk over the rows of one 64-vertex word [64 k, 64 k + 64): rows of at

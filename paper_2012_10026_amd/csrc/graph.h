@@ -34,7 +34,7 @@ struct Graph;
 // Workspace of the single-root search (sized for n_sweep vertices).
 struct BfsWork {
   int64_t n_sweep = 0;
-  int2* dp = nullptr;           // internal (depth, parent) pairs (translate mode)
+  uint64_t* dp = nullptr;       // packed (depth << 32 | parent) per swept vertex
   uint64_t* vis = nullptr;      // reached before the current level
   uint64_t* front = nullptr;    // three rotating frontier bitmaps
   int32_t* qv[2] = {nullptr, nullptr};
@@ -45,8 +45,11 @@ struct BfsWork {
   int32_t n_part = 0;
   int32_t part_grain = 0;       // bu_grain the ranges were built for
   int32_t part_grid = 0;        // grid size the ranges were built for
+  unsigned long long* wctr = nullptr;  // range counters: 3 x max_grid x 16
+  int max_grid = 0;
+  int32_t* vl[2] = {nullptr, nullptr};  // bottom-up vertex lists (n_sweep each)
   BfsCtl* ctl = nullptr;
-  bool clean = false;           // depth/parent hold -1 everywhere
+  bool clean = false;           // every pair holds the unreached value
   int grid = 0;                 // persistent grid size
   int max_per_cu = 1;           // resident 1024-thread workgroups per CU
   int max_per_cu_256 = 1;       // resident 256-thread workgroups per CU
@@ -75,6 +78,8 @@ struct MsEngine {
   int64_t chunk_cap = 0;
   int32_t* bu_part = nullptr;
   int32_t n_part = 0;
+  unsigned long long* wctr = nullptr;  // range counters: 3 x max_grid x 16
+  int max_grid = 0;
   MsCtl* ctl = nullptr;
   int ngraphs = 1;
   rbfs_tuning_t tune{};           // parameters in use (kind RBFS_TUNE_BATCH)
@@ -124,6 +129,8 @@ struct Graph {
   int32_t* cols = nullptr;
   int32_t* perm = nullptr;   // original -> internal (after RCM)
   int32_t* iperm = nullptr;  // internal -> original
+  int32_t* comp_bounds = nullptr;  // after RCM: component intervals, ascending (n_comp + 1)
+  int64_t n_comp = 0;
   BfsWork* bfs = nullptr;
   MsEngine* ms = nullptr;
   rbfs_tuning_t tune_single{};  // parameters of rbfs_bfs

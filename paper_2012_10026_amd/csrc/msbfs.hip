@@ -42,7 +42,6 @@ namespace rbfs {
 struct alignas(128) MsCtl {
   GridBarrier bar;
   alignas(128) unsigned long long qpack[3][16];
-  alignas(128) unsigned long long work[3][8][16];
   alignas(128) unsigned long long done_deg[3][16];  // degree of vertices completed
   alignas(128) unsigned long long edges[3][16];
   int levels;
@@ -77,6 +76,8 @@ struct MsParams {
   int64_t chunk_cap;
   const int32_t* bu_part;
   int32_t n_part;
+  unsigned long long* wctr;  // BU range counters: 3 slots of wstride, 16 per workgroup
+  int64_t wstride;
   const int32_t* roots;    // nroots internal (union) IDs, -1 when not swept;
                            // entry i is root (i mod k) of its graph (bit i mod k)
   int32_t nroots;
@@ -270,10 +271,11 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
       ctl->qpack[r][0] = 0ull;
       ctl->edges[r][0] = 0ull;
       ctl->done_deg[r][0] = 0ull;
-      for (int g = 0; g < 8; ++g) ctl->work[r][g][0] = 0ull;
     }
     ctl->hts[0] = (unsigned long long)wall_clock64();
   }
+  if (threadIdx.x == 0)
+    for (int r = 0; r < 3; ++r) P.wctr[r * P.wstride + blockIdx.x * 16] = 0ull;
   __syncthreads();
   if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
@@ -329,8 +331,8 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
       ctl->qpack[z3][0] = 0ull;
       ctl->edges[z3][0] = 0ull;
       ctl->done_deg[z3][0] = 0ull;
-      for (int g = 0; g < 8; ++g) ctl->work[z3][g][0] = 0ull;
     }
+    if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
     if (dir == 0) {
       // ---- top-down push
       for (int64_t i = gtid; i < nf; i += gsz) {
@@ -386,46 +388,33 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
       }
     } else {
       // ---- bottom-up pull over edge-balanced vertex ranges
-      const int g0 = blockIdx.x & 7;
-      for (int t = 0; t < 8; ++t) {
-        const int g = (g0 + t) & 7;
-        const int64_t lo = (int64_t)P.n_part * g / 8, hi = (int64_t)P.n_part * (g + 1) / 8;
-        for (;;) {
-          unsigned long long p = 0;
-          if (l == 0) {
-            p = __hip_atomic_load(&ctl->work[c3][g][0], __ATOMIC_RELAXED,
-                                  __HIP_MEMORY_SCOPE_AGENT);
-            if (lo + (int64_t)p < hi)
-              p = __hip_atomic_fetch_add(&ctl->work[c3][g][0], 1ull, __ATOMIC_RELAXED,
-                                         __HIP_MEMORY_SCOPE_AGENT);
-          }
-          p = shfl(p, 0);
-          if (lo + (int64_t)p >= hi) break;
-          const int64_t part = lo + (int64_t)p;
-          const int64_t v0 = (int64_t)P.bu_part[part] * kWave;
-          const int64_t v1 = std::min<int64_t>((int64_t)P.bu_part[part + 1] * kWave, P.n_sweep);
-          for (int64_t vb = v0; vb < v1; vb += kWave) {
-            const int64_t v = vb + l;
-            const bool inr = v < v1;
-            uint64_t miss = 0;
-            int64_t b = 0, e = 0;
-            if (inr) {
-              const uint64_t vv = P.vis[v], fv = fcur[v];
-              P.vis[v] = vv | fv;
-              miss = P.amask & ~(vv | fv);
-              if (miss) {
-                b = P.off[v];
-                e = P.off[v + 1];
-              }
+      RangeCursor cur;
+      for (;;) {
+        const int64_t part = next_range(P.wctr + c3 * P.wstride, P.n_part, cur);
+        if (part < 0) break;
+        const int64_t v0 = (int64_t)P.bu_part[part] * kWave;
+        const int64_t v1 = std::min<int64_t>((int64_t)P.bu_part[part + 1] * kWave, P.n_sweep);
+        for (int64_t vb = v0; vb < v1; vb += kWave) {
+          const int64_t v = vb + l;
+          const bool inr = v < v1;
+          uint64_t miss = 0;
+          int64_t b = 0, e = 0;
+          if (inr) {
+            const uint64_t vv = P.vis[v], fv = fcur[v];
+            P.vis[v] = vv | fv;
+            miss = P.amask & ~(vv | fv);
+            if (miss) {
+              b = P.off[v];
+              e = P.off[v + 1];
             }
-            const uint64_t found = ms_pull(P, inr && miss != 0, v, b, e, miss, fcur, L + 1,
-                                           examined);
-            if (found) {
-              fnext[v] = found;
-              if ((miss & ~found) == 0ull) done += e - b;
-            }
-            ms_stage(s_st, found != 0ull, (int32_t)v, e - b, P, qn, qpack);
           }
+          const uint64_t found = ms_pull(P, inr && miss != 0, v, b, e, miss, fcur, L + 1,
+                                         examined);
+          if (found) {
+            fnext[v] = found;
+            if ((miss & ~found) == 0ull) done += e - b;
+          }
+          ms_stage(s_st, found != 0ull, (int32_t)v, e - b, P, qn, qpack);
         }
       }
       ms_flush(s_st, P, qn, qpack);
@@ -590,7 +579,7 @@ void ms_engine_free(MsEngine* m) {
   if (!m) return;
   void* ps[] = {m->uoff, m->ucols, m->uoid, m->vis, m->front, m->dep, m->par, m->qv[0],
                 m->qv[1], m->qe[0], m->qe[1], m->chunk[0], m->chunk[1], m->bu_part, m->ctl,
-                m->roots_dev};
+                m->roots_dev, m->wctr};
   for (void* p : ps)
     if (p) (void)hipFree(p);
   m->uoff = nullptr;
@@ -602,6 +591,7 @@ void ms_engine_free(MsEngine* m) {
   m->qe[0] = m->qe[1] = nullptr;
   m->ctl = nullptr;
   m->roots_dev = nullptr;
+  m->wctr = nullptr;
   if (m->roots_host) (void)hipHostFree(m->roots_host);
   m->roots_host = nullptr;
   if (m->gexec) (void)hipGraphExecDestroy(m->gexec);
@@ -645,6 +635,8 @@ int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipSt
   MS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msbfs_kernel, kMsBlock, 0));
   m->max_per_cu = per_cu < 1 ? 1 : per_cu;
   m->compute_units = compute_units;
+  m->max_grid = 4 * compute_units;  // per_cu is at most 4
+  MS_CHECK(hipMalloc(&m->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)m->max_grid));
   MS_CHECK(hipEventCreate(&m->ev0));
   MS_CHECK(hipEventCreate(&m->ev1));
   MS_CHECK(hipStreamSynchronize(stream));
@@ -699,6 +691,12 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
   P.chunk_cap = m->chunk_cap;
   P.bu_part = m->bu_part;
   P.n_part = m->n_part;
+  P.wctr = m->wctr;
+  P.wstride = 16 * (int64_t)m->max_grid;
+  if (m->grid < 1 || m->grid > m->max_grid) {  // the range counters hold max_grid workgroups
+    set_error("bfs_batch: launch grid outside the workspace");
+    return RBFS_E_STATE;
+  }
   P.roots = m->roots_dev;
   P.nroots = nroots;
   P.k = k;

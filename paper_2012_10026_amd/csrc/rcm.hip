@@ -153,6 +153,23 @@ __global__ void cc_compress_kernel(int32_t* ccp, int64_t nplus, int32_t* csize) 
   }
 }
 
+// Component boundaries in the final (reversed) labelling.  Component roots
+// taken in rank order have Cuthill-McKee label bases b_0 = 0 < b_1 < ... <
+// b_K = nplus, and the whole sequence is reversed at the end, so component j
+// occupies final labels [nplus - b_{j+1}, nplus - b_j).  With pos[k] = j for
+// the root of rank k: bounds[K - j] = nplus - b_j, and bounds[0] = 0.
+__global__ void comp_flag_kernel(const int32_t* ccp, int64_t nplus, int32_t* flag) {
+  GRID_STRIDE(k, nplus) { flag[k] = ccp[k] == (int32_t)k ? 1 : 0; }
+}
+
+__global__ void comp_bounds_kernel(const int32_t* ccp, const int64_t* cbase, const int64_t* pos,
+                                   int64_t nplus, int64_t K, int32_t* bounds) {
+  GRID_STRIDE(k, nplus) {
+    if (ccp[k] == (int32_t)k) bounds[K - pos[k]] = (int32_t)(nplus - cbase[k]);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) bounds[0] = 0;
+}
+
 __global__ void cm_roots_kernel(const int32_t* ccp, const int64_t* cbase, const int32_t* vplus,
                                 int64_t nplus, int32_t* label, int32_t* nextfree,
                                 int32_t* front, int32_t* front_count) {
@@ -396,6 +413,24 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
                      nplus, csize);
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(scan_exclusive_i32(csize, cbase, nplus, g->scratch, stream));
+  // component intervals of the final labelling, for searches to sweep only
+  // the root's component
+  int32_t* cflag = nullptr;
+  int64_t* cpos = nullptr;
+  int32_t* bounds = nullptr;
+  int64_t ncomp = 0;
+  RCM_CHECK(B.alloc(&cflag, nplus));
+  RCM_CHECK(B.alloc(&cpos, nplus + 1));
+  hipLaunchKernelGGL(comp_flag_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp, nplus,
+                     cflag);
+  RCM_CHECK(hipGetLastError());
+  RCM_CHECK(scan_exclusive_i32(cflag, cpos, nplus, g->scratch, stream));
+  RCM_CHECK(hipMemcpyAsync(&ncomp, cpos + nplus, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
+  RCM_CHECK(hipStreamSynchronize(stream));
+  RCM_CHECK(B.alloc(&bounds, ncomp + 1));
+  hipLaunchKernelGGL(comp_bounds_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp,
+                     cbase, cpos, nplus, ncomp, bounds);
+  RCM_CHECK(hipGetLastError());
 
   // 4. level-synchronous Cuthill-McKee over all components
   RCM_CHECK(B.alloc(&label, n));
@@ -520,14 +555,17 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   g->cols = newcols;
   g->perm = perm;
   g->iperm = iperm;
+  g->comp_bounds = bounds;
+  g->n_comp = ncomp;
   B.forget(newoff);
   B.forget(newcols);
   B.forget(perm);
   B.forget(iperm);
+  B.forget(bounds);
   g->n_plus = nplus;
   g->n_sweep = nplus;
   g->reordered = 1;
-  g->bytes += sizeof(int32_t) * 2 * (size_t)n;
+  g->bytes += sizeof(int32_t) * 2 * (size_t)n + sizeof(int32_t) * (size_t)(ncomp + 1);
   free_bfs_work(g);
   free_ms_work(g);
   g->scratch.release();

@@ -427,8 +427,10 @@ int rbfs_tune(rbfs_graph_t* h, int32_t kind, const int32_t* roots, int32_t k, in
   std::vector<Dim> dims;
   if (kind == RBFS_TUNE_SINGLE) {
     dims.push_back({"shape", {{1024, 1}, {1024, 2}, {256, 1}, {256, 2}, {256, 4}}, set_shape});
-    dims.push_back({"lane_row", {{8, 0}, {16, 0}, {32, 0}, {64, 0}, {128, 0}}, set_lane_row});
-    dims.push_back({"bu_grain", {{4, 0}, {8, 0}, {16, 0}, {32, 0}, {64, 0}, {128, 0}},
+    dims.push_back({"lane_row", {{8, 0}, {16, 0}, {32, 0}, {64, 0}, {128, 0}, {256, 0}},
+                    set_lane_row});
+    dims.push_back({"bu_grain", {{8, 0}, {16, 0}, {32, 0}, {64, 0}, {128, 0}, {256, 0},
+                                 {512, 0}, {1024, 0}},
                     set_grain});
     dims.push_back({"td_chunk", {{256, 0}, {512, 0}, {1024, 0}}, set_chunk});
     if (g->reordered && o.output_space == RBFS_OUT_ORIGINAL)

@@ -199,12 +199,35 @@ def test_stats_match_oracle_schedule(rb):
             assert st["mu"] == c["mu"].tolist()
             assert st["reached"] == int((d_o >= 0).sum())
             assert st["component_edges"] == oracle.component_edges(off, d_o)
-            # bottom-up levels read exactly the oracle's count of examined entries
+            # bottom-up levels read exactly the oracle's count of examined
+            # entries over the root's component (after RCM the sweep skips
+            # the other components)
             for lv in range(nlev):
                 if st["dir"][lv] == 1:
-                    assert st["edges"][lv] == c["ebu"][lv]
+                    assert st["edges"][lv] == c["ebc"][lv]
                 else:
                     assert st["edges"][lv] == c["mf"][lv]
+    # forced schedules: every bottom-up level after the first walks the
+    # vertex list the previous one left; a work range taken twice would
+    # show up in the entry counts and in |F|
+    for root in graphgen.sample_roots(off, 6, 11):
+        d_o, _, nlev = oracle.bfs(off, cols, root, perm_o)
+        c = oracle.level_counters(off, cols, d_o, perm_o, nplus)
+        for mode in (rb.DIR_TD_ONLY, rb.DIR_BU_ONLY):
+            d, p, st = G.bfs(root, opts=rb.make_opts(mode), stats=True)
+            assert st["levels"] == nlev and st["nf"] == c["nf"].tolist()
+            for lv in range(1, nlev):
+                want = c["ebc"][lv] if mode == rb.DIR_BU_ONLY else c["mf"][lv]
+                assert st["edges"][lv] == want, (mode, root, lv)
+    # without RCM there are no component intervals: the sweep covers every
+    # vertex, as in Algorithm 2
+    P = rb.Graph(off, cols)
+    for root in graphgen.sample_roots(off, 2, 8):
+        _, _, st = P.bfs(root, opts=rb.make_opts(rb.DIR_BU_ONLY), stats=True)
+        d_o, _, nlev = oracle.bfs(off, cols, root)
+        c = oracle.level_counters(off, cols, d_o)
+        for lv in range(1, nlev):
+            assert st["edges"][lv] == c["ebu"][lv]
 
 
 def test_repeatable(rb):

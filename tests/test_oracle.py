@@ -351,7 +351,23 @@ def test_level_counters_invariants_kron():
         assert c["nu"][d] == c["nu"][d - 1] - c["nf"][d]
         assert c["mu"][d] == c["mu"][d - 1] - c["mf"][d]
     assert np.all(c["ebu"] <= c["mu"])
+    assert np.all(c["ebc"] <= c["ebu"])
     assert c["mu"][0] == cols.shape[0] - c["mf"][0]
+
+
+def test_level_counters_component_scope():
+    # two components: a path 0-1-2 (root 0) and a triangle 3-4-5.  Bottom-up
+    # at level d over the whole swept set also reads every triangle row in
+    # full (2 entries each, no hit possible); the component-scoped count
+    # leaves those out.
+    edges = [(0, 1), (1, 2), (3, 4), (4, 5), (3, 5)]
+    off, cols = csr_of(6, edges)
+    depth, _, nlev = oracle.bfs(off, cols, 0)
+    c = oracle.level_counters(off, cols, depth)
+    assert nlev == 3
+    # level 0: 1 meets 0 first (1 entry); 2's only neighbour 1 is not in F_0 (1)
+    assert c["ebc"].tolist() == [2, 1, 0]
+    assert (c["ebu"] - c["ebc"]).tolist() == [6, 6, 6]
 
 
 def test_heuristic_schedule_hand_cases():
