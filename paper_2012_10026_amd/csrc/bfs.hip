@@ -59,9 +59,9 @@ const float* switch_blob_device(int device);
 
 struct alignas(128) BfsCtl {
   GridBarrier bar;
-  alignas(128) unsigned long long qpack[3][16];     // [rotation][0], own line each
+  alignas(128) unsigned long long qpack[3][8][16];  // [rotation][sub-queue][0], own line each
   alignas(128) unsigned long long edges[3][16];     // entries read this level
-  alignas(128) unsigned long long vlcnt[3][16];     // vertices appended to the list
+  alignas(128) unsigned long long vlcnt[3][8][16];  // vertices appended to each sub-list
   int levels;
   int pad;
   int sweep_lo, sweep_hi;  // bottom-up sweep: the root's component
@@ -78,6 +78,11 @@ struct alignas(128) BfsCtl {
 namespace {
 
 constexpr int kStage = 256;  // staged appends per wave
+// The next frontier (and the bottom-up vertex list) is split into kNQ
+// sub-queues, one per group of workgroups (blockIdx mod kNQ, i.e. one per
+// XCD), each behind its own packed counter: a single grid-wide counter
+// serialises the appends of every wave on one address.
+constexpr int kNQ = 8;
 constexpr int kListRange = 64;  // list vertices per bottom-up work range
 constexpr int kScanStep = 8;    // row entries a lane tests per step
 constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
@@ -89,19 +94,21 @@ struct BfsParams {
   int64_t n_sweep;
   int64_t deg_total;     // degree sum over the swept set
   uint64_t* dp;          // packed (depth << 32 | parent) per swept vertex
+  const int32_t* iperm_par;  // non-null: parents become original IDs at the end
   const int32_t* comp_bounds;  // component intervals (null: one interval)
   int64_t n_comp;
   uint64_t* vis;
   uint64_t* front[3];
-  int32_t* qv[2];
+  int32_t* qv[2];        // kNQ sub-queues of qstride entries each
   int64_t* qe[2];
-  int32_t* chunk[2];
+  int32_t* chunk[2];     // kNQ chunk tables of chunk_cap entries each
   int64_t chunk_cap;
+  int64_t qstride;
   const int32_t* bu_part;
   int32_t n_part;
   unsigned long long* wctr;  // BU range counters: 3 slots of wstride, 16 per workgroup
   int64_t wstride;
-  int32_t* vl[2];            // vertex lists: unvisited vertices left by a bottom-up level
+  int32_t* vl[2];            // vertex lists (kNQ sub-lists of qstride entries)
   int32_t root_orig;
   int32_t init;
   int32_t mode;
@@ -126,13 +133,20 @@ struct StageLds {
   int32_t lcnt[WAVES];
 };
 
-// Publishes this wave's staged vertices to the next queue.
+// Publishes this wave's staged vertices to its sub-queue of the next
+// frontier (qpack: the packed counters of the next level, one line per
+// sub-queue).
 template <class ST>
 __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_idx,
                                             unsigned long long* qpack) {
   const int wv = wave_id(), l = lane_id();
   const int cnt = st.cnt[wv];
   if (cnt == 0) return;
+  const int sq = (int)(blockIdx.x & (kNQ - 1));
+  qpack += sq * 16;
+  int32_t* qv = P.qv[nq_idx] + sq * P.qstride;
+  int64_t* qe = P.qe[nq_idx] + sq * P.qstride;
+  int32_t* chunk = P.chunk[nq_idx] + sq * P.chunk_cap;
   int64_t total = 0;
   for (int j0 = 0; j0 < cnt; j0 += kWave) {
     const int j = j0 + l;
@@ -145,7 +159,7 @@ __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_i
   old = shfl(old, 0);
   const int64_t pos0 = (int64_t)(old >> P.eb);
   int64_t ebase = (int64_t)(old & ((1ull << P.eb) - 1ull));
-  if (pos0 + cnt > P.n_sweep) {
+  if (pos0 + cnt > P.qstride) {
     if (l == 0) atomicOr(&P.ctl->bar.status, kStatusOverflow);
   } else {
     for (int j0 = 0; j0 < cnt; j0 += kWave) {
@@ -156,9 +170,9 @@ __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_i
       if (act) {
         const int64_t pos = pos0 + j;
         const int64_t base = ebase + inc - d;
-        P.qv[nq_idx][pos] = st.v[wv][j];
-        P.qe[nq_idx][pos] = base;
-        mark_chunks(P.chunk[nq_idx], P.chunk_cap, base, d, (int32_t)pos, P.cshift);
+        qv[pos] = st.v[wv][j];
+        qe[pos] = base;
+        mark_chunks(chunk, P.chunk_cap, base, d, (int32_t)pos, P.cshift);
       }
       ebase += shfl(inc, kWave - 1);
     }
@@ -188,13 +202,17 @@ __device__ __forceinline__ void stage(ST& st, bool take, int32_t v, int64_t deg,
   if (base + popc64(m) > kStage - kWave) flush_stage(st, P, nq_idx, qpack);
 }
 
-// Publishes this wave's staged list vertices (appended at *count).
+// Publishes this wave's staged list vertices to its sub-list (out: the
+// sub-lists of cap entries each; count: their counters, one line each).
 template <class ST>
 __device__ __forceinline__ void flush_list(ST& st, int32_t* out, unsigned long long* count,
                                            int64_t cap, BfsCtl* ctl) {
   const int wv = wave_id(), l = lane_id();
   const int cnt = st.lcnt[wv];
   if (cnt == 0) return;
+  const int sq = (int)(blockIdx.x & (kNQ - 1));
+  out += sq * cap;
+  count += sq * 16;
   unsigned long long base = 0;
   if (l == 0)
     base = __hip_atomic_fetch_add(count, (unsigned long long)cnt, __ATOMIC_RELAXED,
@@ -237,6 +255,24 @@ __device__ __forceinline__ void wave_set_bits(uint64_t* words, bool take, int64_
     const uint64_t bits = wave_or64(mine ? (1ull << (v & 63)) : 0ull);
     if (lane_id() == lead) atomicOr((unsigned long long*)&words[wl], bits);
     pend &= ~ballot(mine);
+  }
+}
+
+// visited |= F_d for level d: through the queue (sub-queue sizes qcnt) when
+// the frontier is small, else word by word.
+__device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long long nf,
+                                              const uint64_t* fcur, int64_t W, int64_t gtid,
+                                              int64_t gsz, const long long* qcnt) {
+  if (nf * 8 < W) {
+    for (int q = 0; q < kNQ; ++q) {
+      const int32_t* qv = P.qv[qc] + q * P.qstride;
+      for (int64_t i = gtid; i < qcnt[q]; i += gsz) {
+        const int32_t u = qv[i];
+        atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
+      }
+    }
+  } else {
+    for (int64_t w = gtid; w < W; w += gsz) P.vis[w] |= fcur[w];
   }
 }
 
@@ -333,6 +369,9 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
   __shared__ ChunkLds s_chunk;
   __shared__ StageLds<WAVES> s_st;
+  // sizes of the current frontier's sub-queues and of the last vertex list's
+  // sub-lists (the same in every workgroup)
+  __shared__ long long s_qcnt[kNQ], s_qedg[kNQ], s_lcnt[kNQ];
   BfsCtl* ctl = P.ctl;
   const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t gsz = (int64_t)gridDim.x * BLOCK;
@@ -345,6 +384,12 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     s_st.cnt[threadIdx.x] = 0;
     s_st.lcnt[threadIdx.x] = 0;
   }
+  const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
+  if (threadIdx.x < kNQ) {  // F_0 = {root} sits in sub-queue 0
+    s_qcnt[threadIdx.x] = (threadIdx.x == 0 && root_in) ? 1 : 0;
+    s_qedg[threadIdx.x] = (threadIdx.x == 0) ? dr : 0;
+    s_lcnt[threadIdx.x] = 0;
+  }
 
   // ---- initialisation
   if (P.init) {
@@ -356,15 +401,15 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     P.front[0][w] = (root_in && w == (root >> 6)) ? (1ull << (root & 63)) : 0ull;
     P.front[1][w] = 0ull;
   }
-  const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
   if (gtid == 0) {
     if (!P.init && root_in) P.dp[root] = (uint64_t)(uint32_t)root;
     for (int r = 0; r < 2; ++r) {
-      ctl->qpack[r][0] = 0ull;
+      for (int q = 0; q < kNQ; ++q) {
+        ctl->qpack[r][q][0] = 0ull;
+        ctl->vlcnt[r][q][0] = 0ull;
+      }
       ctl->edges[r][0] = 0ull;
-      ctl->vlcnt[r][0] = 0ull;
     }
-    ctl->qpack[0][0] = root_in ? ((1ull << P.eb) | (unsigned long long)dr) : 0ull;
     ctl->hdir[0] = 0;
     ctl->hood[0] = 0;
     ctl->hnf[0] = 1;
@@ -409,41 +454,45 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   int dir = 0;
   long long nf = root_in ? 1 : 0, mf = dr, mu = P.deg_total - dr;
   long long reached = 1, deg_reached = dr;
-  // vertex list of the last bottom-up level: vl[lsrc][0, lcount) holds the
-  // vertices of the root's component it left unvisited, a superset of the
-  // unvisited ones (top-down levels only shrink that set); -1 = none yet
+  // vertex list of the last bottom-up level: the sub-lists of vl[lsrc]
+  // (s_lcnt entries each) hold the vertices of the root's component it left
+  // unvisited, a superset of the unvisited ones (top-down levels only shrink
+  // that set); -1 = none yet
   int lsrc = -1;
-  long long lcount = 0;
   while (nf > 0) {
     const int c3 = L % 3, n3 = (L + 1) % 3, z3 = (L + 2) % 3;
     const int qc = L & 1, qn = qc ^ 1;
     const uint64_t* fcur = P.front[c3];
     uint64_t* fnext = P.front[n3];
-    unsigned long long* qpack = &ctl->qpack[n3][0];
+    unsigned long long* qpack = &ctl->qpack[n3][0][0];
     int64_t examined = 0;
     // clear what level L+1 will fill
     for (int64_t w = gtid; w < W; w += gsz) P.front[z3][w] = 0ull;
     if (gtid == 0) {
-      ctl->qpack[z3][0] = 0ull;
+      for (int q = 0; q < kNQ; ++q) {
+        ctl->qpack[z3][q][0] = 0ull;
+        ctl->vlcnt[z3][q][0] = 0ull;
+      }
       ctl->edges[z3][0] = 0ull;
-      ctl->vlcnt[z3][0] = 0ull;
     }
     if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
     if (dir == 0) {
       // ---- top-down
-      if (nf * 8 < W) {
-        for (int64_t i = gtid; i < nf; i += gsz) {
-          const int32_t u = P.qv[qc][i];
-          atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
-        }
-      } else {
-        for (int64_t w = gtid; w < W; w += gsz) P.vis[w] |= fcur[w];
-      }
-      const int64_t E = mf;
-      const int64_t nchunks = ceil_div(E, (int64_t)1 << P.cshift);
+      fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
+      // the chunks of the sub-queues, one after the other
+      int64_t nchunks = 0;
+      for (int q = 0; q < kNQ; ++q) nchunks += ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
       for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-        const bool ok = expand_chunk<BLOCK>(s_chunk, c, E, P.qv[qc], P.qe[qc], nf, P.chunk[qc],
-                                     nchunks, P.off, P.cols,
+        int q = 0;
+        int64_t lc = c, nq_ch = ceil_div(s_qedg[0], (int64_t)1 << P.cshift);
+        while (lc >= nq_ch) {
+          lc -= nq_ch;
+          ++q;
+          nq_ch = ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
+        }
+        const bool ok = expand_chunk<BLOCK>(s_chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride,
+                                     P.qe[qc] + q * P.qstride, s_qcnt[q],
+                                     P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols,
                                      [&](bool active, int32_t u, int32_t w) {
           bool claim = false;
           int64_t dw = 0;
@@ -473,7 +522,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         }
       }
       flush_stage(s_st, P, qn, qpack);
-      if (gtid == 0) examined = E;
+      if (gtid == 0) examined = mf;
     } else {
       // ---- bottom-up.  The first bottom-up level sweeps the component's
       // words in edge-balanced ranges; later ones walk only the vertex list
@@ -484,27 +533,30 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       const bool listed = lsrc >= 0;
       const int32_t* vl_in = listed ? P.vl[lsrc] : nullptr;
       int32_t* vl_out = P.vl[listed ? (lsrc ^ 1) : 0];
-      unsigned long long* vlcnt = &ctl->vlcnt[n3][0];
+      unsigned long long* vlcnt = &ctl->vlcnt[n3][0][0];
+      // fold F_d into vis here: the list walk visits no words
+      if (listed) fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
+      int64_t nranges = P.n_part;
       if (listed) {
-        // fold F_d into vis here: the list walk visits no words
-        if (nf * 8 < W) {
-          for (int64_t i = gtid; i < nf; i += gsz) {
-            const int32_t u = P.qv[qc][i];
-            atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
-          }
-        } else {
-          for (int64_t w = kw_lo + gtid; w < kw_hi; w += gsz) P.vis[w] |= fcur[w];
-        }
+        nranges = 0;
+        for (int q = 0; q < kNQ; ++q) nranges += ceil_div(s_lcnt[q], kListRange);
       }
-      const int64_t nranges = listed ? ceil_div(lcount, kListRange) : P.n_part;
       const int wv = wave_id();
       RangeCursor cur;
       for (;;) {
         const int64_t part = next_range(P.wctr + c3 * P.wstride, nranges, cur);
         if (part < 0) break;
         if (listed) {
-          const int64_t i0 = part * kListRange;
-          const int total = (int)std::min<int64_t>(kListRange, lcount - i0);
+          // range `part` of the sub-lists, one after the other
+          int q = 0;
+          int64_t lr = part, nq_r = ceil_div(s_lcnt[0], kListRange);
+          while (lr >= nq_r) {
+            lr -= nq_r;
+            ++q;
+            nq_r = ceil_div(s_lcnt[q], kListRange);
+          }
+          const int64_t i0 = q * P.qstride + lr * kListRange;
+          const int total = (int)std::min<int64_t>(kListRange, s_lcnt[q] - lr * kListRange);
           refill_scan(
               total, P.off, P.cols, fcur, P.lane_row, examined,
               [&](int t) -> int64_t {
@@ -518,7 +570,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 if (found) P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
                 wave_set_bits(fnext, found, v);
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
-                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.n_sweep, ctl);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
               });
           continue;
         }
@@ -568,27 +620,39 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                   P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
                 }
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
-                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.n_sweep, ctl);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
               });
           __builtin_amdgcn_wave_barrier();
           const uint64_t fw = s_st.found[wv][l];
           if (kw < k1 && fw) fnext[kw] = fw;
         }
       }
-      flush_list(s_st, vl_out, vlcnt, P.n_sweep, ctl);
+      flush_list(s_st, vl_out, vlcnt, P.qstride, ctl);
       flush_stage(s_st, P, qn, qpack);
     }
     const int64_t ex = wave_sum(examined);
     if (l == 0 && ex)
-      __hip_atomic_fetch_add(&ctl->edges[c3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
+      __hip_atomic_fetch_add(&ctl->edges[n3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
-    // ---- next level: every workgroup decides the same way
-    const unsigned long long pk =
-        __hip_atomic_load(&ctl->qpack[n3][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const long long nf_new = (long long)(pk >> P.eb);
-    const long long mf_new = (long long)(pk & emask);
+    // ---- next level: every workgroup decides the same way.  Sizes of the
+    // next frontier's sub-queues (and of the new vertex list's sub-lists)
+    if (threadIdx.x < kNQ) {
+      const unsigned long long pk = __hip_atomic_load(&ctl->qpack[n3][threadIdx.x][0],
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_qcnt[threadIdx.x] = (long long)(pk >> P.eb);
+      s_qedg[threadIdx.x] = (long long)(pk & emask);
+      if (dir == 1)
+        s_lcnt[threadIdx.x] = (long long)__hip_atomic_load(
+            &ctl->vlcnt[n3][threadIdx.x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    long long nf_new = 0, mf_new = 0;
+    for (int q = 0; q < kNQ; ++q) {
+      nf_new += s_qcnt[q];
+      mf_new += s_qedg[q];
+    }
     const long long mu_new = mu - mf_new;
     int nd = dir;
     bool ood = false;
@@ -627,7 +691,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
     }
     if (gtid == 0 && L < RBFS_STATS_MAX_LEVELS) {
-      ctl->hedges[L] = (long long)ctl->edges[c3][0];
+      ctl->hedges[L] = (long long)ctl->edges[n3][0];
       ctl->hts[L + 1] = (unsigned long long)wall_clock64();
       if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
         ctl->hdir[L + 1] = (signed char)nd;
@@ -637,11 +701,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         ctl->hmu[L + 1] = mu_new;
       }
     }
-    if (dir == 1) {
-      lsrc = (lsrc >= 0) ? (lsrc ^ 1) : 0;
-      lcount = (long long)__hip_atomic_load(&ctl->vlcnt[n3][0], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-    }
+    if (dir == 1) lsrc = (lsrc >= 0) ? (lsrc ^ 1) : 0;
     nf = nf_new;
     mf = mf_new;
     mu = mu_new;
@@ -649,6 +709,29 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     reached += nf_new;
     deg_reached += mf_new;
     ++L;
+  }
+  // parents as original IDs for the output translation: labels are final
+  // now, and after RCM a parent's label lies near its child's, so the iperm
+  // reads of a workgroup stay close together
+  if (P.iperm_par) {
+    // eight independent entries per thread and step keep enough loads in
+    // flight (the iperm read depends on the pair read)
+    constexpr int kU = 8;
+    for (int64_t i0 = sweep_lo + gtid; i0 < sweep_hi; i0 += kU * gsz) {
+      uint64_t x[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int64_t i = i0 + u * gsz;
+        x[u] = (i < sweep_hi) ? P.dp[i] : kUnreached;
+      }
+      int32_t o[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) o[u] = (x[u] != kUnreached) ? P.iperm_par[(uint32_t)x[u]] : 0;
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (x[u] != kUnreached)
+          P.dp[i0 + u * gsz] = (x[u] & 0xFFFFFFFF00000000ull) | (uint32_t)o[u];
+    }
   }
   if (gtid == 0) {
     ctl->levels = root_in ? L : 1;
@@ -658,15 +741,14 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
 }
 
 // Outputs from the packed internal pairs.  Output index v is an original ID
-// when perm is given (one 8-byte gather per vertex, parents mapped back
-// through iperm), else an internal label.  Indices past the swept set are
-// unreached, except an isolated root.  With `reset`, reached pairs are set
-// back to unreached, so the next search needs no initialisation pass
-// (scattered 8-byte writes instead of one coalesced pass).
-__global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* iperm,
-                              const int32_t* perm_root, int64_t n_sweep, uint64_t* dp,
-                              int32_t* depth_o, int32_t* parent_o, int32_t root_orig,
-                              int reset) {
+// when perm is given (one 8-byte gather per vertex; the search has already
+// replaced the parents by original IDs), else an internal label.  Indices past
+// the swept set are unreached, except an isolated root.  With `reset`, reached
+// pairs are set back to unreached, so the next search needs no
+// initialisation pass (scattered 8-byte writes instead of one coalesced pass).
+__global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* perm_root,
+                              int64_t n_sweep, uint64_t* dp, int32_t* depth_o,
+                              int32_t* parent_o, int32_t root_orig, int reset) {
   const int32_t root_out = (perm || !perm_root) ? root_orig : perm_root[root_orig];
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
@@ -677,8 +759,7 @@ __global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* ipe
       if (x != kUnreached) {
         if (reset) dp[i] = kUnreached;
         d = (int32_t)(x >> 32);
-        const uint32_t pi = (uint32_t)x;
-        p = (pi >= (uint64_t)n_sweep) ? -1 : (iperm ? iperm[pi] : (int32_t)pi);
+        p = (int32_t)(uint32_t)x;
       }
     } else if (v == root_out) {
       d = 0;
@@ -730,13 +811,15 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(hipMalloc(&w->dp, sizeof(uint64_t) * ns));
   BFS_CHECK(hipMalloc(&w->vis, sizeof(uint64_t) * W));
   BFS_CHECK(hipMalloc(&w->front, sizeof(uint64_t) * 3 * W));
-  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->vl[i], sizeof(int32_t) * ns));
+  // every sub-queue and sub-list can hold the whole swept set
+  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->vl[i], sizeof(int32_t) * kNQ * ns));
   for (int i = 0; i < 2; ++i) {
-    BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * ns));
-    BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * ns));
+    BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * kNQ * ns));
+    BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * kNQ * ns));
   }
   w->chunk_cap = ceil_div(g->nnz, (int64_t)1 << kMinChunkShift) + 2;
-  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * w->chunk_cap));
+  for (int i = 0; i < 2; ++i)
+    BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * kNQ * w->chunk_cap));
   BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
   int per_cu = 0;
@@ -755,8 +838,9 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(hipEventCreate(&w->ev2));
   BFS_CHECK(hipStreamSynchronize(stream));
   w->clean = false;
-  g->bytes += (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * (size_t)ns +
-              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * (ns + w->chunk_cap);
+  g->bytes += sizeof(uint64_t) * (size_t)ns +
+              (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * kNQ * (size_t)ns +
+              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * kNQ * w->chunk_cap;
   return 0;
 }
 
@@ -816,6 +900,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.n_sweep = g->n_sweep;
   P.deg_total = g->nnz;
   P.dp = w->dp;
+  P.iperm_par = translate ? g->iperm : nullptr;
   P.comp_bounds = g->reordered ? g->comp_bounds : nullptr;
   P.n_comp = g->n_comp;
   P.init = w->clean ? 0 : 1;
@@ -828,6 +913,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     P.chunk[i] = w->chunk[i];
   }
   P.chunk_cap = w->chunk_cap;
+  P.qstride = g->n_sweep > 0 ? g->n_sweep : 1;
   P.bu_part = w->bu_part;
   P.n_part = w->n_part;
   P.wctr = w->wctr;
@@ -891,9 +977,8 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));
     hipLaunchKernelGGL(output_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       translate ? g->perm : nullptr, translate ? g->iperm : nullptr,
-                       g->reordered ? g->perm : nullptr, g->n_sweep, w->dp, depth, parent, root,
-                       tun.reset ? 1 : 0);
+                       translate ? g->perm : nullptr, g->reordered ? g->perm : nullptr,
+                       g->n_sweep, w->dp, depth, parent, root, tun.reset ? 1 : 0);
     BFS_CHECK(hipGetLastError());
     w->clean = tun.reset != 0;
   }

@@ -5,14 +5,14 @@
 // the hop distance and the parent of v for root j is the smallest-label
 // neighbour of v one level closer to root j.  For a vertex v still missing
 // root j at level d, every neighbour that has bit j in the frontier F_d is at
-// distance d from root j, so scanning v's row in increasing label order and
-// taking, for each missing bit, the first neighbour whose frontier word has
-// it gives exactly those parents.  Both step kinds use that scan:
-//   bottom-up: every vertex with missing bits scans its row until all of
-//     them are found (Algorithm 2's bottom-up loop, per bit);
+// distance d from root j, so either step kind gives exactly those parents:
+//   bottom-up: every vertex with missing bits scans its row in increasing
+//     label order until all of them are found, taking for each missing bit
+//     the first neighbour whose frontier word has it (Algorithm 2's
+//     bottom-up loop, per bit);
 //   top-down: frontier vertices push their bits to their neighbours with
-//     atomicOr; after a barrier, the vertices that received bits scan their
-//     rows for the parents of those bits.
+//     atomicOr, and propose themselves as parent of each pushed bit with an
+//     atomicMin on that bit's parent slot, so the smallest label stays.
 // Visited words, three rotating frontier word arrays, the per-wave staged
 // frontier queue with degree prefix (edge-balanced top-down expansion) and
 // the hierarchical grid barrier follow the single-root kernel.
@@ -22,10 +22,10 @@
 // vertex counts of the graphs before it), where root j of every graph uses
 // bit j; components never touch, so the bits never mix.
 //
-// Per-(vertex, root) results are written vertex-major ([v][64], int32),
-// parents already converted to original IDs (one lookup per distinct hit),
-// then transposed to the caller's root-major original-ID layout by a
-// gather over original IDs; the transpose resets the internal rows it reads.
+// Per-(vertex, root) results are written vertex-major ([v][64], int32) with
+// parents as internal labels, then transposed to the caller's root-major
+// original-ID layout by a gather over original IDs that also maps the parents
+// back; the transpose resets the internal rows it reads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,6 +57,7 @@ struct alignas(128) MsCtl {
 namespace {
 
 constexpr int kMsStage = 256;
+constexpr int kPullStep = 8;  // row entries a lane tests per step
 constexpr int kMsBlock = 1024;
 constexpr int kMsWaves = kMsBlock / kWave;
 
@@ -65,7 +66,6 @@ struct MsParams {
   const int32_t* cols;
   int64_t n_sweep;
   int64_t deg_total;
-  const int32_t* oid;      // internal -> original ID (null: identity)
   uint64_t* vis;
   uint64_t* front[3];
   int32_t* dep;            // [n_sweep][64]
@@ -96,9 +96,6 @@ struct MsStage {
   int32_t cnt[kMsWaves];
 };
 
-__device__ __forceinline__ int32_t orig_id(const MsParams& P, int32_t x) {
-  return P.oid ? P.oid[x] : x;
-}
 
 __device__ __forceinline__ void ms_flush(MsStage& st, const MsParams& P, int nq_idx,
                                          unsigned long long* qpack) {
@@ -158,17 +155,17 @@ __device__ __forceinline__ void ms_stage(MsStage& st, bool take, int32_t v, int6
   if (base + popc64(m) > kMsStage - kWave) ms_flush(st, P, nq_idx, qpack);
 }
 
-// Records level d+1 and parent `x` for every root bit in `bits` of vertex v.
+// Records level d+1 and parent `x` (an internal label; the output transpose
+// maps it back) for every root bit in `bits` of vertex v.
 __device__ __forceinline__ void ms_record(const MsParams& P, int64_t v, uint64_t bits,
                                           int32_t x, int d1) {
-  const int32_t ox = orig_id(P, x);
   int32_t* dr = P.dep + v * 64;
   int32_t* pr = P.par + v * 64;
   while (bits) {
     const int j = ffs64(bits);
     bits &= bits - 1;
     dr[j] = d1;
-    pr[j] = ox;
+    pr[j] = x;
   }
 }
 
@@ -202,17 +199,28 @@ __device__ __forceinline__ uint64_t ms_pull(const MsParams& P, bool active, int6
   uint64_t found = 0;
   const bool hub = active && (e - b) > P.lane_row;
   if (active && !hub && miss) {
-    int64_t j = b;
-    for (; j < e && miss; ++j) {
-      const int32_t x = P.cols[j];
-      const uint64_t hb = fcur[x] & miss;
-      if (hb) {
-        ms_record(P, v, hb, x, d1);
-        miss &= ~hb;
-        found |= hb;
+    // kPullStep entries per step: their loads are independent, so one pair
+    // of memory round trips covers them; bits are taken in row order
+    int64_t j = b, stop = e;
+    for (; j < e && miss; j += kPullStep) {
+      int32_t x[kPullStep];
+      uint64_t fb[kPullStep];
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) x[q] = (j + q < e) ? P.cols[j + q] : 0;
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) fb[q] = (j + q < e) ? fcur[x[q]] : 0ull;
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) {
+        const uint64_t hb = fb[q] & miss;
+        if (hb) {
+          ms_record(P, v, hb, x[q], d1);
+          miss &= ~hb;
+          found |= hb;
+          if (miss == 0ull) stop = j + q + 1;
+        }
       }
     }
-    examined += j - b;
+    examined += (miss == 0ull ? stop : e) - b;
   }
   uint64_t hubs = ballot(hub && miss != 0);
   while (hubs) {
@@ -294,7 +302,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
               atomicOr((unsigned long long*)&P.front[0][r], 1ull << j);
           first = (old == 0ull);
           P.dep[(int64_t)r * 64 + j] = 0;
-          P.par[(int64_t)r * 64 + j] = orig_id(P, r);
+          P.par[(int64_t)r * 64 + j] = r;
           dg = P.off[r + 1] - P.off[r];
         }
       }
@@ -334,7 +342,12 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
     }
     if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
     if (dir == 0) {
-      // ---- top-down push
+      // ---- top-down push.  Every frontier edge (u, w) carries the root bits
+      // of u that w has not seen; for each, (L+1, u) is proposed with an
+      // atomicMin on the bit's parent slot, so the smallest label stays (the
+      // rule of the single-root search), and the bits are ORed into w's next
+      // frontier word.  The OR that completes w's root set adds w's degree to
+      // the completed degree sum.
       for (int64_t i = gtid; i < nf; i += gsz) {
         const int32_t u = P.qv[qc][i];
         P.vis[u] |= fcur[u];
@@ -348,12 +361,28 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
           bool first = false;
           int64_t dw = 0;
           if (active) {
-            const uint64_t cand = fcur[u] & P.amask & ~(P.vis[w] | fcur[w]);
-            if (cand & ~fnext[w]) {
-              const unsigned long long old = atomicOr((unsigned long long*)&fnext[w], cand);
-              if (old == 0ull) {
-                first = true;
-                dw = P.off[w + 1] - P.off[w];
+            const uint64_t seen = P.vis[w] | fcur[w];
+            const uint64_t cand = fcur[u] & P.amask & ~seen;
+            if (cand) {
+              int32_t* dr = P.dep + (int64_t)w * 64;
+              uint32_t* pr = (uint32_t*)P.par + (int64_t)w * 64;
+              uint64_t bits = cand;
+              while (bits) {
+                const int j = ffs64(bits);
+                bits &= bits - 1;
+                dr[j] = L + 1;
+                if (pr[j] > (uint32_t)u) atomicMin(&pr[j], (uint32_t)u);  // stale reads are larger
+              }
+              if (cand & ~fnext[w]) {
+                const unsigned long long old = atomicOr((unsigned long long*)&fnext[w], cand);
+                const int64_t deg = P.off[w + 1] - P.off[w];
+                if (old == 0ull) {
+                  first = true;
+                  dw = deg;
+                }
+                if (((seen | old) & P.amask) != P.amask &&
+                    ((seen | old | cand) & P.amask) == P.amask)
+                  done += deg;
               }
             }
           }
@@ -366,26 +395,6 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
       }
       ms_flush(s_st, P, qn, qpack);
       if (gtid == 0) examined = E;
-      if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
-      // parents of the bits pushed this level
-      const int64_t nn = (int64_t)(__hip_atomic_load(qpack, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT) >> P.eb);
-      const int64_t wgl = (int64_t)blockIdx.x * kMsWaves + wave_id();
-      for (int64_t i0 = wgl * kWave; i0 < nn; i0 += (int64_t)gridDim.x * kMsBlock) {
-        const int64_t i = i0 + l;
-        const bool act = i < nn;
-        int64_t w = 0, b = 0, e = 0;
-        uint64_t bits = 0;
-        if (act) {
-          w = P.qv[qn][i];
-          bits = fnext[w];
-          b = P.off[w];
-          e = P.off[w + 1];
-        }
-        int64_t ex2 = 0;
-        (void)ms_pull(P, act, w, b, e, bits, fcur, L + 1, ex2);
-        if (act && (((P.vis[w] | fcur[w] | bits) & P.amask) == P.amask)) done += e - b;
-      }
     } else {
       // ---- bottom-up pull over edge-balanced vertex ranges
       RangeCursor cur;
@@ -421,10 +430,10 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
     }
     const int64_t ex = wave_sum(examined), dn = wave_sum(done);
     if (l == 0 && ex)
-      __hip_atomic_fetch_add(&ctl->edges[c3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
+      __hip_atomic_fetch_add(&ctl->edges[n3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     if (l == 0 && dn)
-      __hip_atomic_fetch_add(&ctl->done_deg[c3][0], (unsigned long long)dn, __ATOMIC_RELAXED,
+      __hip_atomic_fetch_add(&ctl->done_deg[n3][0], (unsigned long long)dn, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
@@ -433,14 +442,14 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
     const long long nf_new = (long long)(pk >> P.eb);
     const long long mf_new = (long long)(pk & emask);
     const long long mu_new =
-        mu - (long long)__hip_atomic_load(&ctl->done_deg[c3][0], __ATOMIC_RELAXED,
+        mu - (long long)__hip_atomic_load(&ctl->done_deg[n3][0], __ATOMIC_RELAXED,
                                           __HIP_MEMORY_SCOPE_AGENT);
     int nd = dir;
     if (P.mode == RBFS_DIR_TD_ONLY) nd = 0;
     else if (P.mode == RBFS_DIR_BU_ONLY) nd = 1;
     else nd = ms_heuristic(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
     if (gtid == 0 && L < RBFS_STATS_MAX_LEVELS) {
-      ctl->hedges[L] = (long long)ctl->edges[c3][0];
+      ctl->hedges[L] = (long long)ctl->edges[n3][0];
       ctl->hts[L + 1] = (unsigned long long)wall_clock64();
       if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
         ctl->hdir[L + 1] = (signed char)nd;
@@ -476,7 +485,7 @@ __global__ void ms_reset_ctl_kernel(MsCtl* c) {
 // roots are fixed up by ms_roots_fixup_kernel.
 __global__ void ms_translate_kernel(int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
                                     int64_t ubase, int32_t k, int32_t* dep, int32_t* par,
-                                    int32_t* out_dep, int32_t* out_par) {
+                                    const int32_t* oid, int32_t* out_dep, int32_t* out_par) {
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_g;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int64_t i = perm ? perm[v] : v;
@@ -485,7 +494,14 @@ __global__ void ms_translate_kernel(int64_t n_g, const int32_t* perm, int64_t n_
       int4* pr = (int4*)(par + (ubase + i) * 64);
       const int4 m1 = make_int4(-1, -1, -1, -1);
       for (int q = 0; q < (k + 3) / 4; ++q) {
-        const int4 a = dr[q], b = pr[q];
+        const int4 a = dr[q];
+        int4 b = pr[q];  // internal labels -> original IDs
+        if (oid) {
+          b.x = b.x < 0 ? -1 : oid[b.x];
+          b.y = b.y < 0 ? -1 : oid[b.y];
+          b.z = b.z < 0 ? -1 : oid[b.z];
+          b.w = b.w < 0 ? -1 : oid[b.w];
+        }
         const int j = 4 * q;
         out_dep[(int64_t)j * n_g + v] = a.x;
         out_par[(int64_t)j * n_g + v] = b.x;
@@ -678,7 +694,6 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
   P.cols = m->ucols ? m->ucols : m->cols;
   P.n_sweep = m->n_sweep;
   P.deg_total = m->nnz;
-  P.oid = m->uoid ? m->uoid : m->oid;
   P.vis = m->vis;
   for (int i = 0; i < 3; ++i) P.front[i] = m->front + (size_t)i * (m->n_sweep > 0 ? m->n_sweep : 1);
   P.dep = m->dep;
@@ -719,7 +734,8 @@ int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t 
                          int64_t ubase, int32_t k, const int32_t* roots_orig_dev,
                          int32_t* out_dep, int32_t* out_par, hipStream_t stream) {
   hipLaunchKernelGGL(ms_translate_kernel, dim3(grid_blocks(n_g)), dim3(256), 0, stream, n_g,
-                     perm, n_sweep_g, ubase, k, m->dep, m->par, out_dep, out_par);
+                     perm, n_sweep_g, ubase, k, m->dep, m->par, m->uoid ? m->uoid : m->oid,
+                     out_dep, out_par);
   MS_CHECK(hipGetLastError());
   hipLaunchKernelGGL(ms_roots_fixup_kernel, dim3(1), dim3(64), 0, stream, n_g, perm, n_sweep_g,
                      roots_orig_dev, k, out_dep, out_par);
