@@ -244,20 +244,6 @@ __device__ __forceinline__ void stage_list(ST& st, bool take, int32_t v, int32_t
   if (base + popc64(m) > kStage - kWave) flush_list(st, out, count, cap, ctl);
 }
 
-// Sets bit v of `words` for the lanes with take = true: one atomic per
-// distinct word among them.
-__device__ __forceinline__ void wave_set_bits(uint64_t* words, bool take, int64_t v) {
-  uint64_t pend = ballot(take);
-  while (pend) {
-    const int lead = ffs64(pend);
-    const int64_t wl = shfl(v >> 6, lead);
-    const bool mine = take && (v >> 6) == wl;
-    const uint64_t bits = wave_or64(mine ? (1ull << (v & 63)) : 0ull);
-    if (lane_id() == lead) atomicOr((unsigned long long*)&words[wl], bits);
-    pend &= ~ballot(mine);
-  }
-}
-
 // visited |= F_d for level d: through the queue (sub-queue sizes qcnt) when
 // the frontier is small, else word by word.
 __device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long long nf,
@@ -568,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
               },
               [&](bool fin, bool found, int64_t v, int32_t par, int64_t deg) {
                 if (found) P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
-                wave_set_bits(fnext, found, v);
+                wave_set_bits64(fnext, found, v);
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
                 stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
               });

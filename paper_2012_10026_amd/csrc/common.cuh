@@ -79,6 +79,20 @@ __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {
   return x;
 }
 
+// Sets bit v of `words` for the lanes with take = true: one atomic per
+// distinct word among them.  All lanes must call.
+__device__ __forceinline__ void wave_set_bits64(uint64_t* words, bool take, int64_t v) {
+  uint64_t pend = ballot(take);
+  while (pend) {
+    const int lead = ffs64(pend);
+    const int64_t wl = shfl(v >> 6, lead);
+    const bool mine = take && (v >> 6) == wl;
+    const uint64_t bits = wave_or64(mine ? (1ull << (v & 63)) : 0ull);
+    if (lane_id() == lead) atomicOr((unsigned long long*)&words[wl], bits);
+    pend &= ~ballot(mine);
+  }
+}
+
 __device__ __forceinline__ bool test_bit(const uint64_t* bits, uint32_t v) {
   return (bits[v >> 6] >> (v & 63)) & 1ull;
 }

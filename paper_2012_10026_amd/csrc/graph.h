@@ -70,8 +70,7 @@ struct MsEngine {
   int64_t nnz = 0;
   uint64_t* vis = nullptr;
   uint64_t* front = nullptr;      // 3 x n_sweep words
-  int32_t* dep = nullptr;         // [n_sweep][64]
-  int32_t* par = nullptr;         // [n_sweep][64]
+  uint64_t* dp = nullptr;         // [n_sweep][64] packed (depth << 32 | parent)
   int32_t* qv[2] = {nullptr, nullptr};
   int64_t* qe[2] = {nullptr, nullptr};
   int32_t* chunk[2] = {nullptr, nullptr};

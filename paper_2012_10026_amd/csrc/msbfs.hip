@@ -68,8 +68,7 @@ struct MsParams {
   int64_t deg_total;
   uint64_t* vis;
   uint64_t* front[3];
-  int32_t* dep;            // [n_sweep][64]
-  int32_t* par;            // [n_sweep][64]
+  uint64_t* dp;            // [n_sweep][64] packed (depth << 32 | parent), all ones = none
   int32_t* qv[2];
   int64_t* qe[2];
   int32_t* chunk[2];
@@ -155,17 +154,17 @@ __device__ __forceinline__ void ms_stage(MsStage& st, bool take, int32_t v, int6
   if (base + popc64(m) > kMsStage - kWave) ms_flush(st, P, nq_idx, qpack);
 }
 
-// Records level d+1 and parent `x` (an internal label; the output transpose
-// maps it back) for every root bit in `bits` of vertex v.
+// Records level d1 and parent `x` (an internal label; the output transpose
+// maps it back) for every root bit in `bits` of vertex v: one 8-byte store
+// per bit.
 __device__ __forceinline__ void ms_record(const MsParams& P, int64_t v, uint64_t bits,
                                           int32_t x, int d1) {
-  int32_t* dr = P.dep + v * 64;
-  int32_t* pr = P.par + v * 64;
+  uint64_t* row = P.dp + v * 64;
+  const uint64_t val = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)x;
   while (bits) {
     const int j = ffs64(bits);
     bits &= bits - 1;
-    dr[j] = d1;
-    pr[j] = x;
+    row[j] = val;
   }
 }
 
@@ -187,41 +186,17 @@ __device__ __forceinline__ uint64_t wave_exclusive_or(uint64_t x) {
   return l == 0 ? 0ull : ex;
 }
 
-// Each active lane holds vertex v (row cols[b, e)) missing root bits `miss`;
-// it scans the row in increasing label order and records, for every missing
-// bit, the first neighbour whose frontier word carries it.  Returns the bits
-// found.  Long rows are scanned by the whole wave, 64 entries per step; the
-// first lane holding a bit (exclusive OR-scan) owns it.  All lanes call.
-__device__ __forceinline__ uint64_t ms_pull(const MsParams& P, bool active, int64_t v,
-                                            int64_t b, int64_t e, uint64_t miss,
-                                            const uint64_t* fcur, int d1, int64_t& examined) {
+// Whole-wave scans of the long rows: every lane with hub = true holds vertex
+// v (row cols[b, e)) missing root bits `miss`; each such row is scanned by the
+// whole wave, 64 entries per step, where the first lane holding a bit
+// (exclusive OR-scan) owns it.  Returns the bits found on the hub lanes.
+// All lanes call.
+__device__ __forceinline__ uint64_t ms_hub_pull(const MsParams& P, bool hub, int64_t v,
+                                                int64_t b, int64_t e, uint64_t miss,
+                                                const uint64_t* fcur, int d1,
+                                                int64_t& examined) {
   const int l = lane_id();
   uint64_t found = 0;
-  const bool hub = active && (e - b) > P.lane_row;
-  if (active && !hub && miss) {
-    // kPullStep entries per step: their loads are independent, so one pair
-    // of memory round trips covers them; bits are taken in row order
-    int64_t j = b, stop = e;
-    for (; j < e && miss; j += kPullStep) {
-      int32_t x[kPullStep];
-      uint64_t fb[kPullStep];
-#pragma unroll
-      for (int q = 0; q < kPullStep; ++q) x[q] = (j + q < e) ? P.cols[j + q] : 0;
-#pragma unroll
-      for (int q = 0; q < kPullStep; ++q) fb[q] = (j + q < e) ? fcur[x[q]] : 0ull;
-#pragma unroll
-      for (int q = 0; q < kPullStep; ++q) {
-        const uint64_t hb = fb[q] & miss;
-        if (hb) {
-          ms_record(P, v, hb, x[q], d1);
-          miss &= ~hb;
-          found |= hb;
-          if (miss == 0ull) stop = j + q + 1;
-        }
-      }
-    }
-    examined += (miss == 0ull ? stop : e) - b;
-  }
   uint64_t hubs = ballot(hub && miss != 0);
   while (hubs) {
     const int h = ffs64(hubs);
@@ -246,10 +221,111 @@ __device__ __forceinline__ uint64_t ms_pull(const MsParams& P, bool active, int6
       hfound |= all;
       scanned += (j0 + kWave < he ? kWave : he - j0);
     }
-    if (l == h) found |= hfound;
+    if (l == h) found = hfound;
     if (l == 0) examined += scanned;
   }
   return found;
+}
+
+// Bottom-up pull over the vertices [v0, v1) with lane refill.  The vertices
+// are taken 64 at a time (one coalesced load of their visited and frontier
+// words, which also folds F_d into visited); those with missing root bits are
+// handed to idle lanes, and a lane that finishes its vertex takes the next
+// one at once, so a long row does not stall the other 63 lanes.  Each lane
+// scans its row in increasing label order, kPullStep entries per step, and
+// records for every missing bit the first neighbour whose frontier word has
+// it; rows longer than lane_row are scanned by the whole wave.  Vertices that
+// found bits go to the next frontier; `done` gathers the degree of vertices
+// that now have every root.
+__device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int64_t v1,
+                                              const uint64_t* fcur, uint64_t* fnext, int d1,
+                                              int64_t& examined, int64_t& done, MsStage& st,
+                                              int qn, unsigned long long* qpack) {
+  const int l = lane_id();
+  int64_t cb = v0;      // current 64-vertex chunk (same in every lane)
+  uint64_t mch = 0;     // missing bits of vertex cb + l
+  uint64_t cm = 0;      // chunk vertices not handed out yet (same in every lane)
+  auto load_chunk = [&]() {
+    const int64_t u = cb + l;
+    mch = 0;
+    if (u < v1) {
+      const uint64_t vv = P.vis[u], fv = fcur[u];
+      P.vis[u] = vv | fv;
+      mch = P.amask & ~(vv | fv);
+    }
+    cm = ballot(mch != 0ull);
+  };
+  load_chunk();
+  bool busy = false;
+  int64_t v = 0, b = 0, j = 0, e = 0;
+  uint64_t miss = 0, found = 0;
+  for (;;) {
+    // hand candidates to idle lanes, moving on to further chunks as needed
+    bool fresh = false;
+    for (;;) {
+      const uint64_t idle = ballot(!busy && !fresh);
+      if (idle == 0ull) break;
+      if (cm == 0ull) {
+        if (cb + kWave >= v1) break;
+        cb += kWave;
+        load_chunk();
+        continue;
+      }
+      const int k = popc64(cm);
+      const int r = popc64(idle & lanemask_lt());
+      const bool take = !busy && !fresh && r < k;
+      const int p = take ? nth_set_bit64(cm, r) : 0;
+      const uint64_t mp = shfl(mch, p);
+      if (take) {
+        v = cb + p;
+        miss = mp;
+        found = 0;
+        fresh = true;
+      }
+      const int given = k < popc64(idle) ? k : popc64(idle);
+      cm = (given == k) ? 0ull : (cm & ~((1ull << nth_set_bit64(cm, given)) - 1ull));
+    }
+    if (fresh) {
+      b = P.off[v];
+      e = P.off[v + 1];
+      j = b;
+      busy = true;
+    }
+    const bool hub = fresh && (e - b) > P.lane_row;
+    const uint64_t hf = ms_hub_pull(P, hub, v, b, e, miss, fcur, d1, examined);
+    bool fin = false;
+    if (hub) {
+      found = hf;
+      miss &= ~hf;
+      fin = true;
+    } else if (busy) {
+      int32_t x[kPullStep];
+      uint64_t fb[kPullStep];
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) x[q] = (j + q < e) ? P.cols[j + q] : 0;
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) fb[q] = (j + q < e) ? fcur[x[q]] : 0ull;
+      int used = (e - j < kPullStep) ? (int)(e - j) : kPullStep;
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) {
+        const uint64_t hb = fb[q] & miss;
+        if (hb) {
+          ms_record(P, v, hb, x[q], d1);
+          miss &= ~hb;
+          found |= hb;
+          if (miss == 0ull) used = q + 1;
+        }
+      }
+      examined += used;
+      j += kPullStep;
+      fin = miss == 0ull || j >= e;
+    }
+    if (fin && found) fnext[v] = found;
+    if (fin && miss == 0ull) done += e - b;
+    ms_stage(st, fin && found != 0ull, (int32_t)v, e - b, P, qn, qpack);
+    if (fin) busy = false;
+    if (cm == 0ull && cb + kWave >= v1 && ballot(busy) == 0ull) break;
+  }
 }
 
 __device__ __forceinline__ int ms_heuristic(int dir, long long nf, long long mf, long long mu,
@@ -301,8 +377,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
           const unsigned long long old =
               atomicOr((unsigned long long*)&P.front[0][r], 1ull << j);
           first = (old == 0ull);
-          P.dep[(int64_t)r * 64 + j] = 0;
-          P.par[(int64_t)r * 64 + j] = r;
+          P.dp[(int64_t)r * 64 + j] = (uint64_t)(uint32_t)r;  // depth 0, parent itself
           dg = P.off[r + 1] - P.off[r];
         }
       }
@@ -364,14 +439,16 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
             const uint64_t seen = P.vis[w] | fcur[w];
             const uint64_t cand = fcur[u] & P.amask & ~seen;
             if (cand) {
-              int32_t* dr = P.dep + (int64_t)w * 64;
-              uint32_t* pr = (uint32_t*)P.par + (int64_t)w * 64;
+              // (L+1, u) proposed per bit: depth sits in the high half, so
+              // the smallest word is the smallest-label parent of this level
+              unsigned long long* row = (unsigned long long*)P.dp + (int64_t)w * 64;
+              const unsigned long long prop = ((unsigned long long)(uint32_t)(L + 1) << 32) |
+                                              (uint32_t)u;
               uint64_t bits = cand;
               while (bits) {
                 const int j = ffs64(bits);
                 bits &= bits - 1;
-                dr[j] = L + 1;
-                if (pr[j] > (uint32_t)u) atomicMin(&pr[j], (uint32_t)u);  // stale reads are larger
+                if (row[j] > prop) atomicMin(&row[j], prop);  // stale reads are larger
               }
               if (cand & ~fnext[w]) {
                 const unsigned long long old = atomicOr((unsigned long long*)&fnext[w], cand);
@@ -403,28 +480,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
         if (part < 0) break;
         const int64_t v0 = (int64_t)P.bu_part[part] * kWave;
         const int64_t v1 = std::min<int64_t>((int64_t)P.bu_part[part + 1] * kWave, P.n_sweep);
-        for (int64_t vb = v0; vb < v1; vb += kWave) {
-          const int64_t v = vb + l;
-          const bool inr = v < v1;
-          uint64_t miss = 0;
-          int64_t b = 0, e = 0;
-          if (inr) {
-            const uint64_t vv = P.vis[v], fv = fcur[v];
-            P.vis[v] = vv | fv;
-            miss = P.amask & ~(vv | fv);
-            if (miss) {
-              b = P.off[v];
-              e = P.off[v + 1];
-            }
-          }
-          const uint64_t found = ms_pull(P, inr && miss != 0, v, b, e, miss, fcur, L + 1,
-                                         examined);
-          if (found) {
-            fnext[v] = found;
-            if ((miss & ~found) == 0ull) done += e - b;
-          }
-          ms_stage(s_st, found != 0ull, (int32_t)v, e - b, P, qn, qpack);
-        }
+        ms_pull_range(P, v0, v1, fcur, fnext, L + 1, examined, done, s_st, qn, qpack);
       }
       ms_flush(s_st, P, qn, qpack);
     }
@@ -467,7 +523,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
   if (gtid == 0) ctl->levels = L;
 }
 
-__global__ void ms_fill_kernel(int32_t* a, int64_t n, int32_t val) {
+__global__ void ms_fill_kernel(uint64_t* a, int64_t n, uint64_t val) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     a[i] = val;
@@ -480,55 +536,60 @@ __global__ void ms_reset_ctl_kernel(MsCtl* c) {
 }
 
 // Root-major output of one graph: out[j][v] for j < k and original IDs v of
-// the graph.  Vertex v's internal (union) row is gathered (256 contiguous
-// bytes per array) and reset to -1.  Isolated vertices get -1; isolated
-// roots are fixed up by ms_roots_fixup_kernel.
-__global__ void ms_translate_kernel(int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
-                                    int64_t ubase, int32_t k, int32_t* dep, int32_t* par,
-                                    const int32_t* oid, int32_t* out_dep, int32_t* out_par) {
-  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n_g;
-       v += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = perm ? perm[v] : v;
-    if (i < n_sweep_g) {
-      int4* dr = (int4*)(dep + (ubase + i) * 64);
-      int4* pr = (int4*)(par + (ubase + i) * 64);
-      const int4 m1 = make_int4(-1, -1, -1, -1);
-      for (int q = 0; q < (k + 3) / 4; ++q) {
-        const int4 a = dr[q];
-        int4 b = pr[q];  // internal labels -> original IDs
-        if (oid) {
-          b.x = b.x < 0 ? -1 : oid[b.x];
-          b.y = b.y < 0 ? -1 : oid[b.y];
-          b.z = b.z < 0 ? -1 : oid[b.z];
-          b.w = b.w < 0 ? -1 : oid[b.w];
+// the graph, as a tiled transpose through LDS.  A workgroup takes 64
+// consecutive original IDs: each wave reads the packed internal rows of 16 of
+// them (lane = root, one coalesced 512-byte row per vertex, reset to "none"
+// as it goes), then writes 16 of the root rows (lane = vertex, coalesced).
+// Parents go back to original IDs through oid (reusing the last lookup: the
+// roots of a vertex often share a parent).  Isolated vertices get -1;
+// isolated roots are fixed up by ms_roots_fixup_kernel.
+constexpr int kTrBlock = 256;
+__global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
+    int64_t n_g, const int32_t* perm, int64_t n_sweep_g, int64_t ubase, int32_t k, uint64_t* dp,
+    const int32_t* oid, int32_t* out_dep, int32_t* out_par) {
+  constexpr int kRows = kWave / (kTrBlock / kWave);  // vertices (and roots) per wave
+  __shared__ uint64_t tile[kWave][kWave + 1];        // [vertex][root], padded
+  const int wv = wave_id(), l = lane_id();
+  for (int64_t v0 = (int64_t)blockIdx.x * kWave; v0 < n_g; v0 += (int64_t)gridDim.x * kWave) {
+    for (int t = 0; t < kRows; ++t) {
+      const int r = wv * kRows + t;
+      const int64_t v = v0 + r;
+      uint64_t x = ~0ull;
+      if (v < n_g && l < k) {
+        const int64_t i = perm ? perm[v] : v;
+        if (i < n_sweep_g) {
+          uint64_t* row = dp + (ubase + i) * 64;
+          x = row[l];
+          row[l] = ~0ull;
         }
-        const int j = 4 * q;
-        out_dep[(int64_t)j * n_g + v] = a.x;
-        out_par[(int64_t)j * n_g + v] = b.x;
-        if (j + 1 < k) {
-          out_dep[(int64_t)(j + 1) * n_g + v] = a.y;
-          out_par[(int64_t)(j + 1) * n_g + v] = b.y;
-        }
-        if (j + 2 < k) {
-          out_dep[(int64_t)(j + 2) * n_g + v] = a.z;
-          out_par[(int64_t)(j + 2) * n_g + v] = b.z;
-        }
-        if (j + 3 < k) {
-          out_dep[(int64_t)(j + 3) * n_g + v] = a.w;
-          out_par[(int64_t)(j + 3) * n_g + v] = b.w;
-        }
-        dr[q] = m1;
-        pr[q] = m1;
       }
-    } else {
-      for (int j = 0; j < k; ++j) {
-        out_dep[(int64_t)j * n_g + v] = -1;
-        out_par[(int64_t)j * n_g + v] = -1;
+      tile[r][l] = x;
+    }
+    __syncthreads();
+    const int64_t v = v0 + l;
+    int32_t last_in = -1, last_out = -1;
+    for (int t = 0; t < kRows; ++t) {
+      const int j = wv * kRows + t;
+      if (j < k && v < n_g) {
+        const uint64_t x = tile[l][j];
+        const int32_t d = (int32_t)(x >> 32);
+        int32_t p = (int32_t)(uint32_t)x;
+        if (p >= 0 && oid) {
+          if (p != last_in) {
+            last_in = p;
+            last_out = oid[p];
+          }
+          p = last_out;
+        }
+        out_dep[(int64_t)j * n_g + v] = d;
+        out_par[(int64_t)j * n_g + v] = p;
       }
     }
+    __syncthreads();
   }
 }
 
+// Union IDs of the roots (-1 for isolated roots, which are not swept).
 __global__ void ms_roots_kernel(const int32_t* roots_orig, int32_t k, const int32_t* perm,
                                 int64_t n_sweep, int64_t ubase, int32_t* roots_union) {
   const int j = threadIdx.x;
@@ -593,7 +654,7 @@ int grid_blocks(int64_t work) {
 
 void ms_engine_free(MsEngine* m) {
   if (!m) return;
-  void* ps[] = {m->uoff, m->ucols, m->uoid, m->vis, m->front, m->dep, m->par, m->qv[0],
+  void* ps[] = {m->uoff, m->ucols, m->uoid, m->vis, m->front, m->dp, m->qv[0],
                 m->qv[1], m->qe[0], m->qe[1], m->chunk[0], m->chunk[1], m->bu_part, m->ctl,
                 m->roots_dev, m->wctr};
   for (void* p : ps)
@@ -602,7 +663,7 @@ void ms_engine_free(MsEngine* m) {
   m->ucols = nullptr;
   m->uoid = nullptr;
   m->vis = m->front = nullptr;
-  m->dep = m->par = nullptr;
+  m->dp = nullptr;
   m->qv[0] = m->qv[1] = m->chunk[0] = m->chunk[1] = m->bu_part = nullptr;
   m->qe[0] = m->qe[1] = nullptr;
   m->ctl = nullptr;
@@ -630,8 +691,7 @@ int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipSt
   const int64_t ns = m->n_sweep > 0 ? m->n_sweep : 1;
   MS_CHECK(hipMalloc(&m->vis, sizeof(uint64_t) * ns));
   MS_CHECK(hipMalloc(&m->front, sizeof(uint64_t) * 3 * ns));
-  MS_CHECK(hipMalloc(&m->dep, sizeof(int32_t) * 64 * ns));
-  MS_CHECK(hipMalloc(&m->par, sizeof(int32_t) * 64 * ns));
+  MS_CHECK(hipMalloc(&m->dp, sizeof(uint64_t) * 64 * ns));
   for (int i = 0; i < 2; ++i) {
     MS_CHECK(hipMalloc(&m->qv[i], sizeof(int32_t) * ns));
     MS_CHECK(hipMalloc(&m->qe[i], sizeof(int64_t) * ns));
@@ -642,10 +702,8 @@ int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipSt
   MS_CHECK(hipMemsetAsync(m->ctl, 0, sizeof(MsCtl), stream));
   MS_CHECK(hipMalloc(&m->roots_dev, sizeof(int32_t) * 64 * 2 * m->ngraphs));
   MS_CHECK(hipHostMalloc(&m->roots_host, sizeof(int32_t) * 64 * (1 + m->ngraphs)));
-  hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->dep,
-                     64 * ns, -1);
-  hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->par,
-                     64 * ns, -1);
+  hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->dp,
+                     64 * ns, ~0ull);
   MS_CHECK(hipGetLastError());
   int per_cu = 0;
   MS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, msbfs_kernel, kMsBlock, 0));
@@ -696,8 +754,7 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
   P.deg_total = m->nnz;
   P.vis = m->vis;
   for (int i = 0; i < 3; ++i) P.front[i] = m->front + (size_t)i * (m->n_sweep > 0 ? m->n_sweep : 1);
-  P.dep = m->dep;
-  P.par = m->par;
+  P.dp = m->dp;
   for (int i = 0; i < 2; ++i) {
     P.qv[i] = m->qv[i];
     P.qe[i] = m->qe[i];
@@ -733,9 +790,10 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
 int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
                          int64_t ubase, int32_t k, const int32_t* roots_orig_dev,
                          int32_t* out_dep, int32_t* out_par, hipStream_t stream) {
-  hipLaunchKernelGGL(ms_translate_kernel, dim3(grid_blocks(n_g)), dim3(256), 0, stream, n_g,
-                     perm, n_sweep_g, ubase, k, m->dep, m->par, m->uoid ? m->uoid : m->oid,
-                     out_dep, out_par);
+  const int64_t tiles = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n_g, kWave), 1 << 20));
+  hipLaunchKernelGGL(ms_translate_kernel, dim3((unsigned)tiles), dim3(kTrBlock), 0, stream, n_g,
+                     perm, n_sweep_g, ubase, k, m->dp, m->uoid ? m->uoid : m->oid, out_dep,
+                     out_par);
   MS_CHECK(hipGetLastError());
   hipLaunchKernelGGL(ms_roots_fixup_kernel, dim3(1), dim3(64), 0, stream, n_g, perm, n_sweep_g,
                      roots_orig_dev, k, out_dep, out_par);
@@ -788,7 +846,7 @@ static int ensure_ms(Graph* g, hipStream_t stream) {
   int rc = ms_engine_setup(m, g->compute_units, g->wall_rate_khz, stream);
   if (!rc) rc = ms_apply_tuning(m, g->tune_batch, stream);
   if (rc) return rc;
-  g->bytes += sizeof(int32_t) * 128 * (size_t)(g->n_sweep > 0 ? g->n_sweep : 1);
+  g->bytes += sizeof(uint64_t) * 64 * (size_t)(g->n_sweep > 0 ? g->n_sweep : 1);
   return 0;
 }
 
