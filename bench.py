@@ -42,13 +42,15 @@ def host_cpu():
     return model, os.cpu_count()
 
 
-def bfs_alg_bytes(st, n_sweep):
+def bfs_alg_bytes(st, n_sweep, original_ids=True):
     """Algorithmic bytes of one search kernel launch from its per-level
     counters: top-down level: 16 n_f (row offsets) + 4 n_f (queue) +
     4 e_td (columns) + 12 n_new (depth, parent, queue write); bottom-up
     level: 8 n_u (row offsets) + 4 e_bu (columns read up to the first hit) +
-    3 * n_sweep / 8 (visited read, next write) + 8 n_new."""
-    total = 0
+    3 * n_sweep / 8 (visited read, next write) + 8 n_new.  With outputs in
+    original IDs the kernel also does the iperm gather of the output
+    translation: 4 bytes per reached vertex (its parent's original ID)."""
+    total = 4 * st["reached"] if original_ids else 0
     reached = 0
     L = st["levels"]
     for d in range(min(L, len(st["nf"]))):

@@ -11,8 +11,9 @@
 //     the first neighbour whose frontier word has it (Algorithm 2's
 //     bottom-up loop, per bit);
 //   top-down: frontier vertices push their bits to their neighbours with
-//     atomicOr, and propose themselves as parent of each pushed bit with an
-//     atomicMin on that bit's parent slot, so the smallest label stays.
+//     atomicOr, and for each bit the neighbour still misses propose
+//     (depth, parent) = (d+1, u) with a 64-bit atomicMin on the neighbour's
+//     packed word for that root, so the smallest label stays.
 // Visited words, three rotating frontier word arrays, the per-wave staged
 // frontier queue with degree prefix (edge-balanced top-down expansion) and
 // the hierarchical grid barrier follow the single-root kernel.
@@ -22,10 +23,11 @@
 // vertex counts of the graphs before it), where root j of every graph uses
 // bit j; components never touch, so the bits never mix.
 //
-// Per-(vertex, root) results are written vertex-major ([v][64], int32) with
-// parents as internal labels, then transposed to the caller's root-major
-// original-ID layout by a gather over original IDs that also maps the parents
-// back; the transpose resets the internal rows it reads.
+// Per-(vertex, root) results are packed 64-bit words (depth << 32 | parent,
+// all ones = unreached), vertex-major ([v][64]), with parents as internal
+// labels.  A tiled transpose through LDS turns them into the caller's
+// root-major original-ID layout, maps the parents back, and resets the
+// internal rows it reads.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
