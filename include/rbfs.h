@@ -240,8 +240,9 @@ typedef struct rbfs_tuning {
                         by one lane each, longer rows by a whole wave; 1..4096 */
   int32_t bu_grain;  /* bottom-up: edge-balanced work ranges per search
                         workgroup (taken by work stealing); 1..1024 */
-  int32_t td_chunk;  /* top-down: adjacency entries per load-balancing chunk:
-                        256, 512 or 1024 (single-root only) */
+  int32_t td_chunk;  /* top-down: adjacency entries per load-balancing chunk,
+                        a power of two from 256 to 4 * block (single-root
+                        only; batched searches ignore it) */
   int32_t reset;     /* single-root with original-ID outputs: 1 = the output
                         translation clears the internal entries it reads
                         (scattered writes), 0 = the next search

@@ -353,7 +353,7 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
-  __shared__ ChunkLds s_chunk;
+  __shared__ ChunkLdsB<kTdK * BLOCK> s_chunk;
   __shared__ StageLds<WAVES> s_st;
   // sizes of the current frontier's sub-queues and of the last vertex list's
   // sub-lists (the same in every workgroup)
@@ -476,32 +476,45 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           ++q;
           nq_ch = ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
         }
-        const bool ok = expand_chunk<BLOCK>(s_chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride,
-                                     P.qe[qc] + q * P.qstride, s_qcnt[q],
-                                     P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols,
-                                     [&](bool active, int32_t u, int32_t w) {
-          bool claim = false;
-          int64_t dw = 0;
-          if (active) {
-            const uint64_t word = P.vis[w >> 6] | fcur[w >> 6];
-            if (!((word >> (w & 63)) & 1ull)) {
-              // w is unvisited at level start: propose (L+1, u).  The
-              // smallest proposal stays, so the parent is the smallest
-              // label; only the first proposal finds w unreached and claims
-              // it.  A stale read can only be larger than the stored value.
-              const uint64_t prop = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)u;
-              if (P.dp[w] > prop) {
-                claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
-                        kUnreached;
-                if (claim) {
-                  dw = P.off[w + 1] - P.off[w];
-                  atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
-                }
-              }
+        const bool ok = expand_chunk_batch<BLOCK, kTdK>(
+            s_chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride, P.qe[qc] + q * P.qstride,
+            s_qcnt[q], P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols, P.cshift,
+            [&](const bool* act, const int32_t* u, const int32_t* w) {
+          // w is a candidate if unvisited at level start; it then proposes
+          // (L+1, u).  The smallest proposal stays, so the parent is the
+          // smallest label; only the first proposal finds w unreached and
+          // claims it.  A stale read of the pair can only be larger than the
+          // stored value.
+          uint64_t word[kTdK], cur[kTdK];
+          bool cand[kTdK], claim[kTdK];
+          int64_t dw[kTdK];
+#pragma unroll
+          for (int r = 0; r < kTdK; ++r)
+            word[r] = act[r] ? (P.vis[w[r] >> 6] | fcur[w[r] >> 6]) : ~0ull;
+#pragma unroll
+          for (int r = 0; r < kTdK; ++r) {
+            cand[r] = !((word[r] >> (w[r] & 63)) & 1ull);
+            cur[r] = cand[r] ? P.dp[w[r]] : 0ull;
+          }
+#pragma unroll
+          for (int r = 0; r < kTdK; ++r) {
+            const uint64_t prop = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)u[r];
+            claim[r] = false;
+            if (cand[r] && cur[r] > prop)
+              claim[r] = atomicMin((unsigned long long*)&P.dp[w[r]], (unsigned long long)prop) ==
+                         kUnreached;
+          }
+#pragma unroll
+          for (int r = 0; r < kTdK; ++r) {
+            dw[r] = 0;
+            if (claim[r]) {
+              dw[r] = P.off[w[r] + 1] - P.off[w[r]];
+              atomicOr((unsigned long long*)&fnext[w[r] >> 6], 1ull << (w[r] & 63));
             }
           }
-          stage(s_st, claim, w, dw, P, qn, qpack);
-        }, P.cshift);
+#pragma unroll
+          for (int r = 0; r < kTdK; ++r) stage(s_st, claim[r], w[r], dw[r], P, qn, qpack);
+        });
         if (!ok) {
           if (threadIdx.x == 0) atomicOr(&ctl->bar.status, kStatusBadInput);
           break;

@@ -88,4 +88,73 @@ __device__ __forceinline__ bool expand_chunk(ChunkLds& s, int64_t c, int64_t E, 
   return true;
 }
 
+// Chunk staging for expand_chunk_batch: up to CAP entries per chunk.  Row
+// starts are kept relative to the chunk start (the first one clamped to 0),
+// with the column base of each row (row offset minus row start), so an
+// entry's column index is colbase + entry.
+template <int CAP>
+struct ChunkLdsB {
+  int64_t colbase[CAP + 2];
+  int32_t qe[CAP + 2];
+  int32_t u[CAP + 2];
+  int32_t k;
+  int32_t p0;
+};
+
+// expand_chunk with K entries per thread: entry r * BLOCK + threadIdx.x of
+// each round of K * BLOCK entries goes to slot r, and f(act, u, w) receives
+// the K slots at once, so it can issue the K entries' memory accesses
+// together instead of one dependent chain at a time.  Chunks may hold up to
+// K * BLOCK entries (cshift at most log2(K * BLOCK)).
+template <int BLOCK, int K, class F>
+__device__ __forceinline__ bool expand_chunk_batch(ChunkLdsB<K * BLOCK>& s, int64_t c, int64_t E,
+                                                   const int32_t* q, const int64_t* qe,
+                                                   int64_t nq, const int32_t* chunk_pos,
+                                                   int64_t nchunks, const int64_t* off,
+                                                   const int32_t* cols, int cshift, F&& f) {
+  constexpr int CAP = K * BLOCK;
+  const int64_t e0 = c << cshift;
+  const int64_t e1 = (e0 + ((int64_t)1 << cshift) < E) ? e0 + ((int64_t)1 << cshift) : E;
+  const int n = (int)(e1 - e0);
+  if (threadIdx.x == 0) {
+    const int64_t p0 = chunk_pos[c];
+    const int64_t p1 = (c + 1 < nchunks) ? (int64_t)chunk_pos[c + 1] : nq - 1;
+    const int64_t k = p1 - p0 + 1;
+    const bool bad = p0 < 0 || p1 >= nq || k < 1 || k > CAP + 1 || ((int64_t)1 << cshift) > CAP;
+    s.k = bad ? -1 : (int32_t)k;
+    s.p0 = (int32_t)p0;
+  }
+  __syncthreads();
+  const int32_t k = s.k;
+  if (k < 0) return false;
+  const int64_t p0 = s.p0;
+  for (int i = threadIdx.x; i < k; i += BLOCK) {
+    const int32_t u = q[p0 + i];
+    const int64_t a = qe[p0 + i];
+    s.u[i] = u;
+    s.qe[i] = (int32_t)(a > e0 ? a - e0 : 0);
+    s.colbase[i] = off[u] - a;
+  }
+  __syncthreads();
+  for (int base = 0; base < n; base += CAP) {
+    bool act[K];
+    int32_t u[K], w[K];
+#pragma unroll
+    for (int r = 0; r < K; ++r) {
+      const int e = base + r * BLOCK + (int)threadIdx.x;
+      act[r] = e < n;
+      int lo = 0, hi = k - 1;  // last i with qe[i] <= e
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s.qe[mid] <= e) lo = mid; else hi = mid - 1;
+      }
+      u[r] = act[r] ? s.u[lo] : 0;
+      w[r] = act[r] ? cols[s.colbase[lo] + e0 + e] : 0;
+    }
+    f(act, u, w);
+  }
+  __syncthreads();
+  return true;
+}
+
 }  // namespace rbfs

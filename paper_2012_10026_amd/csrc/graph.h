@@ -15,6 +15,11 @@ namespace rbfs {
 constexpr int kChunkShift = 10;
 constexpr int kChunkEdges = 1 << kChunkShift;  // largest top-down chunk
 constexpr int kMinChunkShift = 8;               // smallest (tunable)
+// Single-root top-down step: frontier edges per thread and round.  Their
+// column, bitmap, pair and atomic accesses are issued together, so each thread
+// keeps kTdK independent chains in flight; a chunk holds at most kTdK * block
+// entries.
+constexpr int kTdK = 4;
 
 // Built-in defaults of the tunable parameters and their check.
 rbfs_tuning_t default_tuning(int kind);

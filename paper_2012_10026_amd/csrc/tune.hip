@@ -31,7 +31,7 @@ rbfs_tuning_t default_tuning(int kind) {
   t.per_cu = 1;
   t.lane_row = kLaneRow;
   t.bu_grain = 32;
-  t.td_chunk = kChunkEdges;
+  t.td_chunk = kTdK * 1024;
   t.reset = 0;
   (void)kind;
   return t;
@@ -45,8 +45,8 @@ bool tuning_valid(int kind, const rbfs_tuning_t& t, std::string* why) {
   else if (t.per_cu < 1 || t.per_cu > 4) bad = "per_cu outside [1, 4]";
   else if (t.lane_row < 1 || t.lane_row > 4096) bad = "lane_row outside [1, 4096]";
   else if (t.bu_grain < 1 || t.bu_grain > 1024) bad = "bu_grain outside [1, 1024]";
-  else if (t.td_chunk != 256 && t.td_chunk != 512 && t.td_chunk != 1024)
-    bad = "td_chunk must be 256, 512 or 1024";
+  else if (t.td_chunk < 256 || t.td_chunk > kTdK * t.block || (t.td_chunk & (t.td_chunk - 1)))
+    bad = "td_chunk must be a power of two in [256, 4 * block]";
   else if (t.reset != 0 && t.reset != 1) bad = "reset must be 0 or 1";
   if (bad && why) *why = bad;
   return bad == nullptr;
@@ -196,6 +196,7 @@ struct Dim {
 void set_shape(rbfs_tuning_t& t, std::pair<int, int> v) {
   t.block = v.first;
   t.per_cu = v.second;
+  t.td_chunk = std::min(t.td_chunk, rbfs::kTdK * t.block);  // a chunk fits the block's LDS
 }
 void set_lane_row(rbfs_tuning_t& t, std::pair<int, int> v) { t.lane_row = v.first; }
 void set_grain(rbfs_tuning_t& t, std::pair<int, int> v) { t.bu_grain = v.first; }
@@ -210,7 +211,7 @@ bool same_tuning(const rbfs_tuning_t& a, const rbfs_tuning_t& b) {
 // root once into the candidate buffers and returns the mismatch count,
 // timed(reps) runs the timed repetitions and returns mean ms per call.
 template <class Apply, class Check, class Timed>
-int descend(const std::vector<Dim>& dims, rbfs_tuning_t start, Apply apply, Check check,
+int descend(int kind, const std::vector<Dim>& dims, rbfs_tuning_t start, Apply apply, Check check,
             Timed timed, int reps, rbfs_tuning_t* best_out, rbfs_tune_record_t* records,
             int32_t cap, int32_t* count, bool* any_mismatch) {
   int nrec = 0;
@@ -239,7 +240,7 @@ int descend(const std::vector<Dim>& dims, rbfs_tuning_t start, Apply apply, Chec
     for (const auto& v : d.values) {
       rbfs_tuning_t t = best;
       d.set(t, v);
-      if (same_tuning(t, best)) continue;
+      if (same_tuning(t, best) || !rbfs::tuning_valid(kind, t, nullptr)) continue;
       float ms = 0.f;
       rc = evaluate(t, &ms, &mism);
       if (rc) return rc;
@@ -432,7 +433,8 @@ int rbfs_tune(rbfs_graph_t* h, int32_t kind, const int32_t* roots, int32_t k, in
     dims.push_back({"bu_grain", {{8, 0}, {16, 0}, {32, 0}, {64, 0}, {128, 0}, {256, 0},
                                  {512, 0}, {1024, 0}},
                     set_grain});
-    dims.push_back({"td_chunk", {{256, 0}, {512, 0}, {1024, 0}}, set_chunk});
+    dims.push_back({"td_chunk", {{256, 0}, {512, 0}, {1024, 0}, {2048, 0}, {4096, 0}},
+                    set_chunk});
     if (g->reordered && o.output_space == RBFS_OUT_ORIGINAL)
       dims.push_back({"reset", {{0, 0}, {1, 0}}, set_reset});
   } else {
@@ -458,7 +460,7 @@ int rbfs_tune(rbfs_graph_t* h, int32_t kind, const int32_t* roots, int32_t k, in
             v.end());
   }
   bool mismatch = false;
-  rc = descend(dims, def, apply, check, timed, reps, best, records, cap, count, &mismatch);
+  rc = descend(kind, dims, def, apply, check, timed, reps, best, records, cap, count, &mismatch);
   if (rc) return rc;
   if (mismatch) {
     set_error("rbfs_tune: a candidate's outputs differ from the reference (see records)");
@@ -570,7 +572,8 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
                          [&](std::pair<int, int> s) { return s.second > m->eng.max_per_cu; }),
           v.end());
   bool mismatch = false;
-  rc = descend(dims, def, apply, check, timed, reps, best, records, cap, count, &mismatch);
+  rc = descend(RBFS_TUNE_BATCH, dims, def, apply, check, timed, reps, best, records, cap, count,
+               &mismatch);
   if (rc) return rc;
   if (mismatch) {
     set_error("rbfs_multi_tune: a candidate's outputs differ from the reference (see records)");

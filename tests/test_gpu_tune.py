@@ -35,8 +35,8 @@ def kron(rb):
 
 
 SINGLE_SETTINGS = [
-    dict(block=256, per_cu=1),
-    dict(block=256, per_cu=4),
+    dict(block=256, per_cu=1, td_chunk=512),
+    dict(block=256, per_cu=4, td_chunk=1024),
     dict(block=1024, per_cu=2),
     dict(lane_row=1),
     dict(lane_row=4096),
@@ -44,8 +44,12 @@ SINGLE_SETTINGS = [
     dict(bu_grain=1024),
     dict(td_chunk=256),
     dict(td_chunk=512),
+    dict(td_chunk=1024),
+    dict(td_chunk=2048),
+    dict(block=256, per_cu=2, td_chunk=1024),
     dict(reset=0),
     dict(block=256, per_cu=2, lane_row=8, bu_grain=4, td_chunk=256, reset=0),
+    dict(block=1024, per_cu=1, lane_row=256, bu_grain=256, td_chunk=4096, reset=1),
 ]
 
 
@@ -101,7 +105,8 @@ def test_batch_settings_are_exact(rb, kron, setting):
 
 @pytest.mark.parametrize("bad", [dict(block=512), dict(per_cu=0), dict(per_cu=5),
                                  dict(lane_row=0), dict(bu_grain=2000), dict(td_chunk=128),
-                                 dict(reset=2)])
+                                 dict(td_chunk=3072), dict(td_chunk=8192),
+                                 dict(block=256, td_chunk=2048), dict(reset=2)])
 def test_invalid_tuning_is_rejected(rb, kron, bad):
     G = kron[2]
     before = G.get_tuning()
@@ -142,7 +147,8 @@ def test_tuner_batch(rb, kron):
     roots_b = list(graphgen.sample_roots(off, 64, 9))
     best, recs = G.tune(roots_b, kind=rb.TUNE_BATCH, reps=1)
     assert all(r["mismatches"] == 0 for r in recs)
-    assert all(r["block"] == 1024 and r["td_chunk"] == 1024 for r in recs)
+    t0 = rb.default_tuning(rb.TUNE_BATCH)
+    assert all(r["block"] == 1024 and r["td_chunk"] == t0["td_chunk"] for r in recs)
     assert G.get_tuning(rb.TUNE_BATCH) == best
     d, p = G.bfs_batch(roots_b)
     for j in (0, 63):
