@@ -256,7 +256,8 @@ int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const 
   g->nnz = nnz;
   g->n_sweep = n;
   API_CHECK(hipMalloc(&g->off, sizeof(int64_t) * (size_t)(n + 1)));
-  API_CHECK(hipMalloc(&g->cols, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)));
+  // kColPad entries of slack: row scans read whole aligned 16-byte groups
+  API_CHECK(hipMalloc(&g->cols, sizeof(int32_t) * (size_t)(nnz + rbfs::kColPad)));
   g->bytes = sizeof(int64_t) * (size_t)(n + 1) + sizeof(int32_t) * (size_t)nnz;
   API_CHECK(hipMemcpyAsync(g->off, row_offsets, sizeof(int64_t) * (size_t)(n + 1), kind, stream));
   if (nnz > 0)

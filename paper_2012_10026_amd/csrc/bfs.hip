@@ -84,7 +84,8 @@ constexpr int kStage = 256;  // staged appends per wave
 // serialises the appends of every wave on one address.
 constexpr int kNQ = 8;
 constexpr int kListRange = 64;  // list vertices per bottom-up work range
-constexpr int kScanStep = 8;    // row entries a lane tests per step
+constexpr int kScanStep = 8;    // row entries a lane tests per step (after the first)
+static_assert(kScanStep == 8, "the row scan loads two aligned groups of 4 entries");
 constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
 
 struct BfsParams {
@@ -121,6 +122,16 @@ struct BfsParams {
   uint64_t timeout_ticks;
   const float* sw;       // learned-switch blob (RBFS_DIR_LEARNED)
   BfsCtl* ctl;
+};
+
+// LDS shared by the two step kinds: the chunk staging of the top-down
+// expansion, or the coarse frontier summary of a sparse bottom-up level (a
+// bit per 2^fs vertices).
+template <int BLOCK>
+union StepLds {
+  static constexpr int kFiltWords = BLOCK >= 1024 ? 16384 : 4096;
+  ChunkLdsB<kTdK * BLOCK> chunk;
+  uint32_t filt[kFiltWords];
 };
 
 template <int WAVES>
@@ -267,17 +278,24 @@ __device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long l
 // once, so a long row keeps only its own lane busy instead of stalling the
 // other 63.  Each lane also holds the candidate after its current one with
 // its row bounds already loaded, so taking it over costs no extra memory
-// round trip.  Each row gets the same ascending first-hit scan: kScanStep
-// entries per step (their loads are independent, so one pair of memory round
-// trips covers them all), rows longer than lane_row by the whole wave in one
-// go.  cand(t)
+// round trip.  Each row gets the same ascending first-hit scan in steps over
+// aligned groups of 4 entries (one 16-byte load each): one group on a row's
+// first step, since rows facing a dense frontier mostly hit at once, two
+// groups on later steps; the probes of a step are independent, so one pair
+// of memory round trips covers them all.  Rows longer than lane_row are
+// scanned by the whole wave in one go.  filt (LDS, used when use_filt) is a
+// coarse summary of bits that rules out most probes when the frontier is
+// sparse.
+// cand(t)
 // gives candidate t's vertex (t < 0: none), or -1 to skip it; it is called
 // by all lanes.  done(fin, found, v, par, deg) is called by all lanes after
 // every step; fin marks the lanes that finished a candidate in it.
 template <class Cand, class Done>
 __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const int32_t* cols,
-                                            const uint64_t* bits, int lane_row,
-                                            int64_t& examined, Cand&& cand, Done&& done) {
+                                            const uint64_t* bits, const uint32_t* filt,
+                                            bool use_filt, int fs,
+                                            int lane_row, int64_t& examined, Cand&& cand,
+                                            Done&& done) {
   int next = 0;  // next candidate to hand out (same in every lane)
   bool busy = false, queued = false;
   int64_t v = 0, b = 0, j = 0, e = 0;  // current candidate
@@ -310,16 +328,30 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     const bool hub = fresh && (e - b) > lane_row;
     bool found = false;
     int32_t par = 0;
-    wave_hub_first_hit(hub, b, e, cols, bits, found, par, examined);
+    wave_hub_first_hit(hub, b, e, cols, bits, filt, use_filt, fs, found, par, examined);
     bool fin = hub;
     if (busy && !hub) {
+      // entries [ja, ja + span): entries below j (the previous row) and from
+      // e on are masked; reads past the last row stay inside the column
+      // array's slack
+      const int64_t ja = j & ~(int64_t)3;
+      const bool wide = j != b;
+      const int span = wide ? kScanStep : 4;
       int32_t w[kScanStep];
       bool h[kScanStep];
+      {
+        const int4 x = *(const int4*)(cols + ja);
+        int4 y = make_int4(0, 0, 0, 0);
+        if (wide) y = *(const int4*)(cols + ja + 4);
+        w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
+        w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
+      }
 #pragma unroll
-      for (int q = 0; q < kScanStep; ++q) w[q] = (j + q < e) ? cols[j + q] : 0;
-#pragma unroll
-      for (int q = 0; q < kScanStep; ++q)
-        h[q] = (j + q < e) && test_bit(bits, (uint32_t)w[q]);
+      for (int q = 0; q < kScanStep; ++q) {
+        bool in = q < span && ja + q >= j && ja + q < e;
+        if (use_filt) in = in && lds_bit(filt, (uint32_t)w[q] >> fs);
+        h[q] = in && test_bit(bits, (uint32_t)w[q]);
+      }
       int hq = kScanStep;
 #pragma unroll
       for (int q = kScanStep - 1; q >= 0; --q)
@@ -330,10 +362,10 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
       if (hq < kScanStep) {
         found = true;
         fin = true;
-        examined += hq + 1;
+        examined += ja + hq + 1 - j;
       } else {
-        examined += (e - j < kScanStep) ? (e - j) : kScanStep;
-        j += kScanStep;
+        examined += ((ja + span < e) ? ja + span : e) - j;
+        j = ja + span;
         fin = j >= e;
       }
     }
@@ -353,7 +385,8 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
-  __shared__ ChunkLdsB<kTdK * BLOCK> s_chunk;
+  __shared__ StepLds<BLOCK> s_step;
+  constexpr int kFiltBits = StepLds<BLOCK>::kFiltWords * 32;
   __shared__ StageLds<WAVES> s_st;
   // sizes of the current frontier's sub-queues and of the last vertex list's
   // sub-lists (the same in every workgroup)
@@ -365,6 +398,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   const bool root_in = root < P.n_sweep;
   const int64_t W = ceil_div(P.n_sweep, kWave);
   const uint64_t emask = (1ull << P.eb) - 1ull;
+  int fs = 0;  // coarse summary: vertices per bit = 2^fs
+  while ((((P.n_sweep - 1) >> fs) + 1) > kFiltBits) ++fs;
   const int l = lane_id();
   if (threadIdx.x < WAVES) {
     s_st.cnt[threadIdx.x] = 0;
@@ -477,7 +512,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           nq_ch = ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
         }
         const bool ok = expand_chunk_batch<BLOCK, kTdK>(
-            s_chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride, P.qe[qc] + q * P.qstride,
+            s_step.chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride, P.qe[qc] + q * P.qstride,
             s_qcnt[q], P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols, P.cshift,
             [&](const bool* act, const int32_t* u, const int32_t* w) {
           // w is a candidate if unvisited at level start; it then proposes
@@ -535,6 +570,22 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       unsigned long long* vlcnt = &ctl->vlcnt[n3][0][0];
       // fold F_d into vis here: the list walk visits no words
       if (listed) fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
+      // a sparse frontier: each workgroup builds the coarse summary of F_d
+      // from the frontier queue, so that most row entries skip their probe
+      const bool use_filt = (nf << fs) <= P.n_sweep;
+      if (use_filt) {
+        uint32_t* f = s_step.filt;
+        for (int i = threadIdx.x; i < StepLds<BLOCK>::kFiltWords; i += BLOCK) f[i] = 0u;
+        __syncthreads();
+        for (int q = 0; q < kNQ; ++q) {
+          const int32_t* qv = P.qv[qc] + q * P.qstride;
+          for (int64_t i = threadIdx.x; i < s_qcnt[q]; i += BLOCK) {
+            const uint32_t k = (uint32_t)qv[i] >> fs;
+            atomicOr(&f[k >> 5], 1u << (k & 31));
+          }
+        }
+        __syncthreads();
+      }
       int64_t nranges = P.n_part;
       if (listed) {
         nranges = 0;
@@ -557,7 +608,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           const int64_t i0 = q * P.qstride + lr * kListRange;
           const int total = (int)std::min<int64_t>(kListRange, s_lcnt[q] - lr * kListRange);
           refill_scan(
-              total, P.off, P.cols, fcur, P.lane_row, examined,
+              total, P.off, P.cols, fcur, s_step.filt, use_filt, fs, P.lane_row, examined,
               [&](int t) -> int64_t {
                 if (t < 0) return -1;
                 const int32_t u = vl_in[i0 + t];
@@ -596,7 +647,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           s_st.found[wv][l] = 0ull;
           __builtin_amdgcn_wave_barrier();
           refill_scan(
-              total, P.off, P.cols, fcur, P.lane_row, examined,
+              total, P.off, P.cols, fcur, s_step.filt, use_filt, fs, P.lane_row, examined,
               [&](int t) -> int64_t {
                 // the word holding the t-th unvisited vertex of the batch:
                 // the first lane whose inclusive count exceeds t

@@ -276,8 +276,17 @@ __device__ __forceinline__ int64_t next_range(unsigned long long* ctrs, int64_t 
 // the first hit (in row order).  Sets found / par on the hub lanes; adds the
 // entries read (up to and including the hit) to lane 0's `examined`.  All
 // lanes must call.
+// filt (LDS, used when use_filt): a coarse summary of bits, bit k set when
+// any of the vertices [k << fs, (k + 1) << fs) is set; entries it rules out
+// skip the probe of bits.
+__device__ __forceinline__ bool lds_bit(const uint32_t* filt, uint32_t k) {
+  return (filt[k >> 5] >> (k & 31)) & 1u;
+}
+
 __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t e,
                                                    const int32_t* cols, const uint64_t* bits,
+                                                   const uint32_t* filt, bool use_filt,
+                                                   int fs,
                                                    bool& found, int32_t& par,
                                                    int64_t& examined) {
   const int l = lane_id();
@@ -295,7 +304,7 @@ __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t 
       bool hit = false;
       if (j < he) {
         w = cols[j];
-        hit = test_bit(bits, (uint32_t)w);
+        hit = (!use_filt || lds_bit(filt, (uint32_t)w >> fs)) && test_bit(bits, (uint32_t)w);
       }
       const uint64_t hm = ballot(hit);
       if (hm) {

@@ -21,6 +21,10 @@ constexpr int kMinChunkShift = 8;               // smallest (tunable)
 // entries.
 constexpr int kTdK = 4;
 
+// Slack entries after a graph's column array: the bottom-up row scans read
+// aligned groups of 4 entries and may read up to 7 entries past a row's end.
+constexpr int kColPad = 16;
+
 // Built-in defaults of the tunable parameters and their check.
 rbfs_tuning_t default_tuning(int kind);
 bool tuning_valid(int kind, const rbfs_tuning_t& t, std::string* why);

@@ -531,7 +531,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   uint64_t* k1 = keys;
   uint64_t* k2 = keys2;
   RCM_CHECK(radix_sort_u64(&k1, &k2, nnz, 0, 2 * bn, g->scratch, stream));
-  RCM_CHECK(B.alloc(&newcols, nnz));
+  RCM_CHECK(B.alloc(&newcols, nnz + kColPad));  // slack for aligned group reads
   hipLaunchKernelGGL(keys_to_cols_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, k1, nnz,
                      bn, newcols);
   RCM_CHECK(hipGetLastError());
