@@ -33,6 +33,7 @@
 #ifndef RBFS_H
 #define RBFS_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -144,6 +145,26 @@ const char* rbfs_last_error(void);
 
 /* Current HIP device; RBFS_E_NODEV when there is none. */
 int rbfs_device_info(rbfs_device_info_t* out);
+
+/* Device memory of the library (graph arrays, search workspaces, batch
+ * engines, per-call temporaries) comes from hipMalloc/hipFree unless an
+ * allocator is installed here, e.g. a framework's caching allocator, so that
+ * the caller's memory pool accounts for it (not in the paper: plumbing of the
+ * boundary).  alloc(bytes, stream, ctx) returns device memory of at least
+ * `bytes` bytes, or NULL on failure (the library call then returns
+ * RBFS_E_NOMEM); `stream` is the stream of the library call that asks for it
+ * (NULL: the NULL stream).  free_fn(ptr, stream, ctx) releases a block that
+ * alloc returned; the library has synchronised the work that used it, except
+ * for blocks freed on the stream of the call that used them.  Pass NULL for
+ * both to return to hipMalloc/hipFree.  Process-wide; allowed only while no
+ * graph or multi-graph handle exists (else RBFS_E_STATE), so that every block
+ * goes back to the allocator that made it, and not while another library call
+ * runs.  Both functions must be given or neither (else RBFS_E_INVAL).  The
+ * learned-switch parameters uploaded by rbfs_switch_load keep using hipMalloc:
+ * they live until the process ends. */
+typedef void* (*rbfs_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*rbfs_free_fn)(void* ptr, void* stream, void* ctx);
+int rbfs_set_allocator(rbfs_alloc_fn alloc, rbfs_free_fn free_fn, void* ctx);
 
 /* Create a graph handle on the current HIP device from a canonical undirected
  * CSR (section 3.1, Eq. 2): row_offsets[n+1] (int64, row_offsets[0] = 0,

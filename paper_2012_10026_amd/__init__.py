@@ -6,8 +6,10 @@ HIP kernels.  PyTorch supplies device memory and streams.  The library must
 have been built (``python -m paper_2012_10026_amd._build``); importing the
 binding without it raises, there is no fallback.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -105,6 +107,7 @@ SIGNATURES = {
     "rbfs_last_error": (ctypes.c_char_p, []),
     "rbfs_device_info": (ctypes.c_int, [_P]),
     "rbfs_graph_create": (ctypes.c_int, [_I64, _I64, _P, _P, ctypes.c_uint32, _P, _P]),
+    "rbfs_set_allocator": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_graph_destroy": (ctypes.c_int, [_P]),
     "rbfs_graph_info": (ctypes.c_int, [_P, _P]),
     "rbfs_graph_check": (ctypes.c_int, [_P, _P]),
@@ -134,6 +137,33 @@ SIGNATURES = {
 
 _lib = None
 
+# Device memory of the library: torch's caching allocator by default (set
+# RBFS_ALLOCATOR=hip for hipMalloc/hipFree).  The callbacks run on the thread
+# of the library call that needs memory.
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+def _torch_alloc(nbytes, stream, ctx):
+    import torch
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(),
+                                                  int(stream) if stream else None)
+    except Exception:  # out of memory: the library call returns RBFS_E_NOMEM
+        return None
+
+
+def _torch_free(ptr, stream, ctx):
+    import torch
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_torch_alloc_cb = _ALLOC_FN(_torch_alloc)
+_torch_free_cb = _FREE_FN(_torch_free)
+_allocator = "hip"
+_live_graphs = weakref.WeakSet()
+_live_multis = weakref.WeakSet()
+
 
 def lib():
     """Load librbfs.so; raises if it has not been built."""
@@ -149,7 +179,38 @@ def lib():
             f.restype = res
             f.argtypes = args
         _lib = L
+        if os.environ.get("RBFS_ALLOCATOR", "torch") != "hip":
+            set_allocator("torch")
     return _lib
+
+
+def set_allocator(kind):
+    """'torch': the library's device memory comes from torch's caching
+    allocator (counted by torch.cuda.memory_allocated); 'hip': hipMalloc.
+    Only while no Graph or MultiGraph is open."""
+    global _allocator
+    if kind == "torch":
+        rc = lib().rbfs_set_allocator(ctypes.cast(_torch_alloc_cb, ctypes.c_void_p),
+                                      ctypes.cast(_torch_free_cb, ctypes.c_void_p), None)
+    elif kind == "hip":
+        rc = lib().rbfs_set_allocator(None, None, None)
+    else:
+        raise ValueError("allocator must be 'torch' or 'hip'")
+    _check(rc)
+    _allocator = kind
+
+
+def allocator():
+    return _allocator
+
+
+@atexit.register
+def _close_all():
+    # release library memory while torch's allocator is still alive
+    for m in list(_live_multis):
+        m.close()
+    for g in list(_live_graphs):
+        g.close()
 
 
 def _check(rc):
@@ -244,6 +305,7 @@ class Graph:
         self.nnz = nnz
         _check(lib().rbfs_graph_create(n, nnz, p_off, p_cols, flags, _stream_ptr(self.device),
                                        ctypes.byref(self._h)))
+        _live_graphs.add(self)
 
     def close(self):
         if self._h:
@@ -364,6 +426,7 @@ class MultiGraph:
         self.device = self.graphs[0].device
         _check(lib().rbfs_multi_create(arr, len(self.graphs), _stream_ptr(self.device),
                                        ctypes.byref(self._h)))
+        _live_multis.add(self)
 
     def close(self):
         if self._h:

@@ -4,6 +4,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -123,6 +125,29 @@ int device_ok() {
     }                                                                           \
   } while (0)
 
+// ---- device memory: hipMalloc/hipFree or the caller's allocator
+namespace {
+std::mutex s_alloc_mu;
+rbfs_alloc_fn s_alloc = nullptr;
+rbfs_free_fn s_free = nullptr;
+void* s_alloc_ctx = nullptr;
+std::atomic<long long> s_live{0};
+}  // namespace
+
+hipError_t dev_malloc(void** p, size_t bytes, hipStream_t stream) {
+  if (!s_alloc) return hipMalloc(p, bytes);
+  *p = s_alloc(bytes > 0 ? bytes : 1, (void*)stream, s_alloc_ctx);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
+void dev_free(void* p, hipStream_t stream) {
+  if (!p) return;
+  if (s_free) s_free(p, (void*)stream, s_alloc_ctx);
+  else (void)hipFree(p);
+}
+
+void live_handles_add(int d) { s_live += d; }
+
 static int graph_setup(Graph* g, uint32_t flags, hipStream_t stream) {
   int rc = 0;
   int* d_flags = nullptr;
@@ -130,8 +155,8 @@ static int graph_setup(Graph* g, uint32_t flags, hipStream_t stream) {
   int hflags = 0;
   unsigned long long hstats[2] = {0, 0};
   const int64_t n = g->n, nnz = g->nnz;
-  API_CHECK(hipMalloc(&d_flags, sizeof(int)));
-  API_CHECK(hipMalloc(&d_stats, 2 * sizeof(unsigned long long)));
+  API_CHECK(rbfs::dev_malloc(&d_flags, sizeof(int)));
+  API_CHECK(rbfs::dev_malloc(&d_stats, 2 * sizeof(unsigned long long)));
   API_CHECK(hipMemsetAsync(d_flags, 0, sizeof(int), stream));
   API_CHECK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), stream));
   hipLaunchKernelGGL(check_offsets_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n,
@@ -172,8 +197,8 @@ static int graph_setup(Graph* g, uint32_t flags, hipStream_t stream) {
   g->max_degree = (int64_t)hstats[0];
   g->n_plus = (int64_t)hstats[1];
 fail:
-  if (d_flags) (void)hipFree(d_flags);
-  if (d_stats) (void)hipFree(d_stats);
+  if (d_flags) (void)rbfs::dev_free(d_flags);
+  if (d_stats) (void)rbfs::dev_free(d_stats);
   return rc;
 }
 
@@ -207,6 +232,22 @@ int rbfs_device_info(rbfs_device_info_t* out) {
   out->global_mem_bytes = (int64_t)p.totalGlobalMem;
   out->l2_bytes = p.l2CacheSize;
   strncpy(out->arch, p.gcnArchName, sizeof(out->arch) - 1);
+  return RBFS_OK;
+}
+
+int rbfs_set_allocator(rbfs_alloc_fn alloc, rbfs_free_fn free_fn, void* ctx) {
+  if ((alloc == nullptr) != (free_fn == nullptr)) {
+    set_error("rbfs_set_allocator: give both functions or neither");
+    return RBFS_E_INVAL;
+  }
+  std::lock_guard<std::mutex> lock(rbfs::s_alloc_mu);
+  if (rbfs::s_live.load() != 0) {
+    set_error("rbfs_set_allocator: graph or multi-graph handles still exist");
+    return RBFS_E_STATE;
+  }
+  rbfs::s_alloc = alloc;
+  rbfs::s_free = free_fn;
+  rbfs::s_alloc_ctx = alloc ? ctx : nullptr;
   return RBFS_OK;
 }
 
@@ -255,20 +296,21 @@ int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const 
   g->n = n;
   g->nnz = nnz;
   g->n_sweep = n;
-  API_CHECK(hipMalloc(&g->off, sizeof(int64_t) * (size_t)(n + 1)));
+  API_CHECK(rbfs::dev_malloc(&g->off, sizeof(int64_t) * (size_t)(n + 1)));
   // kColPad entries of slack: row scans read whole aligned 16-byte groups
-  API_CHECK(hipMalloc(&g->cols, sizeof(int32_t) * (size_t)(nnz + rbfs::kColPad)));
+  API_CHECK(rbfs::dev_malloc(&g->cols, sizeof(int32_t) * (size_t)(nnz + rbfs::kColPad)));
   g->bytes = sizeof(int64_t) * (size_t)(n + 1) + sizeof(int32_t) * (size_t)nnz;
   API_CHECK(hipMemcpyAsync(g->off, row_offsets, sizeof(int64_t) * (size_t)(n + 1), kind, stream));
   if (nnz > 0)
     API_CHECK(hipMemcpyAsync(g->cols, cols, sizeof(int32_t) * (size_t)nnz, kind, stream));
   rc = rbfs::graph_setup(g, flags, stream);
   if (rc) goto fail;
+  rbfs::live_handles_add(1);
   *out = h;
   return RBFS_OK;
 fail:
-  if (g->off) (void)hipFree(g->off);
-  if (g->cols) (void)hipFree(g->cols);
+  if (g->off) (void)rbfs::dev_free(g->off);
+  if (g->cols) (void)rbfs::dev_free(g->cols);
   delete h;
   return rc ? rc : RBFS_E_DEVICE;
 }
@@ -277,16 +319,19 @@ int rbfs_graph_destroy(rbfs_graph_t* h) {
   if (!h) return RBFS_OK;
   Graph* g = &h->g;
   (void)hipSetDevice(g->device);
+  // work still queued on any stream may use the memory released below
+  (void)hipDeviceSynchronize();
   rbfs::free_bfs_work(g);
   rbfs::free_ms_work(g);
   g->scratch.release();
   g->timing.destroy();
-  if (g->off) (void)hipFree(g->off);
-  if (g->cols) (void)hipFree(g->cols);
-  if (g->perm) (void)hipFree(g->perm);
-  if (g->iperm) (void)hipFree(g->iperm);
-  if (g->comp_bounds) (void)hipFree(g->comp_bounds);
+  if (g->off) (void)rbfs::dev_free(g->off);
+  if (g->cols) (void)rbfs::dev_free(g->cols);
+  if (g->perm) (void)rbfs::dev_free(g->perm);
+  if (g->iperm) (void)rbfs::dev_free(g->iperm);
+  if (g->comp_bounds) (void)rbfs::dev_free(g->comp_bounds);
   delete h;
+  rbfs::live_handles_add(-1);
   return RBFS_OK;
 }
 
@@ -507,6 +552,7 @@ int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream_,
     delete m;
     return rc;
   }
+  rbfs::live_handles_add(1);
   *out = m;
   return RBFS_OK;
 }
@@ -514,9 +560,11 @@ int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream_,
 int rbfs_multi_destroy(rbfs_multi_t* m) {
   if (!m) return RBFS_OK;
   (void)hipSetDevice(m->device);
+  (void)hipDeviceSynchronize();
   rbfs::ms_engine_free(&m->eng);
   if (m->own_stream) (void)hipStreamDestroy(m->own_stream);
   delete m;
+  rbfs::live_handles_add(-1);
   return RBFS_OK;
 }
 
@@ -662,8 +710,8 @@ int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k,
   int32_t cnt = 0;
   rbfs_stats_t sh, st;
   std::vector<std::vector<float>> ttd, tbu;
-  API_CHECK(hipMalloc(&dd, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
-  API_CHECK(hipMalloc(&dp, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+  API_CHECK(rbfs::dev_malloc(&dd, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
+  API_CHECK(rbfs::dev_malloc(&dp, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
   for (int32_t j = 0; j < k && cnt < cap; ++j) {
     rc = rbfs::bfs_impl(g, roots[j], dd, dp, RBFS_DIR_HEURISTIC, alpha, beta, nullptr, 0,
                         RBFS_OUT_INTERNAL, 0, 0, stream, &sh);
@@ -698,8 +746,8 @@ int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k,
   }
   *count = cnt;
 fail:
-  if (dd) (void)hipFree(dd);
-  if (dp) (void)hipFree(dp);
+  if (dd) (void)rbfs::dev_free(dd);
+  if (dp) (void)rbfs::dev_free(dp);
   return rc;
 }
 

@@ -834,7 +834,7 @@ void free_bfs_work(Graph* g) {
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
                 w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1]};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
   if (w->ev1) (void)hipEventDestroy(w->ev1);
   if (w->ev2) (void)hipEventDestroy(w->ev2);
@@ -858,19 +858,19 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   const int64_t ns = g->n_sweep > 0 ? g->n_sweep : 1;
   const int64_t W = ceil_div(ns, kWave);
   w->n_sweep = g->n_sweep;
-  BFS_CHECK(hipMalloc(&w->dp, sizeof(uint64_t) * ns));
-  BFS_CHECK(hipMalloc(&w->vis, sizeof(uint64_t) * W));
-  BFS_CHECK(hipMalloc(&w->front, sizeof(uint64_t) * 3 * W));
+  BFS_CHECK(rbfs::dev_malloc(&w->dp, sizeof(uint64_t) * ns));
+  BFS_CHECK(rbfs::dev_malloc(&w->vis, sizeof(uint64_t) * W));
+  BFS_CHECK(rbfs::dev_malloc(&w->front, sizeof(uint64_t) * 3 * W));
   // every sub-queue and sub-list can hold the whole swept set
-  for (int i = 0; i < 2; ++i) BFS_CHECK(hipMalloc(&w->vl[i], sizeof(int32_t) * kNQ * ns));
+  for (int i = 0; i < 2; ++i) BFS_CHECK(rbfs::dev_malloc(&w->vl[i], sizeof(int32_t) * kNQ * ns));
   for (int i = 0; i < 2; ++i) {
-    BFS_CHECK(hipMalloc(&w->qv[i], sizeof(int32_t) * kNQ * ns));
-    BFS_CHECK(hipMalloc(&w->qe[i], sizeof(int64_t) * kNQ * ns));
+    BFS_CHECK(rbfs::dev_malloc(&w->qv[i], sizeof(int32_t) * kNQ * ns));
+    BFS_CHECK(rbfs::dev_malloc(&w->qe[i], sizeof(int64_t) * kNQ * ns));
   }
   w->chunk_cap = ceil_div(g->nnz, (int64_t)1 << kMinChunkShift) + 2;
   for (int i = 0; i < 2; ++i)
-    BFS_CHECK(hipMalloc(&w->chunk[i], sizeof(int32_t) * kNQ * w->chunk_cap));
-  BFS_CHECK(hipMalloc(&w->ctl, sizeof(BfsCtl)));
+    BFS_CHECK(rbfs::dev_malloc(&w->chunk[i], sizeof(int32_t) * kNQ * w->chunk_cap));
+  BFS_CHECK(rbfs::dev_malloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
   int per_cu = 0;
   BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel<1024>,
@@ -882,7 +882,7 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
   w->grid = g->compute_units;
   w->max_grid = 4 * g->compute_units;  // per_cu is at most 4
-  BFS_CHECK(hipMalloc(&w->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)w->max_grid));
+  BFS_CHECK(rbfs::dev_malloc(&w->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)w->max_grid));
   BFS_CHECK(hipEventCreate(&w->ev0));
   BFS_CHECK(hipEventCreate(&w->ev1));
   BFS_CHECK(hipEventCreate(&w->ev2));
@@ -911,7 +911,7 @@ static int ensure_bfs_parts(Graph* g, hipStream_t stream) {
   tuned_shape(g, w, &block, &grid);
   const int grain = g->tune_single.bu_grain;
   if (w->bu_part && w->part_grain == grain && w->part_grid == grid) return 0;
-  if (w->bu_part) (void)hipFree(w->bu_part);
+  if (w->bu_part) (void)rbfs::dev_free(w->bu_part);
   w->bu_part = nullptr;
   w->n_part = 0;
   int rc = build_edge_ranges(g->off, g->n_sweep, g->nnz, (int64_t)grain * grid, kWave,

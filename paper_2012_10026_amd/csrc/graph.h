@@ -25,6 +25,18 @@ constexpr int kTdK = 4;
 // aligned groups of 4 entries and may read up to 7 entries past a row's end.
 constexpr int kColPad = 16;
 
+// Device memory of graphs, engines, workspaces and call temporaries: hipMalloc
+// and hipFree, or the allocator installed with rbfs_set_allocator.  stream is
+// the stream the memory will be used on (NULL: the NULL stream).
+hipError_t dev_malloc(void** p, size_t bytes, hipStream_t stream = nullptr);
+template <class T>
+hipError_t dev_malloc(T** p, size_t bytes, hipStream_t stream = nullptr) {
+  return dev_malloc(reinterpret_cast<void**>(p), bytes, stream);
+}
+void dev_free(void* p, hipStream_t stream = nullptr);
+// Live graph and multi-graph handles (the allocator may change only at 0).
+void live_handles_add(int d);
+
 // Built-in defaults of the tunable parameters and their check.
 rbfs_tuning_t default_tuning(int kind);
 bool tuning_valid(int kind, const rbfs_tuning_t& t, std::string* why);

@@ -195,12 +195,12 @@ __global__ void mlp_forward_kernel(const float* w, const float* x, int n, float*
 struct DevBufs {
   std::vector<void*> ps;
   ~DevBufs() {
-    for (void* p : ps) (void)hipFree(p);
+    for (void* p : ps) (void)rbfs::dev_free(p);
   }
   template <class T>
   hipError_t get(T** out, size_t count) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(T) * (count > 0 ? count : 1));
+    hipError_t e = rbfs::dev_malloc(&p, sizeof(T) * (count > 0 ? count : 1));
     if (e == hipSuccess) {
       ps.push_back(p);
       *out = (T*)p;
@@ -244,7 +244,7 @@ int rbfs_switch_load(const float* blob, int32_t n) {
   int dev = 0;
   ML_CHECK(hipGetDevice(&dev));
   if (rbfs::s_switch_dev && rbfs::s_switch_device != dev) {
-    (void)hipFree(rbfs::s_switch_dev);
+    (void)hipFree(rbfs::s_switch_dev);  // process lifetime
     rbfs::s_switch_dev = nullptr;
   }
   if (!rbfs::s_switch_dev) ML_CHECK(hipMalloc(&rbfs::s_switch_dev, sizeof(float) * n));

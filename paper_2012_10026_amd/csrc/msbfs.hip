@@ -660,7 +660,7 @@ void ms_engine_free(MsEngine* m) {
                 m->qv[1], m->qe[0], m->qe[1], m->chunk[0], m->chunk[1], m->bu_part, m->ctl,
                 m->roots_dev, m->wctr};
   for (void* p : ps)
-    if (p) (void)hipFree(p);
+    if (p) (void)rbfs::dev_free(p);
   m->uoff = nullptr;
   m->ucols = nullptr;
   m->uoid = nullptr;
@@ -691,18 +691,18 @@ void free_ms_work(Graph* g) {
 // (off, cols, oid, n_sweep, nnz filled in).
 int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipStream_t stream) {
   const int64_t ns = m->n_sweep > 0 ? m->n_sweep : 1;
-  MS_CHECK(hipMalloc(&m->vis, sizeof(uint64_t) * ns));
-  MS_CHECK(hipMalloc(&m->front, sizeof(uint64_t) * 3 * ns));
-  MS_CHECK(hipMalloc(&m->dp, sizeof(uint64_t) * 64 * ns));
+  MS_CHECK(rbfs::dev_malloc(&m->vis, sizeof(uint64_t) * ns));
+  MS_CHECK(rbfs::dev_malloc(&m->front, sizeof(uint64_t) * 3 * ns));
+  MS_CHECK(rbfs::dev_malloc(&m->dp, sizeof(uint64_t) * 64 * ns));
   for (int i = 0; i < 2; ++i) {
-    MS_CHECK(hipMalloc(&m->qv[i], sizeof(int32_t) * ns));
-    MS_CHECK(hipMalloc(&m->qe[i], sizeof(int64_t) * ns));
+    MS_CHECK(rbfs::dev_malloc(&m->qv[i], sizeof(int32_t) * ns));
+    MS_CHECK(rbfs::dev_malloc(&m->qe[i], sizeof(int64_t) * ns));
   }
   m->chunk_cap = ceil_div(m->nnz, kChunkEdges) + 2;
-  for (int i = 0; i < 2; ++i) MS_CHECK(hipMalloc(&m->chunk[i], sizeof(int32_t) * m->chunk_cap));
-  MS_CHECK(hipMalloc(&m->ctl, sizeof(MsCtl)));
+  for (int i = 0; i < 2; ++i) MS_CHECK(rbfs::dev_malloc(&m->chunk[i], sizeof(int32_t) * m->chunk_cap));
+  MS_CHECK(rbfs::dev_malloc(&m->ctl, sizeof(MsCtl)));
   MS_CHECK(hipMemsetAsync(m->ctl, 0, sizeof(MsCtl), stream));
-  MS_CHECK(hipMalloc(&m->roots_dev, sizeof(int32_t) * 64 * 2 * m->ngraphs));
+  MS_CHECK(rbfs::dev_malloc(&m->roots_dev, sizeof(int32_t) * 64 * 2 * m->ngraphs));
   MS_CHECK(hipHostMalloc(&m->roots_host, sizeof(int32_t) * 64 * (1 + m->ngraphs)));
   hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * ns)), dim3(256), 0, stream, m->dp,
                      64 * ns, ~0ull);
@@ -712,7 +712,7 @@ int ms_engine_setup(MsEngine* m, int compute_units, int64_t wall_rate_khz, hipSt
   m->max_per_cu = per_cu < 1 ? 1 : per_cu;
   m->compute_units = compute_units;
   m->max_grid = 4 * compute_units;  // per_cu is at most 4
-  MS_CHECK(hipMalloc(&m->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)m->max_grid));
+  MS_CHECK(rbfs::dev_malloc(&m->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)m->max_grid));
   MS_CHECK(hipEventCreate(&m->ev0));
   MS_CHECK(hipEventCreate(&m->ev1));
   MS_CHECK(hipStreamSynchronize(stream));
@@ -725,7 +725,7 @@ int ms_apply_tuning(MsEngine* m, const rbfs_tuning_t& t, hipStream_t stream) {
   const int grid = per * m->compute_units;
   if (!m->bu_part || t.bu_grain != m->tune.bu_grain || grid != m->grid) {
     // edge-balanced vertex ranges (in 64-vertex units) for the bottom-up pull
-    if (m->bu_part) (void)hipFree(m->bu_part);
+    if (m->bu_part) (void)rbfs::dev_free(m->bu_part);
     m->bu_part = nullptr;
     m->n_part = 0;
     int rc = build_edge_ranges(m->uoff ? m->uoff : m->off, m->n_sweep, m->nnz,
@@ -871,9 +871,9 @@ int ms_build_union(MsEngine* m, const Graph* const* gs, int count, hipStream_t s
   }
   m->n_sweep = ntot;
   m->nnz = etot;
-  MS_CHECK(hipMalloc(&m->uoff, sizeof(int64_t) * (ntot + 1)));
-  MS_CHECK(hipMalloc(&m->ucols, sizeof(int32_t) * (etot > 0 ? etot : 1)));
-  MS_CHECK(hipMalloc(&m->uoid, sizeof(int32_t) * (ntot > 0 ? ntot : 1)));
+  MS_CHECK(rbfs::dev_malloc(&m->uoff, sizeof(int64_t) * (ntot + 1)));
+  MS_CHECK(rbfs::dev_malloc(&m->ucols, sizeof(int32_t) * (etot > 0 ? etot : 1)));
+  MS_CHECK(rbfs::dev_malloc(&m->uoid, sizeof(int32_t) * (ntot > 0 ? ntot : 1)));
   int64_t ub = 0, eb = 0;
   for (int i = 0; i < count; ++i) {
     const Graph* g = gs[i];

@@ -12,17 +12,18 @@
 #include <hip/hip_runtime.h>
 
 #include "common.cuh"
+#include "graph.h"
 #include "prim.h"
 
 namespace rbfs {
 
 hipError_t Scratch::get(size_t need, void** out) {
   if (need > bytes) {
-    if (ptr) (void)hipFree(ptr);
+    if (ptr) (void)rbfs::dev_free(ptr);
     ptr = nullptr;
     bytes = 0;
     size_t want = need + need / 4 + 256;
-    hipError_t e = hipMalloc(&ptr, want);
+    hipError_t e = rbfs::dev_malloc(&ptr, want);
     if (e != hipSuccess) {
       ptr = nullptr;
       return e;
@@ -34,7 +35,7 @@ hipError_t Scratch::get(size_t need, void** out) {
 }
 
 void Scratch::release() {
-  if (ptr) (void)hipFree(ptr);
+  if (ptr) (void)rbfs::dev_free(ptr);
   ptr = nullptr;
   bytes = 0;
 }

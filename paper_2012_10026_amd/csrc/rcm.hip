@@ -319,12 +319,12 @@ __global__ void keys_to_cols_kernel(const uint64_t* keys, int64_t nnz, int bn, i
 struct Bufs {
   std::vector<void*> ptrs;
   ~Bufs() {
-    for (void* p : ptrs) (void)hipFree(p);
+    for (void* p : ptrs) (void)rbfs::dev_free(p);
   }
   template <class T>
   hipError_t alloc(T** out, int64_t count) {
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)(count > 0 ? count : 1));
+    hipError_t e = rbfs::dev_malloc(&p, sizeof(T) * (size_t)(count > 0 ? count : 1));
     if (e != hipSuccess) return e;
     ptrs.push_back(p);
     *out = (T*)p;
@@ -549,8 +549,8 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   if (ms_out) *ms_out = ms;
 
   // install: the handle takes ownership of the new CSR and the permutation
-  (void)hipFree(g->off);
-  (void)hipFree(g->cols);
+  (void)rbfs::dev_free(g->off);
+  (void)rbfs::dev_free(g->cols);
   g->off = newoff;
   g->cols = newcols;
   g->perm = perm;

@@ -103,7 +103,7 @@ int build_edge_ranges(const int64_t* off, int64_t n_sweep, int64_t nnz, int64_t 
   const int64_t nparts_e = std::max<int64_t>(1, ceil_div(nnz, target));
   const int64_t max_words = std::max<int64_t>(min_words, W / want + 1);
   int32_t* d_b = nullptr;
-  TUNE_CHECK(hipMalloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
+  TUNE_CHECK(rbfs::dev_malloc(&d_b, sizeof(int32_t) * (nparts_e + 1)));
   const int64_t blocks = std::min<int64_t>(ceil_div(nparts_e + 1, 256), 1 << 20);
   hipLaunchKernelGGL(edge_range_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, off,
                      n_sweep, target, nparts_e, d_b);
@@ -113,7 +113,7 @@ int build_edge_ranges(const int64_t* off, int64_t n_sweep, int64_t nnz, int64_t 
     e = hipMemcpyAsync(hb.data(), d_b, sizeof(int32_t) * (nparts_e + 1), hipMemcpyDeviceToHost,
                        stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  (void)hipFree(d_b);
+  (void)rbfs::dev_free(d_b);
   TUNE_CHECK(e);
   // split ranges that span too many (nearly empty) words
   std::vector<int32_t> parts{0};
@@ -127,11 +127,11 @@ int build_edge_ranges(const int64_t* off, int64_t n_sweep, int64_t nnz, int64_t 
   }
   if (parts.back() != (int32_t)W) parts.push_back((int32_t)W);
   int32_t* d = nullptr;
-  TUNE_CHECK(hipMalloc(&d, sizeof(int32_t) * parts.size()));
+  TUNE_CHECK(rbfs::dev_malloc(&d, sizeof(int32_t) * parts.size()));
   e = hipMemcpyAsync(d, parts.data(), sizeof(int32_t) * parts.size(), hipMemcpyHostToDevice,
                      stream);
   if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  if (e != hipSuccess) (void)hipFree(d);
+  if (e != hipSuccess) (void)rbfs::dev_free(d);
   TUNE_CHECK(e);
   *bounds = d;
   *n_part = (int32_t)parts.size() - 1;
@@ -156,7 +156,7 @@ struct TuneBuffers {
   ~TuneBuffers() {
     void* ps[] = {ref_d, ref_p, cand_d, cand_p, diff};
     for (void* p : ps)
-      if (p) (void)hipFree(p);
+      if (p) (void)rbfs::dev_free(p);
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
   }
@@ -365,11 +365,11 @@ int rbfs_tune(rbfs_graph_t* h, int32_t kind, const int32_t* roots, int32_t k, in
   const int64_t n = g->n > 0 ? g->n : 1;
   const int64_t cand_n = kind == RBFS_TUNE_SINGLE ? n : n * k;
   TuneBuffers B;
-  hipError_t e = hipMalloc(&B.ref_d, sizeof(int32_t) * n * k);
-  if (e == hipSuccess) e = hipMalloc(&B.ref_p, sizeof(int32_t) * n * k);
-  if (e == hipSuccess) e = hipMalloc(&B.cand_d, sizeof(int32_t) * cand_n);
-  if (e == hipSuccess) e = hipMalloc(&B.cand_p, sizeof(int32_t) * cand_n);
-  if (e == hipSuccess) e = hipMalloc(&B.diff, sizeof(unsigned long long));
+  hipError_t e = rbfs::dev_malloc(&B.ref_d, sizeof(int32_t) * n * k);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.ref_p, sizeof(int32_t) * n * k);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.cand_d, sizeof(int32_t) * cand_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.cand_p, sizeof(int32_t) * cand_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.diff, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipEventCreate(&B.e0);
   if (e == hipSuccess) e = hipEventCreate(&B.e1);
   if (e != hipSuccess) return hip_fail("allocate", e);
@@ -526,11 +526,11 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
   hipStream_t stream = stream_ ? (hipStream_t)stream_ : m->own_stream;
   const int64_t out_n = std::max<int64_t>(1, total * k);
   TuneBuffers B;
-  hipError_t e = hipMalloc(&B.ref_d, sizeof(int32_t) * out_n);
-  if (e == hipSuccess) e = hipMalloc(&B.ref_p, sizeof(int32_t) * out_n);
-  if (e == hipSuccess) e = hipMalloc(&B.cand_d, sizeof(int32_t) * out_n);
-  if (e == hipSuccess) e = hipMalloc(&B.cand_p, sizeof(int32_t) * out_n);
-  if (e == hipSuccess) e = hipMalloc(&B.diff, sizeof(unsigned long long));
+  hipError_t e = rbfs::dev_malloc(&B.ref_d, sizeof(int32_t) * out_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.ref_p, sizeof(int32_t) * out_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.cand_d, sizeof(int32_t) * out_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.cand_p, sizeof(int32_t) * out_n);
+  if (e == hipSuccess) e = rbfs::dev_malloc(&B.diff, sizeof(unsigned long long));
   if (e == hipSuccess) e = hipEventCreate(&B.e0);
   if (e == hipSuccess) e = hipEventCreate(&B.e1);
   if (e != hipSuccess) return hip_fail("allocate", e);

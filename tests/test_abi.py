@@ -84,3 +84,19 @@ def test_struct_sizes_match_header():
     """rbfs_opts_t layout the binding assumes: 4 x int32, pointer, 3 x int32."""
     assert ctypes.sizeof(rb.Opts) == 40
     assert rb.Opts.schedule.offset == 16 and rb.Opts.flags.offset == 32
+
+
+def test_set_allocator_arguments_without_device():
+    L = rb.lib()
+    cb = ctypes.cast(rb._torch_alloc_cb, ctypes.c_void_p)
+    # one function without the other
+    assert L.rbfs_set_allocator(cb, None, None) == -1
+    assert L.rbfs_set_allocator(None, cb, None) == -1
+    before = rb.allocator()
+    rb.set_allocator("hip")
+    assert rb.allocator() == "hip"
+    rb.set_allocator("torch")
+    assert rb.allocator() == "torch"
+    rb.set_allocator(before)
+    with pytest.raises(ValueError):
+        rb.set_allocator("cuda")
