@@ -260,6 +260,73 @@ def multi_batch(rb, graphgen, steps, cache=None, retune=False):
             "scales": "12..20", "tuning": tuned}
 
 
+ABLATION_GRAPHS = {
+    "kron22": ("kronecker", 22, 1022),
+    "kron24": ("kronecker", 24, 1024),
+    "kron26": ("kronecker", 26, 1026),
+    "chunglu": ("chung-lu", 50_000_000, 4000),
+}
+
+
+def ablation(rb, graphgen, args):
+    """Locality study: the same searches on the graph as generated (random
+    labels) and after RCM, on Kronecker scales 22-26 and the 52.5 M-vertex
+    Chung-Lu graph.  One JSON line per (graph, variant)."""
+    import torch
+    names = args.ablation_graphs.split(",")
+    variants = args.ablation_variants.split(",")
+    cache = rb.TuningCache(args.tuning_cache)
+    arch = rb.device_info()["arch"]
+    for name in names:
+        kind, size, seed = ABLATION_GRAPHS[name]
+        if kind == "kronecker":
+            off, cols = graphgen.kronecker_csr_device(size, 16, seed)
+        else:
+            off, cols = graphgen.chung_lu_csr_device(size, size // 20, seed=seed)
+        roots = graphgen.sample_roots_device(off, args.ablation_roots, args.root_seed)
+        n = off.numel() - 1
+        depth = torch.empty(n, dtype=torch.int32, device="cuda")
+        parent = torch.empty(n, dtype=torch.int32, device="cuda")
+        for variant in variants:
+            G = rb.Graph(off, cols)
+            rcm_ms = None
+            if variant == "rcm":
+                _, rcm_ms = G.rcm_reorder(want_perm=False)
+            t = cache.get(rb.tuning_key(arch, "kronecker", n, rb.TUNE_SINGLE))
+            if t is not None:
+                G.set_tuning(t)
+            plain = rb.make_opts(alpha=args.alpha, beta=args.beta)
+            timed = rb.make_opts(alpha=args.alpha, beta=args.beta, timing=True)
+            stats = [G.bfs(r, depth, parent, opts=plain, stats=True)[2] for r in roots]
+            G.timings()
+            per_root_ms, _ = time_roots(G, roots, depth, parent, timed, args.steps)
+            kernel_ms, total_ms = G.timings()
+            G.check()
+            info = G.info()
+            m_c = [st["component_edges"] for st in stats]
+            n_sweep = info["n_plus"] if variant == "rcm" else n
+            alg = sum(bfs_alg_bytes(st, n_sweep, original_ids=variant == "rcm")
+                      for st in stats) / len(stats)
+            k_ms = sum(kernel_ms) / len(kernel_ms)
+            print(json.dumps({
+                "ablation": name, "variant": variant, "n": n, "nnz": info["nnz"],
+                "n_plus": info["n_plus"], "roots": len(roots),
+                "gteps": hmean_gteps(m_c, per_root_ms),
+                "gteps_search_kernel_only": hmean_gteps(m_c * args.steps, kernel_ms),
+                "kernel_ms_avg": k_ms,
+                "output_ms_avg": (sum(total_ms) - sum(kernel_ms)) / len(kernel_ms),
+                "levels_avg": sum(st["levels"] for st in stats) / len(stats),
+                "edges_examined_avg": sum(sum(st["edges"][:st["levels"]]) for st in stats)
+                / len(stats),
+                "alg_bytes_avg": alg, "achieved_gbs": alg / (k_ms * 1e-3) / 1e9,
+                "rcm_ms": rcm_ms, "tuning": G.get_tuning()}), flush=True)
+            G.close()
+            del G
+            torch.cuda.empty_cache()
+        del off, cols, roots, depth, parent
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -284,6 +351,11 @@ def main():
                     help="JSON file of autotuned parameters (read, and written on a miss)")
     ap.add_argument("--tune-roots", type=int, default=8)
     ap.add_argument("--cpu-budget", type=float, default=30.0)
+    ap.add_argument("--ablation", action="store_true",
+                    help="run the locality study (original labels against RCM) instead")
+    ap.add_argument("--ablation-graphs", default="kron22,kron24,kron26,chunglu")
+    ap.add_argument("--ablation-variants", default="original,rcm")
+    ap.add_argument("--ablation-roots", type=int, default=16)
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
@@ -297,6 +369,9 @@ def main():
     import paper_2012_10026_amd as rb
 
     torch.cuda.set_device(0)
+    if args.ablation:
+        ablation(rb, graphgen, args)
+        return
     dev = rb.device_info()
     t0 = time.perf_counter()
     off, cols = graphgen.kronecker_csr_device(args.scale, args.edgefactor, args.seed)

@@ -15,10 +15,12 @@
  *
  * Determinism.  The paper's parent choice depends on thread timing.  Here
  * every parent is fixed: parent(v) is the neighbour one level closer to the
- * source that has the smallest label in the graph's current labelling
- * (original IDs before rbfs_rcm_reorder, RCM labels after it).  depth(v) is
- * the hop distance, -1 if unreachable.  Both arrays are therefore unique and
- * independent of the direction schedule, of batching and of timing.
+ * source that has the largest label in the graph's current labelling
+ * (original IDs before rbfs_rcm_reorder, RCM labels after it).  After RCM,
+ * labels rise with degree, so this is the neighbour that the degree-ordered
+ * bottom-up scan of Algorithm 6 meets first.  depth(v) is the hop distance,
+ * -1 if unreachable.  Both arrays are therefore unique and independent of the
+ * direction schedule, of batching and of timing.
  *
  * Conventions for every function:
  *   - returns RBFS_OK (0) or a negative RBFS_E_* code; nothing throws;
@@ -202,7 +204,7 @@ int rbfs_graph_iperm(const rbfs_graph_t* g, int32_t* iperm_out, void* stream);
 /* Breadth-first search from `root` (an original ID in [0, n)).
  * depth, parent: device int32[n], fully overwritten: depth = hop distance or
  * -1; parent(root) = root; parent = -1 when unreachable; otherwise the
- * smallest-label neighbour one level up.  With output_space
+ * largest-label neighbour one level up.  With output_space
  * RBFS_OUT_ORIGINAL (default) both are indexed by original ID and parents
  * are original IDs; with RBFS_OUT_INTERNAL, by internal label.
  * Enqueued on `stream` without a host round trip; `stats` (nullable, host)

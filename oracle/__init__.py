@@ -95,7 +95,7 @@ def rcm(off, cols):
 
 
 def bfs(off, cols, root, ell=None):
-    """(depth, parent, nlevels) from root; parent rule: smallest ell label."""
+    """(depth, parent, nlevels) from root; parent rule: largest ell label."""
     off, cols, n = _csr(off, cols)
     ell = _opt_i32(ell)
     depth = np.empty(n, np.int32)

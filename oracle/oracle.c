@@ -20,14 +20,14 @@
  *                         order, reversal, isolated vertices appended.
  *   orc_bfs               Algorithms 1-2 output: hop distance from the source
  *                         and the predecessor map (pi(s) = s, -1 when
- *                         unreachable) with the minimum-label parent rule.
+ *                         unreachable) with the maximum-label parent rule.
  *   orc_level_counters    per-level frontier / unvisited sizes that drive the
  *                         direction switch of Algorithm 2 and the work the
  *                         bottom-up step of Algorithm 2 / 5 does.
  *   orc_heuristic_schedule the alpha/beta direction rule (section 2.1 and
  *                         "Parameter Tuning"), integer form.
  *   orc_certify_bfs       O(nnz) certificate that (depth, parent) is the
- *                         unique BFS result under the minimum-label rule.
+ *                         unique BFS result under the maximum-label rule.
  *   orc_certify_rcm       O(nnz) certificate that a permutation is exactly
  *                         the one Algorithm 3 produces.
  */
@@ -160,9 +160,12 @@ int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, 
 /* ------------------------------------------------------------------------ */
 /* BFS result.  depth[v] = hop distance from root (-1 if unreachable);
  * parent[root] = root; parent[v] = the neighbour u with depth[u] =
- * depth[v] - 1 of smallest label ell[u] (identity labels if ell is NULL);
+ * depth[v] - 1 of largest label ell[u] (identity labels if ell is NULL);
  * parent[v] = -1 if unreachable.  Returns the number of levels (max depth+1).
- */
+ * The predecessor map of sections 2.1 and Algorithms 1-2 may name any
+ * neighbour one level up; fixing the largest label makes it unique, and is
+ * the neighbour that the degree-ordered bottom-up scan of Algorithm 6 meets
+ * first once labels rise with degree (after RCM). */
 int32_t orc_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root,
                 const int32_t* ell, int32_t* depth, int32_t* parent) {
   for (int64_t v = 0; v < n; ++v) {
@@ -189,12 +192,12 @@ int32_t orc_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root
   for (int64_t v = 0; v < n; ++v) {
     if (depth[v] <= 0) continue;
     int32_t best = -1;
-    int64_t best_label = INT64_MAX;
+    int64_t best_label = INT64_MIN;
     for (int64_t e = off[v]; e < off[v + 1]; ++e) {
       int32_t u = cols[e];
       if (depth[u] == depth[v] - 1) {
         int64_t lab = ell ? ell[u] : u;
-        if (lab < best_label) {
+        if (lab > best_label) {
           best_label = lab;
           best = u;
         }
@@ -213,8 +216,8 @@ int32_t orc_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root
  *   nu[d]  = |U_d|, U_d = {v in the swept set : depth[v] > d or unreached}
  *   mu[d]  = sum of deg over U_d
  *   ebu[d] = edges a bottom-up pass over U_d examines when every row is
- *            scanned in increasing label order and stops at the first
- *            neighbour in F_d: 1 + (number of neighbours of smaller label
+ *            scanned in decreasing label order and stops at the first
+ *            neighbour in F_d: 1 + (number of neighbours of larger label
  *            than that neighbour), or deg(v) when there is none.
  *   ebc[d] = the part of ebu[d] spent on vertices of the root's component
  *            (those reached later, depth > d): a bottom-up pass needs to
@@ -242,21 +245,21 @@ void orc_level_counters(int64_t n, const int64_t* off, const int32_t* cols, cons
       nu[d] += 1;
       mu[d] += deg;
       /* bottom-up work on v at level d */
-      int64_t first = INT64_MAX;
+      int64_t first = INT64_MIN;
       for (int64_t e = off[v]; e < off[v + 1]; ++e) {
         int32_t w = cols[e];
         int64_t lw = ell ? ell[w] : w;
-        if (depth[w] == d && lw < first) first = lw;
+        if (depth[w] == d && lw > first) first = lw;
       }
       int64_t work = deg;
-      if (first != INT64_MAX) {
-        int64_t smaller = 0;
+      if (first != INT64_MIN) {
+        int64_t larger = 0;
         for (int64_t e = off[v]; e < off[v + 1]; ++e) {
           int32_t w = cols[e];
           int64_t lw = ell ? ell[w] : w;
-          if (lw < first) smaller++;
+          if (lw > first) larger++;
         }
-        work = 1 + smaller;
+        work = 1 + larger;
       }
       ebu[d] += work;
       if (dv >= 0) ebc[d] += work;
@@ -290,16 +293,16 @@ void orc_heuristic_schedule(int32_t nlev, const int64_t* nf, const int64_t* mf,
 
 /* ------------------------------------------------------------------------ */
 /* BFS certificate.  Returns 0 when (depth, parent) is the BFS result from
- * root under the minimum-label parent rule, else a negative code naming the
+ * root under the maximum-label parent rule, else a negative code naming the
  * first failed rule:
  *   -1 root entries wrong            -2 an edge joins reached and unreached
  *   -3 an edge spans > 1 level        -4 unreached vertex with a parent
  *   -5 parent not a neighbour one level up
- *   -6 a neighbour one level up has a smaller label than the parent
+ *   -6 a neighbour one level up has a larger label than the parent
  *   -7 depth/parent out of range.
  * Rules: the parent chain gives depth >= distance; the edge rule gives
  * depth <= distance; so depth is the distance and the reached set is the
- * component, and the parent is the unique minimum. */
+ * component, and the parent is the unique maximum. */
 int32_t orc_certify_bfs(int64_t n, const int64_t* off, const int32_t* cols, int32_t root,
                         const int32_t* ell, const int32_t* depth, const int32_t* parent) {
   if (root < 0 || root >= n) return -7;
@@ -324,7 +327,7 @@ int32_t orc_certify_bfs(int64_t n, const int64_t* off, const int32_t* cols, int3
         if (w == p) found = 1;
         if (depth[w] == dv - 1) {
           int64_t lw = ell ? ell[w] : w;
-          if (lw < lp) return -6;
+          if (lw > lp) return -6;
         }
       }
       if (!found) return -5;

@@ -3,21 +3,22 @@
 // decision run on the GPU with no host round trip.
 //
 // Labels are the graph's internal labels; the swept set is [0, n_sweep)
-// (the non-isolated prefix after RCM).  parent(v) is the smallest-label
+// (the non-isolated prefix after RCM).  parent(v) is the largest-label
 // neighbour one level up, reached the same way by both step kinds: a scan of
-// v's row in increasing label order that stops at the first neighbour in the
+// v's row in decreasing label order that stops at the first neighbour in the
 // current frontier F_d (any visited neighbour of a vertex first reached at
-// level d+1 lies in F_d), or the minimum over all its frontier neighbours.
-// Depth and parent of a vertex are one 64-bit word, depth in the high half
-// (unreached = all ones), so that ordering the words orders by depth first:
+// level d+1 lies in F_d), or the maximum over all its frontier neighbours.
+// After RCM labels rise with degree, so the downward scan meets the hubs
+// first, as the degree-ordered bottom-up scan of Algorithm 6 does, and most
+// rows stop after a few entries.  Depth and parent of a vertex are one 64-bit
+// word, depth in the high half and the complement of the parent in the low
+// half (unreached = all ones), so that ordering the words orders by depth
+// first and then by decreasing parent label:
 //   top-down (Algorithms 1 and 4): frontier edges (u, w) are spread evenly
 //     over the GPU; every edge into a w unvisited at level start proposes
-//     (d+1, u) with one 64-bit atomicMin: the smallest proposal, i.e. the
-//     smallest-label parent, stays, and the one proposal that finds w
-//     unreached claims w and appends it.  (Scanning w's row for the first
-//     frontier neighbour instead would read nearly whole rows here: after
-//     RCM the hubs that make up the early frontiers carry the highest
-//     labels.);
+//     (d+1, u) with one 64-bit atomicMin: the smallest word, i.e. the
+//     largest-label parent, stays, and the one proposal that finds w
+//     unreached claims w and appends it;
 //   bottom-up (the bottom-up step of Algorithm 2, Algorithm 5): every
 //     unvisited v scans its own row; one wave owns a 64-vertex word, the
 //     found bits come from one ballot and are stored without atomics (the GPU
@@ -88,13 +89,21 @@ constexpr int kScanStep = 8;    // row entries a lane tests per step (after the 
 static_assert(kScanStep == 8, "the row scan loads two aligned groups of 4 entries");
 constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
 
+// Packed search state of a vertex: the depth in the high half and the
+// bitwise complement of the parent in the low half, so that the smallest
+// word has the smallest depth and, within it, the largest parent label.
+__device__ __forceinline__ uint64_t pack_dp(int32_t d, int32_t p) {
+  return ((uint64_t)(uint32_t)d << 32) | (uint32_t)~(uint32_t)p;
+}
+__device__ __forceinline__ int32_t dp_parent(uint64_t x) { return (int32_t)~(uint32_t)x; }
+
 struct BfsParams {
   const int64_t* off;
   const int32_t* cols;
   const int32_t* perm;   // original -> internal, null when not reordered
   int64_t n_sweep;
   int64_t deg_total;     // degree sum over the swept set
-  uint64_t* dp;          // packed (depth << 32 | parent) per swept vertex
+  uint64_t* dp;          // packed (depth << 32 | ~parent) per swept vertex
   const int32_t* iperm_par;  // non-null: parents become original IDs at the end
   const int32_t* comp_bounds;  // component intervals (null: one interval)
   int64_t n_comp;
@@ -278,7 +287,7 @@ __device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long l
 // once, so a long row keeps only its own lane busy instead of stalling the
 // other 63.  Each lane also holds the candidate after its current one with
 // its row bounds already loaded, so taking it over costs no extra memory
-// round trip.  Each row gets the same ascending first-hit scan in steps over
+// round trip.  Each row gets the same downward first-hit scan in steps over
 // aligned groups of 4 entries (one 16-byte load each): one group on a row's
 // first step, since rows facing a dense frontier mostly hit at once, two
 // groups on later steps; the probes of a step are independent, so one pair
@@ -307,7 +316,7 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
       v = vq;
       b = bq;
       e = eq;
-      j = b;
+      j = e;
       busy = true;
       queued = false;
       fresh = true;
@@ -330,43 +339,56 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     int32_t par = 0;
     wave_hub_first_hit(hub, b, e, cols, bits, filt, use_filt, fs, found, par, examined);
     bool fin = hub;
-    if (busy && !hub) {
-      // entries [ja, ja + span): entries below j (the previous row) and from
-      // e on are masked; reads past the last row stay inside the column
-      // array's slack
-      const int64_t ja = j & ~(int64_t)3;
-      const bool wide = j != b;
-      const int span = wide ? kScanStep : 4;
+    if (busy && !hub && j <= b) {
+      fin = true;  // empty row
+    } else if (busy && !hub) {
+      // entries [lo, j) downwards, in aligned groups of 4: the group holding
+      // entry j - 1 (w[0..3]) and, after a row's first step, the one below
+      // it (w[4..7]) when it still holds entries of the row; entries from j
+      // on (the next row) and below b (the previous row) are masked.  Reads
+      // past the last row stay inside the column array's slack.
+      const int64_t ga = (j - 1) & ~(int64_t)3;
+      const bool two = j != e && ga - 1 >= b;
+      const int64_t lo = two ? ga - 4 : ga;
       int32_t w[kScanStep];
       bool h[kScanStep];
       {
-        const int4 x = *(const int4*)(cols + ja);
+        const int4 x = *(const int4*)(cols + ga);
         int4 y = make_int4(0, 0, 0, 0);
-        if (wide) y = *(const int4*)(cols + ja + 4);
+        if (two) y = *(const int4*)(cols + ga - 4);
         w[0] = x.x; w[1] = x.y; w[2] = x.z; w[3] = x.w;
         w[4] = y.x; w[5] = y.y; w[6] = y.z; w[7] = y.w;
       }
 #pragma unroll
       for (int q = 0; q < kScanStep; ++q) {
-        bool in = q < span && ja + q >= j && ja + q < e;
+        const int64_t idx = q < 4 ? ga + q : ga - 8 + q;
+        bool in = (q < 4 || two) && idx >= b && idx < j;
         if (use_filt) in = in && lds_bit(filt, (uint32_t)w[q] >> fs);
         h[q] = in && test_bit(bits, (uint32_t)w[q]);
       }
-      int hq = kScanStep;
+      // the first hit downwards is the highest entry: visit the entries in
+      // increasing index order (w[4..7], then w[0..3]) and keep the last hit
+      int64_t hidx = -1;
 #pragma unroll
-      for (int q = kScanStep - 1; q >= 0; --q)
+      for (int q = 4; q < kScanStep; ++q)
         if (h[q]) {
-          hq = q;
+          hidx = ga - 8 + q;
           par = w[q];
         }
-      if (hq < kScanStep) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (h[q]) {
+          hidx = ga + q;
+          par = w[q];
+        }
+      if (hidx >= 0) {
         found = true;
         fin = true;
-        examined += ja + hq + 1 - j;
+        examined += j - hidx;
       } else {
-        examined += ((ja + span < e) ? ja + span : e) - j;
-        j = ja + span;
-        fin = j >= e;
+        examined += j - ((lo > b) ? lo : b);
+        j = lo;
+        fin = j <= b;
       }
     }
     done(fin, found, v, par, e - b);
@@ -415,7 +437,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   // ---- initialisation
   if (P.init) {
     for (int64_t i = gtid; i < P.n_sweep; i += gsz)
-      P.dp[i] = (i == root) ? (uint64_t)(uint32_t)root : kUnreached;
+      P.dp[i] = (i == root) ? pack_dp(0, root) : kUnreached;
   }
   for (int64_t w = gtid; w < W; w += gsz) {
     P.vis[w] = 0ull;
@@ -423,7 +445,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     P.front[1][w] = 0ull;
   }
   if (gtid == 0) {
-    if (!P.init && root_in) P.dp[root] = (uint64_t)(uint32_t)root;
+    if (!P.init && root_in) P.dp[root] = pack_dp(0, root);
     for (int r = 0; r < 2; ++r) {
       for (int q = 0; q < kNQ; ++q) {
         ctl->qpack[r][q][0] = 0ull;
@@ -516,10 +538,9 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
             s_qcnt[q], P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols, P.cshift,
             [&](const bool* act, const int32_t* u, const int32_t* w) {
           // w is a candidate if unvisited at level start; it then proposes
-          // (L+1, u).  The smallest proposal stays, so the parent is the
-          // smallest label; only the first proposal finds w unreached and
-          // claims it.  A stale read of the pair can only be larger than the
-          // stored value.
+          // (L+1, u).  The smallest word stays, so the parent is the largest
+          // label; only the first proposal finds w unreached and claims it.
+          // A stale read of the word can only be larger than the stored one.
           uint64_t word[kTdK], cur[kTdK];
           bool cand[kTdK], claim[kTdK];
           int64_t dw[kTdK];
@@ -533,7 +554,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           }
 #pragma unroll
           for (int r = 0; r < kTdK; ++r) {
-            const uint64_t prop = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)u[r];
+            const uint64_t prop = pack_dp(L + 1, u[r]);
             claim[r] = false;
             if (cand[r] && cur[r] > prop)
               claim[r] = atomicMin((unsigned long long*)&P.dp[w[r]], (unsigned long long)prop) ==
@@ -617,7 +638,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 return ((word >> (u & 63)) & 1ull) ? -1 : (int64_t)u;
               },
               [&](bool fin, bool found, int64_t v, int32_t par, int64_t deg) {
-                if (found) P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
+                if (found) P.dp[v] = pack_dp(L + 1, par);
                 wave_set_bits64(fnext, found, v);
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
                 stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
@@ -667,7 +688,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 if (found) {
                   atomicOr((unsigned long long*)&s_st.found[wv][(v >> 6) - kb],
                            1ull << (v & 63));
-                  P.dp[v] = ((uint64_t)(uint32_t)(L + 1) << 32) | (uint32_t)par;
+                  P.dp[v] = pack_dp(L + 1, par);
                 }
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
                 stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
@@ -776,11 +797,12 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       }
       int32_t o[kU];
 #pragma unroll
-      for (int u = 0; u < kU; ++u) o[u] = (x[u] != kUnreached) ? P.iperm_par[(uint32_t)x[u]] : 0;
+      for (int u = 0; u < kU; ++u)
+        o[u] = (x[u] != kUnreached) ? P.iperm_par[dp_parent(x[u])] : 0;
 #pragma unroll
       for (int u = 0; u < kU; ++u)
         if (x[u] != kUnreached)
-          P.dp[i0 + u * gsz] = (x[u] & 0xFFFFFFFF00000000ull) | (uint32_t)o[u];
+          P.dp[i0 + u * gsz] = (x[u] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)o[u];
     }
   }
   if (gtid == 0) {
@@ -809,7 +831,7 @@ __global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* per
       if (x != kUnreached) {
         if (reset) dp[i] = kUnreached;
         d = (int32_t)(x >> 32);
-        p = (int32_t)(uint32_t)x;
+        p = dp_parent(x);
       }
     } else if (v == root_out) {
       d = 0;

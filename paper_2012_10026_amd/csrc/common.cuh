@@ -298,11 +298,12 @@ __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t 
     bool hf = false;
     int32_t hp = 0;
     int64_t scanned = he - hb;
-    for (int64_t j0 = hb; j0 < he; j0 += kWave) {
-      const int64_t j = j0 + l;
+    // downwards from the row's end, lane 0 on the highest entry
+    for (int64_t j0 = he; j0 > hb; j0 -= kWave) {
+      const int64_t j = j0 - 1 - l;
       int32_t w = 0;
       bool hit = false;
-      if (j < he) {
+      if (j >= hb) {
         w = cols[j];
         hit = (!use_filt || lds_bit(filt, (uint32_t)w >> fs)) && test_bit(bits, (uint32_t)w);
       }
@@ -311,7 +312,7 @@ __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t 
         const int first = ffs64(hm);
         hp = shfl(w, first);
         hf = true;
-        scanned = j0 - hb + first + 1;
+        scanned = he - j0 + first + 1;
         break;
       }
     }

@@ -55,7 +55,7 @@ struct Graph;
 // Workspace of the single-root search (sized for n_sweep vertices).
 struct BfsWork {
   int64_t n_sweep = 0;
-  uint64_t* dp = nullptr;       // packed (depth << 32 | parent) per swept vertex
+  uint64_t* dp = nullptr;       // packed (depth << 32 | ~parent) per swept vertex
   uint64_t* vis = nullptr;      // reached before the current level
   uint64_t* front = nullptr;    // three rotating frontier bitmaps
   int32_t* qv[2] = {nullptr, nullptr};
@@ -91,7 +91,7 @@ struct MsEngine {
   int64_t nnz = 0;
   uint64_t* vis = nullptr;
   uint64_t* front = nullptr;      // 3 x n_sweep words
-  uint64_t* dp = nullptr;         // [n_sweep][64] packed (depth << 32 | parent)
+  uint64_t* dp = nullptr;         // [n_sweep][64] packed (depth << 32 | ~parent)
   int32_t* qv[2] = {nullptr, nullptr};
   int64_t* qe[2] = {nullptr, nullptr};
   int32_t* chunk[2] = {nullptr, nullptr};

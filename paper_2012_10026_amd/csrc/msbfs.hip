@@ -2,18 +2,19 @@
 // 64-bit word per vertex (multi-source BFS), as one persistent kernel.
 //
 // Row j of the result equals the single-root search from root j: depth is
-// the hop distance and the parent of v for root j is the smallest-label
+// the hop distance and the parent of v for root j is the largest-label
 // neighbour of v one level closer to root j.  For a vertex v still missing
 // root j at level d, every neighbour that has bit j in the frontier F_d is at
 // distance d from root j, so either step kind gives exactly those parents:
-//   bottom-up: every vertex with missing bits scans its row in increasing
+//   bottom-up: every vertex with missing bits scans its row in decreasing
 //     label order until all of them are found, taking for each missing bit
 //     the first neighbour whose frontier word has it (Algorithm 2's
 //     bottom-up loop, per bit);
 //   top-down: frontier vertices push their bits to their neighbours with
 //     atomicOr, and for each bit the neighbour still misses propose
 //     (depth, parent) = (d+1, u) with a 64-bit atomicMin on the neighbour's
-//     packed word for that root, so the smallest label stays.
+//     packed word for that root (the complement of the parent in its low
+//     half), so the largest label stays.
 // Visited words, three rotating frontier word arrays, the per-wave staged
 // frontier queue with degree prefix (edge-balanced top-down expansion) and
 // the hierarchical grid barrier follow the single-root kernel.
@@ -23,7 +24,7 @@
 // vertex counts of the graphs before it), where root j of every graph uses
 // bit j; components never touch, so the bits never mix.
 //
-// Per-(vertex, root) results are packed 64-bit words (depth << 32 | parent,
+// Per-(vertex, root) results are packed 64-bit words (depth << 32 | ~parent,
 // all ones = unreached), vertex-major ([v][64]), with parents as internal
 // labels.  A tiled transpose through LDS turns them into the caller's
 // root-major original-ID layout, maps the parents back, and resets the
@@ -70,7 +71,7 @@ struct MsParams {
   int64_t deg_total;
   uint64_t* vis;
   uint64_t* front[3];
-  uint64_t* dp;            // [n_sweep][64] packed (depth << 32 | parent), all ones = none
+  uint64_t* dp;            // [n_sweep][64] packed (depth << 32 | ~parent), all ones = none
   int32_t* qv[2];
   int64_t* qe[2];
   int32_t* chunk[2];
@@ -162,7 +163,7 @@ __device__ __forceinline__ void ms_stage(MsStage& st, bool take, int32_t v, int6
 __device__ __forceinline__ void ms_record(const MsParams& P, int64_t v, uint64_t bits,
                                           int32_t x, int d1) {
   uint64_t* row = P.dp + v * 64;
-  const uint64_t val = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)x;
+  const uint64_t val = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)~(uint32_t)x;
   while (bits) {
     const int j = ffs64(bits);
     bits &= bits - 1;
@@ -208,11 +209,12 @@ __device__ __forceinline__ uint64_t ms_hub_pull(const MsParams& P, bool hub, int
     uint64_t hmiss = shfl(miss, h);
     uint64_t hfound = 0;
     int64_t scanned = 0;
-    for (int64_t j0 = hb0; j0 < he && hmiss; j0 += kWave) {
-      const int64_t j = j0 + l;
+    // downwards from the row's end, lane 0 on the highest entry
+    for (int64_t j0 = he; j0 > hb0 && hmiss; j0 -= kWave) {
+      const int64_t j = j0 - 1 - l;
       int32_t x = 0;
       uint64_t hb = 0;
-      if (j < he) {
+      if (j >= hb0) {
         x = P.cols[j];
         hb = fcur[x] & hmiss;
       }
@@ -221,7 +223,7 @@ __device__ __forceinline__ uint64_t ms_hub_pull(const MsParams& P, bool hub, int
       const uint64_t all = wave_or(hb);
       hmiss &= ~all;
       hfound |= all;
-      scanned += (j0 + kWave < he ? kWave : he - j0);
+      scanned += (j0 - kWave > hb0 ? kWave : j0 - hb0);
     }
     if (l == h) found = hfound;
     if (l == 0) examined += scanned;
@@ -234,7 +236,7 @@ __device__ __forceinline__ uint64_t ms_hub_pull(const MsParams& P, bool hub, int
 // words, which also folds F_d into visited); those with missing root bits are
 // handed to idle lanes, and a lane that finishes its vertex takes the next
 // one at once, so a long row does not stall the other 63 lanes.  Each lane
-// scans its row in increasing label order, kPullStep entries per step, and
+// scans its row in decreasing label order, kPullStep entries per step, and
 // records for every missing bit the first neighbour whose frontier word has
 // it; rows longer than lane_row are scanned by the whole wave.  Vertices that
 // found bits go to the next frontier; `done` gathers the degree of vertices
@@ -290,7 +292,7 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
     if (fresh) {
       b = P.off[v];
       e = P.off[v + 1];
-      j = b;
+      j = e;
       busy = true;
     }
     const bool hub = fresh && (e - b) > P.lane_row;
@@ -301,13 +303,14 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
       miss &= ~hf;
       fin = true;
     } else if (busy) {
+      // entries j-1, j-2, .. downwards
       int32_t x[kPullStep];
       uint64_t fb[kPullStep];
 #pragma unroll
-      for (int q = 0; q < kPullStep; ++q) x[q] = (j + q < e) ? P.cols[j + q] : 0;
+      for (int q = 0; q < kPullStep; ++q) x[q] = (j - 1 - q >= b) ? P.cols[j - 1 - q] : 0;
 #pragma unroll
-      for (int q = 0; q < kPullStep; ++q) fb[q] = (j + q < e) ? fcur[x[q]] : 0ull;
-      int used = (e - j < kPullStep) ? (int)(e - j) : kPullStep;
+      for (int q = 0; q < kPullStep; ++q) fb[q] = (j - 1 - q >= b) ? fcur[x[q]] : 0ull;
+      int used = (j - b < kPullStep) ? (int)(j - b) : kPullStep;
 #pragma unroll
       for (int q = 0; q < kPullStep; ++q) {
         const uint64_t hb = fb[q] & miss;
@@ -319,8 +322,8 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
         }
       }
       examined += used;
-      j += kPullStep;
-      fin = miss == 0ull || j >= e;
+      j -= kPullStep;
+      fin = miss == 0ull || j <= b;
     }
     if (fin && found) fnext[v] = found;
     if (fin && miss == 0ull) done += e - b;
@@ -379,7 +382,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
           const unsigned long long old =
               atomicOr((unsigned long long*)&P.front[0][r], 1ull << j);
           first = (old == 0ull);
-          P.dp[(int64_t)r * 64 + j] = (uint64_t)(uint32_t)r;  // depth 0, parent itself
+          P.dp[(int64_t)r * 64 + j] = (uint64_t)(uint32_t)~(uint32_t)r;  // depth 0, parent itself
           dg = P.off[r + 1] - P.off[r];
         }
       }
@@ -421,7 +424,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
     if (dir == 0) {
       // ---- top-down push.  Every frontier edge (u, w) carries the root bits
       // of u that w has not seen; for each, (L+1, u) is proposed with an
-      // atomicMin on the bit's parent slot, so the smallest label stays (the
+      // atomicMin on the bit's parent slot, so the largest label stays (the
       // rule of the single-root search), and the bits are ORed into w's next
       // frontier word.  The OR that completes w's root set adds w's degree to
       // the completed degree sum.
@@ -441,11 +444,12 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
             const uint64_t seen = P.vis[w] | fcur[w];
             const uint64_t cand = fcur[u] & P.amask & ~seen;
             if (cand) {
-              // (L+1, u) proposed per bit: depth sits in the high half, so
-              // the smallest word is the smallest-label parent of this level
+              // (L+1, u) proposed per bit: depth sits in the high half and
+              // the complement of the parent in the low half, so the smallest
+              // word is the largest-label parent of this level
               unsigned long long* row = (unsigned long long*)P.dp + (int64_t)w * 64;
               const unsigned long long prop = ((unsigned long long)(uint32_t)(L + 1) << 32) |
-                                              (uint32_t)u;
+                                              (uint32_t)~(uint32_t)u;
               uint64_t bits = cand;
               while (bits) {
                 const int j = ffs64(bits);
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
       if (j < k && v < n_g) {
         const uint64_t x = tile[l][j];
         const int32_t d = (int32_t)(x >> 32);
-        int32_t p = (int32_t)(uint32_t)x;
+        int32_t p = d < 0 ? -1 : (int32_t)~(uint32_t)x;
         if (p >= 0 && oid) {
           if (p != last_in) {
             last_in = p;

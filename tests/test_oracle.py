@@ -88,7 +88,7 @@ def test_canonical_csr_properties_kron():
 
 
 # --------------------------------------------------------------------------
-# BFS: brute force (Floyd-Warshall distances + exhaustive min-label parent)
+# BFS: brute force (Floyd-Warshall distances + exhaustive max-label parent)
 
 def brute_bfs(n, edges, root, ell):
     INF = 10 ** 9
@@ -113,7 +113,7 @@ def brute_bfs(n, edges, root, ell):
     for v in range(n):
         if depth[v] > 0:
             cands = [u for u in adj[v] if depth[u] == depth[v] - 1]
-            parent[v] = min(cands, key=lambda u: ell[u])
+            parent[v] = max(cands, key=lambda u: ell[u])
     parent[root] = root
     return depth, parent
 
@@ -266,7 +266,7 @@ def test_certify_bfs_rejects_mutations():
     root = graphgen.sample_roots(off, 1, 7)[0]
     depth, parent, _ = oracle.bfs(off, cols, root, perm)
     assert oracle.certify_bfs(off, cols, root, depth, parent, perm) == 0
-    # same arrays judged in the wrong label space: some parent is no longer minimal
+    # same arrays judged in the wrong label space: some parent is no longer maximal
     assert oracle.certify_bfs(off, cols, root, depth, parent, None) != 0
     rng = np.random.default_rng(0)
     reached = np.nonzero(depth > 0)[0]
@@ -320,8 +320,9 @@ def test_level_counters_star_closed_form():
     depth, _, _ = oracle.bfs(off, cols, 1)
     c = oracle.level_counters(off, cols, depth)
     assert c["nf"].tolist() == [1, 1, k - 1]
-    # the centre meets the root (label 1) first: 1 edge; leaves 2..k: 1 edge each
-    assert c["ebu"].tolist() == [1 + (k - 1), k - 1, 0]
+    # the centre scans labels k, k-1, .. and meets the root (label 1) last: k
+    # edges; leaves 2..k: 1 edge each (no hit)
+    assert c["ebu"].tolist() == [k + (k - 1), k - 1, 0]
 
 
 def test_level_counters_first_hit_index():
@@ -331,12 +332,13 @@ def test_level_counters_first_hit_index():
     depth, _, _ = oracle.bfs(off, cols, 5)
     assert depth[0] == 2 and depth[3] == 1
     c = oracle.level_counters(off, cols, depth)
-    # at level 1 vertex 0 scans 1, 2, 3 -> 3 edges; with labels reversed it
-    # meets 4 first -> 1 edge.  Vertices 1, 2, 6 have no neighbour in F_1.
+    # at level 1 vertex 0 scans 4 first (largest label) -> 1 edge; with
+    # labels reversed it scans 1, 2, 3 -> 3 edges.  Vertices 1, 2, 6 have no
+    # neighbour in F_1.
     base = c["ebu"][1]
     ell = np.array([6, 5, 4, 3, 2, 1, 0], np.int32)
     c2 = oracle.level_counters(off, cols, depth, ell)
-    assert base - c2["ebu"][1] == 2
+    assert c2["ebu"][1] - base == 2
 
 
 def test_level_counters_invariants_kron():
@@ -365,8 +367,9 @@ def test_level_counters_component_scope():
     depth, _, nlev = oracle.bfs(off, cols, 0)
     c = oracle.level_counters(off, cols, depth)
     assert nlev == 3
-    # level 0: 1 meets 0 first (1 entry); 2's only neighbour 1 is not in F_0 (1)
-    assert c["ebc"].tolist() == [2, 1, 0]
+    # level 0: 1 scans 2 then meets 0 (2 entries); 2's only neighbour 1 is not
+    # in F_0 (1)
+    assert c["ebc"].tolist() == [3, 1, 0]
     assert (c["ebu"] - c["ebc"]).tolist() == [6, 6, 6]
 
 
