@@ -342,14 +342,16 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     if (busy && !hub && j <= b) {
       fin = true;  // empty row
     } else if (busy && !hub) {
-      // entries [lo, j) downwards, in aligned groups of 4: the group holding
+      // entries below j, downwards, in aligned groups of 4: the group holding
       // entry j - 1 (w[0..3]) and, after a row's first step, the one below
       // it (w[4..7]) when it still holds entries of the row; entries from j
       // on (the next row) and below b (the previous row) are masked.  Reads
-      // past the last row stay inside the column array's slack.
+      // past the last row stay inside the column array's slack.  Positions
+      // are kept relative to the top group: entry ga + r for r in [-4, 4).
       const int64_t ga = (j - 1) & ~(int64_t)3;
-      const bool two = j != e && ga - 1 >= b;
-      const int64_t lo = two ? ga - 4 : ga;
+      const int rj = (int)(j - ga);                                // 1..4
+      const int rb = (int)((b - ga > -8) ? b - ga : (int64_t)-8);  // row start
+      const bool two = j != e && rb <= -1;
       int32_t w[kScanStep];
       bool h[kScanStep];
       {
@@ -361,33 +363,34 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
       }
 #pragma unroll
       for (int q = 0; q < kScanStep; ++q) {
-        const int64_t idx = q < 4 ? ga + q : ga - 8 + q;
-        bool in = (q < 4 || two) && idx >= b && idx < j;
+        const int r = q < 4 ? q : q - 8;
+        bool in = (q < 4 || two) && r >= rb && r < rj;
         if (use_filt) in = in && lds_bit(filt, (uint32_t)w[q] >> fs);
         h[q] = in && test_bit(bits, (uint32_t)w[q]);
       }
       // the first hit downwards is the highest entry: visit the entries in
-      // increasing index order (w[4..7], then w[0..3]) and keep the last hit
-      int64_t hidx = -1;
+      // increasing position order (w[4..7], then w[0..3]), keep the last hit
+      int hr = -9;
 #pragma unroll
       for (int q = 4; q < kScanStep; ++q)
         if (h[q]) {
-          hidx = ga - 8 + q;
+          hr = q - 8;
           par = w[q];
         }
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         if (h[q]) {
-          hidx = ga + q;
+          hr = q;
           par = w[q];
         }
-      if (hidx >= 0) {
+      if (hr > -9) {
         found = true;
         fin = true;
-        examined += j - hidx;
+        examined += rj - hr;
       } else {
-        examined += j - ((lo > b) ? lo : b);
-        j = lo;
+        const int rlo = two ? -4 : 0;
+        examined += rj - ((rlo > rb) ? rlo : rb);
+        j = ga + rlo;
         fin = j <= b;
       }
     }
