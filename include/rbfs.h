@@ -109,8 +109,10 @@ typedef struct rbfs_stats {
   int32_t levels;                            /* number of levels expanded */
   int32_t status;                            /* device status word, 0 = ok */
   int8_t dir[RBFS_STATS_MAX_LEVELS];         /* 0 = TD, 1 = BU */
-  int8_t fallback[RBFS_STATS_MAX_LEVELS];    /* learned mode: 1 if the alpha/beta rule
-                                                decided (features out of range) */
+  int8_t fallback[RBFS_STATS_MAX_LEVELS];    /* learned mode: the alpha/beta rule
+                                                decided because the features were
+                                                out of range (1) or the predictions
+                                                within the margin (2); 0 = network */
   int64_t nf[RBFS_STATS_MAX_LEVELS];         /* |F_d| */
   int64_t mf[RBFS_STATS_MAX_LEVELS];         /* degree sum over F_d */
   int64_t mu[RBFS_STATS_MAX_LEVELS];         /* degree sum of unreached after F_d */
@@ -324,9 +326,10 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
  * Not in the paper: the alpha/beta rule of Algorithm 2 (section 2.1,
  * "Parameter Tuning") is replaced by a small network that predicts, from 8
  * per-level features, ln(microseconds) of the next level in each direction
- * (output 0 top-down, 1 bottom-up); the cheaper one is taken, an exact tie
- * keeps the current direction, and inputs outside the training range fall
- * back to the alpha/beta rule.
+ * (output 0 top-down, 1 bottom-up); the cheaper one is taken when the two
+ * predictions differ by at least 0.25 (ln microseconds, about 28 %).  Closer
+ * predictions, which lie within the network's training error, and inputs
+ * outside the training range leave the decision to the alpha/beta rule.
  *
  * Network: x[8] -> ReLU(W1 x + b1)[32] -> ReLU(W2 h1 + b2)[32] -> W3 h2 + b3
  * [2], fp32.  Parameters (1410 floats) in the order W1[32][8] (row = output

@@ -411,6 +411,7 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
   __shared__ StepLds<BLOCK> s_step;
+  __shared__ float s_mlp[kMlpParams];  // learned mode: the network's weights
   constexpr int kFiltBits = StepLds<BLOCK>::kFiltWords * 32;
   __shared__ StageLds<WAVES> s_st;
   // sizes of the current frontier's sub-queues and of the last vertex list's
@@ -431,6 +432,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     s_st.lcnt[threadIdx.x] = 0;
   }
   const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
+  if (P.mode == RBFS_DIR_LEARNED)  // read at every decision: keep them in LDS
+    for (int i = threadIdx.x; i < kMlpParams; i += BLOCK) s_mlp[i] = P.sw[i];
   if (threadIdx.x < kNQ) {  // F_0 = {root} sits in sub-queue 0
     s_qcnt[threadIdx.x] = (threadIdx.x == 0 && root_in) ? 1 : 0;
     s_qedg[threadIdx.x] = (threadIdx.x == 0) ? dr : 0;
@@ -729,7 +732,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     }
     const long long mu_new = mu - mf_new;
     int nd = dir;
-    bool ood = false;
+    int fallback = 0;  // learned mode: 1 out of range, 2 predictions within the margin
     switch (P.mode) {
       case RBFS_DIR_TD_ONLY: nd = 0; break;
       case RBFS_DIR_BU_ONLY: nd = 1; break;
@@ -746,19 +749,22 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         float f[kMlpIn];
         switch_features(f, nf_new, mf_new, mu_new, P.n_sweep - (reached + nf_new), nf, L + 1,
                         dir, P.n_sweep, P.deg_total);
-        ood = switch_ood(P.sw, f, L + 1);
-        if (ood) {
-          nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
+        if (switch_ood(P.sw, f, L + 1)) {
+          fallback = 1;
         } else {
           if (threadIdx.x < kWave) {
             float y0, y1;
-            mlp_forward_wave(P.sw, f, y0, y1);
-            if (threadIdx.x == 0) s_dec = (y1 < y0) ? 1 : ((y0 < y1) ? 0 : dir);
+            mlp_forward_wave(s_mlp, f, y0, y1);
+            if (threadIdx.x == 0)
+              s_dec = (y0 - y1 >= kLearnedMargin) ? 1 : ((y1 - y0 >= kLearnedMargin) ? 0 : -1);
           }
           __syncthreads();
           nd = s_dec;
           __syncthreads();
+          if (nd < 0) fallback = 2;
         }
+        if (fallback)
+          nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
         break;
       }
       default:
@@ -769,7 +775,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       ctl->hts[L + 1] = (unsigned long long)wall_clock64();
       if (L + 1 < RBFS_STATS_MAX_LEVELS && nf_new > 0) {
         ctl->hdir[L + 1] = (signed char)nd;
-        ctl->hood[L + 1] = ood ? 1 : 0;
+        ctl->hood[L + 1] = (signed char)fallback;
         ctl->hnf[L + 1] = nf_new;
         ctl->hmf[L + 1] = mf_new;
         ctl->hmu[L + 1] = mu_new;

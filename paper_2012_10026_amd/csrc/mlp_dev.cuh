@@ -8,6 +8,11 @@
 
 namespace rbfs {
 
+// Value of x in lane k of the wave (k the same in every lane).
+__device__ __forceinline__ float lane_value(float x, int k) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), k));
+}
+
 __device__ __forceinline__ void mlp_forward_wave(const float* __restrict__ w, const float* f,
                                                  float& y0, float& y1) {
   const int j = lane_id() & 31;
@@ -17,12 +22,12 @@ __device__ __forceinline__ void mlp_forward_wave(const float* __restrict__ w, co
   const float h1 = fmaxf(a, 0.0f);
   float c = w[kOffB2 + j];
 #pragma unroll 8
-  for (int k = 0; k < kMlpHid; ++k) c = fmaf(w[kOffW2 + j * kMlpHid + k], __shfl(h1, k, kWave), c);
+  for (int k = 0; k < kMlpHid; ++k) c = fmaf(w[kOffW2 + j * kMlpHid + k], lane_value(h1, k), c);
   const float h2 = fmaxf(c, 0.0f);
   float s0 = w[kOffB3], s1 = w[kOffB3 + 1];
 #pragma unroll 8
   for (int k = 0; k < kMlpHid; ++k) {
-    const float hk = __shfl(h2, k, kWave);
+    const float hk = lane_value(h2, k);
     s0 = fmaf(w[kOffW3 + k], hk, s0);
     s1 = fmaf(w[kOffW3 + kMlpHid + k], hk, s1);
   }

@@ -34,6 +34,10 @@ constexpr int kOffFmin = kMlpParams;
 constexpr int kOffFmax = kOffFmin + kMlpIn;
 constexpr int kOffMaxLevel = kOffFmax + kMlpIn;
 constexpr int kSwitchBlob = kOffMaxLevel + 1;         // 1427
+// The network overrides the alpha/beta rule only when its two predictions
+// differ by at least this much (ln microseconds, about 28 %): closer
+// predictions are within its training error, and the rule decides.
+constexpr float kLearnedMargin = 0.25f;
 
 RBFS_HD float clampf_(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
 

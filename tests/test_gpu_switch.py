@@ -93,7 +93,7 @@ def test_learned_mode_results_are_exact(rb):
             d_o, p_o, _ = oracle.bfs(off, cols, r, perm)
             assert np.array_equal(d.cpu().numpy(), d_o)
             assert np.array_equal(p.cpu().numpy(), p_o)
-            assert sum(st["fallback"]) == 0
+            assert all(x != 1 for x in st["fallback"])  # never out of range
 
 
 def test_out_of_range_falls_back_to_heuristic(rb):
@@ -105,7 +105,7 @@ def test_out_of_range_falls_back_to_heuristic(rb):
     _, _, st_l = G.bfs(root, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
     _, _, st_h = G.bfs(root, opts=rb.make_opts(rb.DIR_HEURISTIC), stats=True)
     assert st_l["dir"] == st_h["dir"]
-    assert all(x == 1 for x in st_l["fallback"][1:])
+    assert all(x == 1 for x in st_l["fallback"][1:])  # 1 = out of range
 
 
 def modeled_cost(samples_by_level, dirs):
