@@ -327,6 +327,36 @@ def ablation(rb, graphgen, args):
         torch.cuda.empty_cache()
 
 
+def ab_grid(rb, graphgen, args):
+    """Grid search of the alpha/beta rule on MI355X: the plain search over
+    the scale-26 graph's roots for every (alpha, beta) pair; one JSON line per
+    pair (harmonic-mean GTEPS and mean search-kernel time)."""
+    import torch
+    off, cols = graphgen.kronecker_csr_device(args.scale, args.edgefactor, args.seed)
+    roots = graphgen.sample_roots_device(off, args.ablation_roots, args.root_seed)
+    G = rb.Graph(off, cols)
+    del off, cols
+    torch.cuda.empty_cache()
+    G.rcm_reorder(want_perm=False)
+    cache = rb.TuningCache(args.tuning_cache)
+    t = cache.get(rb.tuning_key(rb.device_info()["arch"], "kronecker", G.n, rb.TUNE_SINGLE))
+    if t is not None:
+        G.set_tuning(t)
+    n = G.n
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    m_c = [G.bfs(r, depth, parent, stats=True)[2]["component_edges"] for r in roots]
+    for a in [int(x) for x in args.ab_alphas.split(",")]:
+        for b in [int(x) for x in args.ab_betas.split(",")]:
+            timed = rb.make_opts(alpha=a, beta=b, timing=True)
+            G.timings()
+            per_root_ms, _ = time_roots(G, roots, depth, parent, timed, args.steps)
+            kernel_ms, _ = G.timings()
+            print(json.dumps({"alpha": a, "beta": b, "gteps": hmean_gteps(m_c, per_root_ms),
+                              "kernel_ms_avg": sum(kernel_ms) / len(kernel_ms),
+                              "roots": len(roots)}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,6 +386,10 @@ def main():
     ap.add_argument("--ablation-graphs", default="kron22,kron24,kron26,chunglu")
     ap.add_argument("--ablation-variants", default="original,rcm")
     ap.add_argument("--ablation-roots", type=int, default=16)
+    ap.add_argument("--ab-grid", action="store_true",
+                    help="run the alpha/beta grid search of the plain search instead")
+    ap.add_argument("--ab-alphas", default="2,4,8,14,24,48,96")
+    ap.add_argument("--ab-betas", default="6,12,24,48,96")
     ap.add_argument("--copy-calibration-gib", type=float, default=0.0,
                     help="also run a plain device copy of this size (profiler calibration)")
     args = ap.parse_args()
@@ -371,6 +405,9 @@ def main():
     torch.cuda.set_device(0)
     if args.ablation:
         ablation(rb, graphgen, args)
+        return
+    if args.ab_grid:
+        ab_grid(rb, graphgen, args)
         return
     dev = rb.device_info()
     t0 = time.perf_counter()
