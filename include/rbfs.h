@@ -214,6 +214,27 @@ int rbfs_graph_iperm(const rbfs_graph_t* g, int32_t* iperm_out, void* stream);
 int rbfs_bfs(rbfs_graph_t* g, int32_t root, int32_t* depth, int32_t* parent,
              const rbfs_opts_t* opts, void* stream, rbfs_stats_t* stats);
 
+/* Certificate of a search result, checked on the device in O(n + nnz):
+ * *result = 0 when (depth, parent) is exactly what rbfs_bfs from `root` (an
+ * original ID) returns on this graph -- hop distances of section 2.1 with the
+ * predecessor map, the parent being the largest-label neighbour one level up
+ * in the graph's current labels -- else a negative RBFS_CERT_* code of a
+ * rule the outputs break (when several are broken, the most negative code
+ * among those found; the same on every call).  depth, parent: device int32[n]
+ * laid out as rbfs_bfs writes them for `output_space`; read only, values need
+ * not be in range (every parent is range-checked before it is used as an
+ * index).  Synchronises `stream`.  Returns RBFS_E_INVAL for NULL pointers or
+ * an unknown output_space, RBFS_E_RANGE for a root outside [0, n). */
+#define RBFS_CERT_ROOT (-1)       /* root entries wrong, or another vertex at depth 0 */
+#define RBFS_CERT_REACH (-2)      /* an edge joins a reached and an unreached vertex */
+#define RBFS_CERT_LEVEL (-3)      /* an edge spans more than one level */
+#define RBFS_CERT_ORPHAN (-4)     /* an unreached vertex has a parent */
+#define RBFS_CERT_PARENT (-5)     /* parent is not a neighbour one level up */
+#define RBFS_CERT_LARGER (-6)     /* a neighbour one level up has a larger label */
+#define RBFS_CERT_RANGE (-7)      /* depth below -1, or parent outside [-1, n) */
+int rbfs_certify(rbfs_graph_t* g, int32_t root, const int32_t* depth, const int32_t* parent,
+                 int32_t output_space, void* stream, int32_t* result);
+
 /* Synchronise `stream` and report any sticky device status (queue overflow,
  * barrier timeout, corrupt input detected by a kernel) raised by searches on
  * this graph since the last check: RBFS_OK or RBFS_E_DEVICE. */

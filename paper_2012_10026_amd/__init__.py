@@ -23,6 +23,8 @@ HOST_PTRS = 1
 VALIDATE = 2
 DIR_HEURISTIC, DIR_TD_ONLY, DIR_BU_ONLY, DIR_SCHEDULE, DIR_LEARNED = 0, 1, 2, 3, 4
 OUT_ORIGINAL, OUT_INTERNAL = 0, 1
+CERT_ROOT, CERT_REACH, CERT_LEVEL, CERT_ORPHAN, CERT_PARENT, CERT_LARGER, CERT_RANGE = \
+    -1, -2, -3, -4, -5, -6, -7
 STATS_MAX_LEVELS = 64
 MLP_PARAMS = 8 * 32 + 32 + 32 * 32 + 32 + 32 * 2 + 2
 SWITCH_BLOB = MLP_PARAMS + 8 + 8 + 1
@@ -116,6 +118,7 @@ SIGNATURES = {
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
+    "rbfs_certify": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
     "rbfs_multi_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "rbfs_multi_destroy": (ctypes.c_int, [_P]),
     "rbfs_bfs_multi": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
@@ -380,6 +383,16 @@ class Graph:
 
     def check(self):
         _check(lib().rbfs_graph_check(self._h, _stream_ptr(self.device)))
+
+    def certify(self, root, depth, parent, output_space=OUT_ORIGINAL):
+        """Checks (depth, parent) of a search from `root` against the graph on
+        the device; returns 0 if it is the search result, else a negative
+        rule code (CERT_* constants)."""
+        res = ctypes.c_int32(0)
+        _check(lib().rbfs_certify(self._h, int(root), _dptr(depth), _dptr(parent),
+                                  int(output_space), _stream_ptr(self.device),
+                                  ctypes.byref(res)))
+        return res.value
 
     def set_tuning(self, tuning, kind=TUNE_SINGLE):
         t = _as_tuning(tuning)

@@ -3,7 +3,7 @@ times.  Scale 22: the whole RCM permutation and every output of sampled
 roots bit-exact against the oracle.  Scale 26, scale 24 (64-root batch) and
 the 52.5M-vertex Chung-Lu graph: the O(nnz) certificates (the RCM
 certificate pins the whole permutation to Algorithm 3; the BFS certificate
-pins depth and the minimum-label parent of every vertex), plus oracle depth
+pins depth and the largest-label parent of every vertex), plus oracle depth
 for a sampled root.  Graphs come from the device generator, which equals the
 host generator bit for bit (test_gpu_bfs.py)."""
 import numpy as np
@@ -75,6 +75,11 @@ def test_scale26_certified(rb):
     del off_d, cols_d
     torch.cuda.empty_cache()
     certify_graph(rb, G, off, cols, roots, n_bfs_cert=2, n_depth=1)
+    # every root the benchmark times, through the on-device certificate
+    # (itself checked against the oracle's in test_gpu_certify.py)
+    for r in roots:
+        d, p = G.bfs(r)
+        assert G.certify(r, d, p) == 0, r
 
 
 @pytest.mark.timeout(1200)
@@ -93,6 +98,8 @@ def test_scale24_batch_certified(rb):
         assert oracle.certify_bfs(off, cols, roots[j], d, p, perm) == 0
         d1, p1 = G.bfs(roots[j])
         assert np.array_equal(host(d1), d) and np.array_equal(host(p1), p)
+    for j in range(64):
+        assert G.certify(roots[j], dB[j], pB[j]) == 0, j
 
 
 @pytest.mark.timeout(1200)
