@@ -65,10 +65,10 @@ def bfs_alg_bytes(st, n_sweep, original_ids=True):
     return total
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """Per-launch bytes of the search kernel from the committed rocprofv3
-    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources changed
-    since the counters were taken."""
+    FETCH_SIZE / WRITE_SIZE summary, or None when the counters were taken on
+    another workload or the kernel sources changed since."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic_bfs_persistent_kernel.json")
     try:
@@ -78,7 +78,7 @@ def measured_traffic():
         for src in rec["sources"]:
             with open(os.path.join(ROOT, src), "rb") as f:
                 h.update(f.read())
-        if h.hexdigest() != rec["source_sha1"]:
+        if h.hexdigest() != rec["source_sha1"] or rec["workload"] != workload:
             return None
         return rec["traffic_bytes_per_launch"]
     except (OSError, KeyError, ValueError):
@@ -370,6 +370,8 @@ def main():
     ap.add_argument("--alpha", type=int, default=14)
     ap.add_argument("--beta", type=int, default=24)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-certify", action="store_true",
+                    help="skip the on-device certificate of every root's output")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
@@ -456,6 +458,19 @@ def main():
     G.check()
     kernel_ms, total_ms = G.timings()
 
+    certified = None
+    if not args.no_certify:
+        # every root's output through the on-device O(nnz) certificate
+        # (outside the timed region)
+        certified = 0
+        for r in roots:
+            G.bfs(r, depth, parent, opts=plain)
+            code = G.certify(r, depth, parent)
+            if code != 0:
+                raise RuntimeError("certificate failed for root %d: code %d" % (r, code))
+            certified += 1
+        log("# certified %d roots on the device" % certified)
+
     m_c = [st["component_edges"] for st in stats]
     hmean = hmean_gteps(m_c, per_root_ms)
     ms_per_step = t_wall * 1e3 / args.steps
@@ -487,7 +502,9 @@ def main():
                    "n": n, "nnz": info["nnz"], "n_plus": n_sweep},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic(),
+                     "traffic": measured_traffic(
+                         "kronecker scale %d seed %d, %d roots, alpha %d beta %d"
+                         % (args.scale, args.seed, nroot, args.alpha, args.beta)),
                      "kernel": "bfs_persistent_kernel", "kernel_avg_ms": k_avg_ms,
                      "alg_bytes_avg": bytes_avg},
         "rcm_ms": rcm_ms,
@@ -495,6 +512,7 @@ def main():
         "gteps_search_kernel_only": hmean_internal,
         "translate_ms_avg": (sum(total_ms) - sum(kernel_ms)) / max(1, len(kernel_ms)),
         "levels_avg": sum(st["levels"] for st in stats) / nroot,
+        "certified_roots": certified,
         "device": dev,
     }
 

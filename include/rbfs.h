@@ -322,9 +322,11 @@ int rbfs_graph_get_tuning(const rbfs_graph_t* g, int32_t kind, rbfs_tuning_t* t)
  * defaults.  Each candidate runs once per root (compared entry by entry with
  * the reference) and then `reps` timed times.  The search is coordinate
  * descent over launch shape, lane_row, bu_grain, td_chunk and reset, starting
- * from the defaults; a change is kept when it is at least 1 % faster.  The
- * winner is set on the graph and copied to *best (nullable); records[cap]
- * (nullable) receives every candidate timed, *count (nullable) their number.
+ * from the defaults; a change is kept when it is at least 1 % faster, and
+ * the sweep over the parameters repeats while it changes anything (at most
+ * three sweeps).  The winner is set on the graph and copied to *best
+ * (nullable); records[cap] (nullable) receives every candidate timed, *count
+ * (nullable) their number.
  * A candidate whose outputs differ is never chosen and makes the call return
  * RBFS_E_DEVICE after it finishes (its record shows the mismatches).
  * Device memory: 8 * k * n bytes for the reference and 8 * n (single) or

@@ -8,7 +8,8 @@
 // number of edge-balanced bottom-up ranges per workgroup (the work-stealing
 // grain), the top-down chunk length of the edge-balanced expansion, and how
 // the internal arrays are cleared between searches.  The tuner times
-// candidates by coordinate descent from the built-in defaults and accepts a
+// candidates by coordinate descent from the built-in defaults (sweeps over
+// the parameters repeated until one moves nothing, at most three) and accepts a
 // candidate only if its depth and parent arrays equal, entry for entry, those
 // of the defaults on the same roots.
 #include <hip/hip_runtime.h>
@@ -25,15 +26,16 @@
 
 namespace rbfs {
 
+// The defaults are the tuner's winners on the Kronecker graphs of scale 26
+// (single-root and 64-root searches); scales 27 and 28 move only bu_grain.
 rbfs_tuning_t default_tuning(int kind) {
   rbfs_tuning_t t;
   t.block = 1024;
   t.per_cu = 1;
-  t.lane_row = kLaneRow;
-  t.bu_grain = 32;
+  t.lane_row = kind == RBFS_TUNE_BATCH ? 64 : 256;
+  t.bu_grain = kind == RBFS_TUNE_BATCH ? 128 : 64;
   t.td_chunk = kTdK * 1024;
   t.reset = 0;
-  (void)kind;
   return t;
 }
 
@@ -234,36 +236,44 @@ int descend(int kind, const std::vector<Dim>& dims, rbfs_tuning_t start, Apply a
   int64_t mism = 0;
   int rc = evaluate(best, &best_ms, &mism);
   if (rc) return rc;
-  for (const Dim& d : dims) {
-    rbfs_tuning_t dim_best = best;
-    float dim_ms = best_ms;
-    for (const auto& v : d.values) {
-      rbfs_tuning_t t = best;
-      d.set(t, v);
-      if (same_tuning(t, best) || !rbfs::tuning_valid(kind, t, nullptr)) continue;
-      float ms = 0.f;
-      rc = evaluate(t, &ms, &mism);
-      if (rc) return rc;
-      if (mism == 0 && ms < 0.99f * dim_ms) {
-        dim_best = t;
-        dim_ms = ms;
+  // sweeps over the dimensions until one moves nothing: a later dimension's
+  // move can change which value of an earlier one is best
+  constexpr int kMaxSweeps = 3;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    bool moved = false;
+    for (const Dim& d : dims) {
+      rbfs_tuning_t dim_best = best;
+      float dim_ms = best_ms;
+      for (const auto& v : d.values) {
+        rbfs_tuning_t t = best;
+        d.set(t, v);
+        if (same_tuning(t, best) || !rbfs::tuning_valid(kind, t, nullptr)) continue;
+        float ms = 0.f;
+        rc = evaluate(t, &ms, &mism);
+        if (rc) return rc;
+        if (mism == 0 && ms < 0.99f * dim_ms) {
+          dim_best = t;
+          dim_ms = ms;
+        }
+      }
+      if (!same_tuning(dim_best, best)) {
+        // re-time the winner against the incumbent once more before moving
+        float ms_new = 0.f, ms_old = 0.f;
+        rc = apply(dim_best);
+        if (!rc) rc = timed(reps, &ms_new);
+        if (!rc) rc = apply(best);
+        if (!rc) rc = timed(reps, &ms_old);
+        if (rc) return rc;
+        if (ms_new < 0.99f * ms_old) {
+          best = dim_best;
+          best_ms = ms_new;
+          moved = true;
+        } else {
+          best_ms = ms_old;
+        }
       }
     }
-    if (!same_tuning(dim_best, best)) {
-      // re-time the winner against the incumbent once more before moving
-      float ms_new = 0.f, ms_old = 0.f;
-      rc = apply(dim_best);
-      if (!rc) rc = timed(reps, &ms_new);
-      if (!rc) rc = apply(best);
-      if (!rc) rc = timed(reps, &ms_old);
-      if (rc) return rc;
-      if (ms_new < 0.99f * ms_old) {
-        best = dim_best;
-        best_ms = ms_new;
-      } else {
-        best_ms = ms_old;
-      }
-    }
+    if (!moved) break;
   }
   rc = apply(best);
   if (rc) return rc;
