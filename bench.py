@@ -15,6 +15,7 @@ import json
 import math
 import os
 import platform
+import statistics
 import sys
 import time
 
@@ -107,7 +108,7 @@ def cpu_baseline(off_dev, cols_dev, roots, budget_s=30.0):
 
 
 def time_roots(G, roots, depth, parent, opts, steps):
-    """Per-root event times (ms, mean over steps) on the current stream, and
+    """Per-root event times (ms, median over steps) on the current stream, and
     the wall time of all steps."""
     import torch
     stream = torch.cuda.current_stream()
@@ -122,7 +123,7 @@ def time_roots(G, roots, depth, parent, opts, steps):
             evs[s][i][1].record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    per_root = [sum(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(steps)) / steps
+    per_root = [statistics.median(evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(steps))
                 for i in range(len(roots))]
     return per_root, wall
 
@@ -458,17 +459,21 @@ def main():
     G.check()
     kernel_ms, total_ms = G.timings()
 
-    certified = None
-    if not args.no_certify:
-        # every root's output through the on-device O(nnz) certificate
-        # (outside the timed region)
-        certified = 0
-        for r in roots:
-            G.bfs(r, depth, parent, opts=plain)
+    # outside the timed region: every root's output through the on-device
+    # O(nnz) certificate, and the Graph500-style count of generated tuples
+    # with both endpoints reached (self-loops and duplicates included)
+    certified = None if args.no_certify else 0
+    tuples = []
+    for r in roots:
+        G.bfs(r, depth, parent, opts=plain)
+        if certified is not None:
             code = G.certify(r, depth, parent)
             if code != 0:
                 raise RuntimeError("certificate failed for root %d: code %d" % (r, code))
             certified += 1
+        tuples.append(graphgen.kronecker_tuples_reached_device(args.scale, depth,
+                                                               args.edgefactor, args.seed))
+    if certified is not None:
         log("# certified %d roots on the device" % certified)
 
     m_c = [st["component_edges"] for st in stats]
@@ -510,6 +515,8 @@ def main():
         "rcm_ms": rcm_ms,
         "gen_s": t_gen,
         "gteps_search_kernel_only": hmean_internal,
+        "gteps_graph500_tuples": hmean_gteps(tuples, per_root_ms),
+        "giant_component_root_fraction": sum(1 for m in m_c if m == max(m_c)) / nroot,
         "translate_ms_avg": (sum(total_ms) - sum(kernel_ms)) / max(1, len(kernel_ms)),
         "levels_avg": sum(st["levels"] for st in stats) / nroot,
         "certified_roots": certified,

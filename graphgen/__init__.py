@@ -59,6 +59,9 @@ def lib():
         L.gg_dev_kron_csr.restype = c.c_int64
         L.gg_dev_kron_csr.argtypes = [c.c_int, c.c_int64, c.c_uint64, c.c_double, c.c_double,
                                       c.c_double, c.c_void_p, c.c_void_p, c.c_int64, c.c_void_p]
+        L.gg_dev_kron_count_reached.restype = c.c_int64
+        L.gg_dev_kron_count_reached.argtypes = [c.c_int, c.c_int64, c.c_uint64, c.c_double,
+                                                c.c_double, c.c_double, c.c_void_p, c.c_void_p]
         L.gg_dev_cl_csr.restype = c.c_int64
         L.gg_dev_cl_csr.argtypes = [c.c_int64, c.c_int64, c.c_int64, c.c_uint64, c.c_void_p,
                                     c.c_void_p, c.c_void_p, c.c_int64, c.c_void_p]
@@ -181,6 +184,17 @@ def kronecker_csr_device(scale, edgefactor=16, seed=1, abc=KRON_ABC, device="cud
     if nnz < 0:
         raise RuntimeError("gg_dev_kron_csr: " + lib().gg_dev_last_error().decode())
     return off, cols[:nnz]
+
+
+def kronecker_tuples_reached_device(scale, depth, edgefactor=16, seed=1, abc=KRON_ABC):
+    """Tuples of kronecker_csr(scale, edgefactor, seed) (self-loops and
+    duplicates included) whose endpoints both have depth >= 0; depth is a
+    device int32 tensor indexed by vertex ID."""
+    r = lib().gg_dev_kron_count_reached(scale, edgefactor, seed, abc[0], abc[1], abc[2],
+                                        depth.data_ptr(), _torch_stream(depth.device))
+    if r < 0:
+        raise RuntimeError("gg_dev_kron_count_reached: " + lib().gg_dev_last_error().decode())
+    return int(r)
 
 
 def chung_lu_csr_device(ncore, n_iso, seed=1, gamma=2.1, mean_deg=30.0, max_deg=2.0e6,

@@ -65,6 +65,29 @@ __global__ void cl_keys_kernel(uint64_t key, gg_perm_t p, const double* cdf, int
   }
 }
 
+// Number of Kronecker tuples (self-loops and duplicates included) whose two
+// endpoints both have depth >= 0: the Graph500-style edge count of a search.
+__global__ void kron_count_reached_kernel(gg_kron_t k, gg_perm_t p, int64_t m,
+                                          const int32_t* depth, unsigned long long* count) {
+  __shared__ unsigned long long s_sum[256];
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  unsigned long long c = 0;
+  for (; e < m; e += stride) {
+    uint32_t u0, v0;
+    gg_kron_edge(k, e, &u0, &v0);
+    const uint32_t u = gg_perm_apply(p, u0), v = gg_perm_apply(p, v0);
+    c += (depth[u] >= 0 && depth[v] >= 0) ? 1ull : 0ull;
+  }
+  s_sum[threadIdx.x] = c;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) s_sum[threadIdx.x] += s_sum[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicAdd(count, s_sum[0]);
+}
+
 // keys: sorted unique (row << b | col) with the sentinel possibly last.
 __global__ void csr_from_keys_kernel(const uint64_t* keys, int64_t nnz, int64_t n, int b,
                                      int64_t* off, int32_t* cols) {
@@ -172,6 +195,36 @@ int64_t gg_dev_kron_csr(int scale, int64_t edgefactor, uint64_t seed, double A, 
   return r;
 fail:
   if (keys) (void)hipFree(keys);
+  return -4;
+}
+
+// Tuples of the same Kronecker graph with both endpoints reached (depth:
+// device int32[2^scale], indexed by vertex ID).  Returns the count, or a
+// negative value on error.  Synchronises `stream`.
+int64_t gg_dev_kron_count_reached(int scale, int64_t edgefactor, uint64_t seed, double A,
+                                  double B, double C, const int32_t* depth, void* stream_) {
+  hipStream_t stream = (hipStream_t)stream_;
+  if (scale < 1 || scale > 30 || edgefactor < 0 || !depth) {
+    g_err = "bad arguments";
+    return -1;
+  }
+  const int64_t n = (int64_t)1 << scale;
+  const int64_t m = edgefactor * n;
+  unsigned long long* d_count = nullptr;
+  unsigned long long h_count = 0;
+  gg_kron_t k = gg_kron_make(seed, scale, A, B, C);
+  gg_perm_t p = gg_perm_make(seed, n);
+  GG_CHECK(hipMalloc(&d_count, sizeof(unsigned long long)));
+  GG_CHECK(hipMemsetAsync(d_count, 0, sizeof(unsigned long long), stream));
+  hipLaunchKernelGGL(kron_count_reached_kernel, dim3(launch_blocks(m)), dim3(256), 0, stream, k,
+                     p, m, depth, d_count);
+  GG_CHECK(hipGetLastError());
+  GG_CHECK(hipMemcpyAsync(&h_count, d_count, sizeof(h_count), hipMemcpyDeviceToHost, stream));
+  GG_CHECK(hipStreamSynchronize(stream));
+  (void)hipFree(d_count);
+  return (int64_t)h_count;
+fail:
+  if (d_count) (void)hipFree(d_count);
   return -4;
 }
 

@@ -278,3 +278,20 @@ def test_device_generator_matches_host(rb):
                                                  mean_deg=10.0)
     assert np.array_equal(off_d.cpu().numpy(), off_h)
     assert np.array_equal(cols_d.cpu().numpy(), cols_h)
+
+
+def test_device_tuple_count_matches_host(rb):
+    """The benchmark's Graph500-style edge count: generated tuples with both
+    endpoints reached, on the device against the host tuples and the
+    oracle's depths."""
+    n, src, dst = graphgen.kronecker_tuples(12, 16, 5)
+    off, cols = graphgen.csr_from_tuples(n, src, dst)
+    for root in graphgen.sample_roots(off, 3, 3):
+        d_o, _, _ = oracle.bfs(off, cols, root)
+        want = int(np.sum((d_o[src] >= 0) & (d_o[dst] >= 0)))
+        got = graphgen.kronecker_tuples_reached_device(12, torch.from_numpy(d_o).cuda(), 16, 5)
+        assert got == want
+    iso = int(np.flatnonzero(np.diff(off) == 0)[0])
+    d_o, _, _ = oracle.bfs(off, cols, iso)
+    got = graphgen.kronecker_tuples_reached_device(12, torch.from_numpy(d_o).cuda(), 16, 5)
+    assert got == int(np.sum((src == iso) & (dst == iso)))
