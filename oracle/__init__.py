@@ -1,9 +1,9 @@
 """CPU oracle -- TEST INFRASTRUCTURE ONLY.
 
-Plain, slow, obviously correct reference for RCM relabelling (Algorithm 3)
-and the BFS result (Algorithms 1-2, predecessor map with the minimum-label
-parent rule), with per-level counters, the alpha/beta direction rule and
-O(nnz) certificates.  Only tests, the smoke check and the benchmark's
+Plain, slow, obviously correct reference for RCM relabelling (Algorithm 3,
+and the partial RCM of section 4.6) and the BFS result (Algorithms 1-2,
+predecessor map with the largest-label parent rule), with per-level
+counters, the alpha/beta direction rule and O(nnz) certificates.  Only tests, the smoke check and the benchmark's
 CPU-baseline leg import this package; the GPU library never does.
 
 The arithmetic lives in oracle.c (built into liboracle.so with gcc); this
@@ -35,6 +35,8 @@ def lib():
         L.orc_canonical_csr.argtypes = [c.c_int64, c.c_int64, P, P, P, P]
         L.orc_rcm.restype = c.c_int64
         L.orc_rcm.argtypes = [c.c_int64, P, P, P, P]
+        L.orc_rcm_partial.restype = c.c_int64
+        L.orc_rcm_partial.argtypes = [c.c_int64, P, P, c.c_int64, P, P]
         L.orc_bfs.restype = c.c_int32
         L.orc_bfs.argtypes = [c.c_int64, P, P, c.c_int32, P, P, P]
         L.orc_level_counters.restype = None
@@ -92,6 +94,24 @@ def rcm(off, cols):
     perm = np.empty(n, np.int32)
     nplus = lib().orc_rcm(n, _p(off), _p(cols), _p(P), _p(perm))
     return perm, P, int(nplus)
+
+
+def rcm_partial(off, cols, keep):
+    """Partial RCM (section 4.6): the first `keep` vertices of Algorithm 3's
+    Cuthill-McKee sequence reversed into labels [0, keep), the remaining
+    non-isolated vertices after them in increasing id, isolated vertices
+    last.  Returns (perm, iperm, nplus)."""
+    off, cols, n = _csr(off, cols)
+    P = np.empty(n, np.int32)
+    perm = np.empty(n, np.int32)
+    nplus = lib().orc_rcm_partial(n, _p(off), _p(cols), int(keep), _p(P), _p(perm))
+    return perm, P, int(nplus)
+
+
+def keep_for_ratio(p, nplus):
+    """Vertices a p-partial RCM reorders: ceil(p * n+), clamped to [0, n+]."""
+    import math
+    return max(0, min(nplus, math.ceil(p * nplus)))
 
 
 def bfs(off, cols, root, ell=None):

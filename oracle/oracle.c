@@ -18,6 +18,9 @@
  *                         (degree, id), per component a start of minimal
  *                         (degree, id), neighbours appended in (degree, id)
  *                         order, reversal, isolated vertices appended.
+ *   orc_rcm_partial       section 4.6 (partial RCM): Algorithm 3 cut off after
+ *                         a given number of vertices (reading stated at the
+ *                         function).
  *   orc_bfs               Algorithms 1-2 output: hop distance from the source
  *                         and the predecessor map (pi(s) = s, -1 when
  *                         unreachable) with the maximum-label parent rule.
@@ -94,9 +97,14 @@ static int cmp_deg_id(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
-/* P[k] = original vertex that receives label k; perm[v] = label of v.
- * Returns n+ = |V+|, the number of non-isolated vertices. */
-int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, int32_t* perm) {
+/* The Cuthill-McKee sequence of Algorithm 3 (before the reversal), cut off
+ * once `limit` vertices are in it: P[0..placed) in the order the algorithm
+ * appends them.  Components start at the unvisited vertex of least
+ * (degree, id); each vertex taken from the queue appends its unvisited
+ * neighbours in increasing (degree, id).  Returns the number placed,
+ * min(limit, n+); *nplus_out = n+ = |V+|. */
+static int64_t cm_sequence(int64_t n, const int64_t* off, const int32_t* cols, int64_t limit,
+                           int32_t* P, int64_t* nplus_out) {
   g_sort_off = off;
   /* V+: all non-isolated vertices, sorted by (degree, id). */
   int32_t* vplus = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
@@ -104,25 +112,25 @@ int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, 
   for (int64_t v = 0; v < n; ++v)
     if (off[v + 1] > off[v]) vplus[nplus++] = (int32_t)v;
   qsort(vplus, (size_t)nplus, sizeof(int32_t), cmp_deg_id);
+  if (limit > nplus) limit = nplus;
 
   char* visited = (char*)calloc((size_t)n + 1, 1);
   int32_t* nb = NULL; /* scratch for sorted_neighbors */
   int64_t nb_cap = 0;
   int64_t min_index = 0, slow = 0, fast = 0;
-  while (slow < nplus) {
+  while (fast < limit) {
     /* next unvisited vertex of minimal (degree, id) starts a component */
     for (int64_t i = min_index; i < nplus; ++i) {
       if (!visited[vplus[i]]) {
-        P[slow] = vplus[i];
+        P[fast++] = vplus[i];
         visited[vplus[i]] = 1;
         min_index = i + 1;
-        fast = slow + 1;
         break;
       }
     }
     /* explore the component, appending unvisited neighbours of P[slow] in
      * increasing (degree, id) order */
-    while (slow < fast) {
+    while (slow < fast && fast < limit) {
       int32_t u = P[slow];
       int64_t d = off[u + 1] - off[u];
       if (d > nb_cap) {
@@ -132,7 +140,7 @@ int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, 
       }
       memcpy(nb, cols + off[u], sizeof(int32_t) * d);
       qsort(nb, (size_t)d, sizeof(int32_t), cmp_deg_id);
-      for (int64_t j = 0; j < d; ++j) {
+      for (int64_t j = 0; j < d && fast < limit; ++j) {
         if (!visited[nb[j]]) {
           visited[nb[j]] = 1;
           P[fast++] = nb[j];
@@ -141,19 +149,56 @@ int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, 
       slow++;
     }
   }
-  /* reverse, then append the isolated vertices in increasing id */
-  for (int64_t i = 0, j = nplus - 1; i < j; ++i, --j) {
-    int32_t t = P[i];
-    P[i] = P[j];
-    P[j] = t;
+  free(nb);
+  free(visited);
+  free(vplus);
+  *nplus_out = nplus;
+  return fast;
+}
+
+static void reverse_i32(int32_t* a, int64_t len) {
+  for (int64_t i = 0, j = len - 1; i < j; ++i, --j) {
+    int32_t t = a[i];
+    a[i] = a[j];
+    a[j] = t;
   }
+}
+
+/* P[k] = original vertex that receives label k; perm[v] = label of v.
+ * Returns n+ = |V+|, the number of non-isolated vertices. */
+int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, int32_t* perm) {
+  int64_t nplus = 0;
+  cm_sequence(n, off, cols, n, P, &nplus);
+  /* reverse, then append the isolated vertices in increasing id */
+  reverse_i32(P, nplus);
   int64_t k = nplus;
   for (int64_t v = 0; v < n; ++v)
     if (off[v + 1] == off[v]) P[k++] = (int32_t)v;
   for (int64_t i = 0; i < n; ++i) perm[P[i]] = (int32_t)i;
-  free(nb);
-  free(visited);
-  free(vplus);
+  return nplus;
+}
+
+/* Partial RCM (section 4.6): only part of the vertices is reordered.
+ * Reading: the first `keep` vertices of Algorithm 3's Cuthill-McKee sequence
+ * take labels [0, keep) in reverse sequence order; the other non-isolated
+ * vertices follow in increasing id (their order is left alone); the
+ * isolated vertices come last in increasing id.  keep >= n+ is Algorithm 3
+ * itself; keep = 0 only moves the isolated vertices to the end.  A ratio p
+ * of the section maps to keep = ceil(p * n+).  Returns n+. */
+int64_t orc_rcm_partial(int64_t n, const int64_t* off, const int32_t* cols, int64_t keep,
+                        int32_t* P, int32_t* perm) {
+  int64_t nplus = 0;
+  const int64_t placed = cm_sequence(n, off, cols, keep < 0 ? 0 : keep, P, &nplus);
+  reverse_i32(P, placed);
+  char* in_seq = (char*)calloc((size_t)n + 1, 1);
+  for (int64_t i = 0; i < placed; ++i) in_seq[P[i]] = 1;
+  int64_t k = placed;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] > off[v] && !in_seq[v]) P[k++] = (int32_t)v;
+  for (int64_t v = 0; v < n; ++v)
+    if (off[v + 1] == off[v]) P[k++] = (int32_t)v;
+  for (int64_t i = 0; i < n; ++i) perm[P[i]] = (int32_t)i;
+  free(in_seq);
   return nplus;
 }
 

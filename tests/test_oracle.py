@@ -395,3 +395,63 @@ def test_component_edges_closed_form():
     off, cols = csr_of(k + 3, edges + [(k, k + 1)])
     depth, _, _ = oracle.bfs(off, cols, 0)
     assert oracle.component_edges(off, depth) == k * (k - 1) // 2
+
+
+# --------------------------------------------------------------------------
+# partial RCM (section 4.6), under the reading stated in the fixture file
+
+PARTIAL = os.path.join(os.path.dirname(__file__), "golden", "partial_rcm_worked_examples.json")
+with open(PARTIAL) as f:
+    PARTIAL_CASES = json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", PARTIAL_CASES, ids=[c["name"] for c in PARTIAL_CASES])
+def test_partial_rcm_worked_example(case):
+    off, cols = csr_of(case["n"], case["edges"])
+    for keep, want in case["iperm_by_keep"].items():
+        perm, iperm, nplus = oracle.rcm_partial(off, cols, int(keep))
+        assert nplus == case["nplus"]
+        assert iperm.tolist() == want, keep
+        assert np.array_equal(perm[iperm], np.arange(case["n"]))
+    # keep = n+ reproduces the full Algorithm 3 worked result
+    full = oracle.rcm(off, cols)[1]
+    assert full.tolist() == case["iperm_by_keep"][str(case["nplus"])]
+
+
+def partial_from_full(off, iperm_full, nplus, keep):
+    """The same order built from the full RCM: the reversed Cuthill-McKee
+    sequence holds sequence position j at label n+ - 1 - j, so its first
+    `keep` positions are the full labels [n+ - keep, n+)."""
+    head = list(iperm_full[nplus - keep:nplus])
+    rest = sorted(set(int(v) for v in np.flatnonzero(np.diff(off) > 0)) - set(head))
+    iso = [int(v) for v in np.flatnonzero(np.diff(off) == 0)]
+    return head + rest + iso
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_partial_rcm_is_a_prefix_of_the_full_sequence(seed):
+    rng = random.Random(3000 + seed)
+    n = rng.randint(2, 80)
+    (off, cols), _ = random_graph(rng, n, rng.choice([0.02, 0.05, 0.1, 0.3]), rng.randint(0, 5))
+    _, iperm_full, nplus = oracle.rcm(off, cols)
+    for keep in sorted({0, 1, nplus // 3, nplus // 2, nplus - 1, nplus, nplus + 7}):
+        keep = max(0, keep)
+        perm, iperm, np_ = oracle.rcm_partial(off, cols, keep)
+        assert np_ == nplus
+        assert iperm.tolist() == partial_from_full(off, iperm_full, nplus, min(keep, nplus))
+    # keep = 0: only the isolated vertices move (to the end)
+    iperm0 = oracle.rcm_partial(off, cols, 0)[1]
+    deg = np.diff(off)
+    assert iperm0.tolist() == (np.flatnonzero(deg > 0).tolist() + np.flatnonzero(deg == 0).tolist())
+
+
+def test_partial_rcm_kronecker_prefix():
+    off, cols = graphgen.kronecker_csr(11, 16, 9)
+    _, iperm_full, nplus = oracle.rcm(off, cols)
+    for p in (0.1, 0.5, 0.9):
+        keep = oracle.keep_for_ratio(p, nplus)
+        assert keep - 1 < p * nplus <= keep
+        iperm = oracle.rcm_partial(off, cols, keep)[1]
+        assert iperm.tolist() == partial_from_full(off, iperm_full, nplus, keep)
+    assert oracle.keep_for_ratio(1.0, nplus) == nplus
+    assert oracle.keep_for_ratio(0.0, nplus) == 0
