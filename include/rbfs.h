@@ -132,6 +132,8 @@ typedef struct rbfs_graph_info {
   int32_t device;     /* HIP device ordinal */
   int64_t max_degree;
   int64_t device_bytes; /* device memory held by the handle */
+  int64_t rcm_keep;   /* after a reorder: vertices placed by Cuthill-McKee
+                         (n_plus for the full RCM order); 0 before */
 } rbfs_graph_info_t;
 
 typedef struct rbfs_device_info {
@@ -198,6 +200,20 @@ int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
  * ms_out (nullable, host) receives the elapsed time.  Synchronises `stream`.
  * A second call returns RBFS_OK and changes nothing. */
 int rbfs_rcm_reorder(rbfs_graph_t* g, int32_t* perm_out, void* stream, float* ms_out);
+
+/* Partial RCM (section 4.6): as rbfs_rcm_reorder, but only the first `keep`
+ * vertices of Algorithm 3's Cuthill-McKee sequence are reordered.  They take
+ * labels [0, keep) in reverse sequence order; the other non-isolated
+ * vertices follow in increasing original ID; isolated vertices come last in
+ * increasing ID.  keep < 0 or keep >= n_plus gives exactly rbfs_rcm_reorder;
+ * keep = 0 only moves the isolated vertices to the end.  The paper's ratio p
+ * corresponds to keep = ceil(p * n_plus) (n_plus from rbfs_graph_info).  The
+ * search results follow the new labels like after the full order; since
+ * components no longer occupy label intervals, searches sweep all n_plus
+ * vertices.  After either reorder call, a second call of either returns
+ * RBFS_OK and changes nothing. */
+int rbfs_rcm_reorder_partial(rbfs_graph_t* g, int64_t keep, int32_t* perm_out, void* stream,
+                             float* ms_out);
 
 /* Inverse of the current relabelling: iperm_out[new] = old (device int32[n]).
  * Identity before rbfs_rcm_reorder. */

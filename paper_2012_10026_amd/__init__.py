@@ -8,6 +8,7 @@ binding without it raises, there is no fallback.
 """
 import atexit
 import ctypes
+import math
 import os
 import weakref
 
@@ -68,7 +69,8 @@ class Stats(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("n_plus", ctypes.c_int64),
                 ("reordered", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64)]
+                ("max_degree", ctypes.c_int64), ("device_bytes", ctypes.c_int64),
+                ("rcm_keep", ctypes.c_int64)]
 
 
 TUNE_SINGLE, TUNE_BATCH = 0, 1
@@ -115,6 +117,7 @@ SIGNATURES = {
     "rbfs_graph_check": (ctypes.c_int, [_P, _P]),
     "rbfs_graph_timings": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
     "rbfs_rcm_reorder": (ctypes.c_int, [_P, _P, _P, _P]),
+    "rbfs_rcm_reorder_partial": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
@@ -330,15 +333,26 @@ class Graph:
         _check(lib().rbfs_graph_info(self._h, ctypes.byref(i)))
         return {"n": i.n, "nnz": i.nnz, "n_plus": i.n_plus, "reordered": i.reordered,
                 "device": i.device, "max_degree": i.max_degree,
-                "device_bytes": i.device_bytes}
+                "device_bytes": i.device_bytes, "rcm_keep": i.rcm_keep}
 
-    def rcm_reorder(self, want_perm=True):
-        """Relabel by RCM; returns (perm tensor or None, milliseconds)."""
+    def rcm_reorder(self, want_perm=True, partial=None, keep=None):
+        """Relabel by RCM; returns (perm tensor or None, milliseconds).
+        partial=p (a ratio in [0, 1]) or keep=k reorders only the first
+        ceil(p * n_plus) (or k) vertices of the Cuthill-McKee sequence."""
         import torch
         perm = torch.empty(self.n, dtype=torch.int32, device=self.device) if want_perm else None
         ms = ctypes.c_float(0.0)
-        _check(lib().rbfs_rcm_reorder(self._h, _dptr(perm) if perm is not None else None,
-                                      _stream_ptr(self.device), ctypes.byref(ms)))
+        if partial is not None:
+            if keep is not None:
+                raise ValueError("give partial or keep, not both")
+            keep = math.ceil(float(partial) * self.info()["n_plus"])
+        pp = _dptr(perm) if perm is not None else None
+        if keep is None:
+            _check(lib().rbfs_rcm_reorder(self._h, pp, _stream_ptr(self.device),
+                                          ctypes.byref(ms)))
+        else:
+            _check(lib().rbfs_rcm_reorder_partial(self._h, int(keep), pp,
+                                                  _stream_ptr(self.device), ctypes.byref(ms)))
         return perm, ms.value
 
     def iperm(self):

@@ -345,6 +345,7 @@ int rbfs_graph_info(const rbfs_graph_t* h, rbfs_graph_info_t* out) {
   out->n = g->n;
   out->nnz = g->nnz;
   out->n_plus = g->n_plus;
+  out->rcm_keep = g->reordered ? g->rcm_keep : 0;
   out->reordered = g->reordered;
   out->device = g->device;
   out->max_degree = g->max_degree;
@@ -352,7 +353,8 @@ int rbfs_graph_info(const rbfs_graph_t* h, rbfs_graph_info_t* out) {
   return RBFS_OK;
 }
 
-int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream_, float* ms_out) {
+static int rcm_reorder_call(rbfs_graph_t* h, int64_t keep, int32_t* perm_out, void* stream_,
+                            float* ms_out) {
   if (!h) {
     set_error("rbfs_rcm_reorder: NULL graph");
     return RBFS_E_INVAL;
@@ -369,7 +371,7 @@ int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream_, float* m
       set_error("rbfs_rcm_reorder: empty graph");
       return RBFS_E_INVAL;
     }
-    rc = rbfs::rcm_reorder_impl(g, stream, ms_out);
+    rc = rbfs::rcm_reorder_impl(g, stream, ms_out, keep);
     if (rc) return rc;
   } else if (ms_out) {
     *ms_out = 0.f;
@@ -382,6 +384,15 @@ int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream_, float* m
   return RBFS_OK;
 fail:
   return rc;
+}
+
+int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream, float* ms_out) {
+  return rcm_reorder_call(h, -1, perm_out, stream, ms_out);
+}
+
+int rbfs_rcm_reorder_partial(rbfs_graph_t* h, int64_t keep, int32_t* perm_out, void* stream,
+                             float* ms_out) {
+  return rcm_reorder_call(h, keep, perm_out, stream, ms_out);
 }
 
 int rbfs_graph_iperm(const rbfs_graph_t* h, int32_t* iperm_out, void* stream_) {

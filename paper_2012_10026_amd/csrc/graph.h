@@ -145,6 +145,7 @@ struct Graph {
   int64_t n_sweep = 0;     // vertices the searches cover: n_plus after RCM, else n
   int64_t max_degree = 0;
   int reordered = 0;
+  int64_t rcm_keep = 0;    // after RCM: vertices of the Cuthill-McKee sequence reordered
   int64_t* off = nullptr;  // internal CSR
   int32_t* cols = nullptr;
   int32_t* perm = nullptr;   // original -> internal (after RCM)
@@ -165,7 +166,9 @@ struct Graph {
 // Sticky error text for the calling thread.
 void set_error(const std::string& msg);
 
-int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out);
+// keep < 0 or >= n+: the full RCM order; otherwise the partial order that
+// reorders only the first `keep` vertices of the Cuthill-McKee sequence.
+int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep = -1);
 int validate_csr_impl(Graph* g, hipStream_t stream);
 int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, int alpha,
              int beta, const int8_t* sched, int sched_len, int out_space, int flags,

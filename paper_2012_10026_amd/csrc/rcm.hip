@@ -23,6 +23,19 @@
 //   5. reverses the labels over V+, appends the isolated vertices in
 //      increasing id, and rebuilds the CSR in the new labels with every row
 //      ascending (one sort of (new row, new column) keys).
+//
+// Partial RCM (section 4.6) reorders only the first `keep` vertices of the
+// Cuthill-McKee sequence: they take labels [0, keep) in reverse sequence
+// order, the other non-isolated vertices follow in increasing id, isolated
+// vertices last.  A vertex's sequence position depends only on vertices
+// of smaller position (its level, the labels of the level before, the ranks
+// of its level), so the level loop seeds only the components that start
+// below `keep` and expands only vertices labelled below `keep`: every label
+// below `keep` comes out as in the full pass, and a vertex labelled later
+// (possibly at a wrong level, when its true parents were not expanded)
+// always gets a label of at least `keep`, because its component's next free
+// label has passed `keep` by then.  Within a level the labels rise with the
+// sorted position, so the vertices to expand next form a prefix.
 #include <hip/hip_runtime.h>
 
 #include <string>
@@ -171,10 +184,10 @@ __global__ void comp_bounds_kernel(const int32_t* ccp, const int64_t* cbase, con
 }
 
 __global__ void cm_roots_kernel(const int32_t* ccp, const int64_t* cbase, const int32_t* vplus,
-                                int64_t nplus, int32_t* label, int32_t* nextfree,
+                                int64_t nplus, int64_t keep, int32_t* label, int32_t* nextfree,
                                 int32_t* front, int32_t* front_count) {
   GRID_STRIDE(k, nplus) {
-    if (ccp[k] == (int32_t)k) {
+    if (ccp[k] == (int32_t)k && cbase[k] < keep) {
       const int32_t v = vplus[k];
       label[v] = (int32_t)cbase[k];
       nextfree[k] = (int32_t)cbase[k] + 1;
@@ -249,17 +262,29 @@ __global__ void cm_heads_kernel(const uint64_t* keys, int64_t m, int br, const i
   }
 }
 
+// Labels the sorted level and counts the entries labelled below `keep`
+// (they lead the level: labels rise with the sorted position).
 __global__ void cm_assign_kernel(const uint64_t* keys, int64_t m, int br, const int32_t* ccp,
                                  const int32_t* vplus, const int32_t* segstart,
-                                 const int32_t* nextfree, int32_t* label, int32_t* front) {
+                                 const int32_t* nextfree, int64_t keep, int32_t* label,
+                                 int32_t* front, int32_t* below_keep) {
   const uint64_t mask = (1ull << br) - 1ull;
-  GRID_STRIDE(i, m) {
-    const int32_t r = (int32_t)(keys[i] & mask);
-    const int32_t c = ccp[r];
-    const int32_t w = vplus[r];
-    const int32_t s = segstart[c];
-    label[w] = nextfree[c] + (int32_t)(i - s);
-    front[i] = w;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x;
+    bool low = false;
+    if (i < m) {
+      const int32_t r = (int32_t)(keys[i] & mask);
+      const int32_t c = ccp[r];
+      const int32_t w = vplus[r];
+      const int32_t s = segstart[c];
+      const int32_t lab = nextfree[c] + (int32_t)(i - s);
+      label[w] = lab;
+      front[i] = w;
+      low = lab < keep;
+    }
+    const uint64_t bm = ballot(low);
+    if (bm && lane_id() == ffs64(bm)) atomicAdd(below_keep, popc64(bm));
   }
 }
 
@@ -274,15 +299,33 @@ __global__ void cm_advance_kernel(const uint64_t* keys, int64_t m, int br, const
   }
 }
 
+// Vertices of V+ left out of a partial order (no label below keep).
+__global__ void rest_flag_kernel(const int32_t* deg, const int32_t* label, int64_t n,
+                                 int64_t keep, int32_t* flag) {
+  GRID_STRIDE(v, n) {
+    const int32_t l = label[v];
+    flag[v] = (deg[v] > 0 && !(l >= 0 && l < keep)) ? 1 : 0;
+  }
+}
+
+// Final labels: sequence position l < keep -> keep - 1 - l; the rest of V+
+// (pos_rest: their exclusive prefix count in id order; null when keep = n+)
+// -> keep + pos_rest; isolated -> n+ onwards in id order.
 __global__ void perm_kernel(const int32_t* deg, const int32_t* label, const int64_t* pos_nz,
-                            int64_t n, int64_t nplus, int32_t* perm, int32_t* iperm,
-                            int* status) {
+                            const int64_t* pos_rest, int64_t n, int64_t nplus, int64_t keep,
+                            int32_t* perm, int32_t* iperm, int* status) {
   GRID_STRIDE(v, n) {
     int64_t p;
     if (deg[v] > 0) {
       const int32_t l = label[v];
-      if (l < 0 || l >= nplus) atomicOr(status, kStatusBadInput);
-      p = nplus - 1 - l;
+      if (l >= 0 && l < keep) {
+        p = keep - 1 - l;
+      } else if (pos_rest) {
+        p = keep + pos_rest[v];
+      } else {
+        atomicOr(status, kStatusBadInput);
+        p = -1;
+      }
     } else {
       p = nplus + (v - pos_nz[v]);
     }
@@ -347,7 +390,7 @@ struct Bufs {
     }                                                                           \
   } while (0)
 
-int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
+int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_req) {
   const int64_t n = g->n, nnz = g->nnz;
   hipEvent_t e0, e1;
   RCM_CHECK(hipEventCreate(&e0));
@@ -366,7 +409,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   RCM_CHECK(B.alloc(&pos_nz, n + 1));
   RCM_CHECK(B.alloc(&d_max, 1));
   RCM_CHECK(B.alloc(&d_status, 1));
-  RCM_CHECK(B.alloc(&counts, 2));
+  RCM_CHECK(B.alloc(&counts, 3));
   RCM_CHECK(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), stream));
   RCM_CHECK(hipMemsetAsync(d_status, 0, sizeof(int), stream));
   hipLaunchKernelGGL(deg_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n, deg, nz,
@@ -378,6 +421,10 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   RCM_CHECK(hipMemcpyAsync(&nplus, pos_nz + n, sizeof(int64_t), hipMemcpyDeviceToHost, stream));
   RCM_CHECK(hipMemcpyAsync(&maxdeg, d_max, sizeof(maxdeg), hipMemcpyDeviceToHost, stream));
   RCM_CHECK(hipStreamSynchronize(stream));
+  // vertices of the Cuthill-McKee sequence that are reordered (all of V+
+  // unless a partial order is asked for)
+  const int64_t keep = (keep_req < 0 || keep_req > nplus) ? nplus : keep_req;
+  const bool partial = keep < nplus;
 
   // 1. V+ ranked by (degree, id)
   const int bv = bits_for(n);
@@ -445,9 +492,9 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   RCM_CHECK(B.alloc(&chunk_pos, chunk_cap));
   RCM_CHECK(hipMemsetAsync(label, 0xFF, sizeof(int32_t) * (size_t)n, stream));
   RCM_CHECK(hipMemsetAsync(plabel, 0xFF, sizeof(uint32_t) * (size_t)n, stream));
-  RCM_CHECK(hipMemsetAsync(counts, 0, sizeof(int32_t) * 2, stream));
+  RCM_CHECK(hipMemsetAsync(counts, 0, sizeof(int32_t) * 3, stream));
   hipLaunchKernelGGL(cm_roots_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp, cbase,
-                     vplus, nplus, label, nextfree, front, counts);
+                     vplus, nplus, keep, label, nextfree, front, counts);
   RCM_CHECK(hipGetLastError());
   int32_t nf = 0;
   RCM_CHECK(hipMemcpyAsync(&nf, counts, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -477,6 +524,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
     }
     int32_t m = 0;
     RCM_CHECK(hipMemcpyAsync(&m, counts + 1, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    RCM_CHECK(hipMemsetAsync(counts + 2, 0, sizeof(int32_t), stream));
     RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
     RCM_CHECK(hipStreamSynchronize(stream));
     if (status != 0 || m < 0 || m > nplus - labelled) {
@@ -494,18 +542,31 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
                          (int64_t)m, br, ccp, segstart);
       RCM_CHECK(hipGetLastError());
       hipLaunchKernelGGL(cm_assign_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
-                         (int64_t)m, br, ccp, vplus, segstart, nextfree, label, front);
+                         (int64_t)m, br, ccp, vplus, segstart, nextfree, keep, label, front,
+                         counts + 2);
       RCM_CHECK(hipGetLastError());
       hipLaunchKernelGGL(cm_advance_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
                          (int64_t)m, br, ccp, segstart, nextfree);
       RCM_CHECK(hipGetLastError());
     }
+    // the next level expands the prefix labelled below keep (all of it in
+    // a full pass)
+    int32_t below = 0;
+    if (m > 0) {
+      RCM_CHECK(hipMemcpyAsync(&below, counts + 2, sizeof(int32_t), hipMemcpyDeviceToHost,
+                               stream));
+      RCM_CHECK(hipStreamSynchronize(stream));
+    }
+    if (below < 0 || below > m || (!partial && below != m)) {
+      set_error("rcm_reorder: inconsistent level labels (corrupt or non-canonical CSR?)");
+      return -1;
+    }
     labelled += m;
-    nf = m;
+    nf = below;
   }
   RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
   RCM_CHECK(hipStreamSynchronize(stream));
-  if (status != 0 || labelled != nplus) {
+  if (status != 0 || labelled > nplus || (!partial && labelled != nplus)) {
     set_error("rcm_reorder: inconsistent labelling (corrupt or non-canonical CSR?)");
     return -1;
   }
@@ -513,8 +574,27 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   // 5. reversal, isolated vertices, relabelled CSR
   RCM_CHECK(B.alloc(&perm, n));
   RCM_CHECK(B.alloc(&iperm, n));
+  int64_t* pos_rest = nullptr;
+  if (partial) {
+    // the rest of V+ keeps its id order: exclusive count of rest vertices
+    int32_t* rflag = nullptr;
+    RCM_CHECK(B.alloc(&rflag, n));
+    RCM_CHECK(B.alloc(&pos_rest, n + 1));
+    hipLaunchKernelGGL(rest_flag_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, deg, label,
+                       n, keep, rflag);
+    RCM_CHECK(hipGetLastError());
+    RCM_CHECK(scan_exclusive_i32(rflag, pos_rest, n, g->scratch, stream));
+    int64_t nrest = 0;
+    RCM_CHECK(hipMemcpyAsync(&nrest, pos_rest + n, sizeof(int64_t), hipMemcpyDeviceToHost,
+                             stream));
+    RCM_CHECK(hipStreamSynchronize(stream));
+    if (nrest != nplus - keep) {
+      set_error("rcm_reorder: inconsistent partial labelling (corrupt or non-canonical CSR?)");
+      return -1;
+    }
+  }
   hipLaunchKernelGGL(perm_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, deg, label, pos_nz,
-                     n, nplus, perm, iperm, d_status);
+                     pos_rest, n, nplus, keep, perm, iperm, d_status);
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(B.alloc(&newdeg, n));
   RCM_CHECK(B.alloc(&newoff, n + 1));
@@ -555,17 +635,20 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out) {
   g->cols = newcols;
   g->perm = perm;
   g->iperm = iperm;
-  g->comp_bounds = bounds;
-  g->n_comp = ncomp;
+  // a partial order does not keep components in label intervals: searches
+  // then sweep all of V+
+  g->comp_bounds = partial ? nullptr : bounds;
+  g->n_comp = partial ? 0 : ncomp;
   B.forget(newoff);
   B.forget(newcols);
   B.forget(perm);
   B.forget(iperm);
-  B.forget(bounds);
+  if (!partial) B.forget(bounds);
   g->n_plus = nplus;
   g->n_sweep = nplus;
   g->reordered = 1;
-  g->bytes += sizeof(int32_t) * 2 * (size_t)n + sizeof(int32_t) * (size_t)(ncomp + 1);
+  g->rcm_keep = keep;
+  g->bytes += sizeof(int32_t) * 2 * (size_t)n + (partial ? 0 : sizeof(int32_t) * (size_t)(ncomp + 1));
   free_bfs_work(g);
   free_ms_work(g);
   g->scratch.release();
