@@ -271,8 +271,11 @@ ABLATION_GRAPHS = {
 
 def ablation(rb, graphgen, args):
     """Locality study: the same searches on the graph as generated (random
-    labels) and after RCM, on Kronecker scales 22-26 and the 52.5 M-vertex
-    Chung-Lu graph.  One JSON line per (graph, variant)."""
+    labels), after RCM, and after partial RCM (variant "p<ratio>", e.g. p0.25:
+    the first ceil(ratio * n+) vertices of the Cuthill-McKee sequence
+    reordered, p0 only moving isolated vertices to the end), on Kronecker
+    scales 22-26 and the 52.5 M-vertex Chung-Lu graph.  One JSON line per
+    (graph, variant)."""
     import torch
     names = args.ablation_graphs.split(",")
     variants = args.ablation_variants.split(",")
@@ -293,6 +296,11 @@ def ablation(rb, graphgen, args):
             rcm_ms = None
             if variant == "rcm":
                 _, rcm_ms = G.rcm_reorder(want_perm=False)
+            elif variant.startswith("p"):
+                _, rcm_ms = G.rcm_reorder(want_perm=False, partial=float(variant[1:]))
+            elif variant != "original":
+                raise ValueError("unknown variant %r" % variant)
+            reordered = variant != "original"
             t = cache.get(rb.tuning_key(arch, "kronecker", n, rb.TUNE_SINGLE))
             if t is not None:
                 G.set_tuning(t)
@@ -305,8 +313,8 @@ def ablation(rb, graphgen, args):
             G.check()
             info = G.info()
             m_c = [st["component_edges"] for st in stats]
-            n_sweep = info["n_plus"] if variant == "rcm" else n
-            alg = sum(bfs_alg_bytes(st, n_sweep, original_ids=variant == "rcm")
+            n_sweep = info["n_plus"] if reordered else n
+            alg = sum(bfs_alg_bytes(st, n_sweep, original_ids=reordered)
                       for st in stats) / len(stats)
             k_ms = sum(kernel_ms) / len(kernel_ms)
             print(json.dumps({
@@ -320,10 +328,12 @@ def ablation(rb, graphgen, args):
                 "edges_examined_avg": sum(sum(st["edges"][:st["levels"]]) for st in stats)
                 / len(stats),
                 "alg_bytes_avg": alg, "achieved_gbs": alg / (k_ms * 1e-3) / 1e9,
-                "rcm_ms": rcm_ms, "tuning": G.get_tuning()}), flush=True)
+                "rcm_ms": rcm_ms, "rcm_keep": info["rcm_keep"],
+                "tuning": G.get_tuning()}), flush=True)
             G.close()
             del G
-            torch.cuda.empty_cache()
+            # the allocator keeps its blocks between variants, so each RCM's
+            # time is that of its kernels rather than of fresh hipMallocs
         del off, cols, roots, depth, parent
         torch.cuda.empty_cache()
 
