@@ -399,6 +399,8 @@ def main():
     ap.add_argument("--ablation-graphs", default="kron22,kron24,kron26,chunglu")
     ap.add_argument("--ablation-variants", default="original,rcm")
     ap.add_argument("--ablation-roots", type=int, default=16)
+    ap.add_argument("--rcm-only", action="store_true",
+                    help="generate the graph, time its RCM relabelling, print one JSON line")
     ap.add_argument("--ab-grid", action="store_true",
                     help="run the alpha/beta grid search of the plain search instead")
     ap.add_argument("--ab-alphas", default="2,4,8,14,24,48,96")
@@ -421,6 +423,17 @@ def main():
         return
     if args.ab_grid:
         ab_grid(rb, graphgen, args)
+        return
+    if args.rcm_only:
+        # the relabelling alone (for kernel traces of its passes)
+        off, cols = graphgen.kronecker_csr_device(args.scale, args.edgefactor, args.seed)
+        G = rb.Graph(off, cols)
+        del off, cols
+        torch.cuda.empty_cache()
+        _, rcm_ms = G.rcm_reorder(want_perm=False)
+        info = G.info()
+        print(json.dumps({"rcm_ms": rcm_ms, "scale": args.scale, "n": info["n"],
+                          "nnz": info["nnz"], "n_plus": info["n_plus"]}), flush=True)
         return
     dev = rb.device_info()
     t0 = time.perf_counter()
