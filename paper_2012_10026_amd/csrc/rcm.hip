@@ -183,13 +183,18 @@ __global__ void comp_bounds_kernel(const int32_t* ccp, const int64_t* cbase, con
   if (blockIdx.x == 0 && threadIdx.x == 0) bounds[0] = 0;
 }
 
+__device__ __forceinline__ void set_labelled(uint64_t* lbits, int32_t v) {
+  atomicOr((unsigned long long*)&lbits[v >> 6], 1ull << (v & 63));
+}
+
 __global__ void cm_roots_kernel(const int32_t* ccp, const int64_t* cbase, const int32_t* vplus,
-                                int64_t nplus, int64_t keep, int32_t* label, int32_t* nextfree,
-                                int32_t* front, int32_t* front_count) {
+                                int64_t nplus, int64_t keep, int32_t* label, uint64_t* lbits,
+                                int32_t* nextfree, int32_t* front, int32_t* front_count) {
   GRID_STRIDE(k, nplus) {
     if (ccp[k] == (int32_t)k && cbase[k] < keep) {
       const int32_t v = vplus[k];
       label[v] = (int32_t)cbase[k];
+      set_labelled(lbits, v);
       nextfree[k] = (int32_t)cbase[k] + 1;
       const int pos = atomicAdd(front_count, 1);
       front[pos] = v;
@@ -207,34 +212,74 @@ __global__ void mark_kernel(const int64_t* qe, int64_t nq, int32_t* chunk_pos, i
 }
 
 // CM expansion of one level: every unlabelled neighbour w takes the minimum
-// label of its frontier neighbours; the first to touch w appends it.
+// label of its frontier neighbours; the first to touch w appends it.  Most
+// edges of a level lead to labelled vertices; the labelled-vertex bitmap
+// (n / 8 bytes, cache resident) rules them out without reading label[w].
+// Four entries per thread are in flight at once.  The appended vertices are
+// gathered in LDS and published a batch at a time, so the one global
+// counter of the next level sees one atomic per batch instead of one per
+// wave and round.
+constexpr int kCmK = 4;
+constexpr int kCmStage = 2048;  // LDS batch; a chunk appends at most kCmK * kBlock
+
+__device__ __forceinline__ void cm_publish(const int32_t* s_new, int* s_cnt, int* s_base,
+                                           int32_t* next, int32_t* next_count, int64_t next_cap,
+                                           int* status) {
+  const int cnt = *s_cnt;  // read after a barrier
+  if (cnt > 0) {
+    if (threadIdx.x == 0) *s_base = atomicAdd(next_count, cnt);
+    __syncthreads();
+    const int64_t base = *s_base;
+    for (int i = threadIdx.x; i < cnt; i += kBlock) {
+      if (base + i < next_cap) next[base + i] = s_new[i];
+      else atomicOr(status, kStatusOverflow);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *s_cnt = 0;
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void cm_expand_kernel(
     const int32_t* front, const int64_t* qe, int64_t nq, int64_t E, const int32_t* chunk_pos,
     int64_t nchunks, const int64_t* off, const int32_t* cols, const int32_t* label,
-    uint32_t* plabel, int32_t* next, int32_t* next_count, int64_t next_cap, int* status) {
-  __shared__ ChunkLds s;
+    const uint64_t* lbits, uint32_t* plabel, int32_t* next, int32_t* next_count,
+    int64_t next_cap, int* status) {
+  __shared__ ChunkLdsB<kCmK * kBlock> s;
+  __shared__ int32_t s_new[kCmStage];
+  __shared__ int s_cnt, s_base;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
   for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const bool ok = expand_chunk<kBlock>(s, c, E, front, qe, nq, chunk_pos, nchunks, off, cols,
-                                 [&](bool active, int32_t u, int32_t w) {
-      bool first = false;
-      if (active && label[w] < 0) {
+    const bool ok = expand_chunk_batch<kBlock, kCmK>(
+        s, c, E, front, qe, nq, chunk_pos, nchunks, off, cols, kChunkShift,
+        [&](const bool* act, const int32_t* u, const int32_t* w) {
+      bool cand[kCmK], first[kCmK];
+      uint32_t lu[kCmK], pl[kCmK];
+#pragma unroll
+      for (int r = 0; r < kCmK; ++r)
+        cand[r] = act[r] && !((lbits[w[r] >> 6] >> (w[r] & 63)) & 1ull);
+#pragma unroll
+      for (int r = 0; r < kCmK; ++r) {
+        lu[r] = cand[r] ? (uint32_t)label[u[r]] : 0u;
+        pl[r] = cand[r] ? plabel[w[r]] : 0u;
+      }
+#pragma unroll
+      for (int r = 0; r < kCmK; ++r) {
         // a stale read can only be larger: skip the atomic when w already
         // holds a label no larger than u's (then w was touched before)
-        const uint32_t lu = (uint32_t)label[u];
-        if (plabel[w] > lu) {
-          const uint32_t old = atomicMin(&plabel[w], lu);
-          first = (old == kUnset);
-        }
+        first[r] = false;
+        if (cand[r] && pl[r] > lu[r]) first[r] = atomicMin(&plabel[w[r]], lu[r]) == kUnset;
       }
-      const uint64_t m = ballot(first);
-      if (m) {
-        const int leader = ffs64(m);
-        int base = 0;
-        if (lane_id() == leader) base = atomicAdd(next_count, popc64(m));
-        base = shfl(base, leader);
-        const int64_t pos = (int64_t)base + popc64(m & lanemask_lt());
-        if (first) {
-          if (pos < next_cap) next[pos] = w; else atomicOr(status, kStatusOverflow);
+#pragma unroll
+      for (int r = 0; r < kCmK; ++r) {
+        const uint64_t m = ballot(first[r]);
+        if (m) {
+          const int leader = ffs64(m);
+          int base = 0;
+          if (lane_id() == leader) base = atomicAdd(&s_cnt, popc64(m));
+          base = shfl(base, leader);
+          if (first[r]) s_new[base + popc64(m & lanemask_lt())] = w[r];
         }
       }
     });
@@ -242,7 +287,11 @@ __global__ __launch_bounds__(kBlock) void cm_expand_kernel(
       if (threadIdx.x == 0) atomicOr(status, kStatusBadInput);
       return;
     }
+    // expand_chunk_batch ends with a barrier: s_cnt is final for the chunk
+    if (s_cnt > kCmStage - kCmK * kBlock)
+      cm_publish(s_new, &s_cnt, &s_base, next, next_count, next_cap, status);
   }
+  cm_publish(s_new, &s_cnt, &s_base, next, next_count, next_cap, status);
 }
 
 __global__ void cm_keys_kernel(const int32_t* next, int64_t m, const uint32_t* plabel,
@@ -267,7 +316,7 @@ __global__ void cm_heads_kernel(const uint64_t* keys, int64_t m, int br, const i
 __global__ void cm_assign_kernel(const uint64_t* keys, int64_t m, int br, const int32_t* ccp,
                                  const int32_t* vplus, const int32_t* segstart,
                                  const int32_t* nextfree, int64_t keep, int32_t* label,
-                                 int32_t* front, int32_t* below_keep) {
+                                 uint64_t* lbits, int32_t* front, int32_t* below_keep) {
   const uint64_t mask = (1ull << br) - 1ull;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i0 = (int64_t)blockIdx.x * blockDim.x; i0 < m; i0 += stride) {
@@ -280,6 +329,7 @@ __global__ void cm_assign_kernel(const uint64_t* keys, int64_t m, int br, const 
       const int32_t s = segstart[c];
       const int32_t lab = nextfree[c] + (int32_t)(i - s);
       label[w] = lab;
+      set_labelled(lbits, w);
       front[i] = w;
       low = lab < keep;
     }
@@ -480,7 +530,9 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   RCM_CHECK(hipGetLastError());
 
   // 4. level-synchronous Cuthill-McKee over all components
+  uint64_t* lbits = nullptr;  // labelled vertices, one bit each
   RCM_CHECK(B.alloc(&label, n));
+  RCM_CHECK(B.alloc(&lbits, ceil_div(n, kWave)));
   RCM_CHECK(B.alloc(&plabel, n));
   RCM_CHECK(B.alloc(&nextfree, nplus));
   RCM_CHECK(B.alloc(&front, nplus));
@@ -492,9 +544,10 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   RCM_CHECK(B.alloc(&chunk_pos, chunk_cap));
   RCM_CHECK(hipMemsetAsync(label, 0xFF, sizeof(int32_t) * (size_t)n, stream));
   RCM_CHECK(hipMemsetAsync(plabel, 0xFF, sizeof(uint32_t) * (size_t)n, stream));
+  RCM_CHECK(hipMemsetAsync(lbits, 0, sizeof(uint64_t) * (size_t)ceil_div(n, kWave), stream));
   RCM_CHECK(hipMemsetAsync(counts, 0, sizeof(int32_t) * 3, stream));
   hipLaunchKernelGGL(cm_roots_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp, cbase,
-                     vplus, nplus, keep, label, nextfree, front, counts);
+                     vplus, nplus, keep, label, lbits, nextfree, front, counts);
   RCM_CHECK(hipGetLastError());
   int32_t nf = 0;
   RCM_CHECK(hipMemcpyAsync(&nf, counts, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
@@ -518,8 +571,8 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
     if (nchunks > 0) {
       const int64_t gx = nchunks < 65536 ? nchunks : 65536;
       hipLaunchKernelGGL(cm_expand_kernel, dim3((unsigned)gx), dim3(kBlock), 0, stream, front, qe,
-                         (int64_t)nf, E, chunk_pos, nchunks, g->off, g->cols, label, plabel, next,
-                         counts + 1, nplus, d_status);
+                         (int64_t)nf, E, chunk_pos, nchunks, g->off, g->cols, label, lbits, plabel,
+                         next, counts + 1, nplus, d_status);
       RCM_CHECK(hipGetLastError());
     }
     int32_t m = 0;
@@ -542,8 +595,8 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
                          (int64_t)m, br, ccp, segstart);
       RCM_CHECK(hipGetLastError());
       hipLaunchKernelGGL(cm_assign_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
-                         (int64_t)m, br, ccp, vplus, segstart, nextfree, keep, label, front,
-                         counts + 2);
+                         (int64_t)m, br, ccp, vplus, segstart, nextfree, keep, label, lbits,
+                         front, counts + 2);
       RCM_CHECK(hipGetLastError());
       hipLaunchKernelGGL(cm_advance_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
                          (int64_t)m, br, ccp, segstart, nextfree);
