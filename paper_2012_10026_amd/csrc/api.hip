@@ -50,8 +50,12 @@ namespace {
 constexpr int kVBadOffsets = 1, kVColRange = 2, kVSelfLoop = 4, kVUnsorted = 8,
               kVAsymmetric = 16;
 
+// The degree maximum and the non-isolated count are reduced per wave over
+// the wave's whole grid-stride share: one atomic per wave on each of the two
+// words, and few waves (the launch uses kFoldBlocks workgroups).
 __global__ void check_offsets_kernel(const int64_t* off, int64_t n, int64_t nnz, int* flags,
                                      unsigned long long* maxdeg, unsigned long long* nonzero) {
+  int64_t dmax = 0, nz = 0;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     const int64_t a = off[v], b = off[v + 1];
@@ -60,9 +64,15 @@ __global__ void check_offsets_kernel(const int64_t* off, int64_t n, int64_t nnz,
       continue;
     }
     if (b > a) {
-      atomicMax(maxdeg, (unsigned long long)(b - a));
-      atomicAdd(nonzero, 1ull);
+      dmax = (b - a) > dmax ? (b - a) : dmax;
+      ++nz;
     }
+  }
+  dmax = wave_max(dmax);
+  nz = wave_sum(nz);
+  if (lane_id() == 0 && nz > 0) {
+    atomicMax(maxdeg, (unsigned long long)dmax);
+    atomicAdd(nonzero, (unsigned long long)nz);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && (off[0] != 0 || off[n] != nnz))
     atomicOr(flags, kVBadOffsets);
@@ -159,7 +169,9 @@ static int graph_setup(Graph* g, uint32_t flags, hipStream_t stream) {
   API_CHECK(rbfs::dev_malloc(&d_stats, 2 * sizeof(unsigned long long)));
   API_CHECK(hipMemsetAsync(d_flags, 0, sizeof(int), stream));
   API_CHECK(hipMemsetAsync(d_stats, 0, 2 * sizeof(unsigned long long), stream));
-  hipLaunchKernelGGL(check_offsets_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n,
+  hipLaunchKernelGGL(check_offsets_kernel,
+                     dim3((unsigned)std::min<int64_t>(grid_for(n), kFoldBlocks)), dim3(kBlock),
+                     0, stream, g->off, n,
                      nnz, d_flags, d_stats, d_stats + 1);
   API_CHECK(hipGetLastError());
   if (nnz > 0) {

@@ -707,10 +707,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       flush_list(s_st, vl_out, vlcnt, P.qstride, ctl);
       flush_stage(s_st, P, qn, qpack);
     }
-    const int64_t ex = wave_sum(examined);
-    if (l == 0 && ex)
-      __hip_atomic_fetch_add(&ctl->edges[n3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    block_fold_add(&ctl->edges[n3][0], examined);
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
     // ---- next level: every workgroup decides the same way.  Sizes of the

@@ -490,13 +490,8 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
       }
       ms_flush(s_st, P, qn, qpack);
     }
-    const int64_t ex = wave_sum(examined), dn = wave_sum(done);
-    if (l == 0 && ex)
-      __hip_atomic_fetch_add(&ctl->edges[n3][0], (unsigned long long)ex, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
-    if (l == 0 && dn)
-      __hip_atomic_fetch_add(&ctl->done_deg[n3][0], (unsigned long long)dn, __ATOMIC_RELAXED,
-                             __HIP_MEMORY_SCOPE_AGENT);
+    block_fold_add(&ctl->edges[n3][0], examined);
+    block_fold_add(&ctl->done_deg[n3][0], done);
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
     const unsigned long long pk =

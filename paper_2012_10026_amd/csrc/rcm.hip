@@ -58,18 +58,30 @@ int grid_for(int64_t work) {
   return (int)b;
 }
 
+// Grid of a grid-stride kernel that folds a shared counter once per wave:
+// few enough waves that the same-address atomics stay cheap (each costs
+// about 10 ns, in series), enough workgroups to fill the GPU.
+int grid_folding(int64_t work) {
+  const int b = grid_for(work);
+  return b < kFoldBlocks ? b : kFoldBlocks;
+}
+
 #define GRID_STRIDE(i, n) \
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < (n); \
        i += (int64_t)gridDim.x * blockDim.x)
 
 __global__ void deg_kernel(const int64_t* off, int64_t n, int32_t* deg, int32_t* nz,
                            unsigned long long* maxdeg) {
+  int64_t dmax = 0;
   GRID_STRIDE(v, n) {
     const int64_t d = off[v + 1] - off[v];
     deg[v] = (int32_t)d;
     nz[v] = d > 0 ? 1 : 0;
-    if (d > 0) atomicMax(maxdeg, (unsigned long long)d);
+    dmax = d > dmax ? d : dmax;
   }
+  // one atomic per wave on the shared maximum
+  dmax = wave_max(dmax);
+  if (lane_id() == 0 && dmax > 0) atomicMax(maxdeg, (unsigned long long)dmax);
 }
 
 __global__ void deg_keys_kernel(const int32_t* deg, const int64_t* pos_nz, int64_t n, int bv,
@@ -138,11 +150,14 @@ __global__ __launch_bounds__(kBlock) void cc_union_kernel(const int64_t* off, co
 }
 
 // Final root of every rank and the component sizes.  One component usually
-// holds almost every vertex, so the size counts are aggregated per wave
-// (lanes with the wave's first root add with one atomic) instead of one
-// same-address atomic per vertex.
+// holds almost every vertex, so the size counts are aggregated per wave: the
+// lanes holding the wave's running root add to a register, flushed with one
+// atomic when the root changes and at the end, instead of one same-address
+// atomic per vertex or per batch.
 __global__ void cc_compress_kernel(int32_t* ccp, int64_t nplus, int32_t* csize) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int32_t run_root = -1;  // the same in every lane
+  int run_cnt = 0;        // lane 0's tally for run_root
   for (int64_t k0 = (int64_t)blockIdx.x * blockDim.x; k0 < nplus; k0 += stride) {
     const int64_t k = k0 + threadIdx.x;
     const bool act = k < nplus;
@@ -159,11 +174,17 @@ __global__ void cc_compress_kernel(int32_t* ccp, int64_t nplus, int32_t* csize) 
     const uint64_t am = ballot(act);
     if (am == 0) continue;
     const int32_t p0 = shfl(p, ffs64(am));
+    if (p0 != run_root) {
+      if (lane_id() == 0 && run_cnt > 0) atomicAdd(&csize[run_root], run_cnt);
+      run_root = p0;
+      run_cnt = 0;
+    }
     const bool same = act && p == p0;
     const uint64_t sm = ballot(same);
-    if (lane_id() == ffs64(sm)) atomicAdd(&csize[p0], popc64(sm));
+    if (lane_id() == 0) run_cnt += popc64(sm);
     if (act && !same) atomicAdd(&csize[p], 1);
   }
+  if (lane_id() == 0 && run_cnt > 0) atomicAdd(&csize[run_root], run_cnt);
 }
 
 // Component boundaries in the final (reversed) labelling.  Component roots
@@ -462,7 +483,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   RCM_CHECK(B.alloc(&counts, 3));
   RCM_CHECK(hipMemsetAsync(d_max, 0, sizeof(unsigned long long), stream));
   RCM_CHECK(hipMemsetAsync(d_status, 0, sizeof(int), stream));
-  hipLaunchKernelGGL(deg_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off, n, deg, nz,
+  hipLaunchKernelGGL(deg_kernel, dim3(grid_folding(n)), dim3(kBlock), 0, stream, g->off, n, deg, nz,
                      d_max);
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(scan_exclusive_i32(nz, pos_nz, n, g->scratch, stream));
@@ -506,7 +527,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   RCM_CHECK(B.alloc(&csize, nplus));
   RCM_CHECK(B.alloc(&cbase, nplus + 1));
   RCM_CHECK(hipMemsetAsync(csize, 0, sizeof(int32_t) * (nplus > 0 ? nplus : 1), stream));
-  hipLaunchKernelGGL(cc_compress_kernel, dim3(grid_for(nplus)), dim3(kBlock), 0, stream, ccp,
+  hipLaunchKernelGGL(cc_compress_kernel, dim3(grid_folding(nplus)), dim3(kBlock), 0, stream, ccp,
                      nplus, csize);
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(scan_exclusive_i32(csize, cbase, nplus, g->scratch, stream));
@@ -594,7 +615,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
       hipLaunchKernelGGL(cm_heads_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
                          (int64_t)m, br, ccp, segstart);
       RCM_CHECK(hipGetLastError());
-      hipLaunchKernelGGL(cm_assign_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1,
+      hipLaunchKernelGGL(cm_assign_kernel, dim3(grid_folding(m)), dim3(kBlock), 0, stream, k1,
                          (int64_t)m, br, ccp, vplus, segstart, nextfree, keep, label, lbits,
                          front, counts + 2);
       RCM_CHECK(hipGetLastError());
