@@ -487,15 +487,18 @@ def main():
     # with both endpoints reached (self-loops and duplicates included)
     certified = None if args.no_certify else 0
     tuples = []
-    for r in roots:
+    for i, r in enumerate(roots):
+        # a root that the previous search reached has the same component,
+        # hence the same tuple count
+        same = i > 0 and int(depth[r].item()) >= 0
         G.bfs(r, depth, parent, opts=plain)
         if certified is not None:
             code = G.certify(r, depth, parent)
             if code != 0:
                 raise RuntimeError("certificate failed for root %d: code %d" % (r, code))
             certified += 1
-        tuples.append(graphgen.kronecker_tuples_reached_device(args.scale, depth,
-                                                               args.edgefactor, args.seed))
+        tuples.append(tuples[-1] if same else graphgen.kronecker_tuples_reached_device(
+            args.scale, depth, args.edgefactor, args.seed))
     if certified is not None:
         log("# certified %d roots on the device" % certified)
 

@@ -78,7 +78,7 @@ struct alignas(128) BfsCtl {
 
 namespace {
 
-constexpr int kStage = 256;  // staged appends per wave
+constexpr int kStage = 384;  // staged appends per wave
 // The next frontier (and the bottom-up vertex list) is split into kNQ
 // sub-queues, one per group of workgroups (blockIdx mod kNQ, i.e. one per
 // XCD), each behind its own packed counter: a single grid-wide counter
