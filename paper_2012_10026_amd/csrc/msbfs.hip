@@ -536,54 +536,70 @@ __global__ void ms_reset_ctl_kernel(MsCtl* c) {
     p[i] = 0;
 }
 
-// Root-major output of one graph: out[j][v] for j < k and original IDs v of
-// the graph, as a tiled transpose through LDS.  A workgroup takes 64
-// consecutive original IDs: each wave reads the packed internal rows of 16 of
-// them (lane = root, one coalesced 512-byte row per vertex, reset to "none"
-// as it goes), then writes 16 of the root rows (lane = vertex, coalesced).
-// Parents go back to original IDs through oid (reusing the last lookup: the
-// roots of a vertex often share a parent).  Isolated vertices get -1;
-// isolated roots are fixed up by ms_roots_fixup_kernel.
-constexpr int kTrBlock = 256;
+// Root-major outputs, indexed by and holding original IDs, from the packed
+// per-(vertex, root) pairs of the graph, as a tiled transpose through LDS.
+// A workgroup takes 128 consecutive original IDs: each wave reads the packed
+// internal rows of 16 of them (lane = root, one coalesced 512-byte row per
+// vertex, reset to "none" as it goes), then writes 8 of the root rows
+// (lane = vertex, 512-byte runs per row and array).  Parents go back to
+// original IDs through oid.  The loads of each phase are issued together so
+// that their latencies overlap.  Isolated vertices get -1; isolated roots
+// are fixed up by ms_roots_fixup_kernel.
+constexpr int kTrBlock = 512;  // 8 waves
+constexpr int kTrTile = 128;   // vertices per tile
+
 __global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
     int64_t n_g, const int32_t* perm, int64_t n_sweep_g, int64_t ubase, int32_t k, uint64_t* dp,
     const int32_t* oid, int32_t* out_dep, int32_t* out_par) {
-  constexpr int kRows = kWave / (kTrBlock / kWave);  // vertices (and roots) per wave
-  __shared__ uint64_t tile[kWave][kWave + 1];        // [vertex][root], padded
+  constexpr int kWaves = kTrBlock / kWave;
+  constexpr int kRows = kTrTile / kWaves;   // vertices per wave in the read phase
+  constexpr int kRoots = kWave / kWaves;    // roots per wave in the write phase
+  __shared__ uint64_t tile[kTrTile][kWave + 1];  // [vertex][root], padded
   const int wv = wave_id(), l = lane_id();
-  for (int64_t v0 = (int64_t)blockIdx.x * kWave; v0 < n_g; v0 += (int64_t)gridDim.x * kWave) {
+  for (int64_t v0 = (int64_t)blockIdx.x * kTrTile; v0 < n_g;
+       v0 += (int64_t)gridDim.x * kTrTile) {
+    // read phase: the wave's 16 internal rows are fetched together (lanes
+    // 0..15 read the row numbers, then every lane reads its root's entry of
+    // all 16 rows) so that their latencies overlap
+    const int64_t vr = v0 + wv * kRows + (l & (kRows - 1));
+    const int64_t ir = (vr < n_g) ? (perm ? (int64_t)perm[vr] : vr) : n_sweep_g;
+    int64_t iv[kRows];
+    uint64_t xv[kRows];
+#pragma unroll
+    for (int t = 0; t < kRows; ++t) iv[t] = shfl(ir, t);
+#pragma unroll
+    for (int t = 0; t < kRows; ++t)
+      xv[t] = (l < k && iv[t] < n_sweep_g) ? dp[(ubase + iv[t]) * 64 + l] : ~0ull;
+#pragma unroll
     for (int t = 0; t < kRows; ++t) {
-      const int r = wv * kRows + t;
-      const int64_t v = v0 + r;
-      uint64_t x = ~0ull;
-      if (v < n_g && l < k) {
-        const int64_t i = perm ? perm[v] : v;
-        if (i < n_sweep_g) {
-          uint64_t* row = dp + (ubase + i) * 64;
-          x = row[l];
-          row[l] = ~0ull;
-        }
-      }
-      tile[r][l] = x;
+      tile[wv * kRows + t][l] = xv[t];
+      if (l < k && iv[t] < n_sweep_g) dp[(ubase + iv[t]) * 64 + l] = ~0ull;
     }
     __syncthreads();
-    const int64_t v = v0 + l;
-    int32_t last_in = -1, last_out = -1;
-    for (int t = 0; t < kRows; ++t) {
-      const int j = wv * kRows + t;
-      if (j < k && v < n_g) {
-        const uint64_t x = tile[l][j];
-        const int32_t d = (int32_t)(x >> 32);
-        int32_t p = d < 0 ? -1 : (int32_t)~(uint32_t)x;
-        if (p >= 0 && oid) {
-          if (p != last_in) {
-            last_in = p;
-            last_out = oid[p];
-          }
-          p = last_out;
+    // write phase: 8 roots per wave, lane = vertex, two halves of 64
+#pragma unroll
+    for (int h = 0; h < kTrTile / kWave; ++h) {
+      const int vv = h * kWave + l;
+      const int64_t v = v0 + vv;
+      int32_t d[kRoots], p[kRoots];
+#pragma unroll
+      for (int t = 0; t < kRoots; ++t) {
+        const uint64_t x = tile[vv][wv * kRoots + t];
+        d[t] = (int32_t)(x >> 32);
+        p[t] = d[t] < 0 ? -1 : (int32_t)~(uint32_t)x;
+      }
+      if (oid) {
+#pragma unroll
+        for (int t = 0; t < kRoots; ++t)
+          if (p[t] >= 0) p[t] = oid[p[t]];
+      }
+#pragma unroll
+      for (int t = 0; t < kRoots; ++t) {
+        const int j = wv * kRoots + t;
+        if (j < k && v < n_g) {
+          out_dep[(int64_t)j * n_g + v] = d[t];
+          out_par[(int64_t)j * n_g + v] = p[t];
         }
-        out_dep[(int64_t)j * n_g + v] = d;
-        out_par[(int64_t)j * n_g + v] = p;
       }
     }
     __syncthreads();
@@ -791,7 +807,7 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
 int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t n_sweep_g,
                          int64_t ubase, int32_t k, const int32_t* roots_orig_dev,
                          int32_t* out_dep, int32_t* out_par, hipStream_t stream) {
-  const int64_t tiles = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n_g, kWave), 1 << 20));
+  const int64_t tiles = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n_g, kTrTile), 1 << 20));
   hipLaunchKernelGGL(ms_translate_kernel, dim3((unsigned)tiles), dim3(kTrBlock), 0, stream, n_g,
                      perm, n_sweep_g, ubase, k, m->dp, m->uoid ? m->uoid : m->oid, out_dep,
                      out_par);
