@@ -136,16 +136,61 @@ __device__ __forceinline__ void uf_union(int32_t* p, int32_t a, int32_t b) {
   }
 }
 
+// Components in two passes, after Afforest (Sutton, Ben-Nun and Barak,
+// IPDPS 2018).  The sampling pass links every vertex with its first
+// kCcSample neighbours, which already joins most of a power-law graph into
+// its giant component.  The full pass then takes every edge of the vertices
+// that are not (yet) in the component of a chosen vertex `big`: an edge
+// between a skipped vertex and a processed one is taken from the processed
+// end, and two skipped vertices are already joined, so every edge is
+// accounted for.  The hooking rule leaves the minimum rank as root whatever
+// the order, so the result is that of a full pass over all edges.
+constexpr int kCcSample = 2;
+
+__global__ void cc_sample_kernel(const int64_t* off, const int32_t* cols, int64_t n,
+                                 const int32_t* rank, int32_t* ccp) {
+  GRID_STRIDE(v, n) {
+    const int64_t b = off[v], e = off[v + 1];
+    for (int64_t j = b; j < e && j < b + kCcSample; ++j) uf_union(ccp, rank[v], rank[cols[j]]);
+  }
+}
+
+__global__ void cc_big_root_kernel(int32_t* ccp, int32_t big_rank, int32_t* big_root) {
+  *big_root = uf_find(ccp, big_rank);
+}
+
 __global__ __launch_bounds__(kBlock) void cc_union_kernel(const int64_t* off, const int32_t* cols,
                                                           int64_t n, const int32_t* rank,
-                                                          int32_t* ccp) {
+                                                          int32_t* ccp, const int32_t* big_root) {
   const int64_t nwords = ceil_div(n, kWave);
   const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int32_t c = *big_root;
+  const int l = lane_id();
   for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nwords;
        word += wstride) {
-    word_edges(off, cols, n, word, [&](int64_t v, int32_t w, int64_t) {
-      if (v < w) uf_union(ccp, rank[v], rank[w]);
-    });
+    const int64_t v = word * kWave + l;
+    int64_t b = 0, e = 0;
+    int32_t rv = 0;
+    if (v < n) {
+      b = off[v];
+      e = off[v + 1];
+      if (e > b) {
+        rv = rank[v];
+        if (uf_find(ccp, rv) == c) e = b;  // in the big component: skipped
+      }
+    }
+    // rows of at most kLaneRow entries by their own lane, longer by the wave
+    const bool big_row = (e - b) > kLaneRow;
+    if (!big_row)
+      for (int64_t j = b; j < e; ++j) uf_union(ccp, rv, rank[cols[j]]);
+    uint64_t hubs = ballot(big_row);
+    while (hubs) {
+      const int h = ffs64(hubs);
+      hubs &= hubs - 1;
+      const int64_t hb = shfl(b, h), he = shfl(e, h);
+      const int32_t hr = shfl(rv, h);
+      for (int64_t j = hb + l; j < he; j += kWave) uf_union(ccp, hr, rank[cols[j]]);
+    }
   }
 }
 
@@ -521,9 +566,25 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   const int64_t nwords = ceil_div(n, kWave);
   const int wgrid = (int)(ceil_div(nwords, kWavesPerBlock) < (1 << 18)
                               ? ceil_div(nwords, kWavesPerBlock) : (1 << 18));
-  hipLaunchKernelGGL(cc_union_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, g->cols, n,
-                     rank, ccp);
-  RCM_CHECK(hipGetLastError());
+  {
+    int32_t* big_root = nullptr;
+    RCM_CHECK(B.alloc(&big_root, 1));
+    hipLaunchKernelGGL(cc_sample_kernel, dim3(grid_for(n)), dim3(kBlock), 0, stream, g->off,
+                       g->cols, n, rank, ccp);
+    RCM_CHECK(hipGetLastError());
+    if (nplus > 0) {
+      // the last rank is a vertex of maximum degree: in the giant component
+      // of the graphs this is built for (any choice is correct)
+      hipLaunchKernelGGL(cc_big_root_kernel, dim3(1), dim3(1), 0, stream, ccp,
+                         (int32_t)(nplus - 1), big_root);
+      RCM_CHECK(hipGetLastError());
+    } else {
+      RCM_CHECK(hipMemsetAsync(big_root, 0xFF, sizeof(int32_t), stream));
+    }
+    hipLaunchKernelGGL(cc_union_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, g->cols, n,
+                       rank, ccp, big_root);
+    RCM_CHECK(hipGetLastError());
+  }
   RCM_CHECK(B.alloc(&csize, nplus));
   RCM_CHECK(B.alloc(&cbase, nplus + 1));
   RCM_CHECK(hipMemsetAsync(csize, 0, sizeof(int32_t) * (nplus > 0 ? nplus : 1), stream));
