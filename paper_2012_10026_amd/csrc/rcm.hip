@@ -23,7 +23,7 @@
 //   5. reverses the labels over V+, appends the isolated vertices in
 //      increasing id, and rebuilds the CSR in the new labels with every row
 //      ascending (the relabelled rows transposed by one stable sort on the
-//      new column label).
+//      old column, then each group copied to its new row).
 //
 // Partial RCM (section 4.6) reorders only the first `keep` vertices of the
 // Cuthill-McKee sequence: they take labels [0, keep) in reverse sequence
@@ -456,12 +456,14 @@ __global__ void newdeg_kernel(const int32_t* iperm, const int32_t* deg, int64_t 
   GRID_STRIDE(i, n) { newdeg[i] = deg[iperm[i]]; }
 }
 
-// Relabelled CSR as the transpose of the relabelled rows: entry (v, w)
-// becomes the pair (perm[w], perm[v]), stored in new-row order (row perm[v]
-// at newoff[perm[v]]).  A stable sort on the first label alone then groups
-// the pairs by new row perm[w] with the second labels ascending inside each
-// group, and the graph being symmetric, group c is exactly the new row c,
-// already sorted: bn bits of sort instead of 2 bn.
+// Relabelled CSR through one transpose.  Entry (v, w) becomes the pair
+// (w, perm[v]) -- its old column and its new row -- stored in new-row order
+// (row perm[v] at newoff[perm[v]]).  A stable sort on the old column alone
+// groups the pairs by w, with the new labels of w's neighbours ascending
+// inside each group; the groups come out in old order at the old offsets,
+// and one copy of each group w to newoff[perm[w]] gives the new row
+// perm[w], already sorted.  No per-entry relabelling gather is needed: the
+// new labels come one per row.
 __global__ __launch_bounds__(kBlock) void relabel_keys_kernel(const int64_t* off,
                                                               const int32_t* cols, int64_t n,
                                                               int64_t nnz, const int32_t* perm,
@@ -474,14 +476,49 @@ __global__ __launch_bounds__(kBlock) void relabel_keys_kernel(const int64_t* off
     word_edges(off, cols, n, word, [&](int64_t v, int32_t w, int64_t e) {
       const int64_t r = perm[v];
       const int64_t pos = newoff[r] + (e - off[v]);
-      if (pos >= 0 && pos < nnz) keys[pos] = ((uint64_t)(uint32_t)perm[w] << 32) | (uint64_t)r;
+      if (pos >= 0 && pos < nnz) keys[pos] = ((uint64_t)(uint32_t)w << 32) | (uint64_t)r;
       else atomicOr(status, kStatusBadInput);
     });
   }
 }
 
-__global__ void keys_to_cols_kernel(const uint64_t* keys, int64_t nnz, int32_t* cols) {
-  GRID_STRIDE(i, nnz) { cols[i] = (int32_t)(uint32_t)keys[i]; }
+// Group w of the sorted pairs (entries [off[w], off[w + 1])) to new row
+// perm[w]: rows of at most kLaneRow entries by one lane, longer ones by the
+// whole wave.
+__global__ __launch_bounds__(kBlock) void groups_to_rows_kernel(const int64_t* off, int64_t n,
+                                                                int64_t nnz, const int32_t* perm,
+                                                                const int64_t* newoff,
+                                                                const uint64_t* keys,
+                                                                int32_t* newcols, int* status) {
+  const int64_t nwords = ceil_div(n, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int l = lane_id();
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nwords;
+       word += wstride) {
+    const int64_t w = word * kWave + l;
+    int64_t b = 0, e = 0, dst = 0;
+    if (w < n) {
+      b = off[w];
+      e = off[w + 1];
+      if (e > b) {
+        dst = newoff[perm[w]];
+        if (dst < 0 || dst + (e - b) > nnz) {
+          atomicOr(status, kStatusBadInput);
+          e = b;
+        }
+      }
+    }
+    const bool big = (e - b) > kLaneRow;
+    if (!big)
+      for (int64_t j = b; j < e; ++j) newcols[dst + (j - b)] = (int32_t)(uint32_t)keys[j];
+    uint64_t hubs = ballot(big);
+    while (hubs) {
+      const int h = ffs64(hubs);
+      hubs &= hubs - 1;
+      const int64_t hb = shfl(b, h), he = shfl(e, h), hd = shfl(dst, h);
+      for (int64_t j = hb + l; j < he; j += kWave) newcols[hd + (j - hb)] = (int32_t)(uint32_t)keys[j];
+    }
+  }
 }
 
 // Device buffers owned for the duration of one pass.
@@ -757,8 +794,8 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   uint64_t* k2 = keys2;
   RCM_CHECK(radix_sort_u64(&k1, &k2, nnz, 32, 32 + bn, g->scratch, stream));
   RCM_CHECK(B.alloc(&newcols, nnz + kColPad));  // slack for aligned group reads
-  hipLaunchKernelGGL(keys_to_cols_kernel, dim3(grid_for(nnz)), dim3(kBlock), 0, stream, k1, nnz,
-                     newcols);
+  hipLaunchKernelGGL(groups_to_rows_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, n, nnz,
+                     perm, newoff, k1, newcols, d_status);
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
   RCM_CHECK(hipEventRecord(e1, stream));
