@@ -164,26 +164,38 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint64_t* k
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
+// Scatter of one tile.  The tile's keys are first ranked into LDS grouped by
+// digit (digit d's run starts at the tile's exclusive count of smaller
+// digits), then written out run by run, so consecutive threads write
+// consecutive positions of the same run.
 __global__ __launch_bounds__(kBlock) void radix_downsweep_kernel(const uint64_t* in,
                                                                  uint64_t* out, int64_t n,
                                                                  int shift,
                                                                  const int64_t* hist_scan,
                                                                  int64_t ntiles) {
-  __shared__ int64_t s_base[kDigits];
-  __shared__ uint32_t s_run[kDigits];
+  __shared__ int64_t s_base[kDigits];   // output start of this tile's digit-d keys
+  __shared__ uint32_t s_loc[kDigits];   // start of digit d's run in the tile
+  __shared__ uint32_t s_run[kDigits];   // digit-d keys placed so far
   __shared__ uint32_t s_wcnt[kWavesPerBlock][kDigits];
+  __shared__ uint64_t s_keys[kSortTile];
   const int t = threadIdx.x;
-  s_base[t] = hist_scan[(int64_t)t * ntiles + blockIdx.x];
+  const int64_t hs = hist_scan[(int64_t)t * ntiles + blockIdx.x];
+  s_base[t] = hs;
+  const int64_t cnt_t = hist_scan[(int64_t)t * ntiles + blockIdx.x + 1] - hs;
+  int64_t tot;
+  const int64_t loc_t = block_exclusive(cnt_t, &tot);
+  s_loc[t] = (uint32_t)loc_t;
   s_run[t] = 0;
 #pragma unroll
   for (int w = 0; w < kWavesPerBlock; ++w) s_wcnt[w][t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int tile_n = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
   const int wv = wave_id();
   for (int r = 0; r < kSortItems; ++r) {
-    const int64_t i = base + (int64_t)r * kBlock + t;
-    const bool valid = i < n;
-    const uint64_t key = valid ? in[i] : 0ull;
+    const int li = r * kBlock + t;
+    const bool valid = li < tile_n;
+    const uint64_t key = valid ? in[base + li] : 0ull;
     const uint32_t d = valid ? (uint32_t)((key >> shift) & (kDigits - 1)) : 0u;
     uint64_t peers = ballot(valid);
 #pragma unroll
@@ -196,9 +208,9 @@ __global__ __launch_bounds__(kBlock) void radix_downsweep_kernel(const uint64_t*
     if (valid && rank == 0) s_wcnt[wv][d] = (uint32_t)popc64(peers);
     __syncthreads();
     if (valid) {
-      int64_t pos = s_base[d] + (int64_t)s_run[d] + rank;
+      uint32_t pos = s_loc[d] + s_run[d] + (uint32_t)rank;
       for (int w = 0; w < wv; ++w) pos += s_wcnt[w][d];
-      out[pos] = key;
+      s_keys[pos] = key;
     }
     __syncthreads();
     uint32_t add = 0;
@@ -209,6 +221,11 @@ __global__ __launch_bounds__(kBlock) void radix_downsweep_kernel(const uint64_t*
     }
     s_run[t] += add;
     __syncthreads();
+  }
+  for (int i = t; i < tile_n; i += kBlock) {
+    const uint64_t key = s_keys[i];
+    const uint32_t d = (uint32_t)((key >> shift) & (kDigits - 1));
+    out[s_base[d] + (i - (int64_t)s_loc[d])] = key;
   }
 }
 
