@@ -164,39 +164,50 @@ __global__ __launch_bounds__(kBlock) void radix_upsweep_kernel(const uint64_t* k
   hist[(int64_t)threadIdx.x * ntiles + blockIdx.x] = s_h[threadIdx.x];
 }
 
-// Scatter of one tile.  The tile's keys are first ranked into LDS grouped by
-// digit (digit d's run starts at the tile's exclusive count of smaller
-// digits), then written out run by run, so consecutive threads write
-// consecutive positions of the same run.
+// Scatter of one tile.  Each wave ranks its own quarter of the tile (16
+// rounds of 64 consecutive keys) against a per-wave digit count in LDS, with
+// no workgroup barrier between rounds; the counts of earlier waves are then
+// added, the keys are placed in LDS grouped by digit (digit d's run starts at
+// the tile's exclusive count of smaller digits), and written out run by run,
+// so consecutive threads write consecutive positions of the same run.  Keys
+// keep their tile order inside a digit: the sort is stable.
 __global__ __launch_bounds__(kBlock) void radix_downsweep_kernel(const uint64_t* in,
                                                                  uint64_t* out, int64_t n,
                                                                  int shift,
                                                                  const int64_t* hist_scan,
                                                                  int64_t ntiles) {
+  constexpr int kWaveKeys = kSortTile / kWavesPerBlock;  // keys per wave
+  constexpr int kRounds = kWaveKeys / kWave;
   __shared__ int64_t s_base[kDigits];   // output start of this tile's digit-d keys
   __shared__ uint32_t s_loc[kDigits];   // start of digit d's run in the tile
-  __shared__ uint32_t s_run[kDigits];   // digit-d keys placed so far
   __shared__ uint32_t s_wcnt[kWavesPerBlock][kDigits];
   __shared__ uint64_t s_keys[kSortTile];
   const int t = threadIdx.x;
+  const int l = lane_id();
+  const int wv = wave_id();
   const int64_t hs = hist_scan[(int64_t)t * ntiles + blockIdx.x];
   s_base[t] = hs;
   const int64_t cnt_t = hist_scan[(int64_t)t * ntiles + blockIdx.x + 1] - hs;
   int64_t tot;
   const int64_t loc_t = block_exclusive(cnt_t, &tot);
   s_loc[t] = (uint32_t)loc_t;
-  s_run[t] = 0;
 #pragma unroll
   for (int w = 0; w < kWavesPerBlock; ++w) s_wcnt[w][t] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * kSortTile;
   const int tile_n = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
-  const int wv = wave_id();
-  for (int r = 0; r < kSortItems; ++r) {
-    const int li = r * kBlock + t;
+  uint64_t key[kRounds];
+  uint32_t dg[kRounds], rk[kRounds];
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int li = wv * kWaveKeys + r * kWave + l;
+    key[r] = li < tile_n ? in[base + li] : 0ull;
+  }
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r) {
+    const int li = wv * kWaveKeys + r * kWave + l;
     const bool valid = li < tile_n;
-    const uint64_t key = valid ? in[base + li] : 0ull;
-    const uint32_t d = valid ? (uint32_t)((key >> shift) & (kDigits - 1)) : 0u;
+    const uint32_t d = valid ? (uint32_t)((key[r] >> shift) & (kDigits - 1)) : 0u;
     uint64_t peers = ballot(valid);
 #pragma unroll
     for (int b = 0; b < kRadixBits; ++b) {
@@ -205,27 +216,32 @@ __global__ __launch_bounds__(kBlock) void radix_downsweep_kernel(const uint64_t*
       peers &= bit ? m : ~m;
     }
     const int rank = popc64(peers & lanemask_lt());
-    if (valid && rank == 0) s_wcnt[wv][d] = (uint32_t)popc64(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = s_loc[d] + s_run[d] + (uint32_t)rank;
-      for (int w = 0; w < wv; ++w) pos += s_wcnt[w][d];
-      s_keys[pos] = key;
-    }
-    __syncthreads();
-    uint32_t add = 0;
+    const uint32_t before = valid ? s_wcnt[wv][d] : 0u;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) s_wcnt[wv][d] = before + (uint32_t)popc64(peers);
+    __builtin_amdgcn_wave_barrier();
+    dg[r] = valid ? d : kDigits;  // kDigits marks an empty slot
+    rk[r] = before + (uint32_t)rank;
+  }
+  __syncthreads();
+  {  // counts of earlier waves: exclusive prefix over the waves, per digit
+    uint32_t run = 0;
 #pragma unroll
     for (int w = 0; w < kWavesPerBlock; ++w) {
-      add += s_wcnt[w][t];
-      s_wcnt[w][t] = 0;
+      const uint32_t c = s_wcnt[w][t];
+      s_wcnt[w][t] = run;
+      run += c;
     }
-    s_run[t] += add;
-    __syncthreads();
   }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kRounds; ++r)
+    if (dg[r] < kDigits) s_keys[s_loc[dg[r]] + s_wcnt[wv][dg[r]] + rk[r]] = key[r];
+  __syncthreads();
   for (int i = t; i < tile_n; i += kBlock) {
-    const uint64_t key = s_keys[i];
-    const uint32_t d = (uint32_t)((key >> shift) & (kDigits - 1));
-    out[s_base[d] + (i - (int64_t)s_loc[d])] = key;
+    const uint64_t k = s_keys[i];
+    const uint32_t d = (uint32_t)((k >> shift) & (kDigits - 1));
+    out[s_base[d] + (i - (int64_t)s_loc[d])] = k;
   }
 }
 
