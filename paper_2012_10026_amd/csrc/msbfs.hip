@@ -157,20 +157,6 @@ __device__ __forceinline__ void ms_stage(MsStage& st, bool take, int32_t v, int6
   if (base + popc64(m) > kMsStage - kWave) ms_flush(st, P, nq_idx, qpack);
 }
 
-// Records level d1 and parent `x` (an internal label; the output transpose
-// maps it back) for every root bit in `bits` of vertex v: one 8-byte store
-// per bit.
-__device__ __forceinline__ void ms_record(const MsParams& P, int64_t v, uint64_t bits,
-                                          int32_t x, int d1) {
-  uint64_t* row = P.dp + v * 64;
-  const uint64_t val = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)~(uint32_t)x;
-  while (bits) {
-    const int j = ffs64(bits);
-    bits &= bits - 1;
-    row[j] = val;
-  }
-}
-
 __device__ __forceinline__ uint64_t wave_or(uint64_t x) {
 #pragma unroll
   for (int off = kWave / 2; off > 0; off >>= 1) x |= __shfl_xor(x, off, kWave);
@@ -219,7 +205,17 @@ __device__ __forceinline__ uint64_t ms_hub_pull(const MsParams& P, bool hub, int
         hb = fcur[x] & hmiss;
       }
       const uint64_t mine = hb & ~wave_exclusive_or(hb);
-      if (mine) ms_record(P, hv, mine, x, d1);
+      // the row's new pairs, written by the whole wave: lane r writes root
+      // r's entry, once per lane that found something
+      uint64_t ml = ballot(mine != 0ull);
+      uint64_t* row = P.dp + hv * 64;
+      while (ml) {
+        const int sl = ffs64(ml);
+        ml &= ml - 1;
+        const uint64_t sm = shfl(mine, sl);
+        const int32_t sx = shfl(x, sl);
+        if ((sm >> l) & 1ull) row[l] = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)~(uint32_t)sx;
+      }
       const uint64_t all = wave_or(hb);
       hmiss &= ~all;
       hfound |= all;
@@ -298,13 +294,21 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
     const bool hub = fresh && (e - b) > P.lane_row;
     const uint64_t hf = ms_hub_pull(P, hub, v, b, e, miss, fcur, d1, examined);
     bool fin = false;
+    // this step's hits: entry q of the lane's row gives the roots hrec[q]
+    int32_t x[kPullStep];
+    uint64_t hrec[kPullStep];
+    int qmask = 0;
+#pragma unroll
+    for (int q = 0; q < kPullStep; ++q) {
+      x[q] = 0;
+      hrec[q] = 0ull;
+    }
     if (hub) {
       found = hf;
       miss &= ~hf;
       fin = true;
     } else if (busy) {
       // entries j-1, j-2, .. downwards
-      int32_t x[kPullStep];
       uint64_t fb[kPullStep];
 #pragma unroll
       for (int q = 0; q < kPullStep; ++q) x[q] = (j - 1 - q >= b) ? P.cols[j - 1 - q] : 0;
@@ -315,7 +319,8 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
       for (int q = 0; q < kPullStep; ++q) {
         const uint64_t hb = fb[q] & miss;
         if (hb) {
-          ms_record(P, v, hb, x[q], d1);
+          hrec[q] = hb;
+          qmask |= 1 << q;
           miss &= ~hb;
           found |= hb;
           if (miss == 0ull) used = q + 1;
@@ -324,6 +329,25 @@ __device__ __forceinline__ void ms_pull_range(const MsParams& P, int64_t v0, int
       examined += used;
       j -= kPullStep;
       fin = miss == 0ull || j <= b;
+    }
+    // the packed pairs of the hits, written a row at a time by the whole
+    // wave (lane r writes root r's entry): one store per hit covers up to
+    // 64 roots of one vertex instead of one store per root
+    uint64_t wl = ballot(qmask != 0);
+    while (wl) {
+      const int h = ffs64(wl);
+      wl &= wl - 1;
+      uint64_t* row = P.dp + shfl(v, h) * 64;
+      const int qm = shfl(qmask, h);
+#pragma unroll
+      for (int q = 0; q < kPullStep; ++q) {
+        if ((qm >> q) & 1) {
+          const uint64_t hq = shfl(hrec[q], h);
+          const int32_t hx = shfl(x[q], h);
+          if ((hq >> l) & 1ull)
+            row[l] = ((uint64_t)(uint32_t)d1 << 32) | (uint32_t)~(uint32_t)hx;
+        }
+      }
     }
     if (fin && found) fnext[v] = found;
     if (fin && miss == 0ull) done += e - b;
