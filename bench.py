@@ -312,6 +312,24 @@ def ablation(rb, graphgen, args):
             kernel_ms, total_ms = G.timings()
             G.check()
             info = G.info()
+            # load balance: work per workgroup in the heaviest top-down and
+            # bottom-up levels of the first root
+            _, _, st0 = G.bfs(roots[0], depth, parent,
+                              opts=rb.make_opts(alpha=args.alpha, beta=args.beta, wg_work=True),
+                              stats=True)
+            W = G.wg_work()
+            balance = {}
+            for dname, dval in (("td", 0), ("bu", 1)):
+                lv = [d for d in range(W.shape[0]) if st0["dir"][d] == dval]
+                if not lv:
+                    continue
+                d = max(lv, key=lambda x: int(W[x].sum()))
+                row = W[d].astype(float)
+                mean = float(row.mean())
+                balance[dname] = {"level": d, "entries": int(row.sum()), "workgroups": len(row),
+                                  "max_over_mean": float(row.max() / mean) if mean else None,
+                                  "min_over_mean": float(row.min() / mean) if mean else None,
+                                  "cov": float(row.std() / mean) if mean else None}
             m_c = [st["component_edges"] for st in stats]
             n_sweep = info["n_plus"] if reordered else n
             alg = sum(bfs_alg_bytes(st, n_sweep, original_ids=reordered)
@@ -328,7 +346,7 @@ def ablation(rb, graphgen, args):
                 "edges_examined_avg": sum(sum(st["edges"][:st["levels"]]) for st in stats)
                 / len(stats),
                 "alg_bytes_avg": alg, "achieved_gbs": alg / (k_ms * 1e-3) / 1e9,
-                "rcm_ms": rcm_ms, "rcm_keep": info["rcm_keep"],
+                "rcm_ms": rcm_ms, "rcm_keep": info["rcm_keep"], "wg_balance": balance,
                 "tuning": G.get_tuning()}), flush=True)
             G.close()
             del G

@@ -102,6 +102,9 @@ typedef struct rbfs_opts {
 /* opts flags */
 #define RBFS_OPT_TIMING 1 /* record HIP events around the search kernel and
                              the whole call; read them with rbfs_graph_timings */
+#define RBFS_OPT_WG_WORK 2 /* single-root searches: record the adjacency
+                              entries each workgroup processed per level;
+                              read them with rbfs_graph_wg_work */
 
 /* Per-search statistics; asking for them synchronises the stream.  Level d
  * arrays describe the level that expands frontier F_d. */
@@ -255,6 +258,19 @@ int rbfs_certify(rbfs_graph_t* g, int32_t root, const int32_t* depth, const int3
  * barrier timeout, corrupt input detected by a kernel) raised by searches on
  * this graph since the last check: RBFS_OK or RBFS_E_DEVICE. */
 int rbfs_graph_check(rbfs_graph_t* g, void* stream);
+
+/* Work per workgroup of the graph's last single-root search, if it was made
+ * with RBFS_OPT_WG_WORK: the GPU counterpart of the per-thread edge counts
+ * behind the load balancing of sections 3.3-3.4 (Algorithms 4-5).
+ * out[d * grid + w] (host int64, cap entries) = adjacency entries workgroup w
+ * processed in level d: top-down, the frontier edges of the chunks it took;
+ * bottom-up, the row entries it read.  Summed over w, a level gives
+ * rbfs_stats_t's nf-weighted edge count (m_f top-down, edges bottom-up).
+ * *levels (at most RBFS_STATS_MAX_LEVELS) and *grid receive the shape;
+ * out may be NULL to ask for it.  Synchronises `stream`.  RBFS_E_STATE when
+ * the last search was made without the flag. */
+int rbfs_graph_wg_work(rbfs_graph_t* g, int64_t* out, int64_t cap, int32_t* levels, int32_t* grid,
+                       void* stream);
 
 /* Durations of the calls made with RBFS_OPT_TIMING since the last read
  * (oldest first, at most 1024 kept): kernel_ms[i] = search kernel(s) only,

@@ -116,6 +116,7 @@ SIGNATURES = {
     "rbfs_graph_info": (ctypes.c_int, [_P, _P]),
     "rbfs_graph_check": (ctypes.c_int, [_P, _P]),
     "rbfs_graph_timings": (ctypes.c_int, [_P, _P, _P, _I32, _P, _P]),
+    "rbfs_graph_wg_work": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "rbfs_rcm_reorder": (ctypes.c_int, [_P, _P, _P, _P]),
     "rbfs_rcm_reorder_partial": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
@@ -243,6 +244,7 @@ def device_info():
 
 
 OPT_TIMING = 1
+OPT_WG_WORK = 2
 
 
 def default_tuning(kind=TUNE_SINGLE):
@@ -261,9 +263,9 @@ def _records(recs, cnt):
 
 
 def make_opts(direction=DIR_HEURISTIC, alpha=14, beta=24, output_space=OUT_ORIGINAL,
-              schedule=None, tune_profile=0, timing=False):
+              schedule=None, tune_profile=0, timing=False, wg_work=False):
     o = Opts()
-    o.flags = OPT_TIMING if timing else 0
+    o.flags = (OPT_TIMING if timing else 0) | (OPT_WG_WORK if wg_work else 0)
     o.direction = direction
     o.alpha = alpha
     o.beta = beta
@@ -397,6 +399,19 @@ class Graph:
 
     def check(self):
         _check(lib().rbfs_graph_check(self._h, _stream_ptr(self.device)))
+
+    def wg_work(self):
+        """Entries each workgroup processed per level in the last search (made
+        with OPT_WG_WORK): numpy int64 array of shape (levels, grid)."""
+        lv, gr = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(lib().rbfs_graph_wg_work(self._h, None, 0, ctypes.byref(lv), ctypes.byref(gr),
+                                        _stream_ptr(self.device)))
+        out = np.zeros(lv.value * gr.value, dtype=np.int64)
+        if out.size:
+            _check(lib().rbfs_graph_wg_work(self._h, out.ctypes.data_as(ctypes.c_void_p),
+                                            out.size, ctypes.byref(lv), ctypes.byref(gr),
+                                            _stream_ptr(self.device)))
+        return out.reshape(lv.value, gr.value)
 
     def certify(self, root, depth, parent, output_space=OUT_ORIGINAL):
         """Checks (depth, parent) of a search from `root` against the graph on

@@ -471,6 +471,15 @@ int rbfs_bfs(rbfs_graph_t* h, int32_t root, int32_t* depth, int32_t* parent,
                         (hipStream_t)stream_, stats);
 }
 
+int rbfs_graph_wg_work(rbfs_graph_t* h, int64_t* out, int64_t cap, int32_t* levels,
+                       int32_t* grid, void* stream) {
+  if (!h || !levels || !grid || cap < 0 || (cap > 0 && !out)) {
+    set_error("rbfs_graph_wg_work: bad arguments");
+    return RBFS_E_INVAL;
+  }
+  return rbfs::bfs_wg_work(&h->g, out, cap, levels, grid, (hipStream_t)stream);
+}
+
 int rbfs_graph_timings(rbfs_graph_t* h, float* kernel_ms, float* total_ms, int32_t cap,
                        int32_t* count, void* stream_) {
   if (!h || !count || cap < 0 || (cap > 0 && (!kernel_ms || !total_ms))) {

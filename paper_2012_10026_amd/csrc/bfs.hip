@@ -130,6 +130,7 @@ struct BfsParams {
   int32_t cshift;        // log2 of the top-down chunk length
   uint64_t timeout_ticks;
   const float* sw;       // learned-switch blob (RBFS_DIR_LEARNED)
+  int64_t* wg_work;      // non-null: entries each workgroup processed, per level
   BfsCtl* ctl;
 };
 
@@ -515,6 +516,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     uint64_t* fnext = P.front[n3];
     unsigned long long* qpack = &ctl->qpack[n3][0][0];
     int64_t examined = 0;
+    int64_t wg_td = 0;  // top-down: frontier edges of the chunks this workgroup took
     // clear what level L+1 will fill
     for (int64_t w = gtid; w < W; w += gsz) P.front[z3][w] = 0ull;
     if (gtid == 0) {
@@ -538,6 +540,10 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           lc -= nq_ch;
           ++q;
           nq_ch = ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
+        }
+        if (threadIdx.x == 0) {
+          const int64_t e0 = lc << P.cshift;
+          wg_td += std::min<int64_t>((int64_t)1 << P.cshift, s_qedg[q] - e0);
         }
         const bool ok = expand_chunk_batch<BLOCK, kTdK>(
             s_step.chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride, P.qe[qc] + q * P.qstride,
@@ -707,7 +713,9 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       flush_list(s_st, vl_out, vlcnt, P.qstride, ctl);
       flush_stage(s_st, P, qn, qpack);
     }
-    block_fold_add(&ctl->edges[n3][0], examined);
+    const int64_t wg_examined = block_fold_add(&ctl->edges[n3][0], examined);
+    if (P.wg_work && threadIdx.x == 0 && L < RBFS_STATS_MAX_LEVELS)
+      P.wg_work[(int64_t)L * gridDim.x + blockIdx.x] = dir == 0 ? wg_td : wg_examined;
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
     // ---- next level: every workgroup decides the same way.  Sizes of the
@@ -856,11 +864,41 @@ __global__ void reset_ctl_kernel(BfsCtl* c) {
 
 }  // namespace
 
+int bfs_wg_work(Graph* g, int64_t* out, int64_t cap, int32_t* levels, int32_t* grid,
+                hipStream_t stream) {
+  BfsWork* w = g->bfs;
+  if (!w || !w->wg_valid) {
+    set_error("rbfs_graph_wg_work: the last search was not made with RBFS_OPT_WG_WORK");
+    return RBFS_E_STATE;
+  }
+  int lv = 0;
+  hipError_t e = hipMemcpyAsync(&lv, &w->ctl->levels, sizeof(int), hipMemcpyDeviceToHost, stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e != hipSuccess) {
+    set_error(std::string("rbfs_graph_wg_work: ") + hipGetErrorString(e));
+    return RBFS_E_DEVICE;
+  }
+  lv = std::max(0, std::min(lv, (int)RBFS_STATS_MAX_LEVELS));
+  const int64_t need = (int64_t)lv * w->wg_grid;
+  *levels = lv;
+  *grid = w->wg_grid;
+  if (out && cap > 0 && need > 0) {
+    e = hipMemcpy(out, w->wg_work, sizeof(int64_t) * (size_t)std::min(cap, need),
+                  hipMemcpyDeviceToHost);
+    if (e != hipSuccess) {
+      set_error(std::string("rbfs_graph_wg_work: ") + hipGetErrorString(e));
+      return RBFS_E_DEVICE;
+    }
+  }
+  return 0;
+}
+
 void free_bfs_work(Graph* g) {
   BfsWork* w = g->bfs;
   if (!w) return;
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
-                w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1]};
+                w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1],
+                w->wg_work};
   for (void* p : ps)
     if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -1024,6 +1062,14 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     }
   }
 
+  if (flags & RBFS_OPT_WG_WORK) {
+    if (!w->wg_work)
+      BFS_CHECK(rbfs::dev_malloc(&w->wg_work, sizeof(int64_t) * RBFS_STATS_MAX_LEVELS *
+                                                  (size_t)w->max_grid));
+    P.wg_work = w->wg_work;
+  }
+  w->wg_valid = false;
+
   hipEvent_t* tev = nullptr;
   if (flags & RBFS_OPT_TIMING) BFS_CHECK(g->timing.next(&tev));
   if (tev) BFS_CHECK(hipEventRecord(tev[0], stream));
@@ -1044,6 +1090,10 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   if (grid < 1 || grid > w->max_grid) {  // the range counters hold max_grid workgroups
     set_error("bfs: launch grid outside the workspace");
     return RBFS_E_STATE;
+  }
+  if (P.wg_work) {
+    w->wg_grid = grid;
+    w->wg_valid = true;
   }
   if (block == 256)
     hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(grid), dim3(256), 0, stream, P);

@@ -87,21 +87,23 @@ __device__ __forceinline__ int64_t wave_max(int64_t v) {
 // Sums v over the workgroup and adds the total to *ctr with one atomic per
 // workgroup: same-address atomics are served one after another (about
 // 10 ns each), so one per wave of a full-GPU grid would cost tens of
-// microseconds.  Every thread of the workgroup must call it.
+// microseconds.  Returns the workgroup's total in thread 0 (0 elsewhere).
+// Every thread of the workgroup must call it.
 constexpr int kMaxWaves = 16;
-__device__ __forceinline__ void block_fold_add(unsigned long long* ctr, int64_t v) {
+__device__ __forceinline__ int64_t block_fold_add(unsigned long long* ctr, int64_t v) {
   __shared__ int64_t s_part[kMaxWaves];
   const int64_t w = wave_sum(v);
   if (lane_id() == 0) s_part[wave_id()] = w;
   __syncthreads();
+  int64_t t = 0;
   if (threadIdx.x == 0) {
-    int64_t t = 0;
     for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += s_part[i];
     if (t)
       __hip_atomic_fetch_add(ctr, (unsigned long long)t, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
   }
   __syncthreads();
+  return t;
 }
 
 __device__ __forceinline__ uint64_t wave_or64(uint64_t x) {

@@ -75,6 +75,9 @@ struct BfsWork {
   int max_per_cu = 1;           // resident 1024-thread workgroups per CU
   int max_per_cu_256 = 1;       // resident 256-thread workgroups per CU
   hipEvent_t ev0 = nullptr, ev1 = nullptr, ev2 = nullptr;
+  int64_t* wg_work = nullptr;   // RBFS_OPT_WG_WORK: [level][grid] entries per workgroup
+  int wg_grid = 0;              // grid of the recorded search
+  bool wg_valid = false;        // the last search recorded wg_work
 };
 
 // Bit-parallel multi-root search engine over one "union" graph: a single
@@ -178,6 +181,8 @@ int bfs_batch_impl(Graph* g, const int32_t* roots, int32_t k, int32_t* depth, in
                    hipStream_t stream, void* stats);
 int bfs_apply_tuning(Graph* g, hipStream_t stream);
 void free_bfs_work(Graph* g);
+int bfs_wg_work(Graph* g, int64_t* out, int64_t cap, int32_t* levels, int32_t* grid,
+                hipStream_t stream);
 void free_ms_work(Graph* g);
 
 }  // namespace rbfs

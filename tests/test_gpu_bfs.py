@@ -295,3 +295,24 @@ def test_device_tuple_count_matches_host(rb):
     d_o, _, _ = oracle.bfs(off, cols, iso)
     got = graphgen.kronecker_tuples_reached_device(12, torch.from_numpy(d_o).cuda(), 16, 5)
     assert got == int(np.sum((src == iso) & (dst == iso)))
+
+
+def test_workgroup_work_adds_up(rb):
+    """Per-workgroup work of a search (OPT_WG_WORK): summed over the
+    workgroups, every level gives the level's counted work -- its frontier
+    edges m_f top-down, the row entries read bottom-up."""
+    off, cols = kron(14, 3)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    for r in graphgen.sample_roots(off, 3, 4):
+        for mode in (rb.DIR_HEURISTIC, rb.DIR_TD_ONLY, rb.DIR_BU_ONLY):
+            _, _, st = G.bfs(r, opts=rb.make_opts(mode, wg_work=True), stats=True)
+            W = G.wg_work()
+            assert W.shape[0] == st["levels"]
+            for d in range(st["levels"]):
+                want = st["mf"][d] if st["dir"][d] == 0 else st["edges"][d]
+                assert int(W[d].sum()) == want, (r, mode, d)
+                assert (W[d] >= 0).all()
+    G.bfs(0)
+    with pytest.raises(rb.RbfsError):
+        G.wg_work()
