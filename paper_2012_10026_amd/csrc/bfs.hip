@@ -408,7 +408,10 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
   return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
 }
 
-template <int BLOCK>
+// WGW: record each workgroup's work per level (P.wg_work); a separate
+// instantiation, so the searches that do not ask for it run the kernel
+// without that bookkeeping.
+template <int BLOCK, bool WGW>
 __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
   __shared__ StepLds<BLOCK> s_step;
@@ -516,7 +519,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     uint64_t* fnext = P.front[n3];
     unsigned long long* qpack = &ctl->qpack[n3][0][0];
     int64_t examined = 0;
-    int64_t wg_td = 0;  // top-down: frontier edges of the chunks this workgroup took
+    int64_t wg_td = 0;  // WGW, top-down: frontier edges of the chunks this workgroup took
     // clear what level L+1 will fill
     for (int64_t w = gtid; w < W; w += gsz) P.front[z3][w] = 0ull;
     if (gtid == 0) {
@@ -541,7 +544,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           ++q;
           nq_ch = ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
         }
-        if (threadIdx.x == 0) {
+        if (WGW && threadIdx.x == 0) {
           const int64_t e0 = lc << P.cshift;
           wg_td += std::min<int64_t>((int64_t)1 << P.cshift, s_qedg[q] - e0);
         }
@@ -714,7 +717,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       flush_stage(s_st, P, qn, qpack);
     }
     const int64_t wg_examined = block_fold_add(&ctl->edges[n3][0], examined);
-    if (P.wg_work && threadIdx.x == 0 && L < RBFS_STATS_MAX_LEVELS)
+    if (WGW && threadIdx.x == 0 && L < RBFS_STATS_MAX_LEVELS)
       P.wg_work[(int64_t)L * gridDim.x + blockIdx.x] = dir == 0 ? wg_td : wg_examined;
     if (!grid_sync(&ctl->bar, P.timeout_ticks)) return;
 
@@ -938,13 +941,24 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
     BFS_CHECK(rbfs::dev_malloc(&w->chunk[i], sizeof(int32_t) * kNQ * w->chunk_cap));
   BFS_CHECK(rbfs::dev_malloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
-  int per_cu = 0;
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel<1024>,
+  // residency of both instantiations: the grid must fit either
+  int per_cu = 0, per_cu_w = 0;
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                          bfs_persistent_kernel<1024, false>,
                                                           1024, 0));
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w,
+                                                          bfs_persistent_kernel<1024, true>,
+                                                          1024, 0));
+  per_cu = std::min(per_cu, per_cu_w);
   if (per_cu < 1) per_cu = 1;
   w->max_per_cu = per_cu;
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, bfs_persistent_kernel<256>,
-                                                          256, 0));
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
+                                                          bfs_persistent_kernel<256, false>, 256,
+                                                          0));
+  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w,
+                                                          bfs_persistent_kernel<256, true>, 256,
+                                                          0));
+  per_cu = std::min(per_cu, per_cu_w);
   w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
   w->grid = g->compute_units;
   w->max_grid = 4 * g->compute_units;  // per_cu is at most 4
@@ -1096,9 +1110,16 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     w->wg_valid = true;
   }
   if (block == 256)
-    hipLaunchKernelGGL(bfs_persistent_kernel<256>, dim3(grid), dim3(256), 0, stream, P);
+    if (P.wg_work)
+      hipLaunchKernelGGL((bfs_persistent_kernel<256, true>), dim3(grid), dim3(256), 0, stream, P);
+    else
+      hipLaunchKernelGGL((bfs_persistent_kernel<256, false>), dim3(grid), dim3(256), 0, stream, P);
   else
-    hipLaunchKernelGGL(bfs_persistent_kernel<1024>, dim3(grid), dim3(1024), 0, stream, P);
+    if (P.wg_work)
+      hipLaunchKernelGGL((bfs_persistent_kernel<1024, true>), dim3(grid), dim3(1024), 0, stream, P);
+    else
+      hipLaunchKernelGGL((bfs_persistent_kernel<1024, false>), dim3(grid), dim3(1024), 0, stream,
+                         P);
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
