@@ -148,3 +148,44 @@ def test_learned_switch_gain_on_held_out_graph(rb):
           % (cost_l, cost_h, cost_best))
     assert cost_l <= 1.10 * cost_h
     assert cost_best <= cost_l + 1e-3
+
+
+def _chung_lu_graph(rb, seed):
+    off, cols = graphgen.chung_lu_csr(300000, 15000, seed=seed, gamma=2.1, mean_deg=30.0,
+                                      max_deg=20000.0)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    return off, cols, G
+
+
+def test_learned_switch_beats_alpha_beta_on_heavy_tail(rb):
+    """On power-law graphs with exponent 2.1 the fixed alpha/beta thresholds
+    leave the search bottom-up too long at the tail (about 1.47x the per-level
+    best).  Trained on four such graphs, the switch must cut the measured
+    per-level cost of a held-out one by at least 10 % against alpha/beta, and
+    its outputs stay identical to the heuristic schedule's."""
+    rows = []
+    for seed in (1, 2, 3, 4):
+        off, cols, G = _chung_lu_graph(rb, seed)
+        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed), reps=3))
+    rows = np.vstack(rows)
+    order = graphgen.epoch_orders(rows.shape[0], 300, 1)
+    w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
+                            batch=64, lr=3e-3)
+    assert curve[-1] < curve[0]
+    rb.switch_load(rb.make_switch_blob(w, rows))
+    off, cols, G = _chung_lu_graph(rb, 9)
+    cost_l = cost_h = cost_best = 0.0
+    for r in graphgen.sample_roots(off, 8, 5):
+        s = rb.collect_level_samples(G, [r], reps=3)
+        by_level = {int(row[10]): row for row in s}
+        d_l, p_l, st_l = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
+        d_h, p_h, st_h = G.bfs(r, stats=True)
+        assert torch.equal(d_l, d_h) and torch.equal(p_l, p_h)
+        cost_l += modeled_cost(by_level, st_l["dir"])
+        cost_h += modeled_cost(by_level, st_h["dir"])
+        cost_best += sum(np.exp(min(row[8], row[9])) for row in s)
+    print("learned %.1f us, alpha/beta %.1f us, per-level best %.1f us"
+          % (cost_l, cost_h, cost_best))
+    assert cost_l <= 0.90 * cost_h
+    assert cost_best <= cost_l + 1e-3
