@@ -5,7 +5,9 @@ One step = 64 single-root searches (plain alpha = 14 / beta = 24 heuristic,
 outputs in original IDs), inputs resident in HBM.  RCM is timed once,
 separately.  Also measured on the same graph and roots: the learned direction
 switch (trained here on per-level timings of scale 18-24 graphs) and the
-64-root bit-parallel batch; and the 32-graph multi-graph batch.  Launch
+64-root bit-parallel batch; the learned switch on held-out power-law graphs
+(exponent 2.1), where it has headroom over alpha/beta; and the 32-graph
+multi-graph batch.  Launch
 parameters come from the autotuner's JSON cache (tuned on other roots of the
 same graphs; a missing entry is tuned in the run, --retune forces it,
 --no-tune uses the built-in defaults).  Prints one JSON line.
@@ -193,6 +195,54 @@ def schedule_costs(rb, G, roots, learned_opts, plain_opts):
     tot["alpha_beta_best_choice_frac"] = agree_h / max(1, nlev)
     tot["roots"] = len(roots)
     return tot
+
+
+def heavy_tail_switch(rb, graphgen, steps, alpha, beta):
+    """The learned switch on power-law graphs (Chung-Lu, 300000 vertices,
+    exponent 2.1, mean degree 30), where the alpha/beta thresholds stay
+    bottom-up too long at the tail: trained on 4 graphs (8 roots each),
+    measured on a held-out fifth (8 roots).  Loads its own switch blob."""
+    import numpy as np
+    import torch
+
+    def graph(seed):
+        off, cols = graphgen.chung_lu_csr(300000, 15000, seed=seed, gamma=2.1, mean_deg=30.0,
+                                          max_deg=20000.0)
+        G = rb.Graph(off, cols)
+        G.rcm_reorder(want_perm=False)
+        return off, G
+    rows = []
+    for seed in (1, 2, 3, 4):
+        off, G = graph(seed)
+        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed), reps=3))
+        G.close()
+    rows = np.vstack(rows)
+    order = graphgen.epoch_orders(rows.shape[0], 300, 1)
+    w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
+                            batch=64, lr=3e-3)
+    rb.switch_load(rb.make_switch_blob(w, rows))
+    off, G = graph(9)
+    roots = graphgen.sample_roots(off, 8, 5)
+    depth = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(G.n, dtype=torch.int32, device="cuda")
+    learned = rb.make_opts(rb.DIR_LEARNED, alpha=alpha, beta=beta)
+    plain = rb.make_opts(alpha=alpha, beta=beta)
+    for r in roots:
+        G.bfs(r, depth, parent, opts=learned)
+        G.bfs(r, depth, parent, opts=plain)
+    per_l, _ = time_roots(G, roots, depth, parent, learned, max(steps, 5))
+    per_h, _ = time_roots(G, roots, depth, parent, plain, max(steps, 5))
+    out = {"graph": "chung-lu n=300000 exponent 2.1 mean degree 30 (held-out seed 9)",
+           "train_samples": int(rows.shape[0]),
+           "ms_per_root_learned": sum(per_l) / len(per_l),
+           "ms_per_root_alpha_beta": sum(per_h) / len(per_h),
+           "speedup": sum(per_h) / sum(per_l),
+           "schedule_costs_8_roots": schedule_costs(rb, G, roots, learned, plain)}
+    G.close()
+    torch.cuda.empty_cache()
+    log("# learned, heavy tail: %.3f ms against %.3f ms per root (%.2fx)"
+        % (out["ms_per_root_learned"], out["ms_per_root_alpha_beta"], out["speedup"]))
+    return out
 
 
 def tuned_leg(rb, target, roots, cache, graph_class, kind, retune, opts=None, reps=2):
@@ -607,6 +657,8 @@ def main():
                           "schedule_costs_8_roots": schedule_costs(rb, G, roots[:8], learned,
                                                                    plain)}
         log("# learned: %.1f GTEPS (plain %.1f)" % (gl, hmean))
+        out["learned"]["heavy_tail"] = heavy_tail_switch(rb, graphgen, args.steps, args.alpha,
+                                                         args.beta)
     if not args.no_multi:
         out["multi"] = multi_batch(rb, graphgen, args.steps, cache, args.retune)
     if tuning:
