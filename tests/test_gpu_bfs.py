@@ -316,3 +316,32 @@ def test_workgroup_work_adds_up(rb):
     G.bfs(0)
     with pytest.raises(rb.RbfsError):
         G.wg_work()
+
+
+@pytest.mark.parametrize("n", [1, 7])
+@pytest.mark.parametrize("reorder", [False, True], ids=["original", "rcm"])
+def test_edgeless_graph(rb, n, reorder):
+    """No edges at all: every vertex is isolated, so the relabelling is the
+    identity with an empty V+, and every search reaches its root only."""
+    off = np.zeros(n + 1, np.int64)
+    cols = np.zeros(0, np.int32)
+    G = rb.Graph(off, cols)
+    perm_o = oracle.rcm(off, cols)[0]
+    if reorder:
+        perm, _ = G.rcm_reorder()
+        assert np.array_equal(perm.cpu().numpy(), perm_o)
+        assert G.info()["n_plus"] == 0
+        G0 = rb.Graph(off, cols)
+        perm0, _ = G0.rcm_reorder(keep=0)
+        assert np.array_equal(perm0.cpu().numpy(), oracle.rcm_partial(off, cols, 0)[0])
+    roots = list(range(n))
+    for r in roots:
+        d_o, p_o, _ = oracle.bfs(off, cols, r, perm_o if reorder else None)
+        for dirc in (rb.DIR_HEURISTIC, rb.DIR_TD_ONLY, rb.DIR_BU_ONLY):
+            d, p = G.bfs(r, opts=rb.make_opts(dirc))
+            assert np.array_equal(d.cpu().numpy(), d_o) and np.array_equal(p.cpu().numpy(), p_o)
+            assert G.certify(r, d, p) == 0
+    dB, pB = G.bfs_batch(roots)
+    for j, r in enumerate(roots):
+        d_o, p_o, _ = oracle.bfs(off, cols, r, perm_o if reorder else None)
+        assert np.array_equal(dB[j].cpu().numpy(), d_o) and np.array_equal(pB[j].cpu().numpy(), p_o)
