@@ -14,10 +14,12 @@
  * Functions and the passages they follow:
  *   orc_bandwidth         Eq. 1 (matrix bandwidth), in a given labelling.
  *   orc_canonical_csr     section 3.1 / Eq. 2: CSR of the undirected edge set.
- *   orc_rcm               Algorithm 3 (RCM) taken step by step: V+ sorted by
- *                         (degree, id), per component a start of minimal
- *                         (degree, id), neighbours appended in (degree, id)
- *                         order, reversal, isolated vertices appended.
+ *   orc_rcm               RCM (section 3.2, Algorithm 3) from its definition:
+ *                         the Cuthill-McKee order is a breadth-first search
+ *                         per component from its vertex of least
+ *                         (degree, id), children queued in (degree, id)
+ *                         order; that order reversed, isolated vertices
+ *                         appended in increasing id.
  *   orc_rcm_partial       section 4.6 (partial RCM): Algorithm 3 cut off after
  *                         a given number of vertices (reading stated at the
  *                         function).
@@ -85,9 +87,16 @@ int64_t orc_canonical_csr(int64_t n, int64_t m, const int32_t* src, const int32_
 }
 
 /* ------------------------------------------------------------------------ */
-/* Algorithm 3.  The order "increasing degree" is read as increasing
- * (degree, vertex id): ties between equal degrees go to the smaller id. */
-static const int64_t* g_sort_off; /* degree lookup for the comparator */
+/* Cuthill-McKee order (section 3.2), written from its definition: the
+ * vertices of V+ are visited by one breadth-first search per connected
+ * component.  A search starts at the not yet placed vertex of least
+ * (degree, id) -- "increasing degree" with ties to the smaller id -- and
+ * every vertex taken out of the FIFO queue puts its not yet placed
+ * neighbours into the queue in increasing (degree, id).  The order in which
+ * vertices leave the queue is the Cuthill-McKee sequence.  Reversing it
+ * gives RCM (Algorithm 3).  The order "increasing degree" is read as
+ * increasing (degree, vertex id) throughout. */
+static _Thread_local const int64_t* g_sort_off; /* degree lookup for the comparator */
 
 static int cmp_deg_id(const void* a, const void* b) {
   int32_t x = *(const int32_t*)a, y = *(const int32_t*)b;
@@ -97,108 +106,94 @@ static int cmp_deg_id(const void* a, const void* b) {
   return (x > y) - (x < y);
 }
 
-/* The Cuthill-McKee sequence of Algorithm 3 (before the reversal), cut off
- * once `limit` vertices are in it: P[0..placed) in the order the algorithm
- * appends them.  Components start at the unvisited vertex of least
- * (degree, id); each vertex taken from the queue appends its unvisited
- * neighbours in increasing (degree, id).  Returns the number placed,
- * min(limit, n+); *nplus_out = n+ = |V+|. */
+/* seq[0..returned) = the first min(limit, n+) vertices of the Cuthill-McKee
+ * sequence; *nplus_out = n+ = |V+|. */
 static int64_t cm_sequence(int64_t n, const int64_t* off, const int32_t* cols, int64_t limit,
-                           int32_t* P, int64_t* nplus_out) {
+                           int32_t* seq, int64_t* nplus_out) {
   g_sort_off = off;
-  /* V+: all non-isolated vertices, sorted by (degree, id). */
-  int32_t* vplus = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  /* candidate starts: the non-isolated vertices in increasing (degree, id) */
+  int32_t* starts = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
   int64_t nplus = 0;
   for (int64_t v = 0; v < n; ++v)
-    if (off[v + 1] > off[v]) vplus[nplus++] = (int32_t)v;
-  qsort(vplus, (size_t)nplus, sizeof(int32_t), cmp_deg_id);
+    if (off[v + 1] > off[v]) starts[nplus++] = (int32_t)v;
+  qsort(starts, (size_t)nplus, sizeof(int32_t), cmp_deg_id);
   if (limit > nplus) limit = nplus;
 
-  char* visited = (char*)calloc((size_t)n + 1, 1);
-  int32_t* nb = NULL; /* scratch for sorted_neighbors */
-  int64_t nb_cap = 0;
-  int64_t min_index = 0, slow = 0, fast = 0;
-  while (fast < limit) {
-    /* next unvisited vertex of minimal (degree, id) starts a component */
-    for (int64_t i = min_index; i < nplus; ++i) {
-      if (!visited[vplus[i]]) {
-        P[fast++] = vplus[i];
-        visited[vplus[i]] = 1;
-        min_index = i + 1;
-        break;
+  char* queued = (char*)calloc((size_t)n + 1, 1);    /* ever put in the queue */
+  int32_t* queue = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  int32_t* kids = (int32_t*)malloc(sizeof(int32_t) * (n + 1)); /* one vertex's new children */
+  int64_t out = 0;
+  for (int64_t s = 0; s < nplus && out < limit; ++s) {
+    const int32_t start = starts[s];
+    if (queued[start]) continue; /* already in an earlier component */
+    int64_t head = 0, tail = 0;
+    queue[tail++] = start;
+    queued[start] = 1;
+    while (head < tail && out < limit) {
+      const int32_t u = queue[head++];
+      seq[out++] = u;
+      int64_t nk = 0;
+      for (int64_t e = off[u]; e < off[u + 1]; ++e)
+        if (!queued[cols[e]]) kids[nk++] = cols[e];
+      qsort(kids, (size_t)nk, sizeof(int32_t), cmp_deg_id);
+      for (int64_t j = 0; j < nk; ++j) {
+        queued[kids[j]] = 1;
+        queue[tail++] = kids[j];
       }
-    }
-    /* explore the component, appending unvisited neighbours of P[slow] in
-     * increasing (degree, id) order */
-    while (slow < fast && fast < limit) {
-      int32_t u = P[slow];
-      int64_t d = off[u + 1] - off[u];
-      if (d > nb_cap) {
-        free(nb);
-        nb_cap = d;
-        nb = (int32_t*)malloc(sizeof(int32_t) * nb_cap);
-      }
-      memcpy(nb, cols + off[u], sizeof(int32_t) * d);
-      qsort(nb, (size_t)d, sizeof(int32_t), cmp_deg_id);
-      for (int64_t j = 0; j < d && fast < limit; ++j) {
-        if (!visited[nb[j]]) {
-          visited[nb[j]] = 1;
-          P[fast++] = nb[j];
-        }
-      }
-      slow++;
     }
   }
-  free(nb);
-  free(visited);
-  free(vplus);
+  free(kids);
+  free(queue);
+  free(queued);
+  free(starts);
   *nplus_out = nplus;
-  return fast;
+  return out;
 }
 
-static void reverse_i32(int32_t* a, int64_t len) {
-  for (int64_t i = 0, j = len - 1; i < j; ++i, --j) {
-    int32_t t = a[i];
-    a[i] = a[j];
-    a[j] = t;
-  }
-}
-
-/* P[k] = original vertex that receives label k; perm[v] = label of v.
- * Returns n+ = |V+|, the number of non-isolated vertices. */
-int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* P, int32_t* perm) {
+/* iperm[k] = original vertex that receives label k; perm[v] = label of v.
+ * RCM gives sequence position j of the Cuthill-McKee order the label
+ * n+ - 1 - j (the reversal), and the isolated vertices the labels n+ .. n-1
+ * in increasing id.  Returns n+ = |V+|, the number of non-isolated
+ * vertices. */
+int64_t orc_rcm(int64_t n, const int64_t* off, const int32_t* cols, int32_t* iperm,
+                int32_t* perm) {
   int64_t nplus = 0;
-  cm_sequence(n, off, cols, n, P, &nplus);
-  /* reverse, then append the isolated vertices in increasing id */
-  reverse_i32(P, nplus);
+  int32_t* seq = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  cm_sequence(n, off, cols, n, seq, &nplus);
+  for (int64_t j = 0; j < nplus; ++j) iperm[nplus - 1 - j] = seq[j];
   int64_t k = nplus;
   for (int64_t v = 0; v < n; ++v)
-    if (off[v + 1] == off[v]) P[k++] = (int32_t)v;
-  for (int64_t i = 0; i < n; ++i) perm[P[i]] = (int32_t)i;
+    if (off[v + 1] == off[v]) iperm[k++] = (int32_t)v;
+  for (int64_t i = 0; i < n; ++i) perm[iperm[i]] = (int32_t)i;
+  free(seq);
   return nplus;
 }
 
 /* Partial RCM (section 4.6): only part of the vertices is reordered.
- * Reading: the first `keep` vertices of Algorithm 3's Cuthill-McKee sequence
- * take labels [0, keep) in reverse sequence order; the other non-isolated
+ * Reading: the first `keep` vertices of the Cuthill-McKee sequence take
+ * labels [0, keep) in reverse sequence order; the other non-isolated
  * vertices follow in increasing id (their order is left alone); the
  * isolated vertices come last in increasing id.  keep >= n+ is Algorithm 3
  * itself; keep = 0 only moves the isolated vertices to the end.  A ratio p
  * of the section maps to keep = ceil(p * n+).  Returns n+. */
 int64_t orc_rcm_partial(int64_t n, const int64_t* off, const int32_t* cols, int64_t keep,
-                        int32_t* P, int32_t* perm) {
+                        int32_t* iperm, int32_t* perm) {
   int64_t nplus = 0;
-  const int64_t placed = cm_sequence(n, off, cols, keep < 0 ? 0 : keep, P, &nplus);
-  reverse_i32(P, placed);
+  int32_t* seq = (int32_t*)malloc(sizeof(int32_t) * (n + 1));
+  const int64_t placed = cm_sequence(n, off, cols, keep < 0 ? 0 : keep, seq, &nplus);
   char* in_seq = (char*)calloc((size_t)n + 1, 1);
-  for (int64_t i = 0; i < placed; ++i) in_seq[P[i]] = 1;
+  for (int64_t j = 0; j < placed; ++j) {
+    iperm[placed - 1 - j] = seq[j];
+    in_seq[seq[j]] = 1;
+  }
   int64_t k = placed;
   for (int64_t v = 0; v < n; ++v)
-    if (off[v + 1] > off[v] && !in_seq[v]) P[k++] = (int32_t)v;
+    if (off[v + 1] > off[v] && !in_seq[v]) iperm[k++] = (int32_t)v;
   for (int64_t v = 0; v < n; ++v)
-    if (off[v + 1] == off[v]) P[k++] = (int32_t)v;
-  for (int64_t i = 0; i < n; ++i) perm[P[i]] = (int32_t)i;
+    if (off[v + 1] == off[v]) iperm[k++] = (int32_t)v;
+  for (int64_t i = 0; i < n; ++i) perm[iperm[i]] = (int32_t)i;
   free(in_seq);
+  free(seq);
   return nplus;
 }
 
