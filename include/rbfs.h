@@ -105,6 +105,13 @@ typedef struct rbfs_opts {
 #define RBFS_OPT_WG_WORK 2 /* single-root searches: record the adjacency
                               entries each workgroup processed per level;
                               read them with rbfs_graph_wg_work */
+#define RBFS_OPT_ZERO_WAIT 4 /* single-root searches, for tests of the error
+                                path: the search's grid barrier waits for no
+                                time, so the search gives up at its first
+                                barrier with the time-out status (outputs
+                                unspecified; every kernel still exits
+                                normally).  Without stats the call returns
+                                RBFS_OK and rbfs_graph_check reports it. */
 
 /* Per-search statistics; asking for them synchronises the stream.  Level d
  * arrays describe the level that expands frontier F_d. */
@@ -186,7 +193,9 @@ int rbfs_set_allocator(rbfs_alloc_fn alloc, rbfs_free_fn free_fn, void* ctx);
 int rbfs_graph_create(int64_t n, int64_t nnz, const int64_t* row_offsets, const int32_t* cols,
                       uint32_t flags, void* stream, rbfs_graph_t** out);
 
-/* Release a handle and its device memory.  NULL is accepted. */
+/* Release a handle and its device memory.  NULL is accepted.  Returns
+ * RBFS_E_STATE (and releases nothing) while a multi-graph handle built over
+ * this graph exists: destroy that first. */
 int rbfs_graph_destroy(rbfs_graph_t* g);
 
 int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
@@ -201,7 +210,8 @@ int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
  * later searches sweep only the n+ non-isolated vertices.
  * perm_out (nullable, device, int32[n]) receives perm[old] = new.
  * ms_out (nullable, host) receives the elapsed time.  Synchronises `stream`.
- * A second call returns RBFS_OK and changes nothing. */
+ * A second call returns RBFS_OK and changes nothing.  RBFS_E_STATE while a
+ * multi-graph handle built over the graph in its original labels exists. */
 int rbfs_rcm_reorder(rbfs_graph_t* g, int32_t* perm_out, void* stream, float* ms_out);
 
 /* Partial RCM (section 4.6): as rbfs_rcm_reorder, but only the first `keep`
@@ -254,9 +264,12 @@ int rbfs_bfs(rbfs_graph_t* g, int32_t root, int32_t* depth, int32_t* parent,
 int rbfs_certify(rbfs_graph_t* g, int32_t root, const int32_t* depth, const int32_t* parent,
                  int32_t output_space, void* stream, int32_t* result);
 
-/* Synchronise `stream` and report any sticky device status (queue overflow,
- * barrier timeout, corrupt input detected by a kernel) raised by searches on
- * this graph since the last check: RBFS_OK or RBFS_E_DEVICE. */
+/* Synchronise `stream` and report any device status (queue overflow,
+ * barrier time-out, corrupt input detected by a kernel) raised by any
+ * single-root search on this graph since the last check, including those a
+ * call with stats already reported: RBFS_OK or RBFS_E_DEVICE.  The status is
+ * cleared once reported.  (Batched searches report their status at the end
+ * of each call.) */
 int rbfs_graph_check(rbfs_graph_t* g, void* stream);
 
 /* Work per workgroup of the graph's last single-root search, if it was made
@@ -290,7 +303,10 @@ int rbfs_bfs_batch(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t* de
 /* Multi-graph batch: the graphs are packed as one disjoint union (each keeps
  * its own labels, offset by the vertex counts of the graphs before it) and
  * searched together, root j of every graph sharing bit j.  All graphs must be
- * in the same state (all reordered or none) on the same device. */
+ * in the same state (all reordered or none) on the same device.  The handle
+ * copies the member CSRs but keeps using each member's label maps, so until
+ * rbfs_multi_destroy the members may be neither relabelled nor destroyed
+ * (both calls return RBFS_E_STATE meanwhile). */
 int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream,
                       rbfs_multi_t** out);
 int rbfs_multi_destroy(rbfs_multi_t* m);

@@ -245,6 +245,7 @@ def device_info():
 
 OPT_TIMING = 1
 OPT_WG_WORK = 2
+OPT_ZERO_WAIT = 4
 
 
 def default_tuning(kind=TUNE_SINGLE):
@@ -263,9 +264,10 @@ def _records(recs, cnt):
 
 
 def make_opts(direction=DIR_HEURISTIC, alpha=14, beta=24, output_space=OUT_ORIGINAL,
-              schedule=None, tune_profile=0, timing=False, wg_work=False):
+              schedule=None, tune_profile=0, timing=False, wg_work=False, zero_wait=False):
     o = Opts()
-    o.flags = (OPT_TIMING if timing else 0) | (OPT_WG_WORK if wg_work else 0)
+    o.flags = ((OPT_TIMING if timing else 0) | (OPT_WG_WORK if wg_work else 0) |
+               (OPT_ZERO_WAIT if zero_wait else 0))
     o.direction = direction
     o.alpha = alpha
     o.beta = beta
@@ -316,8 +318,10 @@ class Graph:
         _live_graphs.add(self)
 
     def close(self):
+        """Release the graph; raises RbfsError (STATE) while a MultiGraph
+        built over it is open."""
         if self._h:
-            lib().rbfs_graph_destroy(self._h)
+            _check(lib().rbfs_graph_destroy(self._h))
             self._h = ctypes.c_void_p()
 
     def __del__(self):

@@ -330,6 +330,10 @@ fail:
 int rbfs_graph_destroy(rbfs_graph_t* h) {
   if (!h) return RBFS_OK;
   Graph* g = &h->g;
+  if (g->multi_refs > 0) {
+    set_error("rbfs_graph_destroy: a multi-graph handle still uses this graph");
+    return RBFS_E_STATE;
+  }
   (void)hipSetDevice(g->device);
   // work still queued on any stream may use the memory released below
   (void)hipDeviceSynchronize();
@@ -382,6 +386,10 @@ static int rcm_reorder_call(rbfs_graph_t* h, int64_t keep, int32_t* perm_out, vo
     if (g->n == 0) {
       set_error("rbfs_rcm_reorder: empty graph");
       return RBFS_E_INVAL;
+    }
+    if (g->multi_refs > 0) {
+      set_error("rbfs_rcm_reorder: a multi-graph handle uses this graph in its current labels");
+      return RBFS_E_STATE;
     }
     rc = rbfs::rcm_reorder_impl(g, stream, ms_out, keep);
     if (rc) return rc;
@@ -584,6 +592,7 @@ int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream_,
     delete m;
     return rc;
   }
+  for (Graph* g : m->gs) ++g->multi_refs;
   rbfs::live_handles_add(1);
   *out = m;
   return RBFS_OK;
@@ -593,6 +602,7 @@ int rbfs_multi_destroy(rbfs_multi_t* m) {
   if (!m) return RBFS_OK;
   (void)hipSetDevice(m->device);
   (void)hipDeviceSynchronize();
+  for (Graph* g : m->gs) --g->multi_refs;
   rbfs::ms_engine_free(&m->eng);
   if (m->own_stream) (void)hipStreamDestroy(m->own_stream);
   delete m;

@@ -64,7 +64,7 @@ struct alignas(128) BfsCtl {
   alignas(128) unsigned long long edges[3][16];     // entries read this level
   alignas(128) unsigned long long vlcnt[3][8][16];  // vertices appended to each sub-list
   int levels;
-  int pad;
+  int sticky;  // statuses of the searches since the last rbfs_graph_check
   int sweep_lo, sweep_hi;  // bottom-up sweep: the root's component
   long long reached, deg_reached;
   signed char hdir[RBFS_STATS_MAX_LEVELS];
@@ -859,10 +859,21 @@ __global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* per
   }
 }
 
+// Clears the barrier and status of the previous search; its status is kept
+// in `sticky` until rbfs_graph_check reads it.
 __global__ void reset_ctl_kernel(BfsCtl* c) {
+  if (threadIdx.x == 0) c->sticky |= c->bar.status;
+  __syncthreads();
   int* p = (int*)&c->bar;
   for (int i = threadIdx.x; i < (int)(sizeof(GridBarrier) / sizeof(int)); i += blockDim.x)
     p[i] = 0;
+}
+
+__global__ void clear_status_kernel(BfsCtl* c) {
+  if (threadIdx.x == 0) {
+    c->sticky = 0;
+    c->bar.status = 0;
+  }
 }
 
 }  // namespace
@@ -1067,6 +1078,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.lane_row = tun.lane_row;
   P.cshift = bits_for(tun.td_chunk);
   P.timeout_ticks = (uint64_t)g->wall_rate_khz * 1000ull * 4ull;  // 4 s
+  if (flags & RBFS_OPT_ZERO_WAIT) P.timeout_ticks = 0;
   P.ctl = w->ctl;
   if (mode == RBFS_DIR_LEARNED) {
     P.sw = switch_blob_device(g->device);
@@ -1172,13 +1184,20 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
 
 int bfs_check_status(Graph* g, hipStream_t stream) {
   if (!g->bfs) return 0;
-  int st = 0;
-  BFS_CHECK(hipMemcpyAsync(&st, &g->bfs->ctl->bar.status, sizeof(int), hipMemcpyDeviceToHost,
+  int st[2] = {0, 0};
+  BFS_CHECK(hipMemcpyAsync(&st[0], &g->bfs->ctl->bar.status, sizeof(int),
+                           hipMemcpyDeviceToHost, stream));
+  BFS_CHECK(hipMemcpyAsync(&st[1], &g->bfs->ctl->sticky, sizeof(int), hipMemcpyDeviceToHost,
                            stream));
   BFS_CHECK(hipStreamSynchronize(stream));
-  if (st != 0) {
+  if ((st[0] | st[1]) != 0) {
+    // reported once: the next check starts from a clear status
+    hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, stream, g->bfs->ctl);
+    BFS_CHECK(hipGetLastError());
+    BFS_CHECK(hipStreamSynchronize(stream));
     g->bfs->clean = false;
-    set_error("bfs: device status " + std::to_string(st));
+    set_error("bfs: device status " + std::to_string(st[0] | st[1]) +
+              " raised by a search since the last check");
     return RBFS_E_DEVICE;
   }
   return 0;

@@ -16,7 +16,6 @@
 
 #include <algorithm>
 #include <string>
-#include <vector>
 
 #include "../../include/rbfs.h"
 #include "common.cuh"
@@ -66,10 +65,11 @@ __global__ void cert_gather_kernel(int64_t n, const int32_t* iperm, const int32_
 // lane, longer ones by the whole wave.  Vertices whose rows are longer and
 // whose own entries are in order go to the long-row list (lv, *lcount).
 __global__ __launch_bounds__(kCertBlock) void certify_kernel(
-    int64_t n, const int64_t* off, const int32_t* cols, CertMap map, int64_t root,
-    const int32_t* dint, const int32_t* parent, int* result, int32_t* lv, int* lcount,
-    int64_t lcap) {
+    int64_t n, const int64_t* off, const int32_t* cols, CertMap map, const int32_t* root_perm,
+    int32_t root_orig, const int32_t* dint, const int32_t* parent, int* result, int32_t* lv,
+    int* lcount, int64_t lcap) {
   const int l = lane_id();
+  const int64_t root = root_perm ? root_perm[root_orig] : root_orig;
   const int64_t nwaves = ((int64_t)gridDim.x * kCertBlock) / kWave;
   const int64_t w0 = ((int64_t)blockIdx.x * kCertBlock + threadIdx.x) / kWave;
   for (int64_t base = w0 * kWave; base < n; base += nwaves * kWave) {
@@ -149,32 +149,67 @@ __global__ __launch_bounds__(kCertBlock) void certify_kernel(
   }
 }
 
-// Row bounds of the long-row list, for the host to cut them into chunks.
-__global__ void cert_long_bounds_kernel(const int32_t* lv, int64_t nl, const int64_t* off,
-                                        int64_t* lb) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nl;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    lb[2 * i] = off[lv[i]];
-    lb[2 * i + 1] = off[lv[i] + 1];
+// Chunk plan of the long-row list, one workgroup of kPlanBlock threads:
+// row i of the list is cut into ceil(len / kCertChunk) chunks, cpre is the
+// exclusive prefix of those counts (cpre[nl] = number of chunks), and the
+// row's found flag starts at zero.  nl is read from the device counter.
+constexpr int kPlanBlock = 1024;
+__global__ __launch_bounds__(kPlanBlock) void cert_long_plan_kernel(
+    const int32_t* lv, const int* lcount, int64_t lcap, const int64_t* off, int64_t* cpre,
+    int* lfound) {
+  __shared__ int64_t s_wave[kPlanBlock / kWave];
+  __shared__ int64_t s_carry;
+  const int64_t nl = min((int64_t)*lcount, lcap);
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < nl; base += kPlanBlock) {
+    const int64_t i = base + threadIdx.x;
+    int64_t cnt = 0;
+    if (i < nl) {
+      const int64_t v = lv[i];
+      cnt = (off[v + 1] - off[v] + kCertChunk - 1) / kCertChunk;
+      lfound[i] = 0;
+    }
+    const int64_t inc = wave_inclusive_sum(cnt);
+    if (lane_id() == kWave - 1) s_wave[wave_id()] = inc;
+    __syncthreads();
+    int64_t before = s_carry;
+    for (int w = 0; w < wave_id(); ++w) before += s_wave[w];
+    if (i < nl) cpre[i] = before + inc - cnt;
+    __syncthreads();
+    if (threadIdx.x == kPlanBlock - 1) s_carry = before + inc;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) cpre[nl] = s_carry;
 }
 
-// One chunk of a long row per workgroup: chunk c covers entries
-// [cb[c], ce[c]) of long-row list entry ci[c].  A chunk that meets the
-// parent marks the row in lfound.
+// One chunk of a long row per workgroup and step: chunk c belongs to the
+// list row i with cpre[i] <= c < cpre[i + 1] and covers kCertChunk entries of
+// it from (c - cpre[i]) * kCertChunk on.  A chunk that meets the parent
+// marks the row in lfound.
 __global__ __launch_bounds__(kCertBlock) void certify_long_kernel(
-    const int32_t* cols, CertMap map, const int32_t* dint, const int32_t* parent,
-    const int32_t* lv, const int32_t* ci, const int64_t* cb, const int64_t* ce,
-    int64_t nchunks, int* lfound, int* result) {
+    const int64_t* off, const int32_t* cols, CertMap map, const int32_t* dint,
+    const int32_t* parent, const int32_t* lv, const int* lcount, int64_t lcap,
+    const int64_t* cpre, int* lfound, int* result) {
+  const int64_t nl = min((int64_t)*lcount, lcap);
+  const int64_t nchunks = cpre[nl];
   for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
-    const int i = ci[c];
+    int64_t lo = 0, hi = nl;  // largest i with cpre[i] <= c
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (cpre[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    const int64_t i = lo;
     const int64_t v = lv[i];
+    const int64_t cb = off[v] + (c - cpre[i]) * (int64_t)kCertChunk;
+    const int64_t ce = min(off[v + 1], cb + (int64_t)kCertChunk);
     const int32_t dv = dint[v];
     const int32_t pv = parent[map.out(v)];  // in range: checked by the first pass
     const int64_t p = pv >= 0 ? map.in(pv) : -1;
     int code = 0;
     bool found = false;
-    for (int64_t j = cb[c] + threadIdx.x; j < ce[c]; j += kCertBlock) {
+    for (int64_t j = cb + threadIdx.x; j < ce; j += kCertBlock) {
       const int32_t w = cols[j];
       const int cj = cert_edge(dv, p, w, dint[w], found);
       code = cj < code ? cj : code;
@@ -186,13 +221,20 @@ __global__ __launch_bounds__(kCertBlock) void certify_long_kernel(
 
 // A long row of a vertex below the root level whose chunks never met its
 // parent breaks the parent rule.
-__global__ void certify_long_parent_kernel(const int32_t* lv, int64_t nl, const int32_t* dint,
-                                           int64_t root, const int* lfound, int* result) {
+__global__ void certify_long_parent_kernel(const int32_t* lv, const int* lcount, int64_t lcap,
+                                           const int32_t* dint, const int32_t* root_perm,
+                                           int32_t root_orig, const int* lfound, int* result) {
+  const int64_t nl = min((int64_t)*lcount, lcap);
+  const int64_t root = root_perm ? root_perm[root_orig] : root_orig;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nl;
        i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t v = lv[i];
     if (dint[v] > 0 && v != root && !lfound[i]) atomicMin(result, -5);
   }
+}
+
+__global__ void cert_zero_kernel(int* small) {
+  if (threadIdx.x < 4) small[threadIdx.x] = 0;
 }
 
 }  // namespace
@@ -201,145 +243,143 @@ __global__ void certify_long_parent_kernel(const int32_t* lv, int64_t nl, const 
 using rbfs::Graph;
 using rbfs::set_error;
 
-extern "C" int rbfs_certify(rbfs_graph_t* h, int32_t root, const int32_t* depth,
-                            const int32_t* parent, int32_t output_space, void* stream_,
-                            int32_t* result) {
+namespace rbfs {
+namespace {
+
+// Scratch of one certificate, carved from one buffer at 256-byte offsets:
+// result and long-row counter, the long-row list, its found flags and chunk
+// prefix (lcap rows of more than kCertLong entries at most), and, when the
+// outputs are in original IDs of a relabelled graph, the depths in internal
+// order.
+struct CertScratch {
+  int* small = nullptr;     // [0] result, [1] long-row count
+  int32_t* lv = nullptr;
+  int* lf = nullptr;
+  int64_t* cpre = nullptr;
+  int32_t* dint = nullptr;
+  int64_t lcap = 0;
+};
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t cert_layout(const Graph* g, bool gather, unsigned char* base, CertScratch* cs) {
+  const int64_t lcap = g->nnz / kCertLong + 1;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return base ? base + at : nullptr;
+  };
+  CertScratch c;
+  c.lcap = lcap;
+  c.small = (int*)take(4 * sizeof(int));
+  c.lv = (int32_t*)take(sizeof(int32_t) * (size_t)lcap);
+  c.lf = (int*)take(sizeof(int) * (size_t)lcap);
+  c.cpre = (int64_t*)take(sizeof(int64_t) * (size_t)(lcap + 1));
+  if (gather) c.dint = (int32_t*)take(sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1));
+  if (cs) *cs = c;
+  return o;
+}
+
+int cert_args(rbfs_graph_t* h, int32_t root, const int32_t* depth, const int32_t* parent,
+              int32_t output_space, int32_t* result, const char* who) {
   if (!h || !depth || !parent || !result ||
       (output_space != RBFS_OUT_ORIGINAL && output_space != RBFS_OUT_INTERNAL)) {
-    set_error("rbfs_certify: bad arguments");
+    set_error(std::string(who) + ": bad arguments");
     return RBFS_E_INVAL;
   }
-  Graph* g = &h->g;
-  if (root < 0 || root >= g->n) {
-    set_error("rbfs_certify: root out of range");
+  if (root < 0 || root >= h->g.n) {
+    set_error(std::string(who) + ": root out of range");
     return RBFS_E_RANGE;
   }
-  hipStream_t stream = (hipStream_t)stream_;
+  return 0;
+}
+
+// Enqueues the certificate on `stream` with the given scratch, then waits
+// for its result: the only host round trip.
+int cert_run(Graph* g, int32_t root, const int32_t* depth, const int32_t* parent,
+             int32_t output_space, hipStream_t stream, const CertScratch& cs, int32_t* result,
+             const char* who) {
   const bool orig = output_space == RBFS_OUT_ORIGINAL;
-  rbfs::CertMap map{g->reordered && orig ? g->perm : nullptr,
-                    g->reordered && orig ? g->iperm : nullptr};
-  int64_t root_int = root;
-  if (g->reordered) {
-    int32_t r = 0;
-    hipError_t e = hipMemcpyAsync(&r, g->perm + root, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                  stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) {
-      set_error(std::string("rbfs_certify: ") + hipGetErrorString(e));
-      return RBFS_E_DEVICE;
-    }
-    root_int = r;
-  }
+  CertMap map{g->reordered && orig ? g->perm : nullptr,
+              g->reordered && orig ? g->iperm : nullptr};
+  const int32_t* root_perm = g->reordered ? g->perm : nullptr;
   const int64_t n = g->n;
-  // scratch: result word, long-row counter and list, and (with a mapping)
-  // the depths in internal order
-  const bool gather = map.iperm != nullptr;
-  int* d_small = nullptr;   // [0] result, [1] long-row count
-  int32_t* d_lv = nullptr;  // long-row list: each holds more than kCertLong entries
-  const int64_t lcap = g->nnz / rbfs::kCertLong + 1;
-  int32_t* d_dint = nullptr;
-  std::vector<void*> extra;
-  auto release = [&]() {
-    for (void* q : extra) rbfs::dev_free(q, stream);
-    if (d_dint) rbfs::dev_free(d_dint, stream);
-    if (d_lv) rbfs::dev_free(d_lv, stream);
-    if (d_small) rbfs::dev_free(d_small, stream);
-  };
-  hipError_t e = rbfs::dev_malloc(&d_small, 2 * sizeof(int), stream);
-  if (e == hipSuccess) e = rbfs::dev_malloc(&d_lv, sizeof(int32_t) * (size_t)lcap, stream);
-  if (e == hipSuccess && gather)
-    e = rbfs::dev_malloc(&d_dint, sizeof(int32_t) * (size_t)(n > 0 ? n : 1), stream);
-  if (e != hipSuccess) {
-    release();
-    set_error(std::string("rbfs_certify: ") + hipGetErrorString(e));
-    return RBFS_E_NOMEM;
-  }
-  const int32_t* dint = gather ? d_dint : depth;
+  const int32_t* dint = cs.dint ? cs.dint : depth;
   auto grid_of = [](int64_t work) {
     return (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>((work + rbfs::kCertBlock - 1) / rbfs::kCertBlock, 1 << 16));
+        1, std::min<int64_t>((work + kCertBlock - 1) / kCertBlock, 1 << 16));
   };
-  e = hipMemsetAsync(d_small, 0, 2 * sizeof(int), stream);
-  if (e == hipSuccess && gather) {
-    hipLaunchKernelGGL(rbfs::cert_gather_kernel, dim3(grid_of(n)), dim3(rbfs::kCertBlock), 0,
-                       stream, n, map.iperm, depth, d_dint);
+  hipLaunchKernelGGL(cert_zero_kernel, dim3(1), dim3(64), 0, stream, cs.small);
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess && cs.dint) {
+    hipLaunchKernelGGL(cert_gather_kernel, dim3(grid_of(n)), dim3(kCertBlock), 0, stream, n,
+                       map.iperm, depth, cs.dint);
     e = hipGetLastError();
   }
   if (e == hipSuccess) {
-    hipLaunchKernelGGL(rbfs::certify_kernel, dim3(grid_of(n)), dim3(rbfs::kCertBlock), 0, stream,
-                       n, g->off, g->cols, map, root_int, dint, parent, d_small, d_lv,
-                       d_small + 1, lcap);
+    hipLaunchKernelGGL(certify_kernel, dim3(grid_of(n)), dim3(kCertBlock), 0, stream, n, g->off,
+                       g->cols, map, root_perm, root, dint, parent, cs.small, cs.lv,
+                       cs.small + 1, cs.lcap);
     e = hipGetLastError();
   }
-  int hs[2] = {0, 0};
-  if (e == hipSuccess) e = hipMemcpyAsync(hs, d_small, 2 * sizeof(int), hipMemcpyDeviceToHost, stream);
-  if (e == hipSuccess) e = hipStreamSynchronize(stream);
-  const int64_t nl = hs[1];
-  if (e == hipSuccess && nl > 0) {
-    // long rows: chunk table from their bounds, one chunk per workgroup
-    int64_t* d_lb = nullptr;
-    std::vector<int64_t> hlb(2 * nl);
-    e = rbfs::dev_malloc(&d_lb, sizeof(int64_t) * 2 * nl, stream);
-    if (d_lb) extra.push_back(d_lb);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(rbfs::cert_long_bounds_kernel, dim3(grid_of(nl)), dim3(rbfs::kCertBlock),
-                         0, stream, d_lv, nl, g->off, d_lb);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hlb.data(), d_lb, sizeof(int64_t) * 2 * nl, hipMemcpyDeviceToHost,
-                         stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    std::vector<int32_t> ci;
-    std::vector<int64_t> cb, ce;
-    for (int64_t i = 0; e == hipSuccess && i < nl; ++i)
-      for (int64_t j = hlb[2 * i]; j < hlb[2 * i + 1]; j += rbfs::kCertChunk) {
-        ci.push_back((int32_t)i);
-        cb.push_back(j);
-        ce.push_back(std::min<int64_t>(hlb[2 * i + 1], j + rbfs::kCertChunk));
-      }
-    const int64_t nc = (int64_t)ci.size();
-    int32_t* d_ci = nullptr;
-    int64_t *d_cb = nullptr, *d_ce = nullptr;
-    int* d_lf = nullptr;
-    if (e == hipSuccess) e = rbfs::dev_malloc(&d_ci, sizeof(int32_t) * nc, stream);
-    if (d_ci) extra.push_back(d_ci);
-    if (e == hipSuccess) e = rbfs::dev_malloc(&d_cb, sizeof(int64_t) * nc, stream);
-    if (d_cb) extra.push_back(d_cb);
-    if (e == hipSuccess) e = rbfs::dev_malloc(&d_ce, sizeof(int64_t) * nc, stream);
-    if (d_ce) extra.push_back(d_ce);
-    if (e == hipSuccess) e = rbfs::dev_malloc(&d_lf, sizeof(int) * nl, stream);
-    if (d_lf) extra.push_back(d_lf);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_ci, ci.data(), sizeof(int32_t) * nc, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_cb, cb.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(d_ce, ce.data(), sizeof(int64_t) * nc, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemsetAsync(d_lf, 0, sizeof(int) * nl, stream);
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(rbfs::certify_long_kernel,
-                         dim3((unsigned)std::min<int64_t>(nc, 1 << 16)), dim3(rbfs::kCertBlock),
-                         0, stream, g->cols, map, dint, parent, d_lv, d_ci, d_cb, d_ce, nc, d_lf,
-                         d_small);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess) {
-      hipLaunchKernelGGL(rbfs::certify_long_parent_kernel, dim3(grid_of(nl)),
-                         dim3(rbfs::kCertBlock), 0, stream, d_lv, nl, dint, root_int, d_lf,
-                         d_small);
-      e = hipGetLastError();
-    }
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(hs, d_small, sizeof(int), hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(cert_long_plan_kernel, dim3(1), dim3(kPlanBlock), 0, stream, cs.lv,
+                       cs.small + 1, cs.lcap, g->off, cs.cpre, cs.lf);
+    e = hipGetLastError();
   }
-  release();
+  if (e == hipSuccess) {
+    // at most nnz / kCertChunk + (long rows) chunks; most workgroups find
+    // none when there are few long rows
+    const int64_t max_chunks = g->nnz / kCertChunk + cs.lcap;
+    hipLaunchKernelGGL(certify_long_kernel,
+                       dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(max_chunks, 4096))),
+                       dim3(kCertBlock), 0, stream, g->off, g->cols, map, dint, parent, cs.lv,
+                       cs.small + 1, cs.lcap, cs.cpre, cs.lf, cs.small);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(certify_long_parent_kernel, dim3(grid_of(cs.lcap)), dim3(kCertBlock), 0,
+                       stream, cs.lv, cs.small + 1, cs.lcap, dint, root_perm, root, cs.lf,
+                       cs.small);
+    e = hipGetLastError();
+  }
+  int res = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&res, cs.small, sizeof(int), hipMemcpyDeviceToHost,
+                                          stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
   if (e != hipSuccess) {
-    set_error(std::string("rbfs_certify: ") + hipGetErrorString(e));
+    set_error(std::string(who) + ": " + hipGetErrorString(e));
     return RBFS_E_DEVICE;
   }
-  const int res = hs[0];
   *result = res;
   return RBFS_OK;
+}
+
+}  // namespace
+}  // namespace rbfs
+
+extern "C" int rbfs_certify(rbfs_graph_t* h, int32_t root, const int32_t* depth,
+                            const int32_t* parent, int32_t output_space, void* stream_,
+                            int32_t* result) {
+  int rc = rbfs::cert_args(h, root, depth, parent, output_space, result, "rbfs_certify");
+  if (rc) return rc;
+  Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("rbfs_certify: hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  const bool gather = g->reordered && output_space == RBFS_OUT_ORIGINAL;
+  const size_t bytes = rbfs::cert_layout(g, gather, nullptr, nullptr);
+  unsigned char* buf = nullptr;
+  if (rbfs::dev_malloc(&buf, bytes, stream) != hipSuccess || !buf) {
+    set_error("rbfs_certify: out of device memory for the scratch");
+    return RBFS_E_NOMEM;
+  }
+  rbfs::CertScratch cs;
+  rbfs::cert_layout(g, gather, buf, &cs);
+  rc = rbfs::cert_run(g, root, depth, parent, output_space, stream, cs, result, "rbfs_certify");
+  rbfs::dev_free(buf, stream);
+  return rc;
 }

@@ -164,6 +164,10 @@ struct Graph {
   int compute_units = 0;
   int64_t wall_rate_khz = 100000;
   size_t bytes = 0;
+  // multi-graph handles built over this graph: they keep its perm, n and
+  // n_sweep, so while any exists the graph may be neither relabelled nor
+  // destroyed
+  int multi_refs = 0;
 };
 
 // Sticky error text for the calling thread.

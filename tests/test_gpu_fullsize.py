@@ -1,16 +1,20 @@
 """Parity at the benchmark sizes, in the launch configuration the benchmark
-times.  Scale 22: the whole RCM permutation and every output of sampled
-roots bit-exact against the oracle.  Scale 26, scale 24 (64-root batch) and
-the 52.5M-vertex Chung-Lu graph: the O(nnz) certificates (the RCM
-certificate pins the whole permutation to Algorithm 3; the BFS certificate
-pins depth and the largest-label parent of every vertex), plus oracle depth
-for a sampled root.  Graphs come from the device generator, which equals the
+times.  Scale 22: the whole RCM permutation and every output of all 64
+roots bit-exact against the oracle (single-root, batched, and 16 roots in
+learned mode).  Scale 26 and the 52.5M-vertex Chung-Lu graph: the RCM
+certificate (which pins the whole permutation to Algorithm 3), every output
+of the 64 roots -- plain, learned with a network trained on small Kronecker
+graphs (not retrained), and the 64-root batch -- through the on-device
+certificate, and a sample of each through the oracle's O(nnz) certificate,
+which pins depth and the largest-label parent of every vertex.  Scale 24:
+the 64-root batch.  Graphs come from the device generator, which equals the
 host generator bit for bit (test_gpu_bfs.py)."""
 import numpy as np
 import pytest
 
 import graphgen
 import oracle
+from helpers import pmap, train_kronecker_blob
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
@@ -29,8 +33,19 @@ def host(t):
     return t.cpu().numpy()
 
 
+@pytest.fixture(scope="module")
+def kron_blob(rb):
+    """Switch network trained on small Kronecker graphs; the full-size tests
+    evaluate it without retraining."""
+    return train_kronecker_blob(rb)
+
+
 @pytest.mark.timeout(900)
-def test_scale22_bit_exact(rb):
+def test_scale22_bit_exact(rb, kron_blob):
+    """Scale 22 (configuration of the plain benchmark, 64 roots): the whole
+    permutation, and every output of every root bit-exact against the
+    oracle -- single-root searches, the 64-root batch, and learned-switch
+    searches of 16 roots."""
     off_d, cols_d = graphgen.kronecker_csr_device(22, 16, 1022)
     off, cols = host(off_d), host(cols_d)
     roots = graphgen.sample_roots(off, 64, 7)
@@ -40,46 +55,68 @@ def test_scale22_bit_exact(rb):
     perm = host(perm_t)
     perm_o, _, _ = oracle.rcm(off, cols)
     assert np.array_equal(perm, perm_o)
-    for r in roots[:6]:
+    ref = pmap(lambda r: oracle.bfs(off, cols, r, perm_o)[:2], roots)
+    for r, (d_o, p_o) in zip(roots, ref):
         d, p = G.bfs(r)
-        d_o, p_o, _ = oracle.bfs(off, cols, r, perm_o)
-        assert np.array_equal(host(d), d_o)
-        assert np.array_equal(host(p), p_o)
+        assert np.array_equal(host(d), d_o), r
+        assert np.array_equal(host(p), p_o), r
     dB, pB = G.bfs_batch(roots)
-    for j in (0, 31, 63):
-        d_o, p_o, _ = oracle.bfs(off, cols, roots[j], perm_o)
-        assert np.array_equal(host(dB[j]), d_o)
-        assert np.array_equal(host(pB[j]), p_o)
+    for j, (d_o, p_o) in enumerate(ref):
+        assert np.array_equal(host(dB[j]), d_o), j
+        assert np.array_equal(host(pB[j]), p_o), j
+    rb.switch_load(kron_blob)
+    learned = rb.make_opts(rb.DIR_LEARNED)
+    for r, (d_o, p_o) in list(zip(roots, ref))[:16]:
+        d, p = G.bfs(r, opts=learned)
+        assert np.array_equal(host(d), d_o), r
+        assert np.array_equal(host(p), p_o), r
 
 
-def certify_graph(rb, G, off, cols, roots, n_bfs_cert, n_depth):
+def oracle_certified(off, cols, perm, pairs):
+    """pairs: (root, depth, parent) on the host; True for each that the
+    oracle's O(nnz) certificate accepts (run in parallel)."""
+    return pmap(lambda t: oracle.certify_bfs(off, cols, t[0], t[1], t[2], perm), pairs)
+
+
+def check_full_size(rb, G, off, cols, roots, blob, n_oracle):
+    """RCM permutation certified by the oracle; then plain, learned (the
+    given blob, no retraining) and 64-root batched searches: n_oracle
+    outputs of each through the oracle's certificate (one also against the
+    oracle's depth), every output through the on-device certificate."""
     perm_t, rcm_ms = G.rcm_reorder()
     perm = host(perm_t)
     assert oracle.certify_rcm(off, cols, perm) == 0
-    for i, r in enumerate(roots[:n_bfs_cert]):
-        d, p = G.bfs(r)
-        d, p = host(d), host(p)
-        assert oracle.certify_bfs(off, cols, r, d, p, perm) == 0
-        if i < n_depth:
-            d_o, _, _ = oracle.bfs(off, cols, r)  # depth is label independent
-            assert np.array_equal(d, d_o)
+    rb.switch_load(blob)
+    learned = rb.make_opts(rb.DIR_LEARNED)
+    sample = []
+    for i, r in enumerate(roots):
+        for opts in (None, learned):
+            d, p = G.bfs(r, opts=opts)
+            assert G.certify(r, d, p) == 0, (r, opts is not None)
+            if i < n_oracle:
+                sample.append((r, host(d), host(p)))
+    dB, pB = G.bfs_batch(roots)
+    for j, r in enumerate(roots):
+        assert G.certify(r, dB[j], pB[j]) == 0, j
+    step = max(1, len(roots) // n_oracle)
+    for j in range(0, len(roots), step)[:n_oracle]:
+        sample.append((roots[j], host(dB[j]), host(pB[j])))
+    del dB, pB
+    assert oracle_certified(off, cols, perm, sample) == [0] * len(sample)
+    d_o, _, _ = oracle.bfs(off, cols, roots[0])  # depth does not depend on labels
+    assert np.array_equal(sample[0][1], d_o)
     return perm
 
 
 @pytest.mark.timeout(1200)
-def test_scale26_certified(rb):
+def test_scale26_certified(rb, kron_blob):
     off_d, cols_d = graphgen.kronecker_csr_device(26, 16, 1026)
     off, cols = host(off_d), host(cols_d)
     roots = graphgen.sample_roots(off, 64, 7)
     G = rb.Graph(off_d, cols_d)
     del off_d, cols_d
     torch.cuda.empty_cache()
-    certify_graph(rb, G, off, cols, roots, n_bfs_cert=2, n_depth=1)
-    # every root the benchmark times, through the on-device certificate
-    # (itself checked against the oracle's in test_gpu_certify.py)
-    for r in roots:
-        d, p = G.bfs(r)
-        assert G.certify(r, d, p) == 0, r
+    check_full_size(rb, G, off, cols, roots, kron_blob, n_oracle=4)
 
 
 @pytest.mark.timeout(1200)
@@ -103,14 +140,16 @@ def test_scale24_batch_certified(rb):
 
 
 @pytest.mark.timeout(1200)
-def test_chung_lu_50m_certified(rb):
+def test_chung_lu_50m_certified(rb, kron_blob):
+    """The power-law configuration (52.5M vertices): plain, learned with the
+    Kronecker-trained network (no retraining) and 64-root batched."""
     off_d, cols_d = graphgen.chung_lu_csr_device(50_000_000, 2_500_000, seed=4000)
     off, cols = host(off_d), host(cols_d)
     roots = graphgen.sample_roots(off, 64, 7)
     G = rb.Graph(off_d, cols_d)
     del off_d, cols_d
     torch.cuda.empty_cache()
-    certify_graph(rb, G, off, cols, roots, n_bfs_cert=1, n_depth=1)
+    check_full_size(rb, G, off, cols, roots, kron_blob, n_oracle=2)
 
 
 @pytest.mark.timeout(900)

@@ -189,3 +189,105 @@ def test_learned_switch_beats_alpha_beta_on_heavy_tail(rb):
           % (cost_l, cost_h, cost_best))
     assert cost_l <= 0.90 * cost_h
     assert cost_best <= cost_l + 1e-3
+
+
+def _replay_learned(rb, G, off, cols, perm, roots, blob, alpha=14, beta=24):
+    """Runs DIR_LEARNED with stats from each root and checks every level's
+    direction and fallback code against the fp64 decision of the oracle
+    (oracle.mlp.decide) applied to the oracle's level counters.  A level
+    whose exact inputs lie within fp32 error of a threshold (range boundary
+    or margin) may take any outcome the error bound allows; the replay then
+    continues from the direction the kernel took.  Returns how many levels
+    each fallback code decided."""
+    info = G.info()
+    n_sweep = info["n_plus"] if info["reordered"] else info["n"]
+    nnz = info["nnz"]
+    tally = {0: 0, 1: 0, 2: 0}
+    loose = 0
+    for r in roots:
+        d, p, st = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED, alpha=alpha, beta=beta),
+                         stats=True)
+        d_o, p_o, nlev = oracle.bfs(off, cols, r, perm)
+        assert np.array_equal(d.cpu().numpy(), d_o)
+        assert np.array_equal(p.cpu().numpy(), p_o)
+        c = oracle.level_counters(off, cols, d_o, ell=perm, n_sweep=n_sweep)
+        assert st["levels"] == nlev
+        assert st["nf"] == [int(x) for x in c["nf"]]
+        assert st["mf"] == [int(x) for x in c["mf"]]
+        assert st["mu"] == [int(x) for x in c["mu"]]
+        dirs, fbs, outs = mlp.learned_schedule(blob.astype(np.float64), c["nf"], c["mf"],
+                                               c["mu"], c["nu"], n_sweep, nnz, alpha, beta,
+                                               taken=st["dir"])
+        assert st["dir"][0] == 0
+        for lv in range(1, nlev):
+            got = (int(st["dir"][lv]), int(st["fallback"][lv]))
+            assert got in outs[lv], "root %d level %d: kernel %s, oracle allows %s" % (
+                r, lv, got, sorted(outs[lv]))
+            if len(outs[lv]) > 1:
+                loose += 1
+            tally[got[1]] += 1
+    return tally, loose
+
+
+def test_learned_decisions_replay_oracle_random_nets(rb):
+    """Random networks with an unbounded training range: the network decides
+    every level (fallback 0) unless its two predictions lie within the margin
+    (fallback 2); each level's choice equals the fp64 decision."""
+    off, cols, G, perm = _kron_graph(rb, 14, 31)
+    roots = graphgen.sample_roots(off, 6, 7)
+    total = {0: 0, 1: 0, 2: 0}
+    for seed in range(6):
+        w = graphgen.mlp_init_weights(40 + seed).astype(np.float32) * 4.0
+        blob = np.zeros(rb.SWITCH_BLOB, np.float32)
+        blob[:mlp.NPARAMS] = w
+        blob[mlp.NPARAMS:mlp.NPARAMS + 8] = -10.0
+        blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16] = 10.0
+        blob[mlp.NPARAMS + 16] = 64
+        rb.switch_load(blob)
+        tally, _ = _replay_learned(rb, G, off, cols, perm, roots, blob)
+        for k in total:
+            total[k] += tally[k]
+    print("levels decided: network %d, out of range %d, within margin %d"
+          % (total[0], total[1], total[2]))
+    assert total[1] == 0
+    assert total[0] > 0
+
+
+def test_learned_decisions_replay_oracle_trained(rb):
+    """A network trained on the per-level timings of small Kronecker and
+    Chung-Lu graphs, replayed on held-out graphs of both families, with the
+    default and a second (alpha, beta): network, out-of-range and margin
+    decisions all occur and each equals the fp64 decision."""
+    rows = []
+    for scale, seed in [(13, 61), (14, 62)]:
+        off, cols, G, _ = _kron_graph(rb, scale, seed)
+        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 6, seed), reps=2))
+    off, cols = graphgen.chung_lu_csr(60000, 3000, seed=63, gamma=2.1, mean_deg=20.0,
+                                      max_deg=5000.0)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 6, 63), reps=2))
+    rows = np.vstack(rows)
+    order = graphgen.epoch_orders(rows.shape[0], 200, 2)
+    w, _ = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(5).astype(np.float32), order,
+                        batch=64, lr=3e-3)
+    blob = rb.make_switch_blob(w, rows)
+    rb.switch_load(blob)
+    total = {0: 0, 1: 0, 2: 0}
+    loose = 0
+    graphs = [_kron_graph(rb, 15, 64)]
+    off, cols = graphgen.chung_lu_csr(80000, 4000, seed=65, gamma=2.1, mean_deg=20.0,
+                                      max_deg=8000.0)
+    G = rb.Graph(off, cols)
+    perm_t, _ = G.rcm_reorder()
+    graphs.append((off, cols, G, perm_t.cpu().numpy()))
+    for off, cols, G, perm in graphs:
+        roots = graphgen.sample_roots(off, 6, 9)
+        for ab in ((14, 24), (64, 8)):
+            tally, lo = _replay_learned(rb, G, off, cols, perm, roots, blob, *ab)
+            loose += lo
+            for k in total:
+                total[k] += tally[k]
+    print("levels decided: network %d, out of range %d, within margin %d; %d levels "
+          "within fp32 error of a threshold" % (total[0], total[1], total[2], loose))
+    assert total[0] > 0 and total[1] + total[2] > 0
