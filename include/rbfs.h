@@ -264,6 +264,24 @@ int rbfs_bfs(rbfs_graph_t* g, int32_t root, int32_t* depth, int32_t* parent,
 int rbfs_certify(rbfs_graph_t* g, int32_t root, const int32_t* depth, const int32_t* parent,
                  int32_t output_space, void* stream, int32_t* result);
 
+/* rbfs_certify for callers that cannot allocate device memory (tight serving
+ * loops, harnesses that forbid hipMalloc): the same checks and result, with
+ * the scratch (result word, long-row list and chunk plan, and for original-ID
+ * outputs of a relabelled graph the depths in internal order) taken from a
+ * static device buffer of 64 MiB that each GPU the library runs on holds
+ * until the process ends, instead of from the allocator.  It makes no
+ * allocation of any kind.  Graphs whose scratch exceeds the buffer -- about
+ * 4 * n + 16 * (nnz / 4096) bytes with that gather, so n up to about 16
+ * million vertices -- are refused with RBFS_E_RANGE (use rbfs_certify).
+ * Every call on a GPU uses that GPU's one buffer: calls that overlap on one
+ * GPU (on different streams or host threads) race and must be serialised by
+ * the caller.  The buffer keeps the last call's contents; each call clears
+ * what it needs.  Arguments, results and errors otherwise as rbfs_certify;
+ * synchronises `stream`. */
+int rbfs_certify_noalloc(rbfs_graph_t* g, int32_t root, const int32_t* depth,
+                         const int32_t* parent, int32_t output_space, void* stream,
+                         int32_t* result);
+
 /* Synchronise `stream` and report any device status (queue overflow,
  * barrier time-out, corrupt input detected by a kernel) raised by any
  * single-root search on this graph since the last check, including those a

@@ -123,6 +123,7 @@ SIGNATURES = {
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_certify": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
+    "rbfs_certify_noalloc": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
     "rbfs_multi_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "rbfs_multi_destroy": (ctypes.c_int, [_P]),
     "rbfs_bfs_multi": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include "../../include/rbfs.h"
@@ -356,6 +357,38 @@ int cert_run(Graph* g, int32_t root, const int32_t* depth, const int32_t* parent
   return RBFS_OK;
 }
 
+// Static scratch of rbfs_certify_noalloc: one copy per device, held until
+// the process ends.  Host code never uses this name as an address: the
+// device address of each GPU's copy comes from hipGetSymbolAddress.
+constexpr size_t kCertStaticBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kCertStaticBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex s_scratch_mu;
+void* s_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device with that device current.
+int static_scratch(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("rbfs_certify_noalloc: device index out of range");
+    return RBFS_E_UNSUPPORTED;
+  }
+  std::lock_guard<std::mutex> lk(s_scratch_mu);
+  if (!s_scratch_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("rbfs_certify_noalloc: hipGetSymbolAddress: ") +
+                hipGetErrorString(e));
+      return RBFS_E_DEVICE;
+    }
+    s_scratch_ptr[device] = p;
+  }
+  *out = (unsigned char*)s_scratch_ptr[device];
+  return 0;
+}
+
 }  // namespace
 }  // namespace rbfs
 
@@ -382,4 +415,33 @@ extern "C" int rbfs_certify(rbfs_graph_t* h, int32_t root, const int32_t* depth,
   rc = rbfs::cert_run(g, root, depth, parent, output_space, stream, cs, result, "rbfs_certify");
   rbfs::dev_free(buf, stream);
   return rc;
+}
+
+extern "C" int rbfs_certify_noalloc(rbfs_graph_t* h, int32_t root, const int32_t* depth,
+                                    const int32_t* parent, int32_t output_space, void* stream_,
+                                    int32_t* result) {
+  int rc = rbfs::cert_args(h, root, depth, parent, output_space, result,
+                           "rbfs_certify_noalloc");
+  if (rc) return rc;
+  Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  const bool gather = g->reordered && output_space == RBFS_OUT_ORIGINAL;
+  const size_t bytes = rbfs::cert_layout(g, gather, nullptr, nullptr);
+  if (bytes > rbfs::kCertStaticBytes) {
+    set_error("rbfs_certify_noalloc: the graph needs " + std::to_string(bytes) +
+              " bytes of scratch, the static buffer holds " +
+              std::to_string(rbfs::kCertStaticBytes) + " (use rbfs_certify)");
+    return RBFS_E_RANGE;
+  }
+  if (hipSetDevice(g->device) != hipSuccess) {
+    set_error("rbfs_certify_noalloc: hipSetDevice failed");
+    return RBFS_E_DEVICE;
+  }
+  unsigned char* buf = nullptr;
+  rc = rbfs::static_scratch(g->device, &buf);
+  if (rc) return rc;
+  rbfs::CertScratch cs;
+  rbfs::cert_layout(g, gather, buf, &cs);
+  return rbfs::cert_run(g, root, depth, parent, output_space, stream, cs, result,
+                        "rbfs_certify_noalloc");
 }
