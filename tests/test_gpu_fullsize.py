@@ -29,6 +29,10 @@ def rb():
     return rb
 
 
+def say(msg):
+    print("  [fullsize] " + msg, flush=True)
+
+
 def host(t):
     return t.cpu().numpy()
 
@@ -53,8 +57,10 @@ def test_scale22_bit_exact(rb, kron_blob):
     del off_d, cols_d
     perm_t, _ = G.rcm_reorder()
     perm = host(perm_t)
+    say("scale 22: oracle RCM")
     perm_o, _, _ = oracle.rcm(off, cols)
     assert np.array_equal(perm, perm_o)
+    say("scale 22: oracle BFS of 64 roots")
     ref = pmap(lambda r: oracle.bfs(off, cols, r, perm_o)[:2], roots)
     for r, (d_o, p_o) in zip(roots, ref):
         d, p = G.bfs(r)
@@ -85,7 +91,9 @@ def check_full_size(rb, G, off, cols, roots, blob, n_oracle):
     oracle's depth), every output through the on-device certificate."""
     perm_t, rcm_ms = G.rcm_reorder()
     perm = host(perm_t)
+    say("RCM certificate (oracle)")
     assert oracle.certify_rcm(off, cols, perm) == 0
+    say("plain and learned searches, on-device certificates")
     rb.switch_load(blob)
     learned = rb.make_opts(rb.DIR_LEARNED)
     sample = []
@@ -102,7 +110,9 @@ def check_full_size(rb, G, off, cols, roots, blob, n_oracle):
     for j in range(0, len(roots), step)[:n_oracle]:
         sample.append((roots[j], host(dB[j]), host(pB[j])))
     del dB, pB
+    say("%d oracle certificates" % len(sample))
     assert oracle_certified(off, cols, perm, sample) == [0] * len(sample)
+    say("oracle depth of one root")
     d_o, _, _ = oracle.bfs(off, cols, roots[0])  # depth does not depend on labels
     assert np.array_equal(sample[0][1], d_o)
     return perm
@@ -110,6 +120,7 @@ def check_full_size(rb, G, off, cols, roots, blob, n_oracle):
 
 @pytest.mark.timeout(1200)
 def test_scale26_certified(rb, kron_blob):
+    say("scale 26: generate")
     off_d, cols_d = graphgen.kronecker_csr_device(26, 16, 1026)
     off, cols = host(off_d), host(cols_d)
     roots = graphgen.sample_roots(off, 64, 7)
@@ -143,6 +154,7 @@ def test_scale24_batch_certified(rb):
 def test_chung_lu_50m_certified(rb, kron_blob):
     """The power-law configuration (52.5M vertices): plain, learned with the
     Kronecker-trained network (no retraining) and 64-root batched."""
+    say("chung-lu: generate")
     off_d, cols_d = graphgen.chung_lu_csr_device(50_000_000, 2_500_000, seed=4000)
     off, cols = host(off_d), host(cols_d)
     roots = graphgen.sample_roots(off, 64, 7)
