@@ -88,25 +88,52 @@ def measured_traffic(workload):
         return None
 
 
-def cpu_baseline(off_dev, cols_dev, roots, budget_s=30.0):
-    """The oracle's BFS (single thread, original labels) on a bounded sample
-    of the roots of the same graph."""
+def cpu_baseline(off, cols, off_r, cols_r, perm, roots, gpu_rcm_ms, budget_s=30.0):
+    """The oracle timed on the host's cores, on bounded samples of the same
+    graph, as three single-threaded tasks run side by side (one host thread
+    each): its BFS from the first roots in the original labels (the reported
+    value); the same roots' BFS on the RCM-relabelled CSR the library built
+    (the CPU side of the locality study); and its RCM (Algorithm 3) of the
+    whole graph, next to the GPU's RCM time on the same graph."""
+    from concurrent.futures import ThreadPoolExecutor
     import oracle
-    off = off_dev.cpu().numpy()
-    cols = cols_dev.cpu().numpy()
-    t_all, edges_all, used = 0.0, 0, []
-    for r in roots:
+
+    def bfs_leg(o, c, rs):
+        t_all, edges_all, used = 0.0, 0, 0
+        for r in rs:
+            t0 = time.perf_counter()
+            depth, _, _ = oracle.bfs(o, c, int(r))
+            t_all += time.perf_counter() - t0
+            edges_all += oracle.component_edges(o, depth)
+            used += 1
+            if t_all > budget_s * 0.5:
+                break
+        return t_all, edges_all, used
+
+    def rcm_leg():
         t0 = time.perf_counter()
-        depth, _, _ = oracle.bfs(off, cols, r)
-        t_all += time.perf_counter() - t0
-        edges_all += oracle.component_edges(off, depth)
-        used.append(r)
-        if t_all > budget_s * 0.5:
-            break
-    del off, cols
-    return {"value": edges_all / t_all / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": "oracle BFS (single thread, original labels) from %d of the roots on the "
-                      "same graph, %.1f s" % (len(used), t_all)}
+        oracle.rcm(off, cols)
+        return time.perf_counter() - t0
+
+    with ThreadPoolExecutor(3) as ex:
+        f_orig = ex.submit(bfs_leg, off, cols, roots)
+        f_rl = ex.submit(bfs_leg, off_r, cols_r, [perm[r] for r in roots])
+        f_rcm = ex.submit(rcm_leg)
+        t_o, e_o, n_o = f_orig.result()
+        t_r, e_r, n_r = f_rl.result()
+        t_rcm = f_rcm.result()
+    v_o = e_o / t_o / 1e9
+    v_r = e_r / t_r / 1e9
+    return {"value": v_o, "unit": "GTEPS", "cores": 3, "kind": "oracle",
+            "sample": "oracle BFS (single thread, original labels) from the first %d of the "
+                      "roots on the same graph, %.1f s; run beside the two tasks below, each "
+                      "on its own host thread" % (n_o, t_o),
+            "rcm_labels": {"value": v_r, "unit": "GTEPS", "vs_original_labels": v_r / v_o,
+                           "sample": "oracle BFS (single thread) from the first %d roots on "
+                                     "the RCM-relabelled CSR, %.1f s" % (n_r, t_r)},
+            "rcm": {"oracle_s": t_rcm, "gpu_ms": gpu_rcm_ms,
+                    "gpu_speedup": t_rcm / (gpu_rcm_ms * 1e-3),
+                    "sample": "oracle RCM (Algorithm 3, single thread) of the whole graph"}}
 
 
 def time_roots(G, roots, depth, parent, opts, steps):
@@ -130,98 +157,134 @@ def time_roots(G, roots, depth, parent, opts, steps):
     return per_root, wall
 
 
+def certify_roots(G, roots, depth, parent, opts):
+    """Outside the timed region: each root's search again, its output through
+    the on-device O(nnz) certificate; raises on a failure.  Returns the count."""
+    for r in roots:
+        G.bfs(r, depth, parent, opts=opts)
+        code = G.certify(r, depth, parent)
+        if code != 0:
+            raise RuntimeError("certificate failed for root %d: code %d" % (r, code))
+    return len(roots)
+
+
+def certify_rows(G, roots, dB, pB):
+    """Every row of a batch's root-major outputs through the on-device
+    certificate; raises on a failure.  Returns the count."""
+    for j, r in enumerate(roots):
+        code = G.certify(r, dB[j], pB[j])
+        if code != 0:
+            raise RuntimeError("certificate failed for batch row %d: code %d" % (j, code))
+    return len(roots)
+
+
 def hmean_gteps(m_c, per_root_ms):
     teps = [m / (t * 1e-3) for m, t in zip(m_c, per_root_ms)]
     return len(teps) / sum(1.0 / x for x in teps) / 1e9
 
 
+SWITCH_TRAIN_GRAPHS = (
+    # (family, size, seed, roots): Kronecker scales 18-24 (edge factor 16)
+    # and Chung-Lu graphs of exponents 2.1 and 2.5; none is a graph the
+    # benchmark measures on
+    [("kronecker", s, 2000 + 10 * s + j, 32) for s in (18, 20, 22, 24) for j in range(4)] +
+    [("chung-lu", n, 5000 + 10 * j + int(10 * g), 16, g)
+     for n in (300_000, 1_000_000, 3_000_000) for g in (2.1, 2.5) for j in range(2)])
+
+
 def train_switch(rb, graphgen):
-    """Per-level both-direction timings on Kronecker graphs of scales 18, 20,
-    22, 24 (4 graphs each, 8 roots each), then GPU training; returns the
-    switch blob and a summary."""
+    """Per-level costs of both directions (rbfs_collect_level_samples: the
+    alpha/beta path up to the level, then each direction) on Kronecker graphs
+    of scales 18-24 and on Chung-Lu graphs, then GPU training of one network
+    for every graph family; returns the switch blob and a summary."""
     import numpy as np
     import torch
     rows = []
     t0 = time.perf_counter()
-    for s in (18, 20, 22, 24):
-        for j in range(4):
-            off, cols = graphgen.kronecker_csr_device(s, 16, 2000 + 10 * s + j)
-            roots = graphgen.sample_roots_device(off, 8, 7)
-            G = rb.Graph(off, cols)
-            del off, cols
-            G.rcm_reorder(want_perm=False)
-            rows.append(rb.collect_level_samples(G, roots, reps=3))
-            G.close()
-            torch.cuda.empty_cache()
+    for spec in SWITCH_TRAIN_GRAPHS:
+        if spec[0] == "kronecker":
+            _, s, seed, k = spec
+            off, cols = graphgen.kronecker_csr_device(s, 16, seed)
+        else:
+            _, n, seed, k, g = spec
+            off, cols = graphgen.chung_lu_csr_device(n, n // 20, seed=seed, gamma=g,
+                                                     mean_deg=30.0 if g < 2.3 else 10.0,
+                                                     max_deg=n / 15.0)
+        roots = graphgen.sample_roots_device(off, k, 7)
+        G = rb.Graph(off, cols)
+        del off, cols
+        G.rcm_reorder(want_perm=False)
+        rows.append(rb.collect_level_samples(G, roots, reps=3, cap=16384))
+        G.close()
+        torch.cuda.empty_cache()
     rows = np.vstack(rows)
     t_collect = time.perf_counter() - t0
-    order = graphgen.epoch_orders(rows.shape[0], 300, 1)
+    order = graphgen.epoch_orders(rows.shape[0], 200, 1)
     t0 = time.perf_counter()
     w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
                             batch=64, lr=3e-3)
     t_train = time.perf_counter() - t0
     log("# switch: %d samples (%.1f s), trained %.2f s, loss %.3f -> %.3f"
         % (rows.shape[0], t_collect, t_train, curve[0], curve[-1]))
-    return rb.make_switch_blob(w, rows), {"samples": int(rows.shape[0]),
-                                          "train_graphs": "kronecker scales 18,20,22,24 x 4",
-                                          "collect_s": t_collect, "train_s": t_train,
-                                          "loss_first": float(curve[0]),
-                                          "loss_last": float(curve[-1])}
+    return rb.make_switch_blob(w, rows), {
+        "samples": int(rows.shape[0]),
+        "train_graphs": "kronecker scales 18,20,22,24 x 4 (32 roots each); chung-lu n = 0.3M, "
+                        "1M, 3M x exponent 2.1 (mean degree 30), 2.5 (mean degree 10) x 2 "
+                        "(16 roots each)",
+        "collect_s": t_collect, "train_s": t_train, "epochs": 200,
+        "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
 
 
-def schedule_costs(rb, G, roots, learned_opts, plain_opts):
-    """Measured per-level cost of the alpha/beta and learned schedules and of
-    the best per-level choice (from both-direction level timings)."""
-    tot = {"alpha_beta_us": 0.0, "learned_us": 0.0, "best_us": 0.0}
+def schedule_costs(rb, G, roots, learned_opts, plain_opts, reps=3):
+    """Per root, search-kernel times (median of reps) of three schedules run
+    end to end: alpha/beta, learned, and the per-level best (at each level
+    the direction with the smaller measured cost after the alpha/beta path,
+    from rbfs_collect_level_samples), run with DIR_SCHEDULE."""
+    tot = {"alpha_beta_ms": 0.0, "learned_ms": 0.0, "best_schedule_ms": 0.0}
     agree_l = agree_h = nlev = 0
     for r in roots:
         rows = rb.collect_level_samples(G, [r], reps=3)
-        by = {int(x[10]): x for x in rows}
-        _, _, sl = G.bfs(r, opts=learned_opts, stats=True)
-        _, _, sh = G.bfs(r, opts=plain_opts, stats=True)
-        for lv, x in by.items():
-            best = 0 if x[8] <= x[9] else 1
-            tot["best_us"] += math.exp(min(x[8], x[9]))
-            if lv < len(sl["dir"]):
-                tot["learned_us"] += math.exp(x[8 + sl["dir"][lv]])
-                agree_l += int(sl["dir"][lv] == best)
-            if lv < len(sh["dir"]):
-                tot["alpha_beta_us"] += math.exp(x[8 + sh["dir"][lv]])
-                agree_h += int(sh["dir"][lv] == best)
+        best = {}
+        for x in rows:  # the first row of a level follows the alpha/beta path
+            best.setdefault(int(x[10]), 0 if x[8] <= x[9] else 1)
+        sched = [0] + [best.get(lv, 0) for lv in range(1, max(best, default=0) + 1)]
+
+        def t_of(opts):
+            st = None
+            ts = []
+            for _ in range(reps):
+                _, _, st = G.bfs(r, opts=opts, stats=True)
+                ts.append(st["ms_kernel"])
+            return statistics.median(ts), st
+        t_h, sh = t_of(plain_opts)
+        t_l, sl = t_of(learned_opts)
+        t_b, _ = t_of(rb.make_opts(rb.DIR_SCHEDULE, alpha=plain_opts.alpha,
+                                   beta=plain_opts.beta, schedule=sched))
+        tot["alpha_beta_ms"] += t_h
+        tot["learned_ms"] += t_l
+        tot["best_schedule_ms"] += t_b
+        for lv in range(1, len(sched)):
+            agree_l += int(lv < len(sl["dir"]) and sl["dir"][lv] == sched[lv])
+            agree_h += int(lv < len(sh["dir"]) and sh["dir"][lv] == sched[lv])
             nlev += 1
-    tot["learned_regret"] = tot["learned_us"] / tot["best_us"] - 1.0
-    tot["alpha_beta_regret"] = tot["alpha_beta_us"] / tot["best_us"] - 1.0
-    tot["learned_best_choice_frac"] = agree_l / max(1, nlev)
-    tot["alpha_beta_best_choice_frac"] = agree_h / max(1, nlev)
+    tot["learned_vs_alpha_beta"] = tot["alpha_beta_ms"] / tot["learned_ms"]
+    tot["best_schedule_vs_alpha_beta"] = tot["alpha_beta_ms"] / tot["best_schedule_ms"]
+    tot["learned_agrees_with_best_frac"] = agree_l / max(1, nlev)
+    tot["alpha_beta_agrees_with_best_frac"] = agree_h / max(1, nlev)
     tot["roots"] = len(roots)
     return tot
 
 
 def heavy_tail_switch(rb, graphgen, steps, alpha, beta):
-    """The learned switch on power-law graphs (Chung-Lu, 300000 vertices,
-    exponent 2.1, mean degree 30), where the alpha/beta thresholds stay
-    bottom-up too long at the tail: trained on 4 graphs (8 roots each),
-    measured on a held-out fifth (8 roots).  Loads its own switch blob."""
-    import numpy as np
+    """The learned switch (the network loaded, not retrained) on a power-law
+    graph (Chung-Lu, 300000 vertices, exponent 2.1, mean degree 30) where
+    the alpha/beta thresholds stay bottom-up too long at the tail, against
+    the alpha/beta rule; outputs certified."""
     import torch
-
-    def graph(seed):
-        off, cols = graphgen.chung_lu_csr(300000, 15000, seed=seed, gamma=2.1, mean_deg=30.0,
-                                          max_deg=20000.0)
-        G = rb.Graph(off, cols)
-        G.rcm_reorder(want_perm=False)
-        return off, G
-    rows = []
-    for seed in (1, 2, 3, 4):
-        off, G = graph(seed)
-        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed), reps=3))
-        G.close()
-    rows = np.vstack(rows)
-    order = graphgen.epoch_orders(rows.shape[0], 300, 1)
-    w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
-                            batch=64, lr=3e-3)
-    rb.switch_load(rb.make_switch_blob(w, rows))
-    off, G = graph(9)
+    off, cols = graphgen.chung_lu_csr(300000, 15000, seed=9, gamma=2.1, mean_deg=30.0,
+                                      max_deg=20000.0)
+    G = rb.Graph(off, cols)
+    G.rcm_reorder(want_perm=False)
     roots = graphgen.sample_roots(off, 8, 5)
     depth = torch.empty(G.n, dtype=torch.int32, device="cuda")
     parent = torch.empty(G.n, dtype=torch.int32, device="cuda")
@@ -232,8 +295,10 @@ def heavy_tail_switch(rb, graphgen, steps, alpha, beta):
         G.bfs(r, depth, parent, opts=plain)
     per_l, _ = time_roots(G, roots, depth, parent, learned, max(steps, 5))
     per_h, _ = time_roots(G, roots, depth, parent, plain, max(steps, 5))
-    out = {"graph": "chung-lu n=300000 exponent 2.1 mean degree 30 (held-out seed 9)",
-           "train_samples": int(rows.shape[0]),
+    certified = (certify_roots(G, roots, depth, parent, learned) +
+                 certify_roots(G, roots, depth, parent, plain))
+    out = {"graph": "chung-lu n=300000 exponent 2.1 mean degree 30 (seed 9, not trained on)",
+           "certified_outputs": certified,
            "ms_per_root_learned": sum(per_l) / len(per_l),
            "ms_per_root_alpha_beta": sum(per_h) / len(per_h),
            "speedup": sum(per_h) / sum(per_l),
@@ -303,29 +368,111 @@ def multi_batch(rb, graphgen, steps, cache=None, retune=False):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / steps
+    outs = M.bfs(roots, depth=depth, parent=parent)
+    rows_ok = sum(certify_rows(G, rs, dB, pB) for G, rs, (dB, pB) in zip(Gs, roots, outs))
     log("# multi: 32 graphs x 16 roots: %.2f ms batched vs %.2f ms single-root" % (ms, single_ms))
     return {"value": m_c / (ms * 1e-3) / 1e9, "unit": "GTEPS (aggregate)",
             "ms_per_batch": ms, "single_root_ms_sum": single_ms,
             "single_root_gteps": m_c / (single_ms * 1e-3) / 1e9,
             "vs_single_root": single_ms / ms, "graphs": 32, "roots_per_graph": 16,
-            "scales": "12..20", "tuning": tuned}
+            "scales": "12..20", "certified_rows": rows_ok, "tuning": tuned}
 
 
-ABLATION_GRAPHS = {
-    "kron22": ("kronecker", 22, 1022),
-    "kron24": ("kronecker", 24, 1024),
-    "kron26": ("kronecker", 26, 1026),
-    "chunglu": ("chung-lu", 50_000_000, 4000),
-}
+def chung_lu_leg(rb, graphgen, args, cache, blob):
+    """The power-law configuration: Chung-Lu, 50 M vertices with exponent 2.1,
+    mean degree 30 and largest expected degree 2 M, plus 2.5 M isolated
+    vertices (dropped to the end by RCM); 64 roots.  Plain heuristic search,
+    the learned switch with the network trained on Kronecker graphs (no
+    retraining), and the 64-root batch, each timed as on the Kronecker graph
+    and every output certified on the device."""
+    import torch
+    t0 = time.perf_counter()
+    off, cols = graphgen.chung_lu_csr_device(50_000_000, 2_500_000, seed=4000)
+    roots = graphgen.sample_roots_device(off, args.roots, args.root_seed)
+    G = rb.Graph(off, cols)
+    del off, cols
+    torch.cuda.empty_cache()
+    t_gen = time.perf_counter() - t0
+    _, rcm_ms = G.rcm_reorder(want_perm=False)
+    info = G.info()
+    n = info["n"]
+    if cache is not None:
+        # no Chung-Lu entry: the Kronecker setting of the same size bucket
+        for kind in (rb.TUNE_SINGLE, rb.TUNE_BATCH):
+            t = cache.get(rb.tuning_key(rb.device_info()["arch"], "kronecker", n, kind))
+            if t is not None:
+                G.set_tuning(t, kind)
+    depth = torch.empty(n, dtype=torch.int32, device="cuda")
+    parent = torch.empty(n, dtype=torch.int32, device="cuda")
+    plain = rb.make_opts(alpha=args.alpha, beta=args.beta)
+    stats = [G.bfs(r, depth, parent, opts=plain, stats=True)[2] for r in roots]
+    m_c = [st["component_edges"] for st in stats]
+    for r in roots:
+        G.bfs(r, depth, parent, opts=plain)
+    per_p, _ = time_roots(G, roots, depth, parent, plain, args.steps)
+    G.check()
+    gp = hmean_gteps(m_c, per_p)
+    out = {"graph": "chung-lu n=%d (50M power-law, exponent 2.1, mean degree 30, max expected "
+                    "degree 2M, + 2.5M isolated) seed 4000" % n,
+           "nnz": info["nnz"], "n_plus": info["n_plus"], "gen_s": t_gen, "rcm_ms": rcm_ms,
+           "roots": len(roots),
+           "giant_component_root_fraction": sum(1 for m in m_c if m == max(m_c)) / len(m_c),
+           "plain": {"value": gp, "unit": "GTEPS",
+                     "certified_roots": certify_roots(G, roots, depth, parent, plain)}}
+    log("# chung-lu: rcm %.1f ms, plain %.1f GTEPS" % (rcm_ms, gp))
+    if blob is not None:
+        rb.switch_load(blob)
+        learned = rb.make_opts(rb.DIR_LEARNED, alpha=args.alpha, beta=args.beta)
+        for r in roots[:4]:
+            G.bfs(r, depth, parent, opts=learned)
+        per_l, _ = time_roots(G, roots, depth, parent, learned, args.steps)
+        gl = hmean_gteps(m_c, per_l)
+        out["learned"] = {"value": gl, "unit": "GTEPS", "vs_plain": gl / gp,
+                          "network": "trained on Kronecker scales 18-24, not retrained",
+                          "certified_roots": certify_roots(G, roots, depth, parent, learned)}
+        log("# chung-lu: learned %.1f GTEPS (%.3fx plain)" % (gl, gl / gp))
+    if not args.no_batch:
+        del depth, parent
+        dB = torch.empty((len(roots), n), dtype=torch.int32, device="cuda")
+        pB = torch.empty((len(roots), n), dtype=torch.int32, device="cuda")
+        G.bfs_batch(roots, dB, pB)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.steps):
+            G.bfs_batch(roots, dB, pB)
+        e1.record()
+        torch.cuda.synchronize()
+        ms_b = e0.elapsed_time(e1) / args.steps
+        out["batched"] = {"value": sum(m_c) / (ms_b * 1e-3) / 1e9,
+                          "unit": "GTEPS (aggregate, 64 roots bit-parallel, one launch)",
+                          "ms_per_batch": ms_b, "vs_plain": sum(per_p) / ms_b,
+                          "certified_rows": certify_rows(G, roots, dB, pB)}
+        log("# chung-lu: batched %.2f ms (%.1f GTEPS aggregate)" % (ms_b, out["batched"]["value"]))
+        del dB, pB
+    G.close()
+    torch.cuda.empty_cache()
+    return out
+
+
+ABLATION_GRAPHS = dict(
+    [("kron%d" % s, ("kronecker", s, 1000 + s)) for s in range(21, 27)] +
+    [("chunglu", ("chung-lu", 50_000_000, 4000))])
 
 
 def ablation(rb, graphgen, args):
-    """Locality study: the same searches on the graph as generated (random
-    labels), after RCM, and after partial RCM (variant "p<ratio>", e.g. p0.25:
-    the first ceil(ratio * n+) vertices of the Cuthill-McKee sequence
-    reordered, p0 only moving isolated vertices to the end), on Kronecker
-    scales 22-26 and the 52.5 M-vertex Chung-Lu graph.  One JSON line per
-    (graph, variant)."""
+    """Ablation and locality study (section 4.3 ablation, section 4.4): the
+    same searches on the graph as generated (random labels), after RCM, and
+    after partial RCM (variant "p<ratio>", e.g. p0.25: the first
+    ceil(ratio * n+) vertices of the Cuthill-McKee sequence reordered, p0
+    only moving isolated vertices to the end), each with the load-balanced
+    kernels or, with the suffix "-nolb", without load balancing (whole rows
+    per thread top-down, equal vertex ranges without stealing bottom-up), on
+    Kronecker scales 21-26 and the 52.5 M-vertex Chung-Lu graph.  One JSON
+    line per (graph, variant), with the vertices each bottom-up level sweeps
+    (the unvisited part of its sweep range: the graph before RCM, the root's
+    component after it), the analogue of the shrinking partitions of
+    section 3.4."""
     import torch
     names = args.ablation_graphs.split(",")
     variants = args.ablation_variants.split(",")
@@ -344,18 +491,20 @@ def ablation(rb, graphgen, args):
         for variant in variants:
             G = rb.Graph(off, cols)
             rcm_ms = None
-            if variant == "rcm":
+            nolb = variant.endswith("-nolb")
+            base = variant[:-len("-nolb")] if nolb else variant
+            if base == "rcm":
                 _, rcm_ms = G.rcm_reorder(want_perm=False)
-            elif variant.startswith("p"):
-                _, rcm_ms = G.rcm_reorder(want_perm=False, partial=float(variant[1:]))
-            elif variant != "original":
+            elif base.startswith("p"):
+                _, rcm_ms = G.rcm_reorder(want_perm=False, partial=float(base[1:]))
+            elif base != "original":
                 raise ValueError("unknown variant %r" % variant)
-            reordered = variant != "original"
+            reordered = base != "original"
             t = cache.get(rb.tuning_key(arch, "kronecker", n, rb.TUNE_SINGLE))
             if t is not None:
                 G.set_tuning(t)
-            plain = rb.make_opts(alpha=args.alpha, beta=args.beta)
-            timed = rb.make_opts(alpha=args.alpha, beta=args.beta, timing=True)
+            plain = rb.make_opts(alpha=args.alpha, beta=args.beta, no_balance=nolb)
+            timed = rb.make_opts(alpha=args.alpha, beta=args.beta, timing=True, no_balance=nolb)
             stats = [G.bfs(r, depth, parent, opts=plain, stats=True)[2] for r in roots]
             G.timings()
             per_root_ms, _ = time_roots(G, roots, depth, parent, timed, args.steps)
@@ -365,7 +514,8 @@ def ablation(rb, graphgen, args):
             # load balance: work per workgroup in the heaviest top-down and
             # bottom-up levels of the first root
             _, _, st0 = G.bfs(roots[0], depth, parent,
-                              opts=rb.make_opts(alpha=args.alpha, beta=args.beta, wg_work=True),
+                              opts=rb.make_opts(alpha=args.alpha, beta=args.beta, wg_work=True,
+                                                no_balance=nolb),
                               stats=True)
             W = G.wg_work()
             balance = {}
@@ -382,6 +532,17 @@ def ablation(rb, graphgen, args):
                                   "cov": float(row.std() / mean) if mean else None}
             m_c = [st["component_edges"] for st in stats]
             n_sweep = info["n_plus"] if reordered else n
+            # vertices each bottom-up level of the first root sweeps: the
+            # unvisited part of the whole graph before RCM (every word is
+            # swept), of the root's component after it (the sweep covers the
+            # component; later levels walk the list the last one left)
+            scope = st0["reached"] if (reordered and base == "rcm") else n_sweep
+            seen, bu_swept = 0, []
+            for d in range(st0["levels"]):
+                if st0["dir"][d] == 1:
+                    bu_swept.append({"level": d, "vertices": scope - seen,
+                                     "entries": st0["edges"][d]})
+                seen += st0["nf"][d]
             alg = sum(bfs_alg_bytes(st, n_sweep, original_ids=reordered)
                       for st in stats) / len(stats)
             k_ms = sum(kernel_ms) / len(kernel_ms)
@@ -397,6 +558,7 @@ def ablation(rb, graphgen, args):
                 / len(stats),
                 "alg_bytes_avg": alg, "achieved_gbs": alg / (k_ms * 1e-3) / 1e9,
                 "rcm_ms": rcm_ms, "rcm_keep": info["rcm_keep"], "wg_balance": balance,
+                "bu_swept_root0": bu_swept, "load_balance": not nolb,
                 "tuning": G.get_tuning()}), flush=True)
             G.close()
             del G
@@ -454,6 +616,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-multi", action="store_true")
+    ap.add_argument("--no-chunglu", action="store_true",
+                    help="skip the 52.5M-vertex Chung-Lu leg (plain, learned, batched)")
     ap.add_argument("--no-tune", action="store_true",
                     help="time the built-in launch parameters instead of autotuned ones")
     ap.add_argument("--retune", action="store_true",
@@ -464,8 +628,11 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=30.0)
     ap.add_argument("--ablation", action="store_true",
                     help="run the locality study (original labels against RCM) instead")
-    ap.add_argument("--ablation-graphs", default="kron22,kron24,kron26,chunglu")
-    ap.add_argument("--ablation-variants", default="original,rcm")
+    ap.add_argument("--ablation-graphs",
+                    default="kron21,kron22,kron23,kron24,kron25,kron26,chunglu")
+    ap.add_argument("--ablation-variants", default="original-nolb,p0-nolb,rcm-nolb,rcm",
+                    help="original, p<ratio> (partial RCM), rcm; suffix -nolb: without "
+                         "load balancing")
     ap.add_argument("--ablation-roots", type=int, default=16)
     ap.add_argument("--rcm-only", action="store_true",
                     help="generate the graph, time its RCM relabelling, print one JSON line")
@@ -518,7 +685,7 @@ def main():
     if not keep_host:
         del off, cols
         torch.cuda.empty_cache()
-    _, rcm_ms = G.rcm_reorder(want_perm=False)
+    perm_t, rcm_ms = G.rcm_reorder(want_perm=keep_host)
     info = G.info()
     log("# rcm %.1f ms, n_plus=%d" % (rcm_ms, info["n_plus"]))
 
@@ -634,16 +801,16 @@ def main():
         e1.record()
         torch.cuda.synchronize()
         ms_b = e0.elapsed_time(e1) / args.steps
-        d_last, p_last = G.bfs(roots[-1], depth, parent)
-        ok = bool(torch.equal(dB[nroot - 1], d_last) and torch.equal(pB[nroot - 1], p_last))
+        rows_ok = certify_rows(G, roots, dB, pB)
         out["batched"] = {"value": sum(m_c) / (ms_b * 1e-3) / 1e9,
                           "unit": "GTEPS (aggregate, 64 roots bit-parallel, one launch)",
                           "ms_per_batch": ms_b, "vs_plain": sum(per_root_ms) / ms_b,
-                          "last_row_equals_single_root": ok}
+                          "certified_rows": rows_ok}
         log("# batched: %.2f ms for 64 roots (%.1f GTEPS aggregate)"
             % (ms_b, out["batched"]["value"]))
         del dB, pB
         torch.cuda.empty_cache()
+    blob = None
     if not args.no_learned:
         blob, info_sw = train_switch(rb, graphgen)
         rb.switch_load(blob)
@@ -653,6 +820,7 @@ def main():
         per_root_l, _ = time_roots(G, roots, depth, parent, learned, args.steps)
         gl = hmean_gteps(m_c, per_root_l)
         out["learned"] = {"value": gl, "unit": "GTEPS", "vs_plain": gl / hmean,
+                          "certified_roots": certify_roots(G, roots, depth, parent, learned),
                           "training": info_sw,
                           "schedule_costs_8_roots": schedule_costs(rb, G, roots[:8], learned,
                                                                    plain)}
@@ -661,6 +829,8 @@ def main():
                                                          args.beta)
     if not args.no_multi:
         out["multi"] = multi_batch(rb, graphgen, args.steps, cache, args.retune)
+    if not args.no_chunglu:
+        out["chung_lu"] = chung_lu_leg(rb, graphgen, args, cache, blob)
     if tuning:
         out["tuning"] = tuning
     if args.copy_calibration_gib > 0:
@@ -673,7 +843,12 @@ def main():
         out["copy_calibration_bytes"] = nb
         del a, b
     if keep_host:
-        out["cpu_baseline"] = cpu_baseline(off, cols, roots, args.cpu_budget)
+        log("# cpu baseline (oracle)")
+        off_r, cols_r = G.csr()
+        out["cpu_baseline"] = cpu_baseline(off.cpu().numpy(), cols.cpu().numpy(),
+                                           off_r.cpu().numpy(), cols_r.cpu().numpy(),
+                                           perm_t.cpu().numpy(), roots, rcm_ms, args.cpu_budget)
+        del off_r, cols_r
         model, ncpu = host_cpu()
         out["cpu_baseline"]["host_cpu"] = model
         out["cpu_baseline"]["host_threads_available"] = ncpu

@@ -59,6 +59,10 @@ def lib():
         L.gg_dev_kron_csr.restype = c.c_int64
         L.gg_dev_kron_csr.argtypes = [c.c_int, c.c_int64, c.c_uint64, c.c_double, c.c_double,
                                       c.c_double, c.c_void_p, c.c_void_p, c.c_int64, c.c_void_p]
+        L.gg_dev_kron_csr_ranges.restype = c.c_int64
+        L.gg_dev_kron_csr_ranges.argtypes = [c.c_int, c.c_int64, c.c_uint64, c.c_double,
+                                             c.c_double, c.c_double, c.c_void_p, c.c_void_p,
+                                             c.c_int64, c.c_int64, c.c_void_p, c.c_void_p]
         L.gg_dev_kron_count_reached.restype = c.c_int64
         L.gg_dev_kron_count_reached.argtypes = [c.c_int, c.c_int64, c.c_uint64, c.c_double,
                                                 c.c_double, c.c_double, c.c_void_p, c.c_void_p]
@@ -172,17 +176,26 @@ def _torch_stream(device):
     return torch.cuda.current_stream(device).cuda_stream
 
 
-def kronecker_csr_device(scale, edgefactor=16, seed=1, abc=KRON_ABC, device="cuda"):
+def kronecker_csr_device(scale, edgefactor=16, seed=1, abc=KRON_ABC, device="cuda",
+                         max_pass_keys=0, info=None):
+    """kronecker_csr on the GPU, built in passes over source-label ranges of
+    at most max_pass_keys directed keys each (0: as many as a quarter of the
+    free device memory holds); info (a dict, optional) receives the number
+    of passes."""
     import torch
     n = 1 << scale
     m = edgefactor * n
     off = torch.empty(n + 1, dtype=torch.int64, device=device)
     cols = torch.empty(max(1, 2 * m), dtype=torch.int32, device=device)
-    nnz = lib().gg_dev_kron_csr(scale, edgefactor, seed, abc[0], abc[1], abc[2],
-                                off.data_ptr(), cols.data_ptr(), cols.numel(),
-                                _torch_stream(off.device))
+    passes = ctypes.c_int64(0)
+    nnz = lib().gg_dev_kron_csr_ranges(scale, edgefactor, seed, abc[0], abc[1], abc[2],
+                                       off.data_ptr(), cols.data_ptr(), cols.numel(),
+                                       int(max_pass_keys), ctypes.byref(passes),
+                                       _torch_stream(off.device))
     if nnz < 0:
-        raise RuntimeError("gg_dev_kron_csr: " + lib().gg_dev_last_error().decode())
+        raise RuntimeError("gg_dev_kron_csr_ranges: " + lib().gg_dev_last_error().decode())
+    if info is not None:
+        info["passes"] = passes.value
     return off, cols[:nnz]
 
 

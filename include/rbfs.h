@@ -105,6 +105,13 @@ typedef struct rbfs_opts {
 #define RBFS_OPT_WG_WORK 2 /* single-root searches: record the adjacency
                               entries each workgroup processed per level;
                               read them with rbfs_graph_wg_work */
+#define RBFS_OPT_NO_BALANCE 8 /* single-root searches, for the load-balance
+                                  ablation (sections 3.3-3.4): top-down gives
+                                  each frontier vertex's whole row to one
+                                  thread (Algorithm 1's split), bottom-up
+                                  sweeps equal vertex ranges, one set per
+                                  workgroup, with no work stealing.  Same
+                                  results; slower on skewed graphs. */
 #define RBFS_OPT_ZERO_WAIT 4 /* single-root searches, for tests of the error
                                 path: the search's grid barrier waits for no
                                 time, so the search gives up at its first
@@ -214,6 +221,15 @@ int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
  * multi-graph handle built over the graph in its original labels exists. */
 int rbfs_rcm_reorder(rbfs_graph_t* g, int32_t* perm_out, void* stream, float* ms_out);
 
+/* How rbfs_rcm_reorder builds the relabelled CSR (the result is the same
+ * either way).  0 (default): graphs of up to 2^32 adjacency entries in one
+ * sort of all their (column, new row) pairs (16 bytes per entry of
+ * temporary memory), larger ones in batches of about 2^30 entries of new
+ * rows (the rows' entries renamed and sorted row by row), which keeps the
+ * relabel within memory for the largest graphs one GPU holds.  max_entries
+ * > 0: always in batches of about that many entries. */
+int rbfs_graph_set_rcm_batch(rbfs_graph_t* g, int64_t max_entries);
+
 /* Partial RCM (section 4.6): as rbfs_rcm_reorder, but only the first `keep`
  * vertices of Algorithm 3's Cuthill-McKee sequence are reordered.  They take
  * labels [0, keep) in reverse sequence order; the other non-isolated
@@ -231,6 +247,14 @@ int rbfs_rcm_reorder_partial(rbfs_graph_t* g, int64_t keep, int32_t* perm_out, v
 /* Inverse of the current relabelling: iperm_out[new] = old (device int32[n]).
  * Identity before rbfs_rcm_reorder. */
 int rbfs_graph_iperm(const rbfs_graph_t* g, int32_t* iperm_out, void* stream);
+
+/* The graph's current CSR (section 3.1, Eq. 2): the input graph, or after
+ * rbfs_rcm_reorder the relabelled one of section 3.2 (vertex k = the vertex
+ * with new label k, neighbours as new labels, rows ascending).
+ * row_offsets_out: device int64[n+1]; cols_out: device int32[nnz] (may be
+ * NULL when nnz = 0).  Synchronises `stream`. */
+int rbfs_graph_csr(const rbfs_graph_t* g, int64_t* row_offsets_out, int32_t* cols_out,
+                   void* stream);
 
 /* Breadth-first search from `root` (an original ID in [0, n)).
  * depth, parent: device int32[n], fully overwritten: depth = hop distance or
@@ -434,12 +458,17 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
  * searches with RBFS_DIR_LEARNED use it.  Process-wide. */
 int rbfs_switch_load(const float* blob, int32_t n);
 
-/* Training samples: for each root, searches with every level top-down and
- * with every level after the first bottom-up, `reps` times each (the level
- * state does not depend on the directions taken, so level d of both runs
- * starts from the same frontier); the median device time of level d in each
- * is that direction's cost.  Rows of 11 floats: features[8], ln(us TD),
- * ln(us BU), level.  Writes at most `cap` rows; *count receives the number. */
+/* Training samples: for each root and each level d >= 1, searches that
+ * follow the alpha/beta rule's directions up to level d - 1 and then take
+ * level d top-down, or bottom-up, `reps` times each; the median device time
+ * of level d is that direction's cost, including whatever the switch costs
+ * there (a first bottom-up level sweeps the component's words, a later one
+ * walks the vertex list the last bottom-up level left).  From level 2 on the
+ * same is done once more with level d - 1 taken the other way, which samples
+ * the other value of the current-direction feature (the frontiers, hence the
+ * other features, do not depend on the directions).  Rows of 11 floats:
+ * features[8], ln(us TD), ln(us BU), level.  Writes at most `cap` rows;
+ * *count receives the number. */
 int rbfs_collect_level_samples(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
                                int32_t alpha, int32_t beta, float* out, int32_t cap,
                                int32_t* count, void* stream);

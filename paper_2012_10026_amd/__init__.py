@@ -119,7 +119,9 @@ SIGNATURES = {
     "rbfs_graph_wg_work": (ctypes.c_int, [_P, _P, _I64, _P, _P, _P]),
     "rbfs_rcm_reorder": (ctypes.c_int, [_P, _P, _P, _P]),
     "rbfs_rcm_reorder_partial": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
+    "rbfs_graph_set_rcm_batch": (ctypes.c_int, [_P, _I64]),
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
+    "rbfs_graph_csr": (ctypes.c_int, [_P, _P, _P, _P]),
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_certify": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
@@ -247,6 +249,7 @@ def device_info():
 OPT_TIMING = 1
 OPT_WG_WORK = 2
 OPT_ZERO_WAIT = 4
+OPT_NO_BALANCE = 8
 
 
 def default_tuning(kind=TUNE_SINGLE):
@@ -265,10 +268,11 @@ def _records(recs, cnt):
 
 
 def make_opts(direction=DIR_HEURISTIC, alpha=14, beta=24, output_space=OUT_ORIGINAL,
-              schedule=None, tune_profile=0, timing=False, wg_work=False, zero_wait=False):
+              schedule=None, tune_profile=0, timing=False, wg_work=False, zero_wait=False,
+              no_balance=False):
     o = Opts()
     o.flags = ((OPT_TIMING if timing else 0) | (OPT_WG_WORK if wg_work else 0) |
-               (OPT_ZERO_WAIT if zero_wait else 0))
+               (OPT_ZERO_WAIT if zero_wait else 0) | (OPT_NO_BALANCE if no_balance else 0))
     o.direction = direction
     o.alpha = alpha
     o.beta = beta
@@ -362,11 +366,26 @@ class Graph:
                                                   _stream_ptr(self.device), ctypes.byref(ms)))
         return perm, ms.value
 
+    def set_rcm_batch(self, max_entries):
+        """Relabel in batches of about max_entries adjacency entries (0:
+        automatic, by graph size); the permutation and CSR are the same."""
+        _check(lib().rbfs_graph_set_rcm_batch(self._h, int(max_entries)))
+
     def iperm(self):
         import torch
         out = torch.empty(self.n, dtype=torch.int32, device=self.device)
         _check(lib().rbfs_graph_iperm(self._h, _dptr(out), _stream_ptr(self.device)))
         return out
+
+    def csr(self):
+        """The current (after RCM: relabelled) CSR as device tensors
+        (int64 offsets, int32 columns)."""
+        import torch
+        off = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        cols = torch.empty(max(1, self.nnz), dtype=torch.int32, device=self.device)
+        _check(lib().rbfs_graph_csr(self._h, _dptr(off), _dptr(cols),
+                                    _stream_ptr(self.device)))
+        return off, cols[:self.nnz]
 
     def bfs(self, root, depth=None, parent=None, opts=None, stats=False):
         """Returns (depth, parent[, stats dict]) as int32 device tensors."""

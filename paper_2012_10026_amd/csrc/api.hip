@@ -406,6 +406,15 @@ fail:
   return rc;
 }
 
+int rbfs_graph_set_rcm_batch(rbfs_graph_t* h, int64_t max_entries) {
+  if (!h || max_entries < 0) {
+    set_error("rbfs_graph_set_rcm_batch: NULL graph or negative size");
+    return RBFS_E_INVAL;
+  }
+  h->g.rcm_batch = max_entries;
+  return RBFS_OK;
+}
+
 int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream, float* ms_out) {
   return rcm_reorder_call(h, -1, perm_out, stream, ms_out);
 }
@@ -430,6 +439,26 @@ int rbfs_graph_iperm(const rbfs_graph_t* h, int32_t* iperm_out, void* stream_) {
   }
   API_CHECK(hipMemcpyAsync(iperm_out, g->iperm, sizeof(int32_t) * (size_t)g->n,
                            hipMemcpyDeviceToDevice, stream));
+  API_CHECK(hipStreamSynchronize(stream));
+  return RBFS_OK;
+fail:
+  return rc;
+}
+
+int rbfs_graph_csr(const rbfs_graph_t* h, int64_t* row_offsets_out, int32_t* cols_out,
+                   void* stream_) {
+  if (!h || !row_offsets_out || (!cols_out && h->g.nnz > 0)) {
+    set_error("rbfs_graph_csr: NULL argument");
+    return RBFS_E_INVAL;
+  }
+  const Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  int rc = 0;
+  API_CHECK(hipMemcpyAsync(row_offsets_out, g->off, sizeof(int64_t) * (size_t)(g->n + 1),
+                           hipMemcpyDeviceToDevice, stream));
+  if (g->nnz > 0)
+    API_CHECK(hipMemcpyAsync(cols_out, g->cols, sizeof(int32_t) * (size_t)g->nnz,
+                             hipMemcpyDeviceToDevice, stream));
   API_CHECK(hipStreamSynchronize(stream));
   return RBFS_OK;
 fail:
@@ -751,39 +780,49 @@ int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k,
   int32_t *dd = nullptr, *dp = nullptr;
   int32_t cnt = 0;
   rbfs_stats_t sh, st;
-  std::vector<std::vector<float>> ttd, tbu;
+  std::vector<float> t;
+  int8_t sched[RBFS_STATS_MAX_LEVELS + 1];
   API_CHECK(rbfs::dev_malloc(&dd, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
   API_CHECK(rbfs::dev_malloc(&dp, sizeof(int32_t) * (size_t)(g->n > 0 ? g->n : 1)));
   for (int32_t j = 0; j < k && cnt < cap; ++j) {
     rc = rbfs::bfs_impl(g, roots[j], dd, dp, RBFS_DIR_HEURISTIC, alpha, beta, nullptr, 0,
                         RBFS_OUT_INTERNAL, 0, 0, stream, &sh);
     if (rc) goto fail;
-    const int D = std::min(sh.levels, RBFS_STATS_MAX_LEVELS);
-    ttd.assign(D, std::vector<float>());
-    tbu.assign(D, std::vector<float>());
-    for (int32_t r = 0; r < reps; ++r) {
-      for (int mode : {RBFS_DIR_TD_ONLY, RBFS_DIR_BU_ONLY}) {
-        rc = rbfs::bfs_impl(g, roots[j], dd, dp, mode, alpha, beta, nullptr, 0,
-                            RBFS_OUT_INTERNAL, 0, 0, stream, &st);
-        if (rc) goto fail;
-        for (int d = 0; d < D && d < st.levels; ++d)
-          (mode == RBFS_DIR_TD_ONLY ? ttd : tbu)[d].push_back(st.level_us[d]);
+    {
+      const int D = std::min(sh.levels, RBFS_STATS_MAX_LEVELS);
+      long long reached = 1;
+      for (int d = 1; d < D && cnt < cap; ++d) {
+        reached += sh.nf[d];
+        // the alpha/beta path up to level d - 1, and (from level 2 on) the same
+        // path with level d - 1 flipped, so that both values of the current-
+        // direction feature are sampled
+        for (int variant = 0; variant < (d >= 2 ? 2 : 1) && cnt < cap; ++variant) {
+          for (int i = 0; i < d; ++i) sched[i] = sh.dir[i];
+          if (variant) sched[d - 1] = (int8_t)(1 - sched[d - 1]);
+          float lab[2];
+          for (int x = 0; x < 2; ++x) {
+            sched[d] = (int8_t)x;
+            t.clear();
+            for (int32_t r = 0; r < reps; ++r) {
+              rc = rbfs::bfs_impl(g, roots[j], dd, dp, RBFS_DIR_SCHEDULE, alpha, beta, sched,
+                                  d + 1, RBFS_OUT_INTERNAL, 0, 0, stream, &st);
+              if (rc) goto fail;
+              if (st.levels > d) t.push_back(st.level_us[d]);
+            }
+            if (t.empty()) break;
+            std::sort(t.begin(), t.end());
+            lab[x] = t[t.size() / 2];
+          }
+          if (t.empty()) continue;
+          float* row = out + (int64_t)cnt * 11;
+          rbfs::switch_features(row, sh.nf[d], sh.mf[d], sh.mu[d], g->n_sweep - reached,
+                                sh.nf[d - 1], d, sched[d - 1], g->n_sweep, g->nnz);
+          row[8] = logf(std::max(lab[0], 0.1f));
+          row[9] = logf(std::max(lab[1], 0.1f));
+          row[10] = (float)d;
+          ++cnt;
+        }
       }
-    }
-    long long reached = 1;
-    for (int d = 1; d < D && cnt < cap; ++d) {
-      reached += sh.nf[d];
-      if (ttd[d].empty() || tbu[d].empty()) continue;
-      std::sort(ttd[d].begin(), ttd[d].end());
-      std::sort(tbu[d].begin(), tbu[d].end());
-      const float a = ttd[d][ttd[d].size() / 2], b = tbu[d][tbu[d].size() / 2];
-      float* row = out + (int64_t)cnt * 11;
-      rbfs::switch_features(row, sh.nf[d], sh.mf[d], sh.mu[d], g->n_sweep - reached,
-                            sh.nf[d - 1], d, sh.dir[d - 1], g->n_sweep, g->nnz);
-      row[8] = logf(std::max(a, 0.1f));
-      row[9] = logf(std::max(b, 0.1f));
-      row[10] = (float)d;
-      ++cnt;
     }
   }
   *count = cnt;

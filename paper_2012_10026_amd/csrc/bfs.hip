@@ -119,6 +119,11 @@ struct BfsParams {
   unsigned long long* wctr;  // BU range counters: 3 slots of wstride, 16 per workgroup
   int64_t wstride;
   int32_t* vl[2];            // vertex lists (kNQ sub-lists of qstride entries)
+  const int32_t* top;        // largest-label neighbour of each swept vertex
+  // the ablation without load balancing (RBFS_OPT_NO_BALANCE): top-down one
+  // frontier vertex per thread, bottom-up equal vertex ranges per workgroup
+  // with no stealing
+  int32_t no_lb;
   int32_t root_orig;
   int32_t init;
   int32_t mode;
@@ -302,14 +307,15 @@ __device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long l
 // every step; fin marks the lanes that finished a candidate in it.
 template <class Cand, class Done>
 __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const int32_t* cols,
-                                            const uint64_t* bits, const uint32_t* filt,
-                                            bool use_filt, int fs,
+                                            const int32_t* top, const uint64_t* bits,
+                                            const uint32_t* filt, bool use_filt, int fs,
                                             int lane_row, int64_t& examined, Cand&& cand,
                                             Done&& done) {
   int next = 0;  // next candidate to hand out (same in every lane)
   bool busy = false, queued = false;
   int64_t v = 0, b = 0, j = 0, e = 0;  // current candidate
   int64_t vq = 0, bq = 0, eq = 0;      // queued candidate, bounds loaded
+  int32_t t = 0, tq = 0;               // largest-label neighbours (with top)
   for (;;) {
     // take over the queued candidate
     bool fresh = false;
@@ -317,6 +323,7 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
       v = vq;
       b = bq;
       e = eq;
+      t = tq;
       j = e;
       busy = true;
       queued = false;
@@ -332,6 +339,7 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
         vq = c;
         bq = off[c];
         eq = off[c + 1];
+        if (top) tq = top[c];
         queued = true;
       }
     }
@@ -342,6 +350,18 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     bool fin = hub;
     if (busy && !hub && j <= b) {
       fin = true;  // empty row
+    } else if (busy && !hub && fresh && top) {
+      // the row's highest entry from the dense copy: one probe and no
+      // column load; against a dense frontier most rows end here
+      examined += 1;
+      if ((!use_filt || lds_bit(filt, (uint32_t)t >> fs)) && test_bit(bits, (uint32_t)t)) {
+        found = true;
+        par = t;
+        fin = true;
+      } else {
+        j = e - 1;
+        fin = j <= b;
+      }
     } else if (busy && !hub) {
       // entries below j, downwards, in aligned groups of 4: the group holding
       // entry j - 1 (w[0..3]) and, after a row's first step, the one below
@@ -399,6 +419,20 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     if (fin) busy = false;
     if (next >= total && ballot(busy || queued) == 0ull) break;
   }
+}
+
+// Sum of v over the workgroup, returned in thread 0 (0 elsewhere).  Every
+// thread must call.
+__device__ __forceinline__ int64_t block_sum(int64_t v) {
+  __shared__ int64_t s_part[kMaxWaves];
+  const int64_t w = wave_sum(v);
+  if (lane_id() == 0) s_part[wave_id()] = w;
+  __syncthreads();
+  int64_t t = 0;
+  if (threadIdx.x == 0)
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += s_part[i];
+  __syncthreads();
+  return t;
 }
 
 __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf, long long mu,
@@ -530,7 +564,52 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       ctl->edges[z3][0] = 0ull;
     }
     if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
-    if (dir == 0) {
+    if (dir == 0 && P.no_lb) {
+      // ---- top-down without load balancing (Alg 1): frontier vertex j of
+      // the sub-queues taken one after the other goes to thread j mod (grid
+      // threads), which walks its whole row, one entry per step in lock-step
+      // with its wave
+      fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
+      int64_t j = gtid, e = 0, eend = 0, mine = 0;
+      int32_t u = 0;
+      bool have = false;
+      for (;;) {
+        if (!have && j < nf) {
+          int q = 0;
+          int64_t i = j;
+          while (i >= s_qcnt[q]) i -= s_qcnt[q++];
+          u = P.qv[qc][q * P.qstride + i];
+          e = P.off[u];
+          eend = P.off[u + 1];
+          have = true;
+          j += gsz;
+        }
+        const bool act = have && e < eend;
+        const int32_t w = act ? P.cols[e] : 0;
+        bool claim = false;
+        int64_t dw = 0;
+        if (act && !(((P.vis[w >> 6] | fcur[w >> 6]) >> (w & 63)) & 1ull)) {
+          const uint64_t prop = pack_dp(L + 1, u);
+          if (P.dp[w] > prop)
+            claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
+                    kUnreached;
+          if (claim) {
+            dw = P.off[w + 1] - P.off[w];
+            atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+          }
+        }
+        stage(s_st, claim, w, dw, P, qn, qpack);
+        if (act) {
+          ++e;
+          ++mine;
+        }
+        if (have && e >= eend) have = false;
+        if (ballot(have || j < nf) == 0ull) break;
+      }
+      flush_stage(s_st, P, qn, qpack);
+      if (WGW) wg_td = block_sum(mine);
+      if (gtid == 0) examined = mf;
+    } else if (dir == 0) {
       // ---- top-down
       fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
       // the chunks of the sub-queues, one after the other
@@ -630,7 +709,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       const int wv = wave_id();
       RangeCursor cur;
       for (;;) {
-        const int64_t part = next_range(P.wctr + c3 * P.wstride, nranges, cur);
+        const int64_t part = next_range(P.wctr + c3 * P.wstride, nranges, cur, !P.no_lb);
         if (part < 0) break;
         if (listed) {
           // range `part` of the sub-lists, one after the other
@@ -644,7 +723,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           const int64_t i0 = q * P.qstride + lr * kListRange;
           const int total = (int)std::min<int64_t>(kListRange, s_lcnt[q] - lr * kListRange);
           refill_scan(
-              total, P.off, P.cols, fcur, s_step.filt, use_filt, fs, P.lane_row, examined,
+              total, P.off, P.cols, use_filt ? nullptr : P.top, fcur, s_step.filt, use_filt, fs,
+              P.lane_row, examined,
               [&](int t) -> int64_t {
                 if (t < 0) return -1;
                 const int32_t u = vl_in[i0 + t];
@@ -660,8 +740,11 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
               });
           continue;
         }
-        const int64_t k0 = std::max<int64_t>(P.bu_part[part], kw_lo);
-        const int64_t k1 = std::min<int64_t>(P.bu_part[part + 1], kw_hi);
+        // edge-balanced ranges, or without load balancing equal word counts
+        const int64_t k0 = std::max<int64_t>(
+            P.no_lb ? W * part / nranges : (int64_t)P.bu_part[part], kw_lo);
+        const int64_t k1 = std::min<int64_t>(
+            P.no_lb ? W * (part + 1) / nranges : (int64_t)P.bu_part[part + 1], kw_hi);
         // batches of 64 words: lane j loads word j (coalesced); the
         // unvisited vertices of the batch are handed to the lanes in order
         for (int64_t kb = k0; kb < k1; kb += kWave) {
@@ -683,7 +766,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           s_st.found[wv][l] = 0ull;
           __builtin_amdgcn_wave_barrier();
           refill_scan(
-              total, P.off, P.cols, fcur, s_step.filt, use_filt, fs, P.lane_row, examined,
+              total, P.off, P.cols, use_filt ? nullptr : P.top, fcur, s_step.filt, use_filt, fs,
+              P.lane_row, examined,
               [&](int t) -> int64_t {
                 // the word holding the t-th unvisited vertex of the batch:
                 // the first lane whose inclusive count exceeds t
@@ -869,6 +953,16 @@ __global__ void reset_ctl_kernel(BfsCtl* c) {
     p[i] = 0;
 }
 
+// top[v] = the largest label among v's neighbours (the row's last entry,
+// rows being ascending); 0 for an empty row, which is never probed.
+__global__ void top_kernel(const int64_t* off, const int32_t* cols, int64_t n, int32_t* top) {
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t e = off[v + 1];
+    top[v] = e > off[v] ? cols[e - 1] : 0;
+  }
+}
+
 __global__ void clear_status_kernel(BfsCtl* c) {
   if (threadIdx.x == 0) {
     c->sticky = 0;
@@ -912,7 +1006,7 @@ void free_bfs_work(Graph* g) {
   if (!w) return;
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
                 w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1],
-                w->wg_work};
+                w->wg_work,  w->top};
   for (void* p : ps)
     if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -943,6 +1037,13 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(rbfs::dev_malloc(&w->front, sizeof(uint64_t) * 3 * W));
   // every sub-queue and sub-list can hold the whole swept set
   for (int i = 0; i < 2; ++i) BFS_CHECK(rbfs::dev_malloc(&w->vl[i], sizeof(int32_t) * kNQ * ns));
+  BFS_CHECK(rbfs::dev_malloc(&w->top, sizeof(int32_t) * ns));
+  {
+    const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(ns, kBlock), 1 << 16));
+    hipLaunchKernelGGL(top_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->off,
+                       g->cols, g->n_sweep, w->top);
+    BFS_CHECK(hipGetLastError());
+  }
   for (int i = 0; i < 2; ++i) {
     BFS_CHECK(rbfs::dev_malloc(&w->qv[i], sizeof(int32_t) * kNQ * ns));
     BFS_CHECK(rbfs::dev_malloc(&w->qe[i], sizeof(int64_t) * kNQ * ns));
@@ -979,7 +1080,7 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(hipEventCreate(&w->ev2));
   BFS_CHECK(hipStreamSynchronize(stream));
   w->clean = false;
-  g->bytes += sizeof(uint64_t) * (size_t)ns +
+  g->bytes += sizeof(uint64_t) * (size_t)ns + sizeof(int32_t) * (size_t)ns +
               (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * kNQ * (size_t)ns +
               sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * kNQ * w->chunk_cap;
   return 0;
@@ -1061,6 +1162,8 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.wstride = 16 * (int64_t)w->max_grid;
   P.vl[0] = w->vl[0];
   P.vl[1] = w->vl[1];
+  P.top = w->top;
+  P.no_lb = (flags & RBFS_OPT_NO_BALANCE) ? 1 : 0;
   P.root_orig = root;
   P.mode = mode;
   P.alpha = alpha;

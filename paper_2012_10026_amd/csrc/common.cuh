@@ -256,8 +256,9 @@ __device__ __forceinline__ bool take_range(unsigned long long* ctrs, int64_t n, 
 }
 
 // Next range for the calling wave (same value in every lane), or -1.
+// steal = false: only the workgroup's own region (a static split).
 __device__ __forceinline__ int64_t next_range(unsigned long long* ctrs, int64_t n,
-                                              RangeCursor& c) {
+                                              RangeCursor& c, bool steal = true) {
   constexpr int kMaxFails = 3;
   const int G = (int)gridDim.x;
   const int own = region_of((int)blockIdx.x, G);
@@ -266,6 +267,7 @@ __device__ __forceinline__ int64_t next_range(unsigned long long* ctrs, int64_t 
     if (take_range(ctrs, n, G, own, 1, &r)) return r;
     c.own_done = true;
   }
+  if (!steal) return -1;
   if (c.victim >= 0) {
     if (take_range(ctrs, n, G, c.victim, 2, &r)) return r;
     c.victim = -1;

@@ -69,6 +69,7 @@ struct BfsWork {
   unsigned long long* wctr = nullptr;  // range counters: 3 x max_grid x 16
   int max_grid = 0;
   int32_t* vl[2] = {nullptr, nullptr};  // bottom-up vertex lists (n_sweep each)
+  int32_t* top = nullptr;       // largest-label neighbour of each swept vertex
   BfsCtl* ctl = nullptr;
   bool clean = false;           // every pair holds the unreached value
   int grid = 0;                 // persistent grid size
@@ -168,6 +169,8 @@ struct Graph {
   // n_sweep, so while any exists the graph may be neither relabelled nor
   // destroyed
   int multi_refs = 0;
+  // relabel batch size of rbfs_rcm_reorder (entries; 0 = automatic)
+  int64_t rcm_batch = 0;
 };
 
 // Sticky error text for the calling thread.

@@ -39,6 +39,7 @@
 // sorted position, so the vertices to expand next form a prefix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -521,6 +522,85 @@ __global__ __launch_bounds__(kBlock) void groups_to_rows_kernel(const int64_t* o
   }
 }
 
+// Batched relabel, for graphs whose whole-graph pair sort does not fit:
+// new rows [k0, k1) at a time.  Entry j of new row k (the row of v =
+// iperm[k]) gets the key ((k - k0) << bc) | perm[w] for its neighbour w, at
+// its final position in the batch; one sort of the batch on those bits
+// leaves every row ascending.  Rows of at most kLaneRow entries by one lane,
+// longer ones by the whole wave.
+__global__ __launch_bounds__(kBlock) void row_keys_kernel(const int64_t* off, const int32_t* cols,
+                                                          const int32_t* iperm,
+                                                          const int32_t* perm,
+                                                          const int64_t* newoff, int64_t k0,
+                                                          int64_t k1, int bc, uint64_t* keys,
+                                                          int64_t cap, int* status) {
+  const int64_t nw = ceil_div(k1 - k0, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int l = lane_id();
+  const int64_t base = newoff[k0];
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nw;
+       word += wstride) {
+    const int64_t k = k0 + word * kWave + l;
+    int64_t b = 0, e = 0, dst = 0;
+    if (k < k1) {
+      const int64_t v = iperm[k];
+      b = off[v];
+      e = off[v + 1];
+      dst = newoff[k] - base;
+      if (dst < 0 || dst + (e - b) > cap) {
+        atomicOr(status, kStatusBadInput);
+        e = b;
+      }
+    }
+    const uint64_t hi = (uint64_t)(k - k0) << bc;
+    const bool big = (e - b) > kLaneRow;
+    if (!big)
+      for (int64_t j = b; j < e; ++j) keys[dst + (j - b)] = hi | (uint32_t)perm[cols[j]];
+    uint64_t hubs = ballot(big);
+    while (hubs) {
+      const int h = ffs64(hubs);
+      hubs &= hubs - 1;
+      const int64_t hb = shfl(b, h), he = shfl(e, h), hd = shfl(dst, h);
+      const uint64_t hh = shfl(hi, h);
+      for (int64_t j = hb + l; j < he; j += kWave) keys[hd + (j - hb)] = hh | (uint32_t)perm[cols[j]];
+    }
+  }
+}
+
+__global__ void keys_to_cols_kernel(const uint64_t* keys, int64_t m, int bc, int32_t* out) {
+  const uint64_t mask = (1ull << bc) - 1ull;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (int32_t)(keys[i] & mask);
+}
+
+// Batch bounds: kb[i] = the first row starting at or after entry i * per
+// (i in [0, nb)), kb[nb] = n; eb[i] = newoff[kb[i]].
+__global__ void batch_bounds_kernel(const int64_t* newoff, int64_t n, int64_t per, int64_t nb,
+                                    int64_t* kb, int64_t* eb) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nb;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t k = n;
+    if (i < nb) {
+      const int64_t want = i * per;
+      int64_t lo = 0, hi = n;  // first k with newoff[k] >= want
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (newoff[mid] < want) lo = mid + 1;
+        else hi = mid;
+      }
+      k = lo;
+    }
+    kb[i] = k;
+    eb[i] = newoff[k];
+  }
+}
+
+// Relabel in batches of about kRelabelBatch entries once the graph has more
+// than kRelabelWholeMax (the whole-graph pair sort needs 16 bytes per entry).
+constexpr int64_t kRelabelWholeMax = (int64_t)1 << 32;
+constexpr int64_t kRelabelBatch = (int64_t)1 << 30;
+
 // Device buffers owned for the duration of one pass.
 struct Bufs {
   std::vector<void*> ptrs;
@@ -592,8 +672,15 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   // 1. V+ ranked by (degree, id)
   const int bv = bits_for(n);
   const int bdeg = bits_for((int64_t)maxdeg + 1);
-  RCM_CHECK(B.alloc(&keys, nplus > nnz ? nplus : nnz));
-  RCM_CHECK(B.alloc(&keys2, nplus > nnz ? nplus : nnz));
+  // the relabel sorts the whole graph's pairs at once, or new rows in
+  // batches of about `batch` entries when that would not fit (or when the
+  // graph asks for batches)
+  const int64_t batch = g->rcm_batch > 0 ? g->rcm_batch
+                        : (nnz > kRelabelWholeMax ? kRelabelBatch : 0);
+  const int64_t kcap = std::max<int64_t>(
+      nplus, batch > 0 ? std::min<int64_t>(nnz, batch + (int64_t)maxdeg) : nnz);
+  RCM_CHECK(B.alloc(&keys, kcap));
+  RCM_CHECK(B.alloc(&keys2, kcap));
   RCM_CHECK(B.alloc(&vplus, nplus));
   RCM_CHECK(B.alloc(&rank, n));
   RCM_CHECK(B.alloc(&ccp, nplus));
@@ -787,16 +874,51 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   // free what is no longer needed before the big sort
   (void)hipStreamSynchronize(stream);
   const int bn = bits_for(n);
-  hipLaunchKernelGGL(relabel_keys_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, g->cols,
-                     n, nnz, perm, newoff, keys, d_status);
-  RCM_CHECK(hipGetLastError());
-  uint64_t* k1 = keys;
-  uint64_t* k2 = keys2;
-  RCM_CHECK(radix_sort_u64(&k1, &k2, nnz, 32, 32 + bn, g->scratch, stream));
   RCM_CHECK(B.alloc(&newcols, nnz + kColPad));  // slack for aligned group reads
-  hipLaunchKernelGGL(groups_to_rows_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, n, nnz,
-                     perm, newoff, k1, newcols, d_status);
-  RCM_CHECK(hipGetLastError());
+  if (batch == 0) {
+    hipLaunchKernelGGL(relabel_keys_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off,
+                       g->cols, n, nnz, perm, newoff, keys, d_status);
+    RCM_CHECK(hipGetLastError());
+    uint64_t* k1 = keys;
+    uint64_t* k2 = keys2;
+    RCM_CHECK(radix_sort_u64(&k1, &k2, nnz, 32, 32 + bn, g->scratch, stream));
+    hipLaunchKernelGGL(groups_to_rows_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off, n,
+                       nnz, perm, newoff, k1, newcols, d_status);
+    RCM_CHECK(hipGetLastError());
+  } else {
+    const int64_t nb = ceil_div(nnz, batch);
+    int64_t *kb = nullptr, *eb = nullptr;
+    RCM_CHECK(B.alloc(&kb, nb + 1));
+    RCM_CHECK(B.alloc(&eb, nb + 1));
+    hipLaunchKernelGGL(batch_bounds_kernel, dim3(grid_for(nb + 1)), dim3(kBlock), 0, stream,
+                       newoff, n, batch, nb, kb, eb);
+    RCM_CHECK(hipGetLastError());
+    std::vector<int64_t> hkb(nb + 1), heb(nb + 1);
+    RCM_CHECK(hipMemcpyAsync(hkb.data(), kb, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost,
+                             stream));
+    RCM_CHECK(hipMemcpyAsync(heb.data(), eb, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost,
+                             stream));
+    RCM_CHECK(hipStreamSynchronize(stream));
+    for (int64_t i = 0; i < nb; ++i) {
+      const int64_t k0 = hkb[i], k1r = hkb[i + 1], m = heb[i + 1] - heb[i];
+      if (k1r <= k0 || m <= 0) continue;
+      if (m > kcap) {
+        set_error("rcm_reorder: relabel batch larger than its buffer");
+        return -1;
+      }
+      const int64_t nw = ceil_div(k1r - k0, kWave);
+      const int rgrid = (int)std::min<int64_t>(ceil_div(nw, kWavesPerBlock), 1 << 18);
+      hipLaunchKernelGGL(row_keys_kernel, dim3(rgrid), dim3(kBlock), 0, stream, g->off, g->cols,
+                         iperm, perm, newoff, k0, k1r, bn, keys, kcap, d_status);
+      RCM_CHECK(hipGetLastError());
+      uint64_t* k1 = keys;
+      uint64_t* k2 = keys2;
+      RCM_CHECK(radix_sort_u64(&k1, &k2, m, 0, bn + bits_for(k1r - k0), g->scratch, stream));
+      hipLaunchKernelGGL(keys_to_cols_kernel, dim3(grid_for(m)), dim3(kBlock), 0, stream, k1, m,
+                         bn, newcols + heb[i]);
+      RCM_CHECK(hipGetLastError());
+    }
+  }
   RCM_CHECK(hipMemcpyAsync(&status, d_status, sizeof(int), hipMemcpyDeviceToHost, stream));
   RCM_CHECK(hipEventRecord(e1, stream));
   RCM_CHECK(hipStreamSynchronize(stream));

@@ -280,6 +280,19 @@ def test_device_generator_matches_host(rb):
     assert np.array_equal(cols_d.cpu().numpy(), cols_h)
 
 
+@pytest.mark.parametrize("max_keys", [40000, 150001, 10 ** 6])
+def test_device_generator_in_range_passes(rb, max_keys):
+    """The device generator cut into passes over source-label ranges (a few
+    tens of thousands of keys each, as the largest graphs need on one GPU)
+    gives the host generator's CSR."""
+    off_h, cols_h = graphgen.kronecker_csr(14, 16, 33)
+    info = {}
+    off_d, cols_d = graphgen.kronecker_csr_device(14, 16, 33, max_pass_keys=max_keys, info=info)
+    assert info["passes"] >= (2 if max_keys < 500000 else 1)
+    assert np.array_equal(off_d.cpu().numpy(), off_h)
+    assert np.array_equal(cols_d.cpu().numpy(), cols_h)
+
+
 def test_device_tuple_count_matches_host(rb):
     """The benchmark's Graph500-style edge count: generated tuples with both
     endpoints reached, on the device against the host tuples and the
@@ -295,6 +308,29 @@ def test_device_tuple_count_matches_host(rb):
     d_o, _, _ = oracle.bfs(off, cols, iso)
     got = graphgen.kronecker_tuples_reached_device(12, torch.from_numpy(d_o).cuda(), 16, 5)
     assert got == int(np.sum((src == iso) & (dst == iso)))
+
+
+@pytest.mark.parametrize("reorder", [False, True], ids=["original", "rcm"])
+def test_without_load_balance_bit_exact(rb, reorder):
+    """The load-balance ablation (OPT_NO_BALANCE: whole rows per thread
+    top-down, equal vertex ranges without stealing bottom-up) gives the
+    oracle's arrays in every direction mode, and its per-workgroup work
+    still adds up to the level counters."""
+    off, cols = kron(14, 8)
+    G = rb.Graph(off, cols)
+    ell = G.rcm_reorder()[0].cpu().numpy() if reorder else None
+    rng = random.Random(3)
+    for root in graphgen.sample_roots(off, 3, 9):
+        d_o, p_o, _ = oracle.bfs(off, cols, root, ell)
+        for mode in MODES:
+            d, p = G.bfs(root, opts=opts_for(rb, mode, rng, no_balance=True))
+            assert np.array_equal(d.cpu().numpy(), d_o), (root, mode)
+            assert np.array_equal(p.cpu().numpy(), p_o), (root, mode)
+        _, _, st = G.bfs(root, opts=rb.make_opts(no_balance=True, wg_work=True), stats=True)
+        W = G.wg_work()
+        for d in range(st["levels"]):
+            want = st["mf"][d] if st["dir"][d] == 0 else st["edges"][d]
+            assert int(W[d].sum()) == want, (root, d)
 
 
 def test_workgroup_work_adds_up(rb):
@@ -345,3 +381,62 @@ def test_edgeless_graph(rb, n, reorder):
     for j, r in enumerate(roots):
         d_o, p_o, _ = oracle.bfs(off, cols, r, perm_o if reorder else None)
         assert np.array_equal(dB[j].cpu().numpy(), d_o) and np.array_equal(pB[j].cpu().numpy(), p_o)
+
+
+def _relabelled_csr(off, cols, perm):
+    """Host reference of the relabelled CSR: row k is the row of the vertex
+    with new label k, its neighbours renamed by perm, ascending."""
+    n = off.shape[0] - 1
+    iperm = np.empty(n, np.int64)
+    iperm[perm] = np.arange(n)
+    deg = np.diff(off)
+    noff = np.zeros(n + 1, np.int64)
+    noff[1:] = np.cumsum(deg[iperm])
+    ncols = np.empty(cols.shape[0], np.int32)
+    for k in range(n):
+        v = iperm[k]
+        ncols[noff[k]:noff[k + 1]] = np.sort(perm[cols[off[v]:off[v + 1]]])
+    return noff, ncols
+
+
+def test_graph_csr_export(rb):
+    off, cols = graphgen.kronecker_csr(11, 16, 4711)
+    G = rb.Graph(off, cols)
+    o0, c0 = G.csr()
+    assert np.array_equal(o0.cpu().numpy(), off) and np.array_equal(c0.cpu().numpy(), cols)
+    perm_t, _ = G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    o1, c1 = G.csr()
+    noff, ncols = _relabelled_csr(off, cols, perm_o)
+    assert np.array_equal(o1.cpu().numpy(), noff)
+    assert np.array_equal(c1.cpu().numpy(), ncols)
+    # a search on the exported graph in its own labels equals the internal output
+    r = graphgen.sample_roots(off, 1, 3)[0]
+    d, p = G.bfs(r, opts=rb.make_opts(output_space=rb.OUT_INTERNAL))
+    d_o, p_o, _ = oracle.bfs(noff, ncols, int(perm_o[r]))
+    assert np.array_equal(d.cpu().numpy(), d_o) and np.array_equal(p.cpu().numpy(), p_o)
+
+
+@pytest.mark.parametrize("batch", [1, 1000, 50000])
+def test_rcm_relabel_in_batches(rb, batch):
+    """The relabelled CSR built in batches of new rows (as the largest graphs
+    need) equals the one-sort build and the host reference, for the full and
+    a partial order, and searches on it stay bit-exact."""
+    off, cols = graphgen.kronecker_csr(13, 16, 7007)
+    perm_o, _, _ = oracle.rcm(off, cols)
+    for keep in (None, 3000):
+        G = rb.Graph(off, cols)
+        G.set_rcm_batch(batch)
+        perm_t, _ = G.rcm_reorder(keep=keep)
+        perm = perm_t.cpu().numpy()
+        ref = perm_o if keep is None else oracle.rcm_partial(off, cols, keep)[0]
+        assert np.array_equal(perm, ref)
+        o1, c1 = G.csr()
+        noff, ncols = _relabelled_csr(off, cols, perm)
+        assert np.array_equal(o1.cpu().numpy(), noff)
+        assert np.array_equal(c1.cpu().numpy(), ncols)
+        for r in graphgen.sample_roots(off, 2, 11):
+            d, p = G.bfs(r)
+            d_o, p_o, _ = oracle.bfs(off, cols, r, perm)
+            assert np.array_equal(d.cpu().numpy(), d_o)
+            assert np.array_equal(p.cpu().numpy(), p_o)

@@ -108,48 +108,6 @@ def test_out_of_range_falls_back_to_heuristic(rb):
     assert all(x == 1 for x in st_l["fallback"][1:])  # 1 = out of range
 
 
-def modeled_cost(samples_by_level, dirs):
-    """Sum over levels >= 1 of the measured time of the chosen direction."""
-    total = 0.0
-    for lv, d in enumerate(dirs):
-        if lv in samples_by_level:
-            total += np.exp(samples_by_level[lv][8 + d])
-    return total
-
-
-def test_learned_switch_gain_on_held_out_graph(rb):
-    """Train on per-level timings of scale 14-16 graphs; on a held-out scale
-    16 graph the learned schedule's measured per-level cost is compared with
-    the alpha/beta schedule's and with the best possible per-level choice."""
-    train_rows = []
-    for scale, seed in [(14, 1), (15, 2), (16, 3), (16, 4)]:
-        off, cols, G, _ = _kron_graph(rb, scale, seed)
-        roots = graphgen.sample_roots(off, 8, 100 + seed)
-        train_rows.append(rb.collect_level_samples(G, roots, reps=3))
-    rows = np.vstack(train_rows)
-    S = rows[:, :10]
-    order = graphgen.epoch_orders(S.shape[0], 300, 1)
-    w, curve = rb.mlp_train(S, graphgen.mlp_init_weights(0).astype(np.float32), order, batch=64,
-                            lr=3e-3)
-    assert curve[-1] < curve[0]
-    rb.switch_load(rb.make_switch_blob(w, rows))
-    off, cols, G, perm = _kron_graph(rb, 16, 99)
-    roots = graphgen.sample_roots(off, 8, 5)
-    cost_l = cost_h = cost_best = 0.0
-    for r in roots:
-        s = rb.collect_level_samples(G, [r], reps=3)
-        by_level = {int(row[10]): row for row in s}
-        _, _, st_l = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
-        _, _, st_h = G.bfs(r, stats=True)
-        cost_l += modeled_cost(by_level, st_l["dir"])
-        cost_h += modeled_cost(by_level, st_h["dir"])
-        cost_best += sum(np.exp(min(row[8], row[9])) for row in s)
-    print("learned %.1f us, alpha/beta %.1f us, per-level best %.1f us"
-          % (cost_l, cost_h, cost_best))
-    assert cost_l <= 1.10 * cost_h
-    assert cost_best <= cost_l + 1e-3
-
-
 def _chung_lu_graph(rb, seed):
     off, cols = graphgen.chung_lu_csr(300000, 15000, seed=seed, gamma=2.1, mean_deg=30.0,
                                       max_deg=20000.0)
@@ -158,37 +116,89 @@ def _chung_lu_graph(rb, seed):
     return off, cols, G
 
 
-def test_learned_switch_beats_alpha_beta_on_heavy_tail(rb):
-    """On power-law graphs with exponent 2.1 the fixed alpha/beta thresholds
-    leave the search bottom-up too long at the tail (about 1.47x the per-level
-    best).  Trained on four such graphs, the switch must cut the measured
-    per-level cost of a held-out one by at least 10 % against alpha/beta, and
-    its outputs stay identical to the heuristic schedule's."""
+@pytest.fixture(scope="module")
+def mixed_blob(rb):
+    """One network for both families: trained on the level costs of small
+    Kronecker graphs (scales 14-16) and of power-law Chung-Lu graphs
+    (300000 vertices, exponent 2.1), collected along the alpha/beta path."""
     rows = []
+    for scale, seed in [(14, 1), (15, 2), (16, 3), (16, 4)]:
+        off, cols, G, _ = _kron_graph(rb, scale, seed)
+        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed),
+                                             reps=3))
     for seed in (1, 2, 3, 4):
         off, cols, G = _chung_lu_graph(rb, seed)
-        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed), reps=3))
+        rows.append(rb.collect_level_samples(G, graphgen.sample_roots(off, 8, 100 + seed),
+                                             reps=3))
     rows = np.vstack(rows)
     order = graphgen.epoch_orders(rows.shape[0], 300, 1)
     w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
                             batch=64, lr=3e-3)
-    assert curve[-1] < curve[0]
-    rb.switch_load(rb.make_switch_blob(w, rows))
-    off, cols, G = _chung_lu_graph(rb, 9)
-    cost_l = cost_h = cost_best = 0.0
-    for r in graphgen.sample_roots(off, 8, 5):
-        s = rb.collect_level_samples(G, [r], reps=3)
-        by_level = {int(row[10]): row for row in s}
-        d_l, p_l, st_l = G.bfs(r, opts=rb.make_opts(rb.DIR_LEARNED), stats=True)
-        d_h, p_h, st_h = G.bfs(r, stats=True)
+    assert curve[-1] < 0.5 * curve[0]
+    return rb.make_switch_blob(w, rows)
+
+
+def kernel_ms(rb, G, roots, opts, reps=5):
+    """Sum over roots of the median search-kernel time; the outputs of every
+    run are returned for comparison."""
+    total, outs = 0.0, []
+    for r in roots:
+        ts = []
+        for _ in range(reps):
+            d, p, st = G.bfs(r, opts=opts, stats=True)
+            ts.append(st["ms_kernel"])
+        total += float(np.median(ts))
+        outs.append((d, p))
+    return total, outs
+
+
+def test_learned_switch_no_loss_on_held_out_kronecker(rb, mixed_blob):
+    """On a held-out Kronecker graph (scale 16) the learned switch, trained on
+    both families, is no slower than the alpha/beta rule: measured search-
+    kernel time within 3 % (timing noise), outputs identical."""
+    rb.switch_load(mixed_blob)
+    off, cols, G, perm = _kron_graph(rb, 16, 99)
+    roots = graphgen.sample_roots(off, 8, 5)
+    t_l, o_l = kernel_ms(rb, G, roots, rb.make_opts(rb.DIR_LEARNED))
+    t_h, o_h = kernel_ms(rb, G, roots, rb.make_opts())
+    for (d_l, p_l), (d_h, p_h) in zip(o_l, o_h):
         assert torch.equal(d_l, d_h) and torch.equal(p_l, p_h)
-        cost_l += modeled_cost(by_level, st_l["dir"])
-        cost_h += modeled_cost(by_level, st_h["dir"])
-        cost_best += sum(np.exp(min(row[8], row[9])) for row in s)
-    print("learned %.1f us, alpha/beta %.1f us, per-level best %.1f us"
-          % (cost_l, cost_h, cost_best))
-    assert cost_l <= 0.90 * cost_h
-    assert cost_best <= cost_l + 1e-3
+    print("learned %.3f ms, alpha/beta %.3f ms" % (t_l, t_h))
+    assert t_l <= 1.03 * t_h
+
+
+def test_learned_switch_beats_alpha_beta_on_heavy_tail(rb, mixed_blob):
+    """On power-law graphs with exponent 2.1 the fixed alpha/beta thresholds
+    stay bottom-up for a level too many at the tail.  The same network (not
+    retrained for this family) must cut the measured search-kernel time of
+    a held-out such graph by at least 10 % against alpha/beta, with
+    identical outputs."""
+    rb.switch_load(mixed_blob)
+    off, cols, G = _chung_lu_graph(rb, 9)
+    roots = graphgen.sample_roots(off, 8, 5)
+    t_l, o_l = kernel_ms(rb, G, roots, rb.make_opts(rb.DIR_LEARNED))
+    t_h, o_h = kernel_ms(rb, G, roots, rb.make_opts())
+    for (d_l, p_l), (d_h, p_h) in zip(o_l, o_h):
+        assert torch.equal(d_l, d_h) and torch.equal(p_l, p_h)
+    print("learned %.3f ms, alpha/beta %.3f ms" % (t_l, t_h))
+    assert t_l <= 0.90 * t_h
+
+
+def grid_csr(rows, cols_):
+    """CSR of the rows x cols_ 4-neighbour grid (vertex r * cols_ + c)."""
+    nbr = [[] for _ in range(rows * cols_)]
+    for r in range(rows):
+        for c in range(cols_):
+            v = r * cols_ + c
+            if c + 1 < cols_:
+                nbr[v].append(v + 1)
+                nbr[v + 1].append(v)
+            if r + 1 < rows:
+                nbr[v].append(v + cols_)
+                nbr[v + cols_].append(v)
+    off = np.zeros(rows * cols_ + 1, np.int64)
+    off[1:] = np.cumsum([len(x) for x in nbr])
+    return off, np.array([w for x in nbr for w in sorted(x)], np.int32)
 
 
 def _replay_learned(rb, G, off, cols, perm, roots, blob, alpha=14, beta=24):
@@ -212,14 +222,15 @@ def _replay_learned(rb, G, off, cols, perm, roots, blob, alpha=14, beta=24):
         assert np.array_equal(p.cpu().numpy(), p_o)
         c = oracle.level_counters(off, cols, d_o, ell=perm, n_sweep=n_sweep)
         assert st["levels"] == nlev
-        assert st["nf"] == [int(x) for x in c["nf"]]
-        assert st["mf"] == [int(x) for x in c["mf"]]
-        assert st["mu"] == [int(x) for x in c["mu"]]
-        dirs, fbs, outs = mlp.learned_schedule(blob.astype(np.float64), c["nf"], c["mf"],
-                                               c["mu"], c["nu"], n_sweep, nnz, alpha, beta,
-                                               taken=st["dir"])
+        k = min(nlev, rb.STATS_MAX_LEVELS)  # the stats hold the first 64 levels
+        assert st["nf"] == [int(x) for x in c["nf"][:k]]
+        assert st["mf"] == [int(x) for x in c["mf"][:k]]
+        assert st["mu"] == [int(x) for x in c["mu"][:k]]
+        dirs, fbs, outs = mlp.learned_schedule(blob.astype(np.float64), c["nf"][:k],
+                                               c["mf"][:k], c["mu"][:k], c["nu"][:k], n_sweep,
+                                               nnz, alpha, beta, taken=st["dir"])
         assert st["dir"][0] == 0
-        for lv in range(1, nlev):
+        for lv in range(1, k):
             got = (int(st["dir"][lv]), int(st["fallback"][lv]))
             assert got in outs[lv], "root %d level %d: kernel %s, oracle allows %s" % (
                 r, lv, got, sorted(outs[lv]))
@@ -255,7 +266,8 @@ def test_learned_decisions_replay_oracle_random_nets(rb):
 
 def test_learned_decisions_replay_oracle_trained(rb):
     """A network trained on the per-level timings of small Kronecker and
-    Chung-Lu graphs, replayed on held-out graphs of both families, with the
+    Chung-Lu graphs, replayed on held-out graphs of both families and on a
+    2-D grid (whose deep levels lie beyond the training range), with the
     default and a second (alpha, beta): network, out-of-range and margin
     decisions all occur and each equals the fp64 decision."""
     rows = []
@@ -281,6 +293,10 @@ def test_learned_decisions_replay_oracle_trained(rb):
     G = rb.Graph(off, cols)
     perm_t, _ = G.rcm_reorder()
     graphs.append((off, cols, G, perm_t.cpu().numpy()))
+    off, cols = grid_csr(40, 40)
+    G = rb.Graph(off, cols)
+    perm_t, _ = G.rcm_reorder()
+    graphs.append((off, cols, G, perm_t.cpu().numpy()))
     for off, cols, G, perm in graphs:
         roots = graphgen.sample_roots(off, 6, 9)
         for ab in ((14, 24), (64, 8)):
@@ -290,4 +306,4 @@ def test_learned_decisions_replay_oracle_trained(rb):
                 total[k] += tally[k]
     print("levels decided: network %d, out of range %d, within margin %d; %d levels "
           "within fp32 error of a threshold" % (total[0], total[1], total[2], loose))
-    assert total[0] > 0 and total[1] + total[2] > 0
+    assert total[0] > 0 and total[1] > 0 and total[2] > 0
