@@ -187,33 +187,65 @@ SWITCH_TRAIN_GRAPHS = (
     # (family, size, seed, roots): Kronecker scales 18-24 (edge factor 16)
     # and Chung-Lu graphs of exponents 2.1 and 2.5; none is a graph the
     # benchmark measures on
-    [("kronecker", s, 2000 + 10 * s + j, 32) for s in (18, 20, 22, 24) for j in range(4)] +
-    [("chung-lu", n, 5000 + 10 * j + int(10 * g), 16, g)
-     for n in (300_000, 1_000_000, 3_000_000) for g in (2.1, 2.5) for j in range(2)])
+    [("kronecker", s, 2000 + 10 * s + j, 32) for s in (18, 20, 22) for j in range(4)] +
+    [("kronecker", 24, 2240 + j, 16) for j in range(2)] +
+    [("chung-lu", n, 5000 + 10 * j + 21, 40, 2.1)
+     for n in (300_000, 1_000_000, 3_000_000) for j in range(4)] +
+    [("chung-lu", n, 5000 + 10 * j + 25, 32, 2.5) for n in (300_000, 1_000_000) for j in range(2)])
+# held-out graphs on which the decision margin is chosen: the training
+# families, and one Kronecker scale-26 and one 52.5M-vertex Chung-Lu graph of
+# other seeds than the measured ones (the sizes the switch is deployed at)
+SWITCH_VALIDATION_GRAPHS = [("kronecker", 24, 2299, 8), ("kronecker", 26, 2626, 8),
+                            ("chung-lu", 3_000_000, 5999, 8, 2.1),
+                            ("chung-lu", 300_000, 5998, 8, 2.1),
+                            ("chung-lu", 1_000_000, 5997, 8, 2.5),
+                            ("chung-lu-52.5M", 50_000_000, 4001, 8)]
+SWITCH_MARGINS = (0.25, 0.5, 1.0, 2.0, 1e9)
+
+
+def switch_graph(rb, graphgen, spec):
+    if spec[0] == "kronecker":
+        _, s, seed, k = spec
+        off, cols = graphgen.kronecker_csr_device(s, 16, seed)
+    elif spec[0] == "chung-lu-52.5M":
+        _, n, seed, k = spec
+        off, cols = graphgen.chung_lu_csr_device(n, n // 20, seed=seed)
+    else:
+        _, n, seed, k, g = spec
+        off, cols = graphgen.chung_lu_csr_device(n, n // 20, seed=seed, gamma=g,
+                                                 mean_deg=30.0 if g < 2.3 else 10.0,
+                                                 max_deg=n / 15.0)
+    roots = graphgen.sample_roots_device(off, k, 7)
+    G = rb.Graph(off, cols)
+    del off, cols
+    G.rcm_reorder(want_perm=False)
+    return G, roots
+
+
+def kernel_ms_sum(rb, G, roots, opts, reps=3):
+    """Sum over roots of the median search-kernel time."""
+    tot = 0.0
+    for r in roots:
+        tot += statistics.median(G.bfs(r, opts=opts, stats=True)[2]["ms_kernel"]
+                                 for _ in range(reps))
+    return tot
 
 
 def train_switch(rb, graphgen):
     """Per-level costs of both directions (rbfs_collect_level_samples: the
     alpha/beta path up to the level, then each direction) on Kronecker graphs
-    of scales 18-24 and on Chung-Lu graphs, then GPU training of one network
-    for every graph family; returns the switch blob and a summary."""
+    of scales 18-24 and on Chung-Lu graphs, GPU training of one network for
+    every graph family, and the decision margin chosen on held-out graphs of
+    the same families and sizes: the margin whose worst ratio of learned to
+    alpha/beta search time over them is smallest (a margin that never lets
+    the network decide is among the candidates), the geometric mean
+    breaking near-ties.  Returns the switch blob and a summary."""
     import numpy as np
     import torch
     rows = []
     t0 = time.perf_counter()
     for spec in SWITCH_TRAIN_GRAPHS:
-        if spec[0] == "kronecker":
-            _, s, seed, k = spec
-            off, cols = graphgen.kronecker_csr_device(s, 16, seed)
-        else:
-            _, n, seed, k, g = spec
-            off, cols = graphgen.chung_lu_csr_device(n, n // 20, seed=seed, gamma=g,
-                                                     mean_deg=30.0 if g < 2.3 else 10.0,
-                                                     max_deg=n / 15.0)
-        roots = graphgen.sample_roots_device(off, k, 7)
-        G = rb.Graph(off, cols)
-        del off, cols
-        G.rcm_reorder(want_perm=False)
+        G, roots = switch_graph(rb, graphgen, spec)
         rows.append(rb.collect_level_samples(G, roots, reps=3, cap=16384))
         G.close()
         torch.cuda.empty_cache()
@@ -224,15 +256,41 @@ def train_switch(rb, graphgen):
     w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
                             batch=64, lr=3e-3)
     t_train = time.perf_counter() - t0
-    log("# switch: %d samples (%.1f s), trained %.2f s, loss %.3f -> %.3f"
-        % (rows.shape[0], t_collect, t_train, curve[0], curve[-1]))
-    return rb.make_switch_blob(w, rows), {
+    # margin on the validation graphs
+    t0 = time.perf_counter()
+    ratios = {m: [] for m in SWITCH_MARGINS}
+    for spec in SWITCH_VALIDATION_GRAPHS:
+        G, roots = switch_graph(rb, graphgen, spec)
+        for r in roots[:2]:
+            G.bfs(r)
+        t_ab = kernel_ms_sum(rb, G, roots, rb.make_opts())
+        for m in SWITCH_MARGINS:
+            rb.switch_load(rb.make_switch_blob(w, rows, margin=m))
+            ratios[m].append(kernel_ms_sum(rb, G, roots, rb.make_opts(rb.DIR_LEARNED)) / t_ab)
+        G.close()
+        torch.cuda.empty_cache()
+    # the smallest worst ratio; margins within 1.5 % of it (timing noise) are
+    # ranked by their geometric mean ratio
+    best_worst = min(max(ratios[m]) for m in SWITCH_MARGINS)
+    margin = min((m for m in SWITCH_MARGINS if max(ratios[m]) <= best_worst + 0.015),
+                 key=lambda m: sum(math.log(x) for x in ratios[m]))
+    t_val = time.perf_counter() - t0
+    log("# switch: %d samples (%.1f s), trained %.2f s, loss %.3f -> %.3f; margin %.2f "
+        "(worst learned/alpha-beta time on validation %.3f)"
+        % (rows.shape[0], t_collect, t_train, curve[0], curve[-1], margin, max(ratios[margin])))
+    return rb.make_switch_blob(w, rows, margin=margin), {
         "samples": int(rows.shape[0]),
-        "train_graphs": "kronecker scales 18,20,22,24 x 4 (32 roots each); chung-lu n = 0.3M, "
-                        "1M, 3M x exponent 2.1 (mean degree 30), 2.5 (mean degree 10) x 2 "
-                        "(16 roots each)",
-        "collect_s": t_collect, "train_s": t_train, "epochs": 200,
-        "loss_first": float(curve[0]), "loss_last": float(curve[-1])}
+        "train_graphs": "kronecker scales 18,20,22 x 4 (32 roots each), 24 x 2 (16 roots); "
+                        "chung-lu n = 0.3M, 1M, 3M x 4, exponent 2.1, mean degree 30 (40 roots "
+                        "each); n = 0.3M, 1M x 2, exponent 2.5, mean degree 10 (32 roots)",
+        "collect_s": t_collect, "train_s": t_train, "validate_s": t_val, "epochs": 200,
+        "loss_first": float(curve[0]), "loss_last": float(curve[-1]),
+        "margin": margin,
+        "validation_learned_over_alpha_beta_time": {
+            ("%g" % m): [round(x, 4) for x in ratios[m]] for m in SWITCH_MARGINS},
+        "validation_graphs": "kronecker 24 seed 2299, kronecker 26 seed 2626; chung-lu 3M and "
+                             "0.3M exponent 2.1; chung-lu 1M exponent 2.5; chung-lu 52.5M seed "
+                             "4001 (8 roots each)"}
 
 
 def schedule_costs(rb, G, roots, learned_opts, plain_opts, reps=3):
@@ -467,7 +525,7 @@ def ablation(rb, graphgen, args):
     ceil(ratio * n+) vertices of the Cuthill-McKee sequence reordered, p0
     only moving isolated vertices to the end), each with the load-balanced
     kernels or, with the suffix "-nolb", without load balancing (whole rows
-    per thread top-down, equal vertex ranges without stealing bottom-up), on
+    per wave top-down, equal vertex ranges without stealing bottom-up), on
     Kronecker scales 21-26 and the 52.5 M-vertex Chung-Lu graph.  One JSON
     line per (graph, variant), with the vertices each bottom-up level sweeps
     (the unvisited part of its sweep range: the graph before RCM, the root's
@@ -680,11 +738,25 @@ def main():
     tune_roots = graphgen.sample_roots_device(off, 64, args.root_seed + 1000)
     log("# generated scale %d: n=%d nnz=%d in %.1fs" % (args.scale, off.numel() - 1,
                                                         cols.numel(), t_gen))
-    G = rb.Graph(off, cols)
     keep_host = not args.no_cpu
-    if not keep_host:
+    csr_bytes = off.numel() * 8 + cols.numel() * 4
+    if 2 * csr_bytes > 0.85 * dev["global_mem_bytes"]:
+        # the device cannot hold the generator's CSR and the library's copy
+        # at once (scale 30): the CSR goes through host memory
+        if keep_host:
+            raise SystemExit("this scale needs --no-cpu (the CSR is staged in host memory)")
+        t1 = time.perf_counter()
+        off_h, cols_h = off.cpu().numpy(), cols.cpu().numpy()
         del off, cols
         torch.cuda.empty_cache()
+        G = rb.Graph(off_h, cols_h)
+        del off_h, cols_h
+        log("# graph created from host memory in %.1f s" % (time.perf_counter() - t1))
+    else:
+        G = rb.Graph(off, cols)
+        if not keep_host:
+            del off, cols
+            torch.cuda.empty_cache()
     perm_t, rcm_ms = G.rcm_reorder(want_perm=keep_host)
     info = G.info()
     log("# rcm %.1f ms, n_plus=%d" % (rcm_ms, info["n_plus"]))

@@ -179,8 +179,8 @@ def _torch_stream(device):
 def kronecker_csr_device(scale, edgefactor=16, seed=1, abc=KRON_ABC, device="cuda",
                          max_pass_keys=0, info=None):
     """kronecker_csr on the GPU, built in passes over source-label ranges of
-    at most max_pass_keys directed keys each (0: as many as a quarter of the
-    free device memory holds); info (a dict, optional) receives the number
+    at most max_pass_keys directed keys each (0: as many as fit, with the
+    sort's buffers, in 80 % of the free device memory); info (a dict, optional) receives the number
     of passes."""
     import torch
     n = 1 << scale

@@ -276,7 +276,7 @@ fail:
 
 // The same CSR as gg_dev_kron_csr, built in passes over ranges of source
 // labels so that the directed keys of one pass (at most max_pass_keys; 0 =
-// as many as a quarter of the free device memory holds) fit in memory: each
+// as many as fit in 80 % of the free device memory with the sort buffers) fit in memory: each
 // pass regenerates every tuple, keeps the keys whose source lies in its
 // range, sorts and uniques them, and writes those rows.  The passes cover
 // the labels in increasing order, so the result does not depend on how they
@@ -321,7 +321,8 @@ int64_t gg_dev_kron_csr_ranges(int scale, int64_t edgefactor, uint64_t seed, dou
   if (kmax == 0) {
     size_t fr = 0, tot = 0;
     GG_CHECK(hipMemGetInfo(&fr, &tot));
-    kmax = std::min<int64_t>(total, (int64_t)(fr / 4 / (3 * sizeof(uint64_t))));
+    // keys, sorted keys and the sort's temporary copy: 24 bytes a key
+    kmax = std::min<int64_t>(total, (int64_t)((double)fr * 0.8 / (3 * sizeof(uint64_t))));
   }
   if (kmax < maxb) kmax = maxb;  // a pass holds at least one bucket
   if (kmax < 1) kmax = 1;

@@ -108,7 +108,8 @@ typedef struct rbfs_opts {
 #define RBFS_OPT_NO_BALANCE 8 /* single-root searches, for the load-balance
                                   ablation (sections 3.3-3.4): top-down gives
                                   each frontier vertex's whole row to one
-                                  thread (Algorithm 1's split), bottom-up
+                                  wave (Algorithm 1's vertex-per-worker
+                                  split on the GPU's SIMD unit), bottom-up
                                   sweeps equal vertex ranges, one set per
                                   workgroup, with no work stealing.  Same
                                   results; slower on skewed graphs. */
@@ -229,6 +230,22 @@ int rbfs_rcm_reorder(rbfs_graph_t* g, int32_t* perm_out, void* stream, float* ms
  * relabel within memory for the largest graphs one GPU holds.  max_entries
  * > 0: always in batches of about that many entries. */
 int rbfs_graph_set_rcm_batch(rbfs_graph_t* g, int64_t max_entries);
+
+/* Where a batched relabel keeps the old column array.  0 (default): on the
+ * device while there is room for both column arrays, else in pinned host
+ * memory, brought back a slice of old rows at a time (the graph's device
+ * memory then peaks at about one column array, which is what lets the
+ * largest graphs be relabelled on one GPU); 1: always in host memory; -1:
+ * never.  Applies only to batched relabels (rbfs_graph_set_rcm_batch). */
+int rbfs_graph_set_rcm_staging(rbfs_graph_t* g, int32_t mode);
+
+/* Size of the single-root search's frontier sub-queues.  The next frontier
+ * (and the bottom-up vertex list) is appended to 8 sub-queues, one per group
+ * of workgroups, each holding `entries` vertices; what does not fit goes to
+ * one shared overflow queue of n entries, so no size loses vertices.  0
+ * (default): n/4 each, about 3n entries in all.  Results do not depend on
+ * it.  Releases the search workspace (rebuilt by the next search). */
+int rbfs_graph_set_queue_cap(rbfs_graph_t* g, int64_t entries);
 
 /* Partial RCM (section 4.6): as rbfs_rcm_reorder, but only the first `keep`
  * vertices of Algorithm 3's Cuthill-McKee sequence are reordered.  They take
@@ -440,21 +457,22 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
  * "Parameter Tuning") is replaced by a small network that predicts, from 8
  * per-level features, ln(microseconds) of the next level in each direction
  * (output 0 top-down, 1 bottom-up); the cheaper one is taken when the two
- * predictions differ by at least 0.25 (ln microseconds, about 28 %).  Closer
- * predictions, which lie within the network's training error, and inputs
- * outside the training range leave the decision to the alpha/beta rule.
+ * predictions differ by at least the blob's margin (ln microseconds; 0.25 is
+ * about 28 %).  Closer predictions, which lie within the network's training
+ * error, and inputs outside the training range leave the decision to the
+ * alpha/beta rule.
  *
  * Network: x[8] -> ReLU(W1 x + b1)[32] -> ReLU(W2 h1 + b2)[32] -> W3 h2 + b3
  * [2], fp32.  Parameters (1410 floats) in the order W1[32][8] (row = output
  * unit), b1[32], W2[32][32], b2[32], W3[2][32], b3[2].  A switch blob adds
- * fmin[8], fmax[8] (training feature range) and the largest training level:
- * 1427 floats.  Features: log2(1+n_f)/log2(n), log2(1+m_f)/log2(nnz),
+ * fmin[8], fmax[8] (training feature range), the largest training level and
+ * the margin: 1428 floats.  Features: log2(1+n_f)/log2(n), log2(1+m_f)/log2(nnz),
  * log2(1+m_u)/log2(nnz), n_u/n, clamp(log2((1+m_f)/(1+m_u))/16, -2, 2),
  * level/32, current direction, clamp(log2((1+n_f)/(1+n_f_prev))/8, -2, 2),
  * with n the swept vertex count and n_u the swept vertices not yet reached.
  * All buffers of these calls are host memory. */
 
-/* Loads the switch blob (1427 floats) for the current device; later
+/* Loads the switch blob (1428 floats) for the current device; later
  * searches with RBFS_DIR_LEARNED use it.  Process-wide. */
 int rbfs_switch_load(const float* blob, int32_t n);
 

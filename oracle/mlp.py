@@ -103,13 +103,14 @@ def train(samples, w0, order, batch=256, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
 # outputs are predicted ln(microseconds) of level d run top-down (0) or
 # bottom-up (1); the network decides only when the inputs lie inside the
 # widened training range and its two predictions differ by at least the
-# margin; otherwise the alpha/beta rule of Algorithm 2 (section 2.1,
+# margin (ln microseconds, the blob's last value); otherwise the alpha/beta
+# rule of Algorithm 2 (section 2.1,
 # "Parameter Tuning"; integer form) decides.  The switch blob holds the 1410
-# network parameters, then fmin[8], fmax[8] and the largest training level.
+# network parameters, then fmin[8], fmax[8], the largest training level and
+# the margin.
 
-MARGIN = 0.25             # ln microseconds
 OOD_WIDEN = 0.1           # the training range is widened by 10 % of its width
-BLOB = NPARAMS + NIN + NIN + 1
+BLOB = NPARAMS + NIN + NIN + 2  # ... + largest training level + margin
 FALLBACK_NONE, FALLBACK_OOD, FALLBACK_MARGIN = 0, 1, 2
 _U32 = 2.0 ** -24         # unit roundoff of fp32
 # Bound on the absolute error of one fp32 feature: each is at most a few
@@ -200,6 +201,7 @@ def decide(blob, cur_dir, nf, mf, mu, nu, nf_prev, level, n_sweep, nnz, alpha, b
     bounds, more when a threshold lies within them."""
     blob = np.asarray(blob, np.float64)
     w = blob[:NPARAMS]
+    margin = blob[BLOB - 1]
     f = features(nf, mf, mu, nu, nf_prev, level, cur_dir, n_sweep, nnz)
     rule = heuristic_next(cur_dir, nf, mf, mu, nf_prev, n_sweep, alpha, beta)
     lo = blob[NPARAMS:NPARAMS + NIN]
@@ -210,9 +212,9 @@ def decide(blob, cur_dir, nf, mf, mu, nu, nf_prev, level, n_sweep, nnz, alpha, b
     slack = FEATURE_ERR + bnd_err
 
     def net_outcome(gap):
-        if gap >= MARGIN:
+        if gap >= margin:
             return (1, 0)
-        if -gap >= MARGIN:
+        if -gap >= margin:
             return (0, 0)
         return (rule, FALLBACK_MARGIN)
 

@@ -28,7 +28,7 @@ CERT_ROOT, CERT_REACH, CERT_LEVEL, CERT_ORPHAN, CERT_PARENT, CERT_LARGER, CERT_R
     -1, -2, -3, -4, -5, -6, -7
 STATS_MAX_LEVELS = 64
 MLP_PARAMS = 8 * 32 + 32 + 32 * 32 + 32 + 32 * 2 + 2
-SWITCH_BLOB = MLP_PARAMS + 8 + 8 + 1
+SWITCH_BLOB = MLP_PARAMS + 8 + 8 + 1 + 1
 
 
 class RbfsError(RuntimeError):
@@ -120,6 +120,8 @@ SIGNATURES = {
     "rbfs_rcm_reorder": (ctypes.c_int, [_P, _P, _P, _P]),
     "rbfs_rcm_reorder_partial": (ctypes.c_int, [_P, _I64, _P, _P, _P]),
     "rbfs_graph_set_rcm_batch": (ctypes.c_int, [_P, _I64]),
+    "rbfs_graph_set_queue_cap": (ctypes.c_int, [_P, _I64]),
+    "rbfs_graph_set_rcm_staging": (ctypes.c_int, [_P, _I32]),
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_graph_csr": (ctypes.c_int, [_P, _P, _P, _P]),
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
@@ -371,6 +373,17 @@ class Graph:
         automatic, by graph size); the permutation and CSR are the same."""
         _check(lib().rbfs_graph_set_rcm_batch(self._h, int(max_entries)))
 
+    def set_rcm_staging(self, mode):
+        """Old columns of a batched relabel in host memory: 0 when device
+        memory is short (default), 1 always, -1 never."""
+        _check(lib().rbfs_graph_set_rcm_staging(self._h, int(mode)))
+
+    def set_queue_cap(self, entries):
+        """Entries of each frontier sub-queue of single-root searches (0:
+        automatic); the rest goes to a shared overflow queue.  Results do
+        not depend on it."""
+        _check(lib().rbfs_graph_set_queue_cap(self._h, int(entries)))
+
     def iperm(self):
         import torch
         out = torch.empty(self.n, dtype=torch.int32, device=self.device)
@@ -615,14 +628,16 @@ def collect_level_samples(graph, roots, reps=3, alpha=14, beta=24, cap=4096):
     return out[:cnt.value].copy()
 
 
-def make_switch_blob(w, features):
-    """Weights plus the training feature range and the largest level."""
+def make_switch_blob(w, features, margin=0.25):
+    """Weights plus the training feature range, the largest level and the
+    decision margin (ln microseconds)."""
     features = np.asarray(features, np.float32)
     blob = np.zeros(SWITCH_BLOB, np.float32)
     blob[:MLP_PARAMS] = w
     blob[MLP_PARAMS:MLP_PARAMS + 8] = features[:, :8].min(axis=0)
     blob[MLP_PARAMS + 8:MLP_PARAMS + 16] = features[:, :8].max(axis=0)
     blob[MLP_PARAMS + 16] = features[:, 10].max() if features.shape[1] > 10 else 64
+    blob[MLP_PARAMS + 17] = margin
     return blob
 
 

@@ -415,6 +415,27 @@ int rbfs_graph_set_rcm_batch(rbfs_graph_t* h, int64_t max_entries) {
   return RBFS_OK;
 }
 
+int rbfs_graph_set_rcm_staging(rbfs_graph_t* h, int32_t mode) {
+  if (!h || mode < -1 || mode > 1) {
+    set_error("rbfs_graph_set_rcm_staging: NULL graph or mode outside [-1, 1]");
+    return RBFS_E_INVAL;
+  }
+  h->g.rcm_stage = mode;
+  return RBFS_OK;
+}
+
+int rbfs_graph_set_queue_cap(rbfs_graph_t* h, int64_t entries) {
+  if (!h || entries < 0) {
+    set_error("rbfs_graph_set_queue_cap: NULL graph or negative size");
+    return RBFS_E_INVAL;
+  }
+  (void)hipSetDevice(h->g.device);
+  (void)hipDeviceSynchronize();  // the workspace may still be in use
+  h->g.queue_cap = entries;
+  rbfs::free_bfs_work(&h->g);    // rebuilt with the new size by the next search
+  return RBFS_OK;
+}
+
 int rbfs_rcm_reorder(rbfs_graph_t* h, int32_t* perm_out, void* stream, float* ms_out) {
   return rcm_reorder_call(h, -1, perm_out, stream, ms_out);
 }

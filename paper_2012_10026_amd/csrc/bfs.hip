@@ -58,11 +58,21 @@ namespace rbfs {
 
 const float* switch_blob_device(int device);
 
+// The next frontier (and the bottom-up vertex list) is split into kNQ
+// sub-queues, one per group of workgroups (blockIdx mod kNQ, i.e. one per
+// XCD), each behind its own packed counter: a single grid-wide counter
+// serialises the appends of every wave on one address.
+constexpr int kNQ = 8;
+// ... plus one shared overflow sub-queue (and sub-list), index kNQ: a
+// sub-queue holds qcap entries, and a flush that does not fit puts the rest
+// there, so the queues need about 3 n entries in total instead of 8 n.
+constexpr int kNQT = kNQ + 1;
+
 struct alignas(128) BfsCtl {
   GridBarrier bar;
-  alignas(128) unsigned long long qpack[3][8][16];  // [rotation][sub-queue][0], own line each
+  alignas(128) unsigned long long qpack[3][kNQT][16];  // [rotation][sub-queue][0], own line each
   alignas(128) unsigned long long edges[3][16];     // entries read this level
-  alignas(128) unsigned long long vlcnt[3][8][16];  // vertices appended to each sub-list
+  alignas(128) unsigned long long vlcnt[3][kNQT][16];  // vertices appended to each sub-list
   int levels;
   int sticky;  // statuses of the searches since the last rbfs_graph_check
   int sweep_lo, sweep_hi;  // bottom-up sweep: the root's component
@@ -79,11 +89,6 @@ struct alignas(128) BfsCtl {
 namespace {
 
 constexpr int kStage = 384;  // staged appends per wave
-// The next frontier (and the bottom-up vertex list) is split into kNQ
-// sub-queues, one per group of workgroups (blockIdx mod kNQ, i.e. one per
-// XCD), each behind its own packed counter: a single grid-wide counter
-// serialises the appends of every wave on one address.
-constexpr int kNQ = 8;
 constexpr int kListRange = 64;  // list vertices per bottom-up work range
 constexpr int kScanStep = 8;    // row entries a lane tests per step (after the first)
 static_assert(kScanStep == 8, "the row scan loads two aligned groups of 4 entries");
@@ -109,16 +114,17 @@ struct BfsParams {
   int64_t n_comp;
   uint64_t* vis;
   uint64_t* front[3];
-  int32_t* qv[2];        // kNQ sub-queues of qstride entries each
+  int32_t* qv[2];        // kNQ sub-queues of qcap entries each, then the overflow one
   int64_t* qe[2];
   int32_t* chunk[2];     // kNQ chunk tables of chunk_cap entries each
   int64_t chunk_cap;
-  int64_t qstride;
+  int64_t qcap;         // entries of each of the kNQ sub-queues (and sub-lists); the
+                         // overflow one at index kNQ holds n_sweep
   const int32_t* bu_part;
   int32_t n_part;
   unsigned long long* wctr;  // BU range counters: 3 slots of wstride, 16 per workgroup
   int64_t wstride;
-  int32_t* vl[2];            // vertex lists (kNQ sub-lists of qstride entries)
+  int32_t* vl[2];            // vertex lists (kNQ sub-lists of qcap entries, overflow)
   const int32_t* top;        // largest-label neighbour of each swept vertex
   // the ablation without load balancing (RBFS_OPT_NO_BALANCE): top-down one
   // frontier vertex per thread, bottom-up equal vertex ranges per workgroup
@@ -161,7 +167,10 @@ struct StageLds {
 
 // Publishes this wave's staged vertices to its sub-queue of the next
 // frontier (qpack: the packed counters of the next level, one line per
-// sub-queue).
+// sub-queue).  The part that does not fit in the sub-queue's qcap entries
+// goes to the overflow sub-queue (index kNQ), with its own count, degree
+// prefix and chunk marks; the entries inside keep theirs, so the sub-queue
+// holds exactly its first qcap positions (the next level clamps its count).
 template <class ST>
 __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_idx,
                                             unsigned long long* qpack) {
@@ -169,10 +178,6 @@ __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_i
   const int cnt = st.cnt[wv];
   if (cnt == 0) return;
   const int sq = (int)(blockIdx.x & (kNQ - 1));
-  qpack += sq * 16;
-  int32_t* qv = P.qv[nq_idx] + sq * P.qstride;
-  int64_t* qe = P.qe[nq_idx] + sq * P.qstride;
-  int32_t* chunk = P.chunk[nq_idx] + sq * P.chunk_cap;
   int64_t total = 0;
   for (int j0 = 0; j0 < cnt; j0 += kWave) {
     const int j = j0 + l;
@@ -181,27 +186,53 @@ __device__ __forceinline__ void flush_stage(ST& st, const BfsParams& P, int nq_i
   total = wave_sum(total);
   unsigned long long old = 0;
   if (l == 0)
-    old = atomicAdd(qpack, ((unsigned long long)cnt << P.eb) + (unsigned long long)total);
+    old = atomicAdd(qpack + sq * 16,
+                    ((unsigned long long)cnt << P.eb) + (unsigned long long)total);
   old = shfl(old, 0);
   const int64_t pos0 = (int64_t)(old >> P.eb);
-  int64_t ebase = (int64_t)(old & ((1ull << P.eb) - 1ull));
-  if (pos0 + cnt > P.qstride) {
-    if (l == 0) atomicOr(&P.ctl->bar.status, kStatusOverflow);
-  } else {
-    for (int j0 = 0; j0 < cnt; j0 += kWave) {
+  const int64_t ebase0 = (int64_t)(old & ((1ull << P.eb) - 1ull));
+  // entries [0, kin) stay in the sub-queue, [kin, cnt) overflow
+  const int kin = (int)std::max<int64_t>(0, std::min<int64_t>(cnt, P.qcap - pos0));
+  int64_t pos1 = 0, ebase1 = 0, din = 0;
+  if (kin < cnt) {
+    for (int j0 = 0; j0 < kin; j0 += kWave) {
       const int j = j0 + l;
-      const bool act = j < cnt;
-      const int64_t d = act ? (int64_t)st.d[wv][j] : 0;
-      const int64_t inc = wave_inclusive_sum(d);
-      if (act) {
-        const int64_t pos = pos0 + j;
-        const int64_t base = ebase + inc - d;
-        qv[pos] = st.v[wv][j];
-        qe[pos] = base;
-        mark_chunks(chunk, P.chunk_cap, base, d, (int32_t)pos, P.cshift);
-      }
-      ebase += shfl(inc, kWave - 1);
+      din += (j < kin) ? (int64_t)st.d[wv][j] : 0;
     }
+    din = wave_sum(din);
+    unsigned long long o1 = 0;
+    if (l == 0)
+      o1 = atomicAdd(qpack + kNQ * 16, ((unsigned long long)(cnt - kin) << P.eb) +
+                                           (unsigned long long)(total - din));
+    o1 = shfl(o1, 0);
+    pos1 = (int64_t)(o1 >> P.eb);
+    ebase1 = (int64_t)(o1 & ((1ull << P.eb) - 1ull));
+    if (pos1 + (cnt - kin) > P.n_sweep) {  // cannot happen: a level appends each vertex once
+      if (l == 0) atomicOr(&P.ctl->bar.status, kStatusOverflow);
+      __builtin_amdgcn_wave_barrier();
+      if (l == 0) st.cnt[wv] = 0;
+      __builtin_amdgcn_wave_barrier();
+      return;
+    }
+  }
+  int64_t run = 0;  // degree sum of the entries before this round
+  for (int j0 = 0; j0 < cnt; j0 += kWave) {
+    const int j = j0 + l;
+    const bool act = j < cnt;
+    const int64_t d = act ? (int64_t)st.d[wv][j] : 0;
+    const int64_t inc = wave_inclusive_sum(d);
+    if (act) {
+      const int64_t g = run + inc - d;  // degree prefix inside this flush
+      const bool in = j < kin;
+      const int q = in ? sq : kNQ;
+      const int64_t pos = in ? pos0 + j : pos1 + (j - kin);
+      const int64_t base = in ? ebase0 + g : ebase1 + (g - din);
+      P.qv[nq_idx][q * P.qcap + pos] = st.v[wv][j];
+      P.qe[nq_idx][q * P.qcap + pos] = base;
+      mark_chunks(P.chunk[nq_idx] + q * P.chunk_cap, P.chunk_cap, base, d, (int32_t)pos,
+                  P.cshift);
+    }
+    run += shfl(inc, kWave - 1);
   }
   __builtin_amdgcn_wave_barrier();
   if (l == 0) st.cnt[wv] = 0;
@@ -229,25 +260,36 @@ __device__ __forceinline__ void stage(ST& st, bool take, int32_t v, int64_t deg,
 }
 
 // Publishes this wave's staged list vertices to its sub-list (out: the
-// sub-lists of cap entries each; count: their counters, one line each).
+// sub-lists of cap entries each, then the overflow sub-list of n_sweep;
+// count: their counters, one line each).  The part that does not fit goes
+// to the overflow sub-list.
 template <class ST>
 __device__ __forceinline__ void flush_list(ST& st, int32_t* out, unsigned long long* count,
-                                           int64_t cap, BfsCtl* ctl) {
+                                           int64_t cap, int64_t n_sweep, BfsCtl* ctl) {
   const int wv = wave_id(), l = lane_id();
   const int cnt = st.lcnt[wv];
   if (cnt == 0) return;
   const int sq = (int)(blockIdx.x & (kNQ - 1));
-  out += sq * cap;
-  count += sq * 16;
   unsigned long long base = 0;
   if (l == 0)
-    base = __hip_atomic_fetch_add(count, (unsigned long long)cnt, __ATOMIC_RELAXED,
+    base = __hip_atomic_fetch_add(count + sq * 16, (unsigned long long)cnt, __ATOMIC_RELAXED,
                                   __HIP_MEMORY_SCOPE_AGENT);
   base = shfl(base, 0);
-  if ((int64_t)base + cnt > cap) {
+  const int kin = (int)std::max<int64_t>(0, std::min<int64_t>(cnt, cap - (int64_t)base));
+  unsigned long long b1 = 0;
+  if (kin < cnt) {
+    if (l == 0)
+      b1 = __hip_atomic_fetch_add(count + kNQ * 16, (unsigned long long)(cnt - kin),
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b1 = shfl(b1, 0);
+  }
+  if ((int64_t)b1 + (cnt - kin) > n_sweep) {  // cannot happen: each vertex once per level
     if (l == 0) atomicOr(&ctl->bar.status, kStatusOverflow);
   } else {
-    for (int j = l; j < cnt; j += kWave) out[base + j] = st.lv[wv][j];
+    for (int j = l; j < cnt; j += kWave) {
+      if (j < kin) out[sq * cap + (int64_t)base + j] = st.lv[wv][j];
+      else out[kNQ * cap + (int64_t)b1 + (j - kin)] = st.lv[wv][j];
+    }
   }
   __builtin_amdgcn_wave_barrier();
   if (l == 0) st.lcnt[wv] = 0;
@@ -258,7 +300,7 @@ __device__ __forceinline__ void flush_list(ST& st, int32_t* out, unsigned long l
 template <class ST>
 __device__ __forceinline__ void stage_list(ST& st, bool take, int32_t v, int32_t* out,
                                            unsigned long long* count, int64_t cap,
-                                           BfsCtl* ctl) {
+                                           int64_t n_sweep, BfsCtl* ctl) {
   const uint64_t m = ballot(take);
   if (m == 0) return;
   const int wv = wave_id();
@@ -267,7 +309,7 @@ __device__ __forceinline__ void stage_list(ST& st, bool take, int32_t v, int32_t
   if (take) st.lv[wv][base + popc64(m & lanemask_lt())] = v;
   if (lane_id() == 0) st.lcnt[wv] = base + popc64(m);
   __builtin_amdgcn_wave_barrier();
-  if (base + popc64(m) > kStage - kWave) flush_list(st, out, count, cap, ctl);
+  if (base + popc64(m) > kStage - kWave) flush_list(st, out, count, cap, n_sweep, ctl);
 }
 
 // visited |= F_d for level d: through the queue (sub-queue sizes qcnt) when
@@ -276,8 +318,8 @@ __device__ __forceinline__ void fold_frontier(const BfsParams& P, int qc, long l
                                               const uint64_t* fcur, int64_t W, int64_t gtid,
                                               int64_t gsz, const long long* qcnt) {
   if (nf * 8 < W) {
-    for (int q = 0; q < kNQ; ++q) {
-      const int32_t* qv = P.qv[qc] + q * P.qstride;
+    for (int q = 0; q < kNQT; ++q) {
+      const int32_t* qv = P.qv[qc] + q * P.qcap;
       for (int64_t i = gtid; i < qcnt[q]; i += gsz) {
         const int32_t u = qv[i];
         atomicOr((unsigned long long*)&P.vis[u >> 6], 1ull << (u & 63));
@@ -454,7 +496,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   __shared__ StageLds<WAVES> s_st;
   // sizes of the current frontier's sub-queues and of the last vertex list's
   // sub-lists (the same in every workgroup)
-  __shared__ long long s_qcnt[kNQ], s_qedg[kNQ], s_lcnt[kNQ];
+  __shared__ long long s_qcnt[kNQT], s_qedg[kNQT], s_lcnt[kNQT];
   BfsCtl* ctl = P.ctl;
   const int64_t gtid = (int64_t)blockIdx.x * BLOCK + threadIdx.x;
   const int64_t gsz = (int64_t)gridDim.x * BLOCK;
@@ -472,7 +514,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
   if (P.mode == RBFS_DIR_LEARNED)  // read at every decision: keep them in LDS
     for (int i = threadIdx.x; i < kMlpParams; i += BLOCK) s_mlp[i] = P.sw[i];
-  if (threadIdx.x < kNQ) {  // F_0 = {root} sits in sub-queue 0
+  if (threadIdx.x < kNQT) {  // F_0 = {root} sits in sub-queue 0
     s_qcnt[threadIdx.x] = (threadIdx.x == 0 && root_in) ? 1 : 0;
     s_qedg[threadIdx.x] = (threadIdx.x == 0) ? dr : 0;
     s_lcnt[threadIdx.x] = 0;
@@ -491,7 +533,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   if (gtid == 0) {
     if (!P.init && root_in) P.dp[root] = pack_dp(0, root);
     for (int r = 0; r < 2; ++r) {
-      for (int q = 0; q < kNQ; ++q) {
+      for (int q = 0; q < kNQT; ++q) {
         ctl->qpack[r][q][0] = 0ull;
         ctl->vlcnt[r][q][0] = 0ull;
       }
@@ -557,7 +599,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     // clear what level L+1 will fill
     for (int64_t w = gtid; w < W; w += gsz) P.front[z3][w] = 0ull;
     if (gtid == 0) {
-      for (int q = 0; q < kNQ; ++q) {
+      for (int q = 0; q < kNQT; ++q) {
         ctl->qpack[z3][q][0] = 0ull;
         ctl->vlcnt[z3][q][0] = 0ull;
       }
@@ -565,46 +607,37 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     }
     if (threadIdx.x == 0) P.wctr[z3 * P.wstride + blockIdx.x * 16] = 0ull;
     if (dir == 0 && P.no_lb) {
-      // ---- top-down without load balancing (Alg 1): frontier vertex j of
-      // the sub-queues taken one after the other goes to thread j mod (grid
-      // threads), which walks its whole row, one entry per step in lock-step
-      // with its wave
+      // ---- top-down without load balancing (Alg 1's split, one frontier
+      // vertex per SIMD unit): frontier vertex j of the sub-queues taken one
+      // after the other goes to wave j mod (grid waves), which walks its
+      // whole row, 64 entries per step; a hub's row is not split further
       fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
-      int64_t j = gtid, e = 0, eend = 0, mine = 0;
-      int32_t u = 0;
-      bool have = false;
-      for (;;) {
-        if (!have && j < nf) {
-          int q = 0;
-          int64_t i = j;
-          while (i >= s_qcnt[q]) i -= s_qcnt[q++];
-          u = P.qv[qc][q * P.qstride + i];
-          e = P.off[u];
-          eend = P.off[u + 1];
-          have = true;
-          j += gsz;
-        }
-        const bool act = have && e < eend;
-        const int32_t w = act ? P.cols[e] : 0;
-        bool claim = false;
-        int64_t dw = 0;
-        if (act && !(((P.vis[w >> 6] | fcur[w >> 6]) >> (w & 63)) & 1ull)) {
-          const uint64_t prop = pack_dp(L + 1, u);
-          if (P.dp[w] > prop)
-            claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
-                    kUnreached;
-          if (claim) {
-            dw = P.off[w + 1] - P.off[w];
-            atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+      const int64_t nwaves = gsz / kWave;
+      int64_t mine = 0;
+      for (int64_t j = gtid / kWave; j < nf; j += nwaves) {
+        int q = 0;
+        int64_t i = j;
+        while (i >= s_qcnt[q]) i -= s_qcnt[q++];
+        const int32_t u = P.qv[qc][q * P.qcap + i];
+        const int64_t rb = P.off[u], re = P.off[u + 1];
+        for (int64_t e0 = rb; e0 < re; e0 += kWave) {
+          const bool act = e0 + l < re;
+          const int32_t w = act ? P.cols[e0 + l] : 0;
+          bool claim = false;
+          int64_t dw = 0;
+          if (act && !(((P.vis[w >> 6] | fcur[w >> 6]) >> (w & 63)) & 1ull)) {
+            const uint64_t prop = pack_dp(L + 1, u);
+            if (P.dp[w] > prop)
+              claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
+                      kUnreached;
+            if (claim) {
+              dw = P.off[w + 1] - P.off[w];
+              atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
+            }
           }
+          stage(s_st, claim, w, dw, P, qn, qpack);
+          mine += act ? 1 : 0;
         }
-        stage(s_st, claim, w, dw, P, qn, qpack);
-        if (act) {
-          ++e;
-          ++mine;
-        }
-        if (have && e >= eend) have = false;
-        if (ballot(have || j < nf) == 0ull) break;
       }
       flush_stage(s_st, P, qn, qpack);
       if (WGW) wg_td = block_sum(mine);
@@ -614,7 +647,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
       // the chunks of the sub-queues, one after the other
       int64_t nchunks = 0;
-      for (int q = 0; q < kNQ; ++q) nchunks += ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
+      for (int q = 0; q < kNQT; ++q) nchunks += ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
       for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
         int q = 0;
         int64_t lc = c, nq_ch = ceil_div(s_qedg[0], (int64_t)1 << P.cshift);
@@ -628,7 +661,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           wg_td += std::min<int64_t>((int64_t)1 << P.cshift, s_qedg[q] - e0);
         }
         const bool ok = expand_chunk_batch<BLOCK, kTdK>(
-            s_step.chunk, lc, s_qedg[q], P.qv[qc] + q * P.qstride, P.qe[qc] + q * P.qstride,
+            s_step.chunk, lc, s_qedg[q], P.qv[qc] + q * P.qcap, P.qe[qc] + q * P.qcap,
             s_qcnt[q], P.chunk[qc] + q * P.chunk_cap, nq_ch, P.off, P.cols, P.cshift,
             [&](const bool* act, const int32_t* u, const int32_t* w) {
           // w is a candidate if unvisited at level start; it then proposes
@@ -692,8 +725,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         uint32_t* f = s_step.filt;
         for (int i = threadIdx.x; i < StepLds<BLOCK>::kFiltWords; i += BLOCK) f[i] = 0u;
         __syncthreads();
-        for (int q = 0; q < kNQ; ++q) {
-          const int32_t* qv = P.qv[qc] + q * P.qstride;
+        for (int q = 0; q < kNQT; ++q) {
+          const int32_t* qv = P.qv[qc] + q * P.qcap;
           for (int64_t i = threadIdx.x; i < s_qcnt[q]; i += BLOCK) {
             const uint32_t k = (uint32_t)qv[i] >> fs;
             atomicOr(&f[k >> 5], 1u << (k & 31));
@@ -704,7 +737,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       int64_t nranges = P.n_part;
       if (listed) {
         nranges = 0;
-        for (int q = 0; q < kNQ; ++q) nranges += ceil_div(s_lcnt[q], kListRange);
+        for (int q = 0; q < kNQT; ++q) nranges += ceil_div(s_lcnt[q], kListRange);
       }
       const int wv = wave_id();
       RangeCursor cur;
@@ -720,7 +753,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
             ++q;
             nq_r = ceil_div(s_lcnt[q], kListRange);
           }
-          const int64_t i0 = q * P.qstride + lr * kListRange;
+          const int64_t i0 = q * P.qcap + lr * kListRange;
           const int total = (int)std::min<int64_t>(kListRange, s_lcnt[q] - lr * kListRange);
           refill_scan(
               total, P.off, P.cols, use_filt ? nullptr : P.top, fcur, s_step.filt, use_filt, fs,
@@ -736,7 +769,8 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 if (found) P.dp[v] = pack_dp(L + 1, par);
                 wave_set_bits64(fnext, found, v);
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
-                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qcap, P.n_sweep,
+                           ctl);
               });
           continue;
         }
@@ -790,14 +824,15 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                   P.dp[v] = pack_dp(L + 1, par);
                 }
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
-                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qstride, ctl);
+                stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qcap, P.n_sweep,
+                           ctl);
               });
           __builtin_amdgcn_wave_barrier();
           const uint64_t fw = s_st.found[wv][l];
           if (kw < k1 && fw) fnext[kw] = fw;
         }
       }
-      flush_list(s_st, vl_out, vlcnt, P.qstride, ctl);
+      flush_list(s_st, vl_out, vlcnt, P.qcap, P.n_sweep, ctl);
       flush_stage(s_st, P, qn, qpack);
     }
     const int64_t wg_examined = block_fold_add(&ctl->edges[n3][0], examined);
@@ -807,18 +842,30 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
 
     // ---- next level: every workgroup decides the same way.  Sizes of the
     // next frontier's sub-queues (and of the new vertex list's sub-lists)
-    if (threadIdx.x < kNQ) {
-      const unsigned long long pk = __hip_atomic_load(&ctl->qpack[n3][threadIdx.x][0],
+    if (threadIdx.x < kNQT) {
+      const int q = threadIdx.x;
+      const unsigned long long pk = __hip_atomic_load(&ctl->qpack[n3][q][0],
                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      s_qcnt[threadIdx.x] = (long long)(pk >> P.eb);
-      s_qedg[threadIdx.x] = (long long)(pk & emask);
-      if (dir == 1)
-        s_lcnt[threadIdx.x] = (long long)__hip_atomic_load(
-            &ctl->vlcnt[n3][threadIdx.x][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      long long qc_n = (long long)(pk >> P.eb), qe_n = (long long)(pk & emask);
+      if (q < kNQ && qc_n > P.qcap) {
+        // the sub-queue overflowed: it holds its first qcap entries, whose
+        // degree sum ends with the last one's
+        const int64_t last = q * P.qcap + P.qcap - 1;
+        const int32_t v = P.qv[qn][last];
+        qc_n = P.qcap;
+        qe_n = P.qe[qn][last] + (P.off[v + 1] - P.off[v]);
+      }
+      s_qcnt[q] = qc_n;
+      s_qedg[q] = qe_n;
+      if (dir == 1) {
+        const long long lc_n = (long long)__hip_atomic_load(
+            &ctl->vlcnt[n3][q][0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        s_lcnt[q] = (q < kNQ && lc_n > P.qcap) ? P.qcap : lc_n;
+      }
     }
     __syncthreads();
     long long nf_new = 0, mf_new = 0;
-    for (int q = 0; q < kNQ; ++q) {
+    for (int q = 0; q < kNQT; ++q) {
       nf_new += s_qcnt[q];
       mf_new += s_qedg[q];
     }
@@ -835,24 +882,19 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         break;
       }
       case RBFS_DIR_LEARNED: {
-        // every workgroup evaluates the network on identical inputs with the
-        // same fixed-order arithmetic, so all take the same decision
-        __shared__ int s_dec;
+        // every wave of every workgroup evaluates the network on identical
+        // inputs with the same fixed-order arithmetic, so all take the same
+        // decision without a workgroup barrier
         float f[kMlpIn];
         switch_features(f, nf_new, mf_new, mu_new, P.n_sweep - (reached + nf_new), nf, L + 1,
                         dir, P.n_sweep, P.deg_total);
         if (switch_ood(P.sw, f, L + 1)) {
           fallback = 1;
         } else {
-          if (threadIdx.x < kWave) {
-            float y0, y1;
-            mlp_forward_wave(s_mlp, f, y0, y1);
-            if (threadIdx.x == 0)
-              s_dec = (y0 - y1 >= kLearnedMargin) ? 1 : ((y1 - y0 >= kLearnedMargin) ? 0 : -1);
-          }
-          __syncthreads();
-          nd = s_dec;
-          __syncthreads();
+          float y0, y1;
+          mlp_forward_wave(s_mlp, f, y0, y1);
+          const float margin = P.sw[kOffMargin];
+          nd = (y0 - y1 >= margin) ? 1 : ((y1 - y0 >= margin) ? 0 : -1);
           if (nd < 0) fallback = 2;
         }
         if (fallback)
@@ -1035,8 +1077,11 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(rbfs::dev_malloc(&w->dp, sizeof(uint64_t) * ns));
   BFS_CHECK(rbfs::dev_malloc(&w->vis, sizeof(uint64_t) * W));
   BFS_CHECK(rbfs::dev_malloc(&w->front, sizeof(uint64_t) * 3 * W));
-  // every sub-queue and sub-list can hold the whole swept set
-  for (int i = 0; i < 2; ++i) BFS_CHECK(rbfs::dev_malloc(&w->vl[i], sizeof(int32_t) * kNQ * ns));
+  // kNQ sub-queues (sub-lists) of qcap entries each, then the overflow one
+  // of ns: a level appends each vertex at most once, so nothing is lost
+  w->qcap = g->queue_cap > 0 ? g->queue_cap : (ns + 3) / 4 + kStage;
+  const int64_t qlen = kNQ * w->qcap + ns;
+  for (int i = 0; i < 2; ++i) BFS_CHECK(rbfs::dev_malloc(&w->vl[i], sizeof(int32_t) * qlen));
   BFS_CHECK(rbfs::dev_malloc(&w->top, sizeof(int32_t) * ns));
   {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(ns, kBlock), 1 << 16));
@@ -1045,12 +1090,10 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
     BFS_CHECK(hipGetLastError());
   }
   for (int i = 0; i < 2; ++i) {
-    BFS_CHECK(rbfs::dev_malloc(&w->qv[i], sizeof(int32_t) * kNQ * ns));
-    BFS_CHECK(rbfs::dev_malloc(&w->qe[i], sizeof(int64_t) * kNQ * ns));
+    BFS_CHECK(rbfs::dev_malloc(&w->qv[i], sizeof(int32_t) * qlen));
+    BFS_CHECK(rbfs::dev_malloc(&w->qe[i], sizeof(int64_t) * qlen));
   }
-  w->chunk_cap = ceil_div(g->nnz, (int64_t)1 << kMinChunkShift) + 2;
-  for (int i = 0; i < 2; ++i)
-    BFS_CHECK(rbfs::dev_malloc(&w->chunk[i], sizeof(int32_t) * kNQ * w->chunk_cap));
+  // chunk tables for the tuned chunk length (rebuilt if a shorter one is set)
   BFS_CHECK(rbfs::dev_malloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
   // residency of both instantiations: the grid must fit either
@@ -1081,8 +1124,8 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   BFS_CHECK(hipStreamSynchronize(stream));
   w->clean = false;
   g->bytes += sizeof(uint64_t) * (size_t)ns + sizeof(int32_t) * (size_t)ns +
-              (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * kNQ * (size_t)ns +
-              sizeof(uint64_t) * 4 * W + sizeof(int32_t) * 2 * kNQ * w->chunk_cap;
+              (sizeof(int32_t) * 2 + sizeof(int32_t) * 2 + sizeof(int64_t) * 2) * (size_t)qlen +
+              sizeof(uint64_t) * 4 * W;
   return 0;
 }
 
@@ -1099,6 +1142,19 @@ static void tuned_shape(const Graph* g, const BfsWork* w, int* block, int* grid)
 // per workgroup of the tuned grid.  Synchronises `stream` when it builds.
 static int ensure_bfs_parts(Graph* g, hipStream_t stream) {
   BfsWork* w = g->bfs;
+  // chunk tables for chunks of the tuned length: nnz / td_chunk + 2 entries
+  // per sub-queue
+  const int cs = bits_for(g->tune_single.td_chunk);
+  if (!w->chunk[0] || cs < w->chunk_shift) {
+    for (int i = 0; i < 2; ++i) {
+      if (w->chunk[i]) (void)rbfs::dev_free(w->chunk[i]);
+      w->chunk[i] = nullptr;
+    }
+    w->chunk_cap = ceil_div(g->nnz, (int64_t)1 << cs) + 2;
+    for (int i = 0; i < 2; ++i)
+      BFS_CHECK(rbfs::dev_malloc(&w->chunk[i], sizeof(int32_t) * kNQT * w->chunk_cap));
+    w->chunk_shift = cs;
+  }
   int block, grid;
   tuned_shape(g, w, &block, &grid);
   const int grain = g->tune_single.bu_grain;
@@ -1155,7 +1211,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     P.chunk[i] = w->chunk[i];
   }
   P.chunk_cap = w->chunk_cap;
-  P.qstride = g->n_sweep > 0 ? g->n_sweep : 1;
+  P.qcap = w->qcap;
   P.bu_part = w->bu_part;
   P.n_part = w->n_part;
   P.wctr = w->wctr;

@@ -62,6 +62,8 @@ struct BfsWork {
   int64_t* qe[2] = {nullptr, nullptr};
   int32_t* chunk[2] = {nullptr, nullptr};
   int64_t chunk_cap = 0;
+  int chunk_shift = 0;          // log2 of the chunk length the tables are sized for
+  int64_t qcap = 0;             // entries of each sub-queue / sub-list (then the overflow one)
   int32_t* bu_part = nullptr;
   int32_t n_part = 0;
   int32_t part_grain = 0;       // bu_grain the ranges were built for
@@ -171,6 +173,11 @@ struct Graph {
   int multi_refs = 0;
   // relabel batch size of rbfs_rcm_reorder (entries; 0 = automatic)
   int64_t rcm_batch = 0;
+  // relabel with the old columns in host memory: 0 = when the device is short
+  // of memory, 1 = always (with batches), -1 = never
+  int rcm_stage = 0;
+  // single-root search: entries of each frontier sub-queue (0 = automatic)
+  int64_t queue_cap = 0;
 };
 
 // Sticky error text for the calling thread.

@@ -39,6 +39,8 @@
 // sorted position, so the vertices to expand next form a prefix.
 #include <hip/hip_runtime.h>
 
+#include <stdlib.h>
+
 #include <algorithm>
 #include <string>
 #include <vector>
@@ -596,6 +598,73 @@ __global__ void batch_bounds_kernel(const int64_t* newoff, int64_t n, int64_t pe
   }
 }
 
+// Staged relabel (the old columns in host memory): old rows [v0, v1), whose
+// columns st holds from entry e0 on, renamed by perm and copied to their new
+// rows; each row is sorted afterwards.
+__global__ __launch_bounds__(kBlock) void scatter_rows_kernel(const int64_t* off, int64_t v0,
+                                                              int64_t v1, int64_t e0,
+                                                              const int32_t* st,
+                                                              const int32_t* perm,
+                                                              const int64_t* newoff,
+                                                              int32_t* newcols) {
+  const int64_t nw = ceil_div(v1 - v0, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int l = lane_id();
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nw;
+       word += wstride) {
+    const int64_t v = v0 + word * kWave + l;
+    int64_t b = 0, e = 0, dst = 0;
+    if (v < v1) {
+      b = off[v];
+      e = off[v + 1];
+      dst = newoff[perm[v]];
+    }
+    const bool big = (e - b) > kLaneRow;
+    if (!big)
+      for (int64_t j = b; j < e; ++j) newcols[dst + (j - b)] = perm[st[j - e0]];
+    uint64_t hubs = ballot(big);
+    while (hubs) {
+      const int h = ffs64(hubs);
+      hubs &= hubs - 1;
+      const int64_t hb = shfl(b, h), he = shfl(e, h), hd = shfl(dst, h);
+      for (int64_t j = hb + l; j < he; j += kWave) newcols[hd + (j - hb)] = perm[st[j - e0]];
+    }
+  }
+}
+
+// Keys of new rows [k0, k1) already renamed in place: ((k - k0) << bc) |
+// column, at the entry's offset from the batch start.
+__global__ __launch_bounds__(kBlock) void inplace_keys_kernel(const int64_t* newoff, int64_t k0,
+                                                              int64_t k1, int bc,
+                                                              const int32_t* newcols,
+                                                              uint64_t* keys) {
+  const int64_t nw = ceil_div(k1 - k0, kWave);
+  const int64_t wstride = (int64_t)gridDim.x * kWavesPerBlock;
+  const int l = lane_id();
+  const int64_t base = newoff[k0];
+  for (int64_t word = (int64_t)blockIdx.x * kWavesPerBlock + wave_id(); word < nw;
+       word += wstride) {
+    const int64_t k = k0 + word * kWave + l;
+    int64_t b = 0, e = 0;
+    if (k < k1) {
+      b = newoff[k];
+      e = newoff[k + 1];
+    }
+    const uint64_t hi = (uint64_t)(k - k0) << bc;
+    const bool big = (e - b) > kLaneRow;
+    if (!big)
+      for (int64_t j = b; j < e; ++j) keys[j - base] = hi | (uint32_t)newcols[j];
+    uint64_t hubs = ballot(big);
+    while (hubs) {
+      const int h = ffs64(hubs);
+      hubs &= hubs - 1;
+      const int64_t hb = shfl(b, h), he = shfl(e, h);
+      const uint64_t hh = shfl(hi, h);
+      for (int64_t j = hb + l; j < he; j += kWave) keys[j - base] = hh | (uint32_t)newcols[j];
+    }
+  }
+}
+
 // Relabel in batches of about kRelabelBatch entries once the graph has more
 // than kRelabelWholeMax (the whole-graph pair sort needs 16 bytes per entry).
 constexpr int64_t kRelabelWholeMax = (int64_t)1 << 32;
@@ -620,6 +689,14 @@ struct Bufs {
     for (auto& q : ptrs)
       if (q == p) q = nullptr;
   }
+  // frees p now (a buffer of this pass no longer needed)
+  void release(void* p) {
+    for (auto& q : ptrs)
+      if (q == p && q) {
+        (void)rbfs::dev_free(q);
+        q = nullptr;
+      }
+  }
 };
 
 }  // namespace
@@ -632,6 +709,95 @@ struct Bufs {
       return e_ == hipErrorOutOfMemory ? -3 : -4;                                \
     }                                                                           \
   } while (0)
+
+// Staged relabel: the old columns move to host memory (freeing their device
+// copy), the relabelled column array is allocated, and slices of old
+// rows come back one at a time to be renamed and copied to their new rows
+// (sorted by the caller).  On failure after the move the old columns are
+// put back on the device.
+static int stage_relabel(Graph* g, int64_t n, int64_t nnz, const int32_t* perm,
+                         const int64_t* newoff, uint64_t* kbuf, int64_t kcap, Bufs& B,
+                         int32_t** newcols_out, hipStream_t stream) {
+  int32_t* newcols = nullptr;
+  int rc = 0;
+  // ordinary (pageable) host memory: the copies go through the runtime's
+  // own staging buffers, and nothing of this size is pinned
+  int32_t* hcols = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz + kColPad));
+  if (!hcols) {
+    set_error("rcm_reorder: no host memory for the staged relabel");
+    return -3;
+  }
+  hipError_t e = hipStreamSynchronize(stream);
+  auto fail = [&](const char* what, hipError_t err) {
+    set_error(std::string("rcm_reorder (staged relabel): ") + what + ": " +
+              hipGetErrorString(err));
+    return err == hipErrorOutOfMemory ? -3 : -4;
+  };
+  if (e == hipSuccess)
+    e = hipMemcpy(hcols, g->cols, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) {
+    free(hcols);
+    return fail("copy to host", e);
+  }
+  (void)rbfs::dev_free(g->cols);
+  g->cols = nullptr;
+  e = B.alloc(&newcols, nnz + kColPad);
+  // old rows in slices of at most the key buffer's size (it is free now)
+  int32_t* st = (int32_t*)kbuf;
+  const int64_t per = std::max<int64_t>(1, kcap);  // int32 entries in 8 * kcap bytes / 2
+  const int64_t nb = ceil_div(nnz, per);
+  int64_t *kb = nullptr, *eb = nullptr;
+  std::vector<int64_t> hkb, heb;
+  if (e == hipSuccess) e = B.alloc(&kb, nb + 1);
+  if (e == hipSuccess) e = B.alloc(&eb, nb + 1);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(batch_bounds_kernel, dim3(grid_for(nb + 1)), dim3(kBlock), 0, stream,
+                       g->off, n, per, nb, kb, eb);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    hkb.resize(nb + 1);
+    heb.resize(nb + 1);
+    e = hipMemcpyAsync(hkb.data(), kb, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost,
+                       stream);
+  }
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(heb.data(), eb, sizeof(int64_t) * (nb + 1), hipMemcpyDeviceToHost,
+                       stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(stream);
+  for (int64_t i = 0; e == hipSuccess && i < nb; ++i) {
+    const int64_t v0 = hkb[i], v1 = hkb[i + 1], e0 = heb[i], m = heb[i + 1] - heb[i];
+    if (v1 <= v0 || m <= 0) continue;
+    if (m > 2 * kcap) {  // a slice larger than the buffer: a row longer than kcap
+      set_error("rcm_reorder: staged relabel slice larger than its buffer");
+      rc = -1;
+      break;
+    }
+    e = hipMemcpy(st, hcols + e0, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice);
+    if (e != hipSuccess) break;
+    const int64_t nw = ceil_div(v1 - v0, kWave);
+    hipLaunchKernelGGL(scatter_rows_kernel,
+                       dim3((unsigned)std::min<int64_t>(ceil_div(nw, kWavesPerBlock), 1 << 18)),
+                       dim3(kBlock), 0, stream, g->off, v0, v1, e0, st, perm, newoff, newcols);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);  // st is reused
+  }
+  if (e != hipSuccess || rc) {
+    // put the old columns back so that the graph stays usable
+    if (newcols) B.release(newcols);
+    int32_t* back = nullptr;
+    if (rbfs::dev_malloc(&back, sizeof(int32_t) * (size_t)(nnz + kColPad), stream) ==
+            hipSuccess &&
+        hipMemcpy(back, hcols, sizeof(int32_t) * (size_t)(nnz + kColPad),
+                  hipMemcpyHostToDevice) == hipSuccess)
+      g->cols = back;
+    free(hcols);
+    return rc ? rc : fail("slices", e);
+  }
+  free(hcols);
+  *newcols_out = newcols;
+  return 0;
+}
 
 int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_req) {
   const int64_t n = g->n, nnz = g->nnz;
@@ -872,9 +1038,27 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
   RCM_CHECK(hipGetLastError());
   RCM_CHECK(scan_exclusive_i32(newdeg, newoff, n, g->scratch, stream));
   // free what is no longer needed before the big sort
-  (void)hipStreamSynchronize(stream);
+  RCM_CHECK(hipStreamSynchronize(stream));
+  for (void* q : {(void*)deg, (void*)nz, (void*)pos_nz, (void*)vplus, (void*)rank, (void*)ccp,
+                  (void*)csize, (void*)cbase, (void*)cflag, (void*)cpos, (void*)label,
+                  (void*)lbits, (void*)plabel, (void*)nextfree, (void*)front, (void*)next,
+                  (void*)segstart, (void*)tmpdeg, (void*)qe, (void*)chunk_pos, (void*)newdeg,
+                  (void*)pos_rest})
+    B.release(q);
   const int bn = bits_for(n);
-  RCM_CHECK(B.alloc(&newcols, nnz + kColPad));  // slack for aligned group reads
+  // the relabelled columns need nnz more entries next to the old ones; when
+  // the device cannot hold both (the largest graphs), the old columns wait in
+  // pinned host memory and come back a slice of old rows at a time
+  bool staged = false;
+  if (batch > 0) {
+    size_t fr = 0, tot = 0;
+    RCM_CHECK(hipMemGetInfo(&fr, &tot));
+    const size_t need = sizeof(int32_t) * (size_t)(nnz + kColPad) + ((size_t)4 << 30);
+    staged = g->rcm_stage > 0 || (g->rcm_stage == 0 && fr < need);
+  }
+  if (!staged) {
+    RCM_CHECK(B.alloc(&newcols, nnz + kColPad));  // slack for aligned group reads
+  }
   if (batch == 0) {
     hipLaunchKernelGGL(relabel_keys_kernel, dim3(wgrid), dim3(kBlock), 0, stream, g->off,
                        g->cols, n, nnz, perm, newoff, keys, d_status);
@@ -886,6 +1070,12 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
                        nnz, perm, newoff, k1, newcols, d_status);
     RCM_CHECK(hipGetLastError());
   } else {
+    if (staged) {
+      int rc = stage_relabel(g, n, nnz, perm, newoff, keys, kcap, B, &newcols, stream);
+      if (rc) return rc;
+    }
+    // batches of new rows: keys ((k - k0) << bn | new column), sorted, back
+    // into the rows
     const int64_t nb = ceil_div(nnz, batch);
     int64_t *kb = nullptr, *eb = nullptr;
     RCM_CHECK(B.alloc(&kb, nb + 1));
@@ -908,8 +1098,12 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
       }
       const int64_t nw = ceil_div(k1r - k0, kWave);
       const int rgrid = (int)std::min<int64_t>(ceil_div(nw, kWavesPerBlock), 1 << 18);
-      hipLaunchKernelGGL(row_keys_kernel, dim3(rgrid), dim3(kBlock), 0, stream, g->off, g->cols,
-                         iperm, perm, newoff, k0, k1r, bn, keys, kcap, d_status);
+      if (staged)
+        hipLaunchKernelGGL(inplace_keys_kernel, dim3(rgrid), dim3(kBlock), 0, stream, newoff, k0,
+                           k1r, bn, newcols, keys);
+      else
+        hipLaunchKernelGGL(row_keys_kernel, dim3(rgrid), dim3(kBlock), 0, stream, g->off,
+                           g->cols, iperm, perm, newoff, k0, k1r, bn, keys, kcap, d_status);
       RCM_CHECK(hipGetLastError());
       uint64_t* k1 = keys;
       uint64_t* k2 = keys2;
@@ -934,7 +1128,7 @@ int rcm_reorder_impl(Graph* g, hipStream_t stream, float* ms_out, int64_t keep_r
 
   // install: the handle takes ownership of the new CSR and the permutation
   (void)rbfs::dev_free(g->off);
-  (void)rbfs::dev_free(g->cols);
+  if (g->cols) (void)rbfs::dev_free(g->cols);
   g->off = newoff;
   g->cols = newcols;
   g->perm = perm;

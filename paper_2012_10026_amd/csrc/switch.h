@@ -8,6 +8,10 @@
 //                          widened by 10 % of its width, fall back to the
 //                          alpha/beta rule)
 //   max_level              largest level seen in training (as a float)
+//   margin                 the network decides only when its two predictions
+//                          differ by at least this much (ln microseconds);
+//                          closer ones leave the decision to the alpha/beta
+//                          rule
 #pragma once
 #include <math.h>
 #include <stdint.h>
@@ -33,11 +37,8 @@ constexpr int kMlpParams = kOffB3 + kMlpOut;          // 1410
 constexpr int kOffFmin = kMlpParams;
 constexpr int kOffFmax = kOffFmin + kMlpIn;
 constexpr int kOffMaxLevel = kOffFmax + kMlpIn;
-constexpr int kSwitchBlob = kOffMaxLevel + 1;         // 1427
-// The network overrides the alpha/beta rule only when its two predictions
-// differ by at least this much (ln microseconds, about 28 %): closer
-// predictions are within its training error, and the rule decides.
-constexpr float kLearnedMargin = 0.25f;
+constexpr int kOffMargin = kOffMaxLevel + 1;
+constexpr int kSwitchBlob = kOffMargin + 1;           // 1428
 
 RBFS_HD float clampf_(float x, float lo, float hi) { return x < lo ? lo : (x > hi ? hi : x); }
 

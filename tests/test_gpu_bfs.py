@@ -312,7 +312,7 @@ def test_device_tuple_count_matches_host(rb):
 
 @pytest.mark.parametrize("reorder", [False, True], ids=["original", "rcm"])
 def test_without_load_balance_bit_exact(rb, reorder):
-    """The load-balance ablation (OPT_NO_BALANCE: whole rows per thread
+    """The load-balance ablation (OPT_NO_BALANCE: whole rows per wave
     top-down, equal vertex ranges without stealing bottom-up) gives the
     oracle's arrays in every direction mode, and its per-workgroup work
     still adds up to the level counters."""
@@ -417,16 +417,19 @@ def test_graph_csr_export(rb):
     assert np.array_equal(d.cpu().numpy(), d_o) and np.array_equal(p.cpu().numpy(), p_o)
 
 
+@pytest.mark.parametrize("stage", [-1, 1], ids=["device", "host-staged"])
 @pytest.mark.parametrize("batch", [1, 1000, 50000])
-def test_rcm_relabel_in_batches(rb, batch):
+def test_rcm_relabel_in_batches(rb, batch, stage):
     """The relabelled CSR built in batches of new rows (as the largest graphs
-    need) equals the one-sort build and the host reference, for the full and
-    a partial order, and searches on it stay bit-exact."""
+    need), with the old columns on the device or staged in host memory,
+    equals the host reference, for the full and a partial order, and
+    searches on it stay bit-exact."""
     off, cols = graphgen.kronecker_csr(13, 16, 7007)
     perm_o, _, _ = oracle.rcm(off, cols)
     for keep in (None, 3000):
         G = rb.Graph(off, cols)
         G.set_rcm_batch(batch)
+        G.set_rcm_staging(stage)
         perm_t, _ = G.rcm_reorder(keep=keep)
         perm = perm_t.cpu().numpy()
         ref = perm_o if keep is None else oracle.rcm_partial(off, cols, keep)[0]
@@ -440,3 +443,29 @@ def test_rcm_relabel_in_batches(rb, batch):
             d_o, p_o, _ = oracle.bfs(off, cols, r, perm)
             assert np.array_equal(d.cpu().numpy(), d_o)
             assert np.array_equal(p.cpu().numpy(), p_o)
+
+
+@pytest.mark.parametrize("cap", [1, 64, 5000])
+def test_small_subqueues_spill_exactly(rb, cap):
+    """Frontier sub-queues of a few entries (every flush spills into the
+    shared overflow queue): outputs and level counters stay the oracle's in
+    every direction mode, with and without load balancing."""
+    off, cols = kron(14, 12)
+    rng = random.Random(cap)
+    for reorder in (False, True):
+        G = rb.Graph(off, cols)
+        G.set_queue_cap(cap)
+        ell = G.rcm_reorder()[0].cpu().numpy() if reorder else None
+        n_sweep = G.info()["n_plus"] if reorder else G.n
+        for root in graphgen.sample_roots(off, 2, 21):
+            d_o, p_o, _ = oracle.bfs(off, cols, root, ell)
+            c = oracle.level_counters(off, cols, d_o, ell=ell, n_sweep=n_sweep)
+            for mode in MODES:
+                for nb in (False, True):
+                    d, p, st = G.bfs(root, opts=opts_for(rb, mode, rng, no_balance=nb),
+                                     stats=True)
+                    assert np.array_equal(d.cpu().numpy(), d_o), (root, mode, nb)
+                    assert np.array_equal(p.cpu().numpy(), p_o), (root, mode, nb)
+                    assert st["nf"] == [int(x) for x in c["nf"]]
+                    assert st["mf"] == [int(x) for x in c["mf"]]
+        G.check()

@@ -254,6 +254,7 @@ def test_learned_decisions_replay_oracle_random_nets(rb):
         blob[mlp.NPARAMS:mlp.NPARAMS + 8] = -10.0
         blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16] = 10.0
         blob[mlp.NPARAMS + 16] = 64
+        blob[mlp.NPARAMS + 17] = 0.25
         rb.switch_load(blob)
         tally, _ = _replay_learned(rb, G, off, cols, perm, roots, blob)
         for k in total:

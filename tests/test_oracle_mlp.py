@@ -112,7 +112,7 @@ def test_adam_three_steps_closed_form():
 
 # ---- learned direction decision -------------------------------------------
 
-def _blob(b3=(0.0, 0.0), lo=-1.0, hi=1.0, max_level=10):
+def _blob(b3=(0.0, 0.0), lo=-1.0, hi=1.0, max_level=10, margin=0.25):
     """Switch blob of the bias-only network y = b3 with training range
     [lo, hi] for every feature."""
     blob = np.zeros(mlp.BLOB)
@@ -120,6 +120,7 @@ def _blob(b3=(0.0, 0.0), lo=-1.0, hi=1.0, max_level=10):
     blob[mlp.NPARAMS:mlp.NPARAMS + 8] = lo
     blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16] = hi
     blob[mlp.NPARAMS + 16] = max_level
+    blob[mlp.NPARAMS + 17] = margin
     return blob
 
 
@@ -187,6 +188,10 @@ def test_decide_network_and_fallbacks():
     # fp32 the difference may round either way, so both outcomes are allowed
     d, fb, oc = _decide(_blob(b3=(2.25, 2.0)), 0)
     assert (d, fb) == (1, 0) and oc == {(1, 0), (0, 2)}
+    # the margin is the blob's: with 0.1 the 0.2 difference decides, with
+    # 1.5 a difference of 1 does not
+    assert _decide(_blob(b3=(2.2, 2.0), margin=0.1), 0)[:2] == (1, 0)
+    assert _decide(_blob(b3=(3.0, 2.0), margin=1.5), 0)[:2] == (0, 2)
     # out of range: level beyond the training maximum, or a feature outside
     assert _decide(_blob(b3=(3.0, 2.0), max_level=1), 0)[:3] == (0, 1, {(0, 1)})
     assert _decide(_blob(b3=(3.0, 2.0), lo=0.9, hi=1.0), 1)[:3] == (1, 1, {(1, 1)})
