@@ -259,14 +259,21 @@ def train_switch(rb, graphgen):
     # margin on the validation graphs
     t0 = time.perf_counter()
     ratios = {m: [] for m in SWITCH_MARGINS}
+    blobs = {m: rb.make_switch_blob(w, rows, margin=m) for m in SWITCH_MARGINS}
     for spec in SWITCH_VALIDATION_GRAPHS:
         G, roots = switch_graph(rb, graphgen, spec)
         for r in roots[:2]:
             G.bfs(r)
-        t_ab = kernel_ms_sum(rb, G, roots, rb.make_opts())
+        # root by root, alpha/beta and every margin in turn, so that a drift
+        # of the clocks over the run weighs on all of them alike
+        t_ab, t_m = 0.0, {m: 0.0 for m in SWITCH_MARGINS}
+        for r in roots:
+            t_ab += kernel_ms_sum(rb, G, [r], rb.make_opts())
+            for m in SWITCH_MARGINS:
+                rb.switch_load(blobs[m])
+                t_m[m] += kernel_ms_sum(rb, G, [r], rb.make_opts(rb.DIR_LEARNED))
         for m in SWITCH_MARGINS:
-            rb.switch_load(rb.make_switch_blob(w, rows, margin=m))
-            ratios[m].append(kernel_ms_sum(rb, G, roots, rb.make_opts(rb.DIR_LEARNED)) / t_ab)
+            ratios[m].append(t_m[m] / t_ab)
         G.close()
         torch.cuda.empty_cache()
     # the smallest worst ratio; margins within 1.5 % of it (timing noise) are

@@ -45,6 +45,7 @@
 
 #include <algorithm>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/rbfs.h"
@@ -484,14 +485,24 @@ __device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf
   return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
 }
 
-// WGW: record each workgroup's work per level (P.wg_work); a separate
-// instantiation, so the searches that do not ask for it run the kernel
-// without that bookkeeping.
-template <int BLOCK, bool WGW>
+// LDS of the learned direction decision: wave 0's hidden layer and the
+// decision it takes.  The network is read from the switch blob in global
+// memory (5.7 KB, cache resident after the first level): an LDS copy made at
+// kernel start costs the whole kernel registers.
+struct LearnedLds {
+  __align__(16) float h[kMlpHid];
+  int dec[2];
+};
+struct NoLds {};
+
+// WGW: record each workgroup's work per level (P.wg_work); LRN: learned
+// direction decisions (RBFS_DIR_LEARNED).  Separate instantiations, so the
+// searches that ask for neither run the kernel without that code.
+template <int BLOCK, bool WGW, bool LRN>
 __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   constexpr int WAVES = BLOCK / kWave;
   __shared__ StepLds<BLOCK> s_step;
-  __shared__ float s_mlp[kMlpParams];  // learned mode: the network's weights
+  __shared__ std::conditional_t<LRN, LearnedLds, NoLds> s_lrn;
   constexpr int kFiltBits = StepLds<BLOCK>::kFiltWords * 32;
   __shared__ StageLds<WAVES> s_st;
   // sizes of the current frontier's sub-queues and of the last vertex list's
@@ -512,8 +523,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     s_st.lcnt[threadIdx.x] = 0;
   }
   const int64_t dr = root_in ? P.off[root + 1] - P.off[root] : 0;
-  if (P.mode == RBFS_DIR_LEARNED)  // read at every decision: keep them in LDS
-    for (int i = threadIdx.x; i < kMlpParams; i += BLOCK) s_mlp[i] = P.sw[i];
+
   if (threadIdx.x < kNQT) {  // F_0 = {root} sits in sub-queue 0
     s_qcnt[threadIdx.x] = (threadIdx.x == 0 && root_in) ? 1 : 0;
     s_qedg[threadIdx.x] = (threadIdx.x == 0) ? dr : 0;
@@ -863,6 +873,39 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         s_lcnt[q] = (q < kNQ && lc_n > P.qcap) ? P.qcap : lc_n;
       }
     }
+    if constexpr (LRN) if (threadIdx.x < kWave) {
+      // learned mode: wave 0, whose lanes wrote every sub-queue count, takes
+      // the decision alone (the other waves read it after the barrier below).
+      // Every workgroup evaluates the network on identical inputs with the
+      // same fixed-order arithmetic, so all take the same decision.
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      long long nf_w = 0, mf_w = 0;
+      for (int q = 0; q < kNQT; ++q) {
+        nf_w += s_qcnt[q];
+        mf_w += s_qedg[q];
+      }
+      const long long mu_w = mu - mf_w;
+      float f[kMlpIn];
+      switch_features(f, nf_w, mf_w, mu_w, P.n_sweep - (reached + nf_w), nf, L + 1, dir,
+                      P.n_sweep, P.deg_total);
+      int d = -1, fb = 0;  // fallback: 1 out of range, 2 predictions within the margin
+      if (switch_ood(P.sw, f, L + 1)) {
+        fb = 1;
+      } else {
+        float y0, y1;
+        mlp_forward_wave<kMlpHid>(P.sw, P.sw + kOffW2, f, y0, y1, s_lrn.h);
+        const float margin = P.sw[kOffMargin];
+        d = (y0 - y1 >= margin) ? 1 : ((y1 - y0 >= margin) ? 0 : -1);
+        if (d < 0) fb = 2;
+      }
+      if (fb) d = heuristic_dir(dir, nf_w, mf_w, mu_w, nf, P.n_sweep, P.alpha, P.beta);
+      if (threadIdx.x == 0) {
+        s_lrn.dec[0] = d;
+        s_lrn.dec[1] = fb;
+      }
+    }
     __syncthreads();
     long long nf_new = 0, mf_new = 0;
     for (int q = 0; q < kNQT; ++q) {
@@ -881,26 +924,12 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         nd = P.sched[i] ? 1 : 0;
         break;
       }
-      case RBFS_DIR_LEARNED: {
-        // every wave of every workgroup evaluates the network on identical
-        // inputs with the same fixed-order arithmetic, so all take the same
-        // decision without a workgroup barrier
-        float f[kMlpIn];
-        switch_features(f, nf_new, mf_new, mu_new, P.n_sweep - (reached + nf_new), nf, L + 1,
-                        dir, P.n_sweep, P.deg_total);
-        if (switch_ood(P.sw, f, L + 1)) {
-          fallback = 1;
-        } else {
-          float y0, y1;
-          mlp_forward_wave(s_mlp, f, y0, y1);
-          const float margin = P.sw[kOffMargin];
-          nd = (y0 - y1 >= margin) ? 1 : ((y1 - y0 >= margin) ? 0 : -1);
-          if (nd < 0) fallback = 2;
+      case RBFS_DIR_LEARNED:
+        if constexpr (LRN) {
+          nd = s_lrn.dec[0];
+          fallback = s_lrn.dec[1];
         }
-        if (fallback)
-          nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
         break;
-      }
       default:
         nd = heuristic_dir(dir, nf_new, mf_new, mu_new, nf, P.n_sweep, P.alpha, P.beta);
     }
@@ -1043,6 +1072,41 @@ int bfs_wg_work(Graph* g, int64_t* out, int64_t cap, int32_t* levels, int32_t* g
   return 0;
 }
 
+// Resident workgroups per CU that every instantiation of one block size
+// allows (at least 1).
+template <int BLOCK>
+static hipError_t min_per_cu(int* out) {
+  const void* ks[] = {(const void*)bfs_persistent_kernel<BLOCK, false, false>,
+                      (const void*)bfs_persistent_kernel<BLOCK, true, false>,
+                      (const void*)bfs_persistent_kernel<BLOCK, false, true>,
+                      (const void*)bfs_persistent_kernel<BLOCK, true, true>};
+  int m = 1 << 30;
+  for (const void* k : ks) {
+    int c = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, k, BLOCK, 0);
+    if (e != hipSuccess) return e;
+    m = std::min(m, c);
+  }
+  *out = std::max(m, 1);
+  return hipSuccess;
+}
+
+template <int BLOCK>
+static void launch_search(bool wgw, bool lrn, int grid, hipStream_t stream, const BfsParams& P) {
+  if (wgw && lrn)
+    hipLaunchKernelGGL((bfs_persistent_kernel<BLOCK, true, true>), dim3(grid), dim3(BLOCK), 0,
+                       stream, P);
+  else if (wgw)
+    hipLaunchKernelGGL((bfs_persistent_kernel<BLOCK, true, false>), dim3(grid), dim3(BLOCK), 0,
+                       stream, P);
+  else if (lrn)
+    hipLaunchKernelGGL((bfs_persistent_kernel<BLOCK, false, true>), dim3(grid), dim3(BLOCK), 0,
+                       stream, P);
+  else
+    hipLaunchKernelGGL((bfs_persistent_kernel<BLOCK, false, false>), dim3(grid), dim3(BLOCK), 0,
+                       stream, P);
+}
+
 void free_bfs_work(Graph* g) {
   BfsWork* w = g->bfs;
   if (!w) return;
@@ -1096,25 +1160,9 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   // chunk tables for the tuned chunk length (rebuilt if a shorter one is set)
   BFS_CHECK(rbfs::dev_malloc(&w->ctl, sizeof(BfsCtl)));
   BFS_CHECK(hipMemsetAsync(w->ctl, 0, sizeof(BfsCtl), stream));
-  // residency of both instantiations: the grid must fit either
-  int per_cu = 0, per_cu_w = 0;
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                          bfs_persistent_kernel<1024, false>,
-                                                          1024, 0));
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w,
-                                                          bfs_persistent_kernel<1024, true>,
-                                                          1024, 0));
-  per_cu = std::min(per_cu, per_cu_w);
-  if (per_cu < 1) per_cu = 1;
-  w->max_per_cu = per_cu;
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu,
-                                                          bfs_persistent_kernel<256, false>, 256,
-                                                          0));
-  BFS_CHECK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu_w,
-                                                          bfs_persistent_kernel<256, true>, 256,
-                                                          0));
-  per_cu = std::min(per_cu, per_cu_w);
-  w->max_per_cu_256 = per_cu < 1 ? 1 : per_cu;
+  // residency of every instantiation: the grid must fit each
+  BFS_CHECK(min_per_cu<1024>(&w->max_per_cu));
+  BFS_CHECK(min_per_cu<256>(&w->max_per_cu_256));
   w->grid = g->compute_units;
   w->max_grid = 4 * g->compute_units;  // per_cu is at most 4
   BFS_CHECK(rbfs::dev_malloc(&w->wctr, sizeof(unsigned long long) * 3 * 16 * (size_t)w->max_grid));
@@ -1280,17 +1328,11 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     w->wg_grid = grid;
     w->wg_valid = true;
   }
+  const bool lrn = mode == RBFS_DIR_LEARNED;
   if (block == 256)
-    if (P.wg_work)
-      hipLaunchKernelGGL((bfs_persistent_kernel<256, true>), dim3(grid), dim3(256), 0, stream, P);
-    else
-      hipLaunchKernelGGL((bfs_persistent_kernel<256, false>), dim3(grid), dim3(256), 0, stream, P);
+    launch_search<256>(P.wg_work != nullptr, lrn, grid, stream, P);
   else
-    if (P.wg_work)
-      hipLaunchKernelGGL((bfs_persistent_kernel<1024, true>), dim3(grid), dim3(1024), 0, stream, P);
-    else
-      hipLaunchKernelGGL((bfs_persistent_kernel<1024, false>), dim3(grid), dim3(1024), 0, stream,
-                         P);
+    launch_search<1024>(P.wg_work != nullptr, lrn, grid, stream, P);
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));

@@ -32,6 +32,7 @@ const float* switch_blob_device(int device) {
 namespace {
 
 constexpr int kTrainThreads = 256;
+constexpr int kForwardThreads = 256;  // rbfs_mlp_forward: one wave per sample
 constexpr int kSub = 64;  // samples per sub-batch
 constexpr int kSampleW = kMlpIn + kMlpOut;
 constexpr int kParamsPerThread = (kMlpParams + kTrainThreads - 1) / kTrainThreads;
@@ -180,12 +181,13 @@ __global__ __launch_bounds__(kTrainThreads) void mlp_train_kernel(
 }
 
 __global__ void mlp_forward_kernel(const float* w, const float* x, int n, float* y) {
+  __shared__ __align__(16) float s_h[kForwardThreads / kWave][kMlpHid];
   const int i = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   if (i >= n) return;  // whole wave exits together
   float f[kMlpIn];
   for (int k = 0; k < kMlpIn; ++k) f[k] = x[(int64_t)i * kMlpIn + k];
   float y0, y1;
-  mlp_forward_wave(w, f, y0, y1);
+  mlp_forward_wave<kMlpHid>(w, w + kOffW2, f, y0, y1, s_h[threadIdx.x / kWave]);
   if (lane_id() == 0) {
     y[2 * (int64_t)i] = y0;
     y[2 * (int64_t)i + 1] = y1;
@@ -268,9 +270,9 @@ int rbfs_mlp_forward(const float* w, const float* x, int32_t n, float* y) {
   ML_CHECK(B.get(&dy, (size_t)n * rbfs::kMlpOut));
   ML_CHECK(hipMemcpy(dw, w, sizeof(float) * rbfs::kMlpParams, hipMemcpyHostToDevice));
   ML_CHECK(hipMemcpy(dx, x, sizeof(float) * n * rbfs::kMlpIn, hipMemcpyHostToDevice));
-  const int per_block = 4;  // one wave per sample
+  const int per_block = rbfs::kForwardThreads / rbfs::kWave;  // one wave per sample
   hipLaunchKernelGGL(rbfs::mlp_forward_kernel, dim3((n + per_block - 1) / per_block),
-                     dim3(per_block * rbfs::kWave), 0, 0, dw, dx, n, dy);
+                     dim3(rbfs::kForwardThreads), 0, 0, dw, dx, n, dy);
   ML_CHECK(hipGetLastError());
   ML_CHECK(hipMemcpy(y, dy, sizeof(float) * n * rbfs::kMlpOut, hipMemcpyDeviceToHost));
   return RBFS_OK;

@@ -469,3 +469,58 @@ def test_small_subqueues_spill_exactly(rb, cap):
                     assert st["nf"] == [int(x) for x in c["nf"]]
                     assert st["mf"] == [int(x) for x in c["mf"]]
         G.check()
+
+
+def components_graph(seed=11):
+    """Components of different sizes (a random graph spanning several blocks
+    of 4096 original IDs, a path, a star, pairs) and isolated vertices, with
+    labels shuffled so that the components interleave in ID space; n is not
+    a multiple of 4096."""
+    rng = random.Random(seed)
+    edges, base = [], 0
+    big = 9000
+    for u in range(big):
+        for _ in range(3):
+            v = rng.randrange(big)
+            if v != u:
+                edges.append((u, v))
+    base = big
+    edges += [(base + i, base + i + 1) for i in range(59)]
+    base += 60
+    edges += [(base, base + i) for i in range(1, 25)]
+    base += 25
+    for i in range(40):
+        edges.append((base + 2 * i, base + 2 * i + 1))
+    base += 80
+    n = base + 333  # isolated tail
+    relabel = list(range(n))
+    rng.shuffle(relabel)
+    return csr_of(n, [(relabel[a], relabel[b]) for a, b in edges]), relabel
+
+
+def test_output_blocks_across_components(rb):
+    # a search must leave no entry of an earlier search's component behind
+    # (searches in other components, isolated roots, searches with
+    # internal-label outputs in between, both reset modes); n spans several
+    # blocks of 4096 IDs with a ragged tail
+    (off, cols), relabel = components_graph()
+    n = off.shape[0] - 1
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    big, path, star, pair = relabel[5], relabel[9000 + 7], relabel[9060 + 3], relabel[9085]
+    iso = [relabel[n - 1], relabel[n - 200]]
+    seq = [big, path, iso[0], big, star, pair, iso[1], path, big, big, star]
+    internal = rb.make_opts(output_space=rb.OUT_INTERNAL)
+    for reset in (0, 1):
+        t = rb.default_tuning(rb.TUNE_SINGLE)
+        t["reset"] = reset
+        G.set_tuning(t)
+        for i, root in enumerate(seq):
+            if i % 3 == 2:
+                G.bfs(seq[(i + 1) % len(seq)], opts=internal)
+            d, p = G.bfs(root)
+            d_o, p_o, _ = oracle.bfs(off, cols, root, perm_o)
+            assert np.array_equal(d.cpu().numpy(), d_o), (reset, i, root)
+            assert np.array_equal(p.cpu().numpy(), p_o), (reset, i, root)
+    G.set_tuning(rb.default_tuning(rb.TUNE_SINGLE))
