@@ -397,9 +397,9 @@ typedef struct rbfs_tuning {
                         a power of two from 256 to 4 * block (single-root
                         only; batched searches ignore it) */
   int32_t reset;     /* single-root with original-ID outputs: 1 = the output
-                        translation clears the internal entries it reads
-                        (scattered writes), 0 = the next search
-                        re-initialises them in one coalesced pass */
+                        translation sets the internal entries it reads back
+                        to unreached, 0 = the next search re-initialises
+                        them in one coalesced pass */
 } rbfs_tuning_t;
 
 #define RBFS_TUNE_SINGLE 0 /* rbfs_bfs */

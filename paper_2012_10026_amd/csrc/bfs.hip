@@ -110,7 +110,6 @@ struct BfsParams {
   int64_t n_sweep;
   int64_t deg_total;     // degree sum over the swept set
   uint64_t* dp;          // packed (depth << 32 | ~parent) per swept vertex
-  const int32_t* iperm_par;  // non-null: parents become original IDs at the end
   const int32_t* comp_bounds;  // component intervals (null: one interval)
   int64_t n_comp;
   uint64_t* vis;
@@ -953,30 +952,6 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     deg_reached += mf_new;
     ++L;
   }
-  // parents as original IDs for the output translation: labels are final
-  // now, and after RCM a parent's label lies near its child's, so the iperm
-  // reads of a workgroup stay close together
-  if (P.iperm_par) {
-    // eight independent entries per thread and step keep enough loads in
-    // flight (the iperm read depends on the pair read)
-    constexpr int kU = 8;
-    for (int64_t i0 = sweep_lo + gtid; i0 < sweep_hi; i0 += kU * gsz) {
-      uint64_t x[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u) {
-        const int64_t i = i0 + u * gsz;
-        x[u] = (i < sweep_hi) ? P.dp[i] : kUnreached;
-      }
-      int32_t o[kU];
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        o[u] = (x[u] != kUnreached) ? P.iperm_par[dp_parent(x[u])] : 0;
-#pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (x[u] != kUnreached)
-          P.dp[i0 + u * gsz] = (x[u] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)o[u];
-    }
-  }
   if (gtid == 0) {
     ctl->levels = root_in ? L : 1;
     ctl->reached = reached;
@@ -984,24 +959,23 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   }
 }
 
-// Outputs from the packed internal pairs.  Output index v is an original ID
-// when perm is given (one 8-byte gather per vertex; the search has already
-// replaced the parents by original IDs), else an internal label.  Indices past
-// the swept set are unreached, except an isolated root.  With `reset`, reached
-// pairs are set back to unreached, so the next search needs no
-// initialisation pass (scattered 8-byte writes instead of one coalesced pass).
-__global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* perm_root,
-                              int64_t n_sweep, uint64_t* dp, int32_t* depth_o,
-                              int32_t* parent_o, int32_t root_orig, int reset) {
-  const int32_t root_out = (perm || !perm_root) ? root_orig : perm_root[root_orig];
+// Outputs in internal labels (or of a graph that was not relabelled) from the
+// packed pairs: output index v is the label itself.  Indices past the swept
+// set are unreached, except an isolated root (perm_root: original -> internal
+// of a relabelled graph).  With `reset`, reached pairs are set back to
+// unreached, so the next search needs no initialisation pass (scattered
+// 8-byte writes instead of one coalesced pass).
+__global__ void output_kernel(int64_t n, const int32_t* perm_root, int64_t n_sweep, uint64_t* dp,
+                              int32_t* depth_o, int32_t* parent_o, int32_t root_orig,
+                              int reset) {
+  const int32_t root_out = perm_root ? perm_root[root_orig] : root_orig;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = perm ? perm[v] : v;
     int32_t d = -1, p = -1;
-    if (i < n_sweep) {
-      const uint64_t x = dp[i];
+    if (v < n_sweep) {
+      const uint64_t x = dp[v];
       if (x != kUnreached) {
-        if (reset) dp[i] = kUnreached;
+        if (reset) dp[v] = kUnreached;
         d = (int32_t)(x >> 32);
         p = dp_parent(x);
       }
@@ -1012,6 +986,202 @@ __global__ void output_kernel(int64_t n, const int32_t* perm, const int32_t* per
     depth_o[v] = d;
     parent_o[v] = p;
   }
+}
+
+// ---- original-ID outputs of a relabelled graph in three coalesced passes.
+// A random permutation of the 8-byte pairs costs one memory request per
+// vertex as a gather (or scatter); this GPU serves such requests at about
+// 50 G/s whatever the array size, so the vertices are moved in stages whose
+// reads and writes are runs instead:
+//   A: the reached labels of the root's component, read in label order, are
+//      grouped in LDS by bucket (a range of 2^(kOutWin + as) original IDs)
+//      and written as one run per bucket and tile;
+//   B: each bucket's entries are grouped the same way by window (2^kOutWin
+//      original IDs);
+//   C: each window is assembled in LDS (unreached, then its entries) and
+//      written out in original-ID order.
+// Regions: bucket a owns positions [wstart[a << as], wstart[(a + 1) << as])
+// of the pass-A arrays and window w owns [wstart[w], wstart[w + 1]) of the
+// pass-B arrays (wstart: exclusive counts of swept labels per window, the
+// most a search can reach); cnt_a / cnt_w count what a search put there.
+// Pass C clears both counters for the next search.
+constexpr int kOutWin = 13;                 // window: 8192 original IDs
+constexpr int kOutWinSize = 1 << kOutWin;
+constexpr int kOutThreads = 512;
+constexpr int kOutPer = 8;                  // entries per thread and tile
+constexpr int kOutTile = kOutThreads * kOutPer;
+constexpr int kOutMaxKeys = 1024;           // buckets (A) or windows per bucket (B)
+
+struct OutStage {
+  uint64_t v[kOutTile];
+  int32_t o[kOutTile];
+  uint16_t key[kOutTile];
+  int32_t hist[kOutMaxKeys];
+  int32_t scan[kOutMaxKeys];
+  int32_t base[kOutMaxKeys];
+};
+
+// Groups a tile's entries by key in LDS and writes each key's group as one
+// run at dest_of(key) + (reserved slot): every thread holds up to kOutPer
+// entries (value, original ID, key, valid).
+template <class DestOf, class Reserve>
+__device__ __forceinline__ void out_group_write(OutStage& S, int nkeys, const uint64_t* v,
+                                                const int32_t* o, const int* key,
+                                                const bool* ok, uint64_t* dst_v,
+                                                int32_t* dst_o, DestOf&& dest_of,
+                                                Reserve&& reserve) {
+  const int t = threadIdx.x;
+  for (int k = t; k < nkeys; k += kOutThreads) S.hist[k] = 0;
+  __syncthreads();
+  int rank[kOutPer];
+#pragma unroll
+  for (int e = 0; e < kOutPer; ++e) rank[e] = ok[e] ? atomicAdd(&S.hist[key[e]], 1) : 0;
+  __syncthreads();
+  // exclusive scan of the counts (one wave per 64 keys, then the wave totals)
+  if (t < kWave) {
+    int64_t carry = 0;
+    for (int k0 = 0; k0 < nkeys; k0 += kWave) {
+      const int k = k0 + t;
+      const int64_t c = k < nkeys ? S.hist[k] : 0;
+      const int64_t inc = wave_inclusive_sum(c);
+      if (k < nkeys) S.scan[k] = (int32_t)(carry + inc - c);
+      carry += shfl(inc, kWave - 1);
+    }
+  }
+  for (int k = t; k < nkeys; k += kOutThreads)
+    S.base[k] = S.hist[k] > 0 ? reserve(k, S.hist[k]) : 0;
+  __syncthreads();
+  const int total = S.scan[nkeys - 1] + S.hist[nkeys - 1];
+#pragma unroll
+  for (int e = 0; e < kOutPer; ++e)
+    if (ok[e]) {
+      const int slot = S.scan[key[e]] + rank[e];
+      S.v[slot] = v[e];
+      S.o[slot] = o[e];
+      S.key[slot] = (uint16_t)key[e];
+    }
+  __syncthreads();
+  for (int k = t; k < total; k += kOutThreads) {
+    const int kk = S.key[k];
+    const int64_t d = dest_of(kk) + S.base[kk] + (k - S.scan[kk]);
+    dst_v[d] = S.v[k];
+    dst_o[d] = S.o[k];
+  }
+  __syncthreads();
+}
+
+// Pass A: the reached labels of [sweep_lo, sweep_hi), with parents as
+// original IDs, grouped by bucket.
+// With `reset`, the entries read are set back to unreached (the next search
+// then needs no initialisation pass).
+__global__ __launch_bounds__(kOutThreads) void out_pass_a_kernel(
+    const BfsCtl* ctl, uint64_t* dp, const int32_t* iperm, int as, int na,
+    const int64_t* wstart, int32_t* cnt_a, uint64_t* av, int32_t* ao, int reset) {
+  __shared__ OutStage S;
+  const int64_t lo = ctl->sweep_lo, hi = ctl->sweep_hi;
+  const int sh = kOutWin + as;
+  for (int64_t t0 = lo + (int64_t)blockIdx.x * kOutTile; t0 < hi;
+       t0 += (int64_t)gridDim.x * kOutTile) {
+    uint64_t v[kOutPer];
+    int32_t o[kOutPer];
+    int key[kOutPer];
+    bool ok[kOutPer];
+#pragma unroll
+    for (int e = 0; e < kOutPer; ++e) {
+      const int64_t i = t0 + e * kOutThreads + threadIdx.x;
+      const uint64_t x = i < hi ? dp[i] : kUnreached;
+      // the label's original ID is loaded together with its pair
+      const int32_t oi = i < hi ? iperm[i] : 0;
+      ok[e] = x != kUnreached;
+      v[e] = x;
+      o[e] = ok[e] ? oi : 0;
+      if (reset && ok[e]) dp[i] = kUnreached;
+    }
+#pragma unroll
+    for (int e = 0; e < kOutPer; ++e) {
+      key[e] = o[e] >> sh;
+      if (ok[e])
+        v[e] = (v[e] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)iperm[dp_parent(v[e])];
+    }
+    out_group_write(
+        S, na, v, o, key, ok, av, ao, [&](int a) { return wstart[(int64_t)a << as]; },
+        [&](int a, int c) { return atomicAdd(&cnt_a[a], c); });
+  }
+}
+
+// Pass B: chunk c of bucket a (chunks: kOutTile entries of a bucket's
+// region; chunk_start[a] = first chunk of bucket a) grouped by window.
+__global__ __launch_bounds__(kOutThreads) void out_pass_b_kernel(
+    int as, int na, const int64_t* wstart, const int32_t* chunk_start, const int32_t* cnt_a,
+    const uint64_t* av, const int32_t* ao, int32_t* cnt_w, uint64_t* bv, int32_t* bo) {
+  __shared__ OutStage S;
+  // bucket of this chunk: the last a with chunk_start[a] <= blockIdx.x
+  int a = 0, b = na;
+  while (b - a > 1) {
+    const int m = (a + b) >> 1;
+    if (chunk_start[m] <= (int)blockIdx.x) a = m; else b = m;
+  }
+  const int64_t c = (int64_t)blockIdx.x - chunk_start[a];
+  const int64_t r0 = wstart[(int64_t)a << as] + c * kOutTile;
+  const int64_t r1 = std::min<int64_t>(r0 + kOutTile, wstart[(int64_t)a << as] + cnt_a[a]);
+  if (r0 >= r1) return;  // whole workgroup
+  const int64_t w0 = (int64_t)a << as;
+  uint64_t v[kOutPer];
+  int32_t o[kOutPer];
+  int key[kOutPer];
+  bool ok[kOutPer];
+#pragma unroll
+  for (int e = 0; e < kOutPer; ++e) {
+    const int64_t k = r0 + e * kOutThreads + threadIdx.x;
+    ok[e] = k < r1;
+    v[e] = ok[e] ? av[k] : 0ull;
+    o[e] = ok[e] ? ao[k] : 0;
+    key[e] = (int)((o[e] >> kOutWin) - w0);
+  }
+  out_group_write(
+      S, 1 << as, v, o, key, ok, bv, bo, [&](int w) { return wstart[w0 + w]; },
+      [&](int w, int cnt) { return atomicAdd(&cnt_w[w0 + w], cnt); });
+}
+
+// Pass C: window w assembled in LDS and written in original-ID order; an
+// isolated root gets depth 0 and itself as parent.  Clears the counters.
+__global__ __launch_bounds__(kOutThreads) void out_pass_c_kernel(
+    int64_t n, int na, const int64_t* wstart, int32_t* cnt_w, int32_t* cnt_a, const uint64_t* bv,
+    const int32_t* bo, const int32_t* perm, int64_t n_sweep, int32_t root_orig,
+    int32_t* depth_o, int32_t* parent_o) {
+  __shared__ int32_t s_d[kOutWinSize], s_p[kOutWinSize];
+  const int64_t w = blockIdx.x;
+  const int64_t v0 = w << kOutWin;
+  const int len = (int)std::min<int64_t>(kOutWinSize, n - v0);
+  const int64_t rr = perm[root_orig] >= n_sweep ? root_orig - v0 : -1;
+  for (int t = threadIdx.x; t < len; t += kOutThreads) {
+    s_d[t] = t == rr ? 0 : -1;
+    s_p[t] = t == rr ? root_orig : -1;
+  }
+  const int64_t k0 = wstart[w], k1 = k0 + cnt_w[w];
+  __syncthreads();
+  for (int64_t k = k0 + threadIdx.x; k < k1; k += kOutThreads) {
+    const uint64_t x = bv[k];
+    const int t = (int)(bo[k] - v0);
+    s_d[t] = (int32_t)(x >> 32);
+    s_p[t] = dp_parent(x);
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < len; t += kOutThreads) {
+    depth_o[v0 + t] = s_d[t];
+    parent_o[v0 + t] = s_p[t];
+  }
+  if (threadIdx.x == 0) {
+    cnt_w[w] = 0;
+    if (w < na) cnt_a[w] = 0;
+  }
+}
+
+// Layout of the three passes: swept labels per window.
+__global__ void out_hist_kernel(int64_t n_sweep, const int32_t* iperm, int32_t* hist) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_sweep;
+       i += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&hist[iperm[i] >> kOutWin], 1);
 }
 
 // Clears the barrier and status of the previous search; its status is kept
@@ -1112,7 +1282,8 @@ void free_bfs_work(Graph* g) {
   if (!w) return;
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
                 w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1],
-                w->wg_work,  w->top};
+                w->wg_work,  w->top,   w->oav,   w->oao,   w->obv,   w->obo,
+                w->owstart,  w->ocnt_a, w->ocnt_w, w->ochunk};
   for (void* p : ps)
     if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -1177,6 +1348,85 @@ static int ensure_bfs_work(Graph* g, hipStream_t stream) {
   return 0;
 }
 
+// Layout of the three output passes of a relabelled graph: the swept labels
+// per window of original IDs and the pass-B chunks per bucket.  Synchronises
+// `stream`.
+static int ensure_out_layout(Graph* g, hipStream_t stream) {
+  BfsWork* w = g->bfs;
+  if (w->owstart) return 0;
+  const int64_t ns = g->n_sweep;
+  const int64_t nwin = ceil_div(g->n > 0 ? g->n : 1, (int64_t)kOutWinSize);
+  const int as = std::max(0, bits_for(nwin) - 8);
+  const int na = (int)ceil_div(nwin, (int64_t)1 << as);
+  int32_t* hist = nullptr;
+  auto fail = [&](hipError_t e) {
+    (void)hipStreamSynchronize(stream);
+    if (hist) rbfs::dev_free(hist);
+    for (void** q : {(void**)&w->oav, (void**)&w->oao, (void**)&w->obv, (void**)&w->obo,
+                     (void**)&w->owstart, (void**)&w->ocnt_a, (void**)&w->ocnt_w,
+                     (void**)&w->ochunk})
+      if (*q) {
+        rbfs::dev_free(*q);
+        *q = nullptr;
+      }
+    set_error(std::string("bfs: output layout: ") + hipGetErrorString(e));
+    return RBFS_E_DEVICE;
+  };
+  hipError_t e = hipSuccess;
+  const size_t m = (size_t)(ns > 0 ? ns : 1);
+  if ((e = rbfs::dev_malloc(&w->oav, sizeof(uint64_t) * m)) != hipSuccess) return fail(e);
+  if ((e = rbfs::dev_malloc(&w->oao, sizeof(int32_t) * m)) != hipSuccess) return fail(e);
+  if ((e = rbfs::dev_malloc(&w->obv, sizeof(uint64_t) * m)) != hipSuccess) return fail(e);
+  if ((e = rbfs::dev_malloc(&w->obo, sizeof(int32_t) * m)) != hipSuccess) return fail(e);
+  if ((e = rbfs::dev_malloc(&w->owstart, sizeof(int64_t) * (size_t)(nwin + 1))) != hipSuccess)
+    return fail(e);
+  if ((e = rbfs::dev_malloc(&w->ocnt_a, sizeof(int32_t) * (size_t)na)) != hipSuccess)
+    return fail(e);
+  if ((e = rbfs::dev_malloc(&w->ocnt_w, sizeof(int32_t) * (size_t)nwin)) != hipSuccess)
+    return fail(e);
+  if ((e = rbfs::dev_malloc(&w->ochunk, sizeof(int32_t) * (size_t)(na + 1))) != hipSuccess)
+    return fail(e);
+  if ((e = rbfs::dev_malloc(&hist, sizeof(int32_t) * (size_t)nwin)) != hipSuccess) return fail(e);
+  if ((e = hipMemsetAsync(hist, 0, sizeof(int32_t) * (size_t)nwin, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(w->ocnt_a, 0, sizeof(int32_t) * (size_t)na, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(w->ocnt_w, 0, sizeof(int32_t) * (size_t)nwin, stream)) != hipSuccess)
+    return fail(e);
+  if (ns > 0) {
+    const unsigned blocks =
+        (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ns, kBlock), 1 << 16));
+    hipLaunchKernelGGL(out_hist_kernel, dim3(blocks), dim3(kBlock), 0, stream, ns, g->iperm,
+                       hist);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(e);
+  }
+  if ((e = scan_exclusive_i32(hist, w->owstart, nwin, g->scratch, stream)) != hipSuccess)
+    return fail(e);
+  std::vector<int64_t> ws((size_t)nwin + 1);
+  if ((e = hipMemcpyAsync(ws.data(), w->owstart, sizeof(int64_t) * ws.size(),
+                          hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(stream)) != hipSuccess)
+    return fail(e);
+  std::vector<int32_t> chunk((size_t)na + 1);
+  int64_t nc = 0;
+  for (int a = 0; a < na; ++a) {
+    chunk[a] = (int32_t)nc;
+    const int64_t cap = ws[std::min<int64_t>((int64_t)(a + 1) << as, nwin)] - ws[(int64_t)a << as];
+    nc += ceil_div(cap, (int64_t)kOutTile);
+  }
+  chunk[na] = (int32_t)nc;
+  if ((e = hipMemcpyAsync(w->ochunk, chunk.data(), sizeof(int32_t) * chunk.size(),
+                          hipMemcpyHostToDevice, stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(stream)) != hipSuccess)
+    return fail(e);
+  rbfs::dev_free(hist);
+  w->onwin = nwin;
+  w->ona = na;
+  w->oas = as;
+  w->onchunk = (int)nc;
+  g->bytes += (2 * sizeof(uint64_t) + 2 * sizeof(int32_t)) * m +
+              sizeof(int64_t) * (size_t)(nwin + 1) + sizeof(int32_t) * (size_t)(nwin + 2 * na + 1);
+  return 0;
+}
+
 // Launch shape of the graph's single-root tuning, clamped to residency.
 static void tuned_shape(const Graph* g, const BfsWork* w, int* block, int* grid) {
   const rbfs_tuning_t& t = g->tune_single;
@@ -1233,6 +1483,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BfsWork* w = g->bfs;
   const rbfs_tuning_t& tun = g->tune_single;
   const bool translate = g->reordered && out_space == RBFS_OUT_ORIGINAL;
+  if (translate && (rc = ensure_out_layout(g, stream)) != 0) return rc;
   const int bits_n = bits_for(g->n_sweep + 2);
   const int eb = 64 - bits_n;
   if (((uint64_t)g->nnz >> eb) != 0) {
@@ -1246,7 +1497,6 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.n_sweep = g->n_sweep;
   P.deg_total = g->nnz;
   P.dp = w->dp;
-  P.iperm_par = translate ? g->iperm : nullptr;
   P.comp_bounds = g->reordered ? g->comp_bounds : nullptr;
   P.n_comp = g->n_comp;
   P.init = w->clean ? 0 : 1;
@@ -1336,14 +1586,28 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipGetLastError());
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
-  {
+  if (translate) {
+    const unsigned ga = (unsigned)std::max<int64_t>(
+        1, std::min<int64_t>(ceil_div(g->n_sweep, (int64_t)kOutTile), 4096));
+    hipLaunchKernelGGL(out_pass_a_kernel, dim3(ga), dim3(kOutThreads), 0, stream, w->ctl, w->dp,
+                       g->iperm, w->oas, w->ona, w->owstart, w->ocnt_a, w->oav, w->oao,
+                       tun.reset ? 1 : 0);
+    if (w->onchunk > 0)
+      hipLaunchKernelGGL(out_pass_b_kernel, dim3((unsigned)w->onchunk), dim3(kOutThreads), 0,
+                         stream, w->oas, w->ona, w->owstart, w->ochunk, w->ocnt_a, w->oav,
+                         w->oao, w->ocnt_w, w->obv, w->obo);
+    hipLaunchKernelGGL(out_pass_c_kernel, dim3((unsigned)w->onwin), dim3(kOutThreads), 0, stream,
+                       g->n, w->ona, w->owstart, w->ocnt_w, w->ocnt_a, w->obv, w->obo, g->perm,
+                       g->n_sweep, root, depth, parent);
+    BFS_CHECK(hipGetLastError());
+  } else {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));
     hipLaunchKernelGGL(output_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       translate ? g->perm : nullptr, g->reordered ? g->perm : nullptr,
-                       g->n_sweep, w->dp, depth, parent, root, tun.reset ? 1 : 0);
+                       g->reordered ? g->perm : nullptr, g->n_sweep, w->dp, depth, parent, root,
+                       tun.reset ? 1 : 0);
     BFS_CHECK(hipGetLastError());
-    w->clean = tun.reset != 0;
   }
+  w->clean = tun.reset != 0;
   BFS_CHECK(hipEventRecord(w->ev2, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[2], stream));
   if (stats) {

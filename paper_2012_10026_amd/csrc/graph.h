@@ -72,6 +72,19 @@ struct BfsWork {
   int max_grid = 0;
   int32_t* vl[2] = {nullptr, nullptr};  // bottom-up vertex lists (n_sweep each)
   int32_t* top = nullptr;       // largest-label neighbour of each swept vertex
+  // original-ID outputs after RCM (built at the first such search): the
+  // staging arrays of the three output passes and their layout
+  uint64_t* oav = nullptr;      // pass A: pairs grouped by bucket (n_sweep)
+  int32_t* oao = nullptr;       // ... their original IDs
+  uint64_t* obv = nullptr;      // pass B: pairs grouped by window (n_sweep)
+  int32_t* obo = nullptr;
+  int64_t* owstart = nullptr;   // first position of each window (windows + 1)
+  int32_t* ocnt_a = nullptr;    // entries a search put in each bucket
+  int32_t* ocnt_w = nullptr;    // ... in each window
+  int32_t* ochunk = nullptr;    // first pass-B chunk of each bucket (buckets + 1)
+  int64_t onwin = 0;            // windows
+  int ona = 0, oas = 0;         // buckets; windows per bucket = 2^oas
+  int onchunk = 0;              // pass-B chunks
   BfsCtl* ctl = nullptr;
   bool clean = false;           // every pair holds the unreached value
   int grid = 0;                 // persistent grid size
