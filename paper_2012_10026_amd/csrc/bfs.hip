@@ -993,18 +993,19 @@ __global__ void output_kernel(int64_t n, const int32_t* perm_root, int64_t n_swe
 // vertex as a gather (or scatter); this GPU serves such requests at about
 // 50 G/s whatever the array size, so the vertices are moved in stages whose
 // reads and writes are runs instead:
-//   A: the reached labels of the root's component, read in label order, are
+//   A: tile t of the swept labels (kOutTile of them, in label order) is
 //      grouped in LDS by bucket (a range of 2^(kOutWin + as) original IDs)
-//      and written as one run per bucket and tile;
-//   B: each bucket's entries are grouped the same way by window (2^kOutWin
-//      original IDs);
+//      and each group written as one run at its fixed place gA[a][t]
+//      (unreached labels included, marked unreached);
+//   B: each bucket's region is grouped the same way by window (2^kOutWin
+//      original IDs), skipping unreached entries;
 //   C: each window is assembled in LDS (unreached, then its entries) and
 //      written out in original-ID order.
-// Regions: bucket a owns positions [wstart[a << as], wstart[(a + 1) << as])
-// of the pass-A arrays and window w owns [wstart[w], wstart[w + 1]) of the
-// pass-B arrays (wstart: exclusive counts of swept labels per window, the
-// most a search can reach); cnt_a / cnt_w count what a search put there.
-// Pass C clears both counters for the next search.
+// Pass-A places come from the layout (counts of labels per tile and
+// bucket), so no two workgroups contend for a counter; pass B reserves its
+// runs in each window with one atomic per chunk and window.  Window w owns
+// positions [wstart[w], wstart[w + 1]) of the pass-B arrays; cnt_w counts
+// what a search put there, and pass C clears it for the next search.
 constexpr int kOutWin = 13;                 // window: 8192 original IDs
 constexpr int kOutWinSize = 1 << kOutWin;
 constexpr int kOutThreads = 512;
@@ -1070,49 +1071,43 @@ __device__ __forceinline__ void out_group_write(OutStage& S, int nkeys, const ui
   __syncthreads();
 }
 
-// Pass A: the reached labels of [sweep_lo, sweep_hi), with parents as
-// original IDs, grouped by bucket.
-// With `reset`, the entries read are set back to unreached (the next search
+// Pass A: tile blockIdx.x of the swept labels, parents as original IDs.
+// With `reset`, reached entries are set back to unreached (the next search
 // then needs no initialisation pass).
 __global__ __launch_bounds__(kOutThreads) void out_pass_a_kernel(
-    const BfsCtl* ctl, uint64_t* dp, const int32_t* iperm, int as, int na,
-    const int64_t* wstart, int32_t* cnt_a, uint64_t* av, int32_t* ao, int reset) {
+    int64_t n_sweep, int64_t ntiles, uint64_t* dp, const int32_t* iperm, int as, int na,
+    const int64_t* gA, uint64_t* av, int32_t* ao, int reset) {
   __shared__ OutStage S;
-  const int64_t lo = ctl->sweep_lo, hi = ctl->sweep_hi;
+  const int64_t t0 = (int64_t)blockIdx.x * kOutTile;
   const int sh = kOutWin + as;
-  for (int64_t t0 = lo + (int64_t)blockIdx.x * kOutTile; t0 < hi;
-       t0 += (int64_t)gridDim.x * kOutTile) {
-    uint64_t v[kOutPer];
-    int32_t o[kOutPer];
-    int key[kOutPer];
-    bool ok[kOutPer];
+  uint64_t v[kOutPer];
+  int32_t o[kOutPer];
+  int key[kOutPer];
+  bool ok[kOutPer];
 #pragma unroll
-    for (int e = 0; e < kOutPer; ++e) {
-      const int64_t i = t0 + e * kOutThreads + threadIdx.x;
-      const uint64_t x = i < hi ? dp[i] : kUnreached;
-      // the label's original ID is loaded together with its pair
-      const int32_t oi = i < hi ? iperm[i] : 0;
-      ok[e] = x != kUnreached;
-      v[e] = x;
-      o[e] = ok[e] ? oi : 0;
-      if (reset && ok[e]) dp[i] = kUnreached;
-    }
-#pragma unroll
-    for (int e = 0; e < kOutPer; ++e) {
-      key[e] = o[e] >> sh;
-      if (ok[e])
-        v[e] = (v[e] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)iperm[dp_parent(v[e])];
-    }
-    out_group_write(
-        S, na, v, o, key, ok, av, ao, [&](int a) { return wstart[(int64_t)a << as]; },
-        [&](int a, int c) { return atomicAdd(&cnt_a[a], c); });
+  for (int e = 0; e < kOutPer; ++e) {
+    const int64_t i = t0 + e * kOutThreads + threadIdx.x;
+    ok[e] = i < n_sweep;
+    v[e] = ok[e] ? dp[i] : kUnreached;
+    o[e] = ok[e] ? iperm[i] : 0;
+    if (reset && v[e] != kUnreached) dp[i] = kUnreached;
   }
+#pragma unroll
+  for (int e = 0; e < kOutPer; ++e) {
+    key[e] = o[e] >> sh;
+    if (v[e] != kUnreached)
+      v[e] = (v[e] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)iperm[dp_parent(v[e])];
+  }
+  out_group_write(
+      S, na, v, o, key, ok, av, ao,
+      [&](int a) { return gA[(int64_t)a * ntiles + blockIdx.x]; },
+      [&](int, int) { return 0; });
 }
 
 // Pass B: chunk c of bucket a (chunks: kOutTile entries of a bucket's
 // region; chunk_start[a] = first chunk of bucket a) grouped by window.
 __global__ __launch_bounds__(kOutThreads) void out_pass_b_kernel(
-    int as, int na, const int64_t* wstart, const int32_t* chunk_start, const int32_t* cnt_a,
+    int64_t nwin, int as, int na, const int64_t* wstart, const int32_t* chunk_start,
     const uint64_t* av, const int32_t* ao, int32_t* cnt_w, uint64_t* bv, int32_t* bo) {
   __shared__ OutStage S;
   // bucket of this chunk: the last a with chunk_start[a] <= blockIdx.x
@@ -1121,11 +1116,10 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_b_kernel(
     const int m = (a + b) >> 1;
     if (chunk_start[m] <= (int)blockIdx.x) a = m; else b = m;
   }
-  const int64_t c = (int64_t)blockIdx.x - chunk_start[a];
-  const int64_t r0 = wstart[(int64_t)a << as] + c * kOutTile;
-  const int64_t r1 = std::min<int64_t>(r0 + kOutTile, wstart[(int64_t)a << as] + cnt_a[a]);
-  if (r0 >= r1) return;  // whole workgroup
   const int64_t w0 = (int64_t)a << as;
+  const int64_t c = (int64_t)blockIdx.x - chunk_start[a];
+  const int64_t r0 = wstart[w0] + c * kOutTile;
+  const int64_t r1 = std::min<int64_t>(r0 + kOutTile, wstart[std::min(w0 + (1 << as), nwin)]);
   uint64_t v[kOutPer];
   int32_t o[kOutPer];
   int key[kOutPer];
@@ -1133,9 +1127,9 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_b_kernel(
 #pragma unroll
   for (int e = 0; e < kOutPer; ++e) {
     const int64_t k = r0 + e * kOutThreads + threadIdx.x;
-    ok[e] = k < r1;
-    v[e] = ok[e] ? av[k] : 0ull;
-    o[e] = ok[e] ? ao[k] : 0;
+    v[e] = k < r1 ? av[k] : kUnreached;
+    o[e] = k < r1 ? ao[k] : 0;
+    ok[e] = v[e] != kUnreached;
     key[e] = (int)((o[e] >> kOutWin) - w0);
   }
   out_group_write(
@@ -1146,7 +1140,7 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_b_kernel(
 // Pass C: window w assembled in LDS and written in original-ID order; an
 // isolated root gets depth 0 and itself as parent.  Clears the counters.
 __global__ __launch_bounds__(kOutThreads) void out_pass_c_kernel(
-    int64_t n, int na, const int64_t* wstart, int32_t* cnt_w, int32_t* cnt_a, const uint64_t* bv,
+    int64_t n, const int64_t* wstart, int32_t* cnt_w, const uint64_t* bv,
     const int32_t* bo, const int32_t* perm, int64_t n_sweep, int32_t root_orig,
     int32_t* depth_o, int32_t* parent_o) {
   __shared__ int32_t s_d[kOutWinSize], s_p[kOutWinSize];
@@ -1171,17 +1165,19 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_c_kernel(
     depth_o[v0 + t] = s_d[t];
     parent_o[v0 + t] = s_p[t];
   }
-  if (threadIdx.x == 0) {
-    cnt_w[w] = 0;
-    if (w < na) cnt_a[w] = 0;
-  }
+  if (threadIdx.x == 0) cnt_w[w] = 0;
 }
 
-// Layout of the three passes: swept labels per window.
-__global__ void out_hist_kernel(int64_t n_sweep, const int32_t* iperm, int32_t* hist) {
+// Layout of the three passes: swept labels per window, and per bucket and
+// pass-A tile (bucket-major).
+__global__ void out_hist_kernel(int64_t n_sweep, const int32_t* iperm, int as, int64_t ntiles,
+                                int32_t* hist_w, int32_t* hist_at) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_sweep;
-       i += (int64_t)gridDim.x * blockDim.x)
-    atomicAdd(&hist[iperm[i] >> kOutWin], 1);
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t w = iperm[i] >> kOutWin;
+    atomicAdd(&hist_w[w], 1);
+    atomicAdd(&hist_at[(int64_t)(w >> as) * ntiles + i / kOutTile], 1);
+  }
 }
 
 // Clears the barrier and status of the previous search; its status is kept
@@ -1283,7 +1279,7 @@ void free_bfs_work(Graph* g) {
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
                 w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1],
                 w->wg_work,  w->top,   w->oav,   w->oao,   w->obv,   w->obo,
-                w->owstart,  w->ocnt_a, w->ocnt_w, w->ochunk};
+                w->owstart,  w->ogA,    w->ocnt_w, w->ochunk};
   for (void* p : ps)
     if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -1358,12 +1354,15 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
   const int64_t nwin = ceil_div(g->n > 0 ? g->n : 1, (int64_t)kOutWinSize);
   const int as = std::max(0, bits_for(nwin) - 8);
   const int na = (int)ceil_div(nwin, (int64_t)1 << as);
-  int32_t* hist = nullptr;
+  const int64_t ntiles = ceil_div(ns, (int64_t)kOutTile);
+  const int64_t nat = (int64_t)na * ntiles;
+  int32_t *hist_w = nullptr, *hist_at = nullptr;
   auto fail = [&](hipError_t e) {
     (void)hipStreamSynchronize(stream);
-    if (hist) rbfs::dev_free(hist);
+    if (hist_w) rbfs::dev_free(hist_w);
+    if (hist_at) rbfs::dev_free(hist_at);
     for (void** q : {(void**)&w->oav, (void**)&w->oao, (void**)&w->obv, (void**)&w->obo,
-                     (void**)&w->owstart, (void**)&w->ocnt_a, (void**)&w->ocnt_w,
+                     (void**)&w->owstart, (void**)&w->ogA, (void**)&w->ocnt_w,
                      (void**)&w->ochunk})
       if (*q) {
         rbfs::dev_free(*q);
@@ -1380,25 +1379,33 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
   if ((e = rbfs::dev_malloc(&w->obo, sizeof(int32_t) * m)) != hipSuccess) return fail(e);
   if ((e = rbfs::dev_malloc(&w->owstart, sizeof(int64_t) * (size_t)(nwin + 1))) != hipSuccess)
     return fail(e);
-  if ((e = rbfs::dev_malloc(&w->ocnt_a, sizeof(int32_t) * (size_t)na)) != hipSuccess)
+  if ((e = rbfs::dev_malloc(&w->ogA, sizeof(int64_t) * (size_t)(nat + 1))) != hipSuccess)
     return fail(e);
   if ((e = rbfs::dev_malloc(&w->ocnt_w, sizeof(int32_t) * (size_t)nwin)) != hipSuccess)
     return fail(e);
   if ((e = rbfs::dev_malloc(&w->ochunk, sizeof(int32_t) * (size_t)(na + 1))) != hipSuccess)
     return fail(e);
-  if ((e = rbfs::dev_malloc(&hist, sizeof(int32_t) * (size_t)nwin)) != hipSuccess) return fail(e);
-  if ((e = hipMemsetAsync(hist, 0, sizeof(int32_t) * (size_t)nwin, stream)) != hipSuccess ||
-      (e = hipMemsetAsync(w->ocnt_a, 0, sizeof(int32_t) * (size_t)na, stream)) != hipSuccess ||
+  if ((e = rbfs::dev_malloc(&hist_w, sizeof(int32_t) * (size_t)nwin)) != hipSuccess)
+    return fail(e);
+  if ((e = rbfs::dev_malloc(&hist_at, sizeof(int32_t) * (size_t)std::max<int64_t>(nat, 1))) !=
+      hipSuccess)
+    return fail(e);
+  if ((e = hipMemsetAsync(hist_w, 0, sizeof(int32_t) * (size_t)nwin, stream)) != hipSuccess ||
+      (e = hipMemsetAsync(hist_at, 0, sizeof(int32_t) * (size_t)std::max<int64_t>(nat, 1),
+                          stream)) != hipSuccess ||
       (e = hipMemsetAsync(w->ocnt_w, 0, sizeof(int32_t) * (size_t)nwin, stream)) != hipSuccess)
     return fail(e);
   if (ns > 0) {
     const unsigned blocks =
         (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(ns, kBlock), 1 << 16));
-    hipLaunchKernelGGL(out_hist_kernel, dim3(blocks), dim3(kBlock), 0, stream, ns, g->iperm,
-                       hist);
+    hipLaunchKernelGGL(out_hist_kernel, dim3(blocks), dim3(kBlock), 0, stream, ns, g->iperm, as,
+                       ntiles, hist_w, hist_at);
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   }
-  if ((e = scan_exclusive_i32(hist, w->owstart, nwin, g->scratch, stream)) != hipSuccess)
+  // (the second scan may regrow the scratch the first one uses: wait between)
+  if ((e = scan_exclusive_i32(hist_w, w->owstart, nwin, g->scratch, stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(stream)) != hipSuccess ||
+      (e = scan_exclusive_i32(hist_at, w->ogA, nat, g->scratch, stream)) != hipSuccess)
     return fail(e);
   std::vector<int64_t> ws((size_t)nwin + 1);
   if ((e = hipMemcpyAsync(ws.data(), w->owstart, sizeof(int64_t) * ws.size(),
@@ -1417,13 +1424,15 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
                           hipMemcpyHostToDevice, stream)) != hipSuccess ||
       (e = hipStreamSynchronize(stream)) != hipSuccess)
     return fail(e);
-  rbfs::dev_free(hist);
+  rbfs::dev_free(hist_w);
+  rbfs::dev_free(hist_at);
   w->onwin = nwin;
   w->ona = na;
   w->oas = as;
+  w->ontiles = ntiles;
   w->onchunk = (int)nc;
   g->bytes += (2 * sizeof(uint64_t) + 2 * sizeof(int32_t)) * m +
-              sizeof(int64_t) * (size_t)(nwin + 1) + sizeof(int32_t) * (size_t)(nwin + 2 * na + 1);
+              sizeof(int64_t) * (size_t)(nwin + nat + 2) + sizeof(int32_t) * (size_t)(nwin + na + 1);
   return 0;
 }
 
@@ -1587,18 +1596,17 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   BFS_CHECK(hipEventRecord(w->ev1, stream));
   if (tev) BFS_CHECK(hipEventRecord(tev[1], stream));
   if (translate) {
-    const unsigned ga = (unsigned)std::max<int64_t>(
-        1, std::min<int64_t>(ceil_div(g->n_sweep, (int64_t)kOutTile), 4096));
-    hipLaunchKernelGGL(out_pass_a_kernel, dim3(ga), dim3(kOutThreads), 0, stream, w->ctl, w->dp,
-                       g->iperm, w->oas, w->ona, w->owstart, w->ocnt_a, w->oav, w->oao,
-                       tun.reset ? 1 : 0);
+    if (w->ontiles > 0)
+      hipLaunchKernelGGL(out_pass_a_kernel, dim3((unsigned)w->ontiles), dim3(kOutThreads), 0,
+                         stream, g->n_sweep, w->ontiles, w->dp, g->iperm, w->oas, w->ona, w->ogA,
+                         w->oav, w->oao, tun.reset ? 1 : 0);
     if (w->onchunk > 0)
       hipLaunchKernelGGL(out_pass_b_kernel, dim3((unsigned)w->onchunk), dim3(kOutThreads), 0,
-                         stream, w->oas, w->ona, w->owstart, w->ochunk, w->ocnt_a, w->oav,
-                         w->oao, w->ocnt_w, w->obv, w->obo);
+                         stream, w->onwin, w->oas, w->ona, w->owstart, w->ochunk, w->oav, w->oao,
+                         w->ocnt_w, w->obv, w->obo);
     hipLaunchKernelGGL(out_pass_c_kernel, dim3((unsigned)w->onwin), dim3(kOutThreads), 0, stream,
-                       g->n, w->ona, w->owstart, w->ocnt_w, w->ocnt_a, w->obv, w->obo, g->perm,
-                       g->n_sweep, root, depth, parent);
+                       g->n, w->owstart, w->ocnt_w, w->obv, w->obo, g->perm, g->n_sweep, root,
+                       depth, parent);
     BFS_CHECK(hipGetLastError());
   } else {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));
