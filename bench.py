@@ -493,7 +493,7 @@ def chung_lu_leg(rb, graphgen, args, cache, blob):
         per_l, _ = time_roots(G, roots, depth, parent, learned, args.steps)
         gl = hmean_gteps(m_c, per_l)
         out["learned"] = {"value": gl, "unit": "GTEPS", "vs_plain": gl / gp,
-                          "network": "trained on Kronecker scales 18-24, not retrained",
+                          "network": "the one trained in this run (Kronecker scales 18-24 and Chung-Lu graphs of 0.3-3M vertices), not retrained for this graph",
                           "certified_roots": certify_roots(G, roots, depth, parent, learned)}
         log("# chung-lu: learned %.1f GTEPS (%.3fx plain)" % (gl, gl / gp))
     if not args.no_batch:
