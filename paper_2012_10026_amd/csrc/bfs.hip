@@ -1017,9 +1017,9 @@ struct OutStage {
   uint64_t v[kOutTile];
   int32_t o[kOutTile];
   uint16_t key[kOutTile];
+  int64_t start[kOutMaxKeys];  // where each key's run goes
   int32_t hist[kOutMaxKeys];
   int32_t scan[kOutMaxKeys];
-  int32_t base[kOutMaxKeys];
 };
 
 // Groups a tile's entries by key in LDS and writes each key's group as one
@@ -1049,8 +1049,9 @@ __device__ __forceinline__ void out_group_write(OutStage& S, int nkeys, const ui
       carry += shfl(inc, kWave - 1);
     }
   }
+  // each key's run start, read once per tile
   for (int k = t; k < nkeys; k += kOutThreads)
-    S.base[k] = S.hist[k] > 0 ? reserve(k, S.hist[k]) : 0;
+    if (S.hist[k] > 0) S.start[k] = dest_of(k) + reserve(k, S.hist[k]);
   __syncthreads();
   const int total = S.scan[nkeys - 1] + S.hist[nkeys - 1];
 #pragma unroll
@@ -1064,7 +1065,7 @@ __device__ __forceinline__ void out_group_write(OutStage& S, int nkeys, const ui
   __syncthreads();
   for (int k = t; k < total; k += kOutThreads) {
     const int kk = S.key[k];
-    const int64_t d = dest_of(kk) + S.base[kk] + (k - S.scan[kk]);
+    const int64_t d = S.start[kk] + (k - S.scan[kk]);
     dst_v[d] = S.v[k];
     dst_o[d] = S.o[k];
   }
@@ -1100,7 +1101,7 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_a_kernel(
   }
   out_group_write(
       S, na, v, o, key, ok, av, ao,
-      [&](int a) { return gA[(int64_t)a * ntiles + blockIdx.x]; },
+      [&](int a) { return gA[(int64_t)blockIdx.x * na + a]; },
       [&](int, int) { return 0; });
 }
 
@@ -1169,7 +1170,17 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_c_kernel(
 }
 
 // Layout of the three passes: swept labels per window, and per bucket and
-// pass-A tile (bucket-major).
+// pass-A tile (bucket-major, for the scan that places the runs).
+// Run places per (bucket, tile), bucket-major, to tile-major: a pass-A tile
+// then reads its bucket places from one contiguous block.
+__global__ void out_transpose_kernel(int64_t na, int64_t ntiles, const int64_t* in, int64_t* out) {
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < na * ntiles;
+       j += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = j / na, a = j - t * na;
+    out[j] = in[a * ntiles + t];
+  }
+}
+
 __global__ void out_hist_kernel(int64_t n_sweep, const int32_t* iperm, int as, int64_t ntiles,
                                 int32_t* hist_w, int32_t* hist_at) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_sweep;
@@ -1403,10 +1414,23 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
     if ((e = hipGetLastError()) != hipSuccess) return fail(e);
   }
   // (the second scan may regrow the scratch the first one uses: wait between)
-  if ((e = scan_exclusive_i32(hist_w, w->owstart, nwin, g->scratch, stream)) != hipSuccess ||
-      (e = hipStreamSynchronize(stream)) != hipSuccess ||
-      (e = scan_exclusive_i32(hist_at, w->ogA, nat, g->scratch, stream)) != hipSuccess)
-    return fail(e);
+  {
+    int64_t* tmp = nullptr;
+    if ((e = rbfs::dev_malloc(&tmp, sizeof(int64_t) * (size_t)(nat + 1))) != hipSuccess)
+      return fail(e);
+    if ((e = scan_exclusive_i32(hist_w, w->owstart, nwin, g->scratch, stream)) == hipSuccess &&
+        (e = hipStreamSynchronize(stream)) == hipSuccess &&
+        (e = scan_exclusive_i32(hist_at, tmp, nat, g->scratch, stream)) == hipSuccess && nat > 0) {
+      const unsigned blocks =
+          (unsigned)std::max<int64_t>(1, std::min<int64_t>(ceil_div(nat, kBlock), 1 << 16));
+      hipLaunchKernelGGL(out_transpose_kernel, dim3(blocks), dim3(kBlock), 0, stream,
+                         (int64_t)na, ntiles, tmp, w->ogA);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    rbfs::dev_free(tmp);
+    if (e != hipSuccess) return fail(e);
+  }
   std::vector<int64_t> ws((size_t)nwin + 1);
   if ((e = hipMemcpyAsync(ws.data(), w->owstart, sizeof(int64_t) * ws.size(),
                           hipMemcpyDeviceToHost, stream)) != hipSuccess ||

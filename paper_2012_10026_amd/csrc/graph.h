@@ -79,7 +79,7 @@ struct BfsWork {
   uint64_t* obv = nullptr;      // pass B: pairs grouped by window (n_sweep)
   int32_t* obo = nullptr;
   int64_t* owstart = nullptr;   // first position of each window (windows + 1)
-  int64_t* ogA = nullptr;       // pass-A run of each (bucket, tile), bucket-major
+  int64_t* ogA = nullptr;       // pass-A run of each (tile, bucket), tile-major
   int64_t ontiles = 0;          // pass-A tiles
   int32_t* ocnt_w = nullptr;    // ... in each window
   int32_t* ochunk = nullptr;    // first pass-B chunk of each bucket (buckets + 1)
