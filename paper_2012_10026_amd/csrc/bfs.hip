@@ -1289,8 +1289,7 @@ void free_bfs_work(Graph* g) {
   if (!w) return;
   void* ps[] = {w->dp,       w->vis,      w->front,   w->qv[0], w->qv[1], w->qe[0], w->qe[1],
                 w->chunk[0], w->chunk[1], w->bu_part, w->ctl,   w->wctr,  w->vl[0], w->vl[1],
-                w->wg_work,  w->top,   w->oav,   w->oao,   w->obv,   w->obo,
-                w->owstart,  w->ogA,    w->ocnt_w, w->ochunk};
+                w->wg_work,  w->top,   w->owstart, w->ogA, w->ocnt_w, w->ochunk};
   for (void* p : ps)
     if (p) (void)rbfs::dev_free(p);
   if (w->ev0) (void)hipEventDestroy(w->ev0);
@@ -1372,9 +1371,7 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
     (void)hipStreamSynchronize(stream);
     if (hist_w) rbfs::dev_free(hist_w);
     if (hist_at) rbfs::dev_free(hist_at);
-    for (void** q : {(void**)&w->oav, (void**)&w->oao, (void**)&w->obv, (void**)&w->obo,
-                     (void**)&w->owstart, (void**)&w->ogA, (void**)&w->ocnt_w,
-                     (void**)&w->ochunk})
+    for (void** q : {(void**)&w->owstart, (void**)&w->ogA, (void**)&w->ocnt_w, (void**)&w->ochunk})
       if (*q) {
         rbfs::dev_free(*q);
         *q = nullptr;
@@ -1383,11 +1380,6 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
     return RBFS_E_DEVICE;
   };
   hipError_t e = hipSuccess;
-  const size_t m = (size_t)(ns > 0 ? ns : 1);
-  if ((e = rbfs::dev_malloc(&w->oav, sizeof(uint64_t) * m)) != hipSuccess) return fail(e);
-  if ((e = rbfs::dev_malloc(&w->oao, sizeof(int32_t) * m)) != hipSuccess) return fail(e);
-  if ((e = rbfs::dev_malloc(&w->obv, sizeof(uint64_t) * m)) != hipSuccess) return fail(e);
-  if ((e = rbfs::dev_malloc(&w->obo, sizeof(int32_t) * m)) != hipSuccess) return fail(e);
   if ((e = rbfs::dev_malloc(&w->owstart, sizeof(int64_t) * (size_t)(nwin + 1))) != hipSuccess)
     return fail(e);
   if ((e = rbfs::dev_malloc(&w->ogA, sizeof(int64_t) * (size_t)(nat + 1))) != hipSuccess)
@@ -1455,8 +1447,7 @@ static int ensure_out_layout(Graph* g, hipStream_t stream) {
   w->oas = as;
   w->ontiles = ntiles;
   w->onchunk = (int)nc;
-  g->bytes += (2 * sizeof(uint64_t) + 2 * sizeof(int32_t)) * m +
-              sizeof(int64_t) * (size_t)(nwin + nat + 2) + sizeof(int32_t) * (size_t)(nwin + na + 1);
+  g->bytes += sizeof(int64_t) * (size_t)(nwin + nat + 2) + sizeof(int32_t) * (size_t)(nwin + na + 1);
   return 0;
 }
 
@@ -1623,14 +1614,15 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     if (w->ontiles > 0)
       hipLaunchKernelGGL(out_pass_a_kernel, dim3((unsigned)w->ontiles), dim3(kOutThreads), 0,
                          stream, g->n_sweep, w->ontiles, w->dp, g->iperm, w->oas, w->ona, w->ogA,
-                         w->oav, w->oao, tun.reset ? 1 : 0);
+                         (uint64_t*)w->qe[0], w->qv[0], tun.reset ? 1 : 0);
     if (w->onchunk > 0)
       hipLaunchKernelGGL(out_pass_b_kernel, dim3((unsigned)w->onchunk), dim3(kOutThreads), 0,
-                         stream, w->onwin, w->oas, w->ona, w->owstart, w->ochunk, w->oav, w->oao,
-                         w->ocnt_w, w->obv, w->obo);
+                         stream, w->onwin, w->oas, w->ona, w->owstart, w->ochunk,
+                         (const uint64_t*)w->qe[0], w->qv[0], w->ocnt_w, (uint64_t*)w->qe[1],
+                         w->qv[1]);
     hipLaunchKernelGGL(out_pass_c_kernel, dim3((unsigned)w->onwin), dim3(kOutThreads), 0, stream,
-                       g->n, w->owstart, w->ocnt_w, w->obv, w->obo, g->perm, g->n_sweep, root,
-                       depth, parent);
+                       g->n, w->owstart, w->ocnt_w, (const uint64_t*)w->qe[1], w->qv[1], g->perm,
+                       g->n_sweep, root, depth, parent);
     BFS_CHECK(hipGetLastError());
   } else {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));

@@ -73,11 +73,9 @@ struct BfsWork {
   int32_t* vl[2] = {nullptr, nullptr};  // bottom-up vertex lists (n_sweep each)
   int32_t* top = nullptr;       // largest-label neighbour of each swept vertex
   // original-ID outputs after RCM (built at the first such search): the
-  // staging arrays of the three output passes and their layout
-  uint64_t* oav = nullptr;      // pass A: pairs grouped by bucket (n_sweep)
-  int32_t* oao = nullptr;       // ... their original IDs
-  uint64_t* obv = nullptr;      // pass B: pairs grouped by window (n_sweep)
-  int32_t* obo = nullptr;
+  // layout of the three output passes, whose staging arrays are the frontier
+  // queues (idle once the search kernel has finished): pass A writes pairs
+  // to qe[0] and original IDs to qv[0], pass B to qe[1] and qv[1]
   int64_t* owstart = nullptr;   // first position of each window (windows + 1)
   int64_t* ogA = nullptr;       // pass-A run of each (tile, bucket), tile-major
   int64_t ontiles = 0;          // pass-A tiles
