@@ -95,11 +95,20 @@ constexpr int kScanStep = 8;    // row entries a lane tests per step (after the 
 static_assert(kScanStep == 8, "the row scan loads two aligned groups of 4 entries");
 constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
 
-// Packed search state of a vertex: the depth in the high half and the
+// Packed search state of a vertex: the depth field in the high half and the
 // bitwise complement of the parent in the low half, so that the smallest
 // word has the smallest depth and, within it, the largest parent label.
-__device__ __forceinline__ uint64_t pack_dp(int32_t d, int32_t p) {
-  return ((uint64_t)(uint32_t)d << 32) | (uint32_t)~(uint32_t)p;
+// The depth field is base + depth, with a base that each search lowers by
+// at least n_sweep + 1: every word left by an earlier search then compares
+// above every word of this one, as an unreached word does, so a search needs
+// no initialisation pass until the base runs out.
+__device__ __forceinline__ uint64_t pack_dp(uint32_t dfield, int32_t p) {
+  return ((uint64_t)dfield << 32) | (uint32_t)~(uint32_t)p;
+}
+// True when word x was written by the search whose base is `base` (n_sweep
+// bounds its depths).
+__device__ __forceinline__ bool dp_current(uint64_t x, uint32_t base, int64_t n_sweep) {
+  return (uint64_t)(uint32_t)((uint32_t)(x >> 32) - base) <= (uint64_t)n_sweep;
 }
 __device__ __forceinline__ int32_t dp_parent(uint64_t x) { return (int32_t)~(uint32_t)x; }
 
@@ -132,6 +141,7 @@ struct BfsParams {
   int32_t no_lb;
   int32_t root_orig;
   int32_t init;
+  uint32_t base;         // depth field of depth 0 (see pack_dp)
   int32_t mode;
   int32_t alpha, beta;
   int32_t sched_len;
@@ -532,7 +542,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
   // ---- initialisation
   if (P.init) {
     for (int64_t i = gtid; i < P.n_sweep; i += gsz)
-      P.dp[i] = (i == root) ? pack_dp(0, root) : kUnreached;
+      P.dp[i] = (i == root) ? pack_dp(P.base, root) : kUnreached;
   }
   for (int64_t w = gtid; w < W; w += gsz) {
     P.vis[w] = 0ull;
@@ -540,7 +550,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
     P.front[1][w] = 0ull;
   }
   if (gtid == 0) {
-    if (!P.init && root_in) P.dp[root] = pack_dp(0, root);
+    if (!P.init && root_in) P.dp[root] = pack_dp(P.base, root);
     for (int r = 0; r < 2; ++r) {
       for (int q = 0; q < kNQT; ++q) {
         ctl->qpack[r][q][0] = 0ull;
@@ -635,10 +645,12 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           bool claim = false;
           int64_t dw = 0;
           if (act && !(((P.vis[w >> 6] | fcur[w >> 6]) >> (w & 63)) & 1ull)) {
-            const uint64_t prop = pack_dp(L + 1, u);
+            const uint64_t prop = pack_dp(P.base + (uint32_t)(L + 1), u);
+            // a claim: the word held was not written by this search
             if (P.dp[w] > prop)
-              claim = atomicMin((unsigned long long*)&P.dp[w], (unsigned long long)prop) ==
-                      kUnreached;
+              claim = (uint32_t)(atomicMin((unsigned long long*)&P.dp[w],
+                                           (unsigned long long)prop) >> 32) >
+                      P.base + (uint32_t)(L + 1);
             if (claim) {
               dw = P.off[w + 1] - P.off[w];
               atomicOr((unsigned long long*)&fnext[w >> 6], 1ull << (w & 63));
@@ -690,11 +702,13 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           }
 #pragma unroll
           for (int r = 0; r < kTdK; ++r) {
-            const uint64_t prop = pack_dp(L + 1, u[r]);
+            const uint64_t prop = pack_dp(P.base + (uint32_t)(L + 1), u[r]);
             claim[r] = false;
+            // a claim: the word held was not written by this search
             if (cand[r] && cur[r] > prop)
-              claim[r] = atomicMin((unsigned long long*)&P.dp[w[r]], (unsigned long long)prop) ==
-                         kUnreached;
+              claim[r] = (uint32_t)(atomicMin((unsigned long long*)&P.dp[w[r]],
+                                              (unsigned long long)prop) >> 32) >
+                         P.base + (uint32_t)(L + 1);
           }
 #pragma unroll
           for (int r = 0; r < kTdK; ++r) {
@@ -775,7 +789,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 return ((word >> (u & 63)) & 1ull) ? -1 : (int64_t)u;
               },
               [&](bool fin, bool found, int64_t v, int32_t par, int64_t deg) {
-                if (found) P.dp[v] = pack_dp(L + 1, par);
+                if (found) P.dp[v] = pack_dp(P.base + (uint32_t)(L + 1), par);
                 wave_set_bits64(fnext, found, v);
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
                 stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qcap, P.n_sweep,
@@ -830,7 +844,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
                 if (found) {
                   atomicOr((unsigned long long*)&s_st.found[wv][(v >> 6) - kb],
                            1ull << (v & 63));
-                  P.dp[v] = pack_dp(L + 1, par);
+                  P.dp[v] = pack_dp(P.base + (uint32_t)(L + 1), par);
                 }
                 stage(s_st, found, (int32_t)v, deg, P, qn, qpack);
                 stage_list(s_st, fin && !found, (int32_t)v, vl_out, vlcnt, P.qcap, P.n_sweep,
@@ -966,17 +980,17 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
 // unreached, so the next search needs no initialisation pass (scattered
 // 8-byte writes instead of one coalesced pass).
 __global__ void output_kernel(int64_t n, const int32_t* perm_root, int64_t n_sweep, uint64_t* dp,
-                              int32_t* depth_o, int32_t* parent_o, int32_t root_orig,
-                              int reset) {
+                              uint32_t base, int32_t* depth_o, int32_t* parent_o,
+                              int32_t root_orig, int reset) {
   const int32_t root_out = perm_root ? perm_root[root_orig] : root_orig;
   for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
        v += (int64_t)gridDim.x * blockDim.x) {
     int32_t d = -1, p = -1;
     if (v < n_sweep) {
       const uint64_t x = dp[v];
-      if (x != kUnreached) {
-        if (reset) dp[v] = kUnreached;
-        d = (int32_t)(x >> 32);
+      if (reset && x != kUnreached) dp[v] = kUnreached;
+      if (dp_current(x, base, n_sweep)) {
+        d = (int32_t)((uint32_t)(x >> 32) - base);
         p = dp_parent(x);
       }
     } else if (v == root_out) {
@@ -1072,12 +1086,13 @@ __device__ __forceinline__ void out_group_write(OutStage& S, int nkeys, const ui
   __syncthreads();
 }
 
-// Pass A: tile blockIdx.x of the swept labels, parents as original IDs.
-// With `reset`, reached entries are set back to unreached (the next search
-// then needs no initialisation pass).
+// Pass A: tile blockIdx.x of the swept labels, as (depth, parent's original
+// ID) pairs, unreached ones marked.  With `reset`, every entry read is set
+// to unreached (the next search then starts a new base with no
+// initialisation pass).
 __global__ __launch_bounds__(kOutThreads) void out_pass_a_kernel(
-    int64_t n_sweep, int64_t ntiles, uint64_t* dp, const int32_t* iperm, int as, int na,
-    const int64_t* gA, uint64_t* av, int32_t* ao, int reset) {
+    int64_t n_sweep, int64_t ntiles, uint64_t* dp, uint32_t base, const int32_t* iperm, int as,
+    int na, const int64_t* gA, uint64_t* av, int32_t* ao, int reset) {
   __shared__ OutStage S;
   const int64_t t0 = (int64_t)blockIdx.x * kOutTile;
   const int sh = kOutWin + as;
@@ -1096,8 +1111,9 @@ __global__ __launch_bounds__(kOutThreads) void out_pass_a_kernel(
 #pragma unroll
   for (int e = 0; e < kOutPer; ++e) {
     key[e] = o[e] >> sh;
-    if (v[e] != kUnreached)
-      v[e] = (v[e] & 0xFFFFFFFF00000000ull) | (uint32_t)~(uint32_t)iperm[dp_parent(v[e])];
+    v[e] = dp_current(v[e], base, n_sweep)
+               ? pack_dp((uint32_t)(v[e] >> 32) - base, iperm[dp_parent(v[e])])
+               : kUnreached;
   }
   out_group_write(
       S, na, v, o, key, ok, av, ao,
@@ -1523,7 +1539,27 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   P.dp = w->dp;
   P.comp_bounds = g->reordered ? g->comp_bounds : nullptr;
   P.n_comp = g->n_comp;
-  P.init = w->clean ? 0 : 1;
+  // the depth-field base: lowered by at least n_sweep + 1 per search, so that
+  // every word an earlier search left compares above this one's; a new run
+  // of bases starts from the top after a full initialisation, or when the
+  // last output pass left every word unreached.  The step is at least 2^26,
+  // so a run is at most 64 searches long whatever the graph.
+  {
+    const uint64_t step = std::max<uint64_t>((uint64_t)g->n_sweep + 1, 1ull << 26);
+    const uint32_t top = (uint32_t)(0xFFFFFFFFull - step);
+    if (w->clean) {
+      P.init = 0;
+      P.base = top;
+    } else if (w->base_valid && (uint64_t)w->base >= step) {
+      P.init = 0;
+      P.base = (uint32_t)(w->base - step);
+    } else {
+      P.init = 1;
+      P.base = top;
+    }
+    w->base = P.base;
+    w->base_valid = true;
+  }
   const int64_t W = ceil_div(g->n_sweep > 0 ? g->n_sweep : 1, kWave);
   P.vis = w->vis;
   for (int i = 0; i < 3; ++i) P.front[i] = w->front + (size_t)i * W;
@@ -1613,8 +1649,8 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   if (translate) {
     if (w->ontiles > 0)
       hipLaunchKernelGGL(out_pass_a_kernel, dim3((unsigned)w->ontiles), dim3(kOutThreads), 0,
-                         stream, g->n_sweep, w->ontiles, w->dp, g->iperm, w->oas, w->ona, w->ogA,
-                         (uint64_t*)w->qe[0], w->qv[0], tun.reset ? 1 : 0);
+                         stream, g->n_sweep, w->ontiles, w->dp, P.base, g->iperm, w->oas, w->ona,
+                         w->ogA, (uint64_t*)w->qe[0], w->qv[0], tun.reset ? 1 : 0);
     if (w->onchunk > 0)
       hipLaunchKernelGGL(out_pass_b_kernel, dim3((unsigned)w->onchunk), dim3(kOutThreads), 0,
                          stream, w->onwin, w->oas, w->ona, w->owstart, w->ochunk,
@@ -1627,8 +1663,8 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
   } else {
     const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(ceil_div(g->n, kBlock), 1 << 20));
     hipLaunchKernelGGL(output_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, stream, g->n,
-                       g->reordered ? g->perm : nullptr, g->n_sweep, w->dp, depth, parent, root,
-                       tun.reset ? 1 : 0);
+                       g->reordered ? g->perm : nullptr, g->n_sweep, w->dp, P.base, depth, parent,
+                       root, tun.reset ? 1 : 0);
     BFS_CHECK(hipGetLastError());
   }
   w->clean = tun.reset != 0;
@@ -1664,6 +1700,7 @@ int bfs_impl(Graph* g, int32_t root, int32_t* depth, int32_t* parent, int mode, 
     BFS_CHECK(hipEventElapsedTime(&stats->ms_total, w->ev0, w->ev2));
     if (st != 0) {
       w->clean = false;
+      w->base_valid = false;  // the next search initialises every word
       set_error("bfs: device status " + std::to_string(st));
       return RBFS_E_DEVICE;
     }
@@ -1685,6 +1722,7 @@ int bfs_check_status(Graph* g, hipStream_t stream) {
     BFS_CHECK(hipGetLastError());
     BFS_CHECK(hipStreamSynchronize(stream));
     g->bfs->clean = false;
+    g->bfs->base_valid = false;
     set_error("bfs: device status " + std::to_string(st[0] | st[1]) +
               " raised by a search since the last check");
     return RBFS_E_DEVICE;

@@ -86,6 +86,8 @@ struct BfsWork {
   int onchunk = 0;              // pass-B chunks
   BfsCtl* ctl = nullptr;
   bool clean = false;           // every pair holds the unreached value
+  uint32_t base = 0;            // depth-field base of the last search (see bfs.hip)
+  bool base_valid = false;
   int grid = 0;                 // persistent grid size
   int max_per_cu = 1;           // resident 1024-thread workgroups per CU
   int max_per_cu_256 = 1;       // resident 256-thread workgroups per CU

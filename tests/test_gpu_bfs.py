@@ -524,3 +524,38 @@ def test_output_blocks_across_components(rb):
             assert np.array_equal(d.cpu().numpy(), d_o), (reset, i, root)
             assert np.array_equal(p.cpu().numpy(), p_o), (reset, i, root)
     G.set_tuning(rb.default_tuning(rb.TUNE_SINGLE))
+
+
+def test_searches_in_a_row_across_base_runs(rb):
+    # each search lowers the depth-field base instead of re-initialising the
+    # packed pairs; a run of bases lasts at most 64 searches, then one search
+    # initialises.  150 searches in a row (three runs), roots in different
+    # components and isolated ones, both output spaces and both reset modes,
+    # each compared with the oracle
+    (off, cols), relabel = components_graph(seed=23)
+    n = off.shape[0] - 1
+    G = rb.Graph(off, cols)
+    G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    iperm = G.iperm().cpu().numpy()
+    roots = [relabel[5], relabel[9000 + 7], relabel[n - 1], relabel[9060 + 3], relabel[77]]
+    expect = {r: oracle.bfs(off, cols, r, perm_o)[:2] for r in roots}
+    internal = rb.make_opts(output_space=rb.OUT_INTERNAL)
+    for i in range(150):
+        if i == 100:
+            t = rb.default_tuning(rb.TUNE_SINGLE)
+            t["reset"] = 1 - t["reset"]
+            G.set_tuning(t)
+        r = roots[i % len(roots)]
+        d_o, p_o = expect[r]
+        if i % 7 == 3:
+            d, p = G.bfs(r, opts=internal)
+            d, p = d.cpu().numpy(), p.cpu().numpy()
+            exp_p = np.where(p_o >= 0, np.argsort(iperm)[np.maximum(p_o, 0)], -1)
+            assert np.array_equal(d[np.argsort(iperm)], d_o), i
+            assert np.array_equal(p[np.argsort(iperm)], exp_p), i
+        else:
+            d, p = G.bfs(r)
+            assert np.array_equal(d.cpu().numpy(), d_o), i
+            assert np.array_equal(p.cpu().numpy(), p_o), i
+    G.set_tuning(rb.default_tuning(rb.TUNE_SINGLE))
