@@ -629,6 +629,7 @@ int rbfs_multi_create(rbfs_graph_t* const* graphs, int32_t count, void* stream_,
     return RBFS_E_RANGE;
   }
   m->eng.ngraphs = count;
+  m->eng.fixed_base = true;  // the search is captured and replayed
   std::vector<const Graph*> cg(m->gs.begin(), m->gs.end());
   int rc = rbfs::ms_build_union(&m->eng, cg.data(), count, stream);
   if (!rc) rc = rbfs::ms_engine_setup(&m->eng, graphs[0]->g.compute_units,

@@ -130,6 +130,13 @@ struct MsEngine {
   int grid = 0;
   int64_t wall_rate_khz = 100000;
   hipGraphExec_t gexec = nullptr; // captured multi-graph search
+  // depth-field base of the packed pairs (see the single-root search): a
+  // single-graph engine lowers it every batch and its outputs leave the
+  // pairs in place; a captured (multi-graph) one keeps it fixed and clears
+  // the pairs it translates, since a replay cannot change kernel arguments
+  uint32_t base = 0xFFFFFFFFu;
+  bool base_valid = true;         // every pair below the base's run holds all ones
+  bool fixed_base = false;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
 };
 

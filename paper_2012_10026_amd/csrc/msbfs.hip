@@ -71,7 +71,8 @@ struct MsParams {
   int64_t deg_total;
   uint64_t* vis;
   uint64_t* front[3];
-  uint64_t* dp;            // [n_sweep][64] packed (depth << 32 | ~parent), all ones = none
+  uint64_t* dp;            // [n_sweep][64] packed (depth field << 32 | ~parent), all ones = none
+  uint32_t base;           // depth field of depth 0: base + depth (see the single-root search)
   int32_t* qv[2];
   int64_t* qe[2];
   int32_t* chunk[2];
@@ -406,7 +407,8 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
           const unsigned long long old =
               atomicOr((unsigned long long*)&P.front[0][r], 1ull << j);
           first = (old == 0ull);
-          P.dp[(int64_t)r * 64 + j] = (uint64_t)(uint32_t)~(uint32_t)r;  // depth 0, parent itself
+          // depth 0, parent itself
+          P.dp[(int64_t)r * 64 + j] = ((uint64_t)P.base << 32) | (uint32_t)~(uint32_t)r;
           dg = P.off[r + 1] - P.off[r];
         }
       }
@@ -472,7 +474,7 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
               // the complement of the parent in the low half, so the smallest
               // word is the largest-label parent of this level
               unsigned long long* row = (unsigned long long*)P.dp + (int64_t)w * 64;
-              const unsigned long long prop = ((unsigned long long)(uint32_t)(L + 1) << 32) |
+              const unsigned long long prop = ((unsigned long long)(P.base + (uint32_t)(L + 1)) << 32) |
                                               (uint32_t)~(uint32_t)u;
               uint64_t bits = cand;
               while (bits) {
@@ -510,7 +512,8 @@ __global__ __launch_bounds__(kMsBlock) void msbfs_kernel(MsParams P) {
         if (part < 0) break;
         const int64_t v0 = (int64_t)P.bu_part[part] * kWave;
         const int64_t v1 = std::min<int64_t>((int64_t)P.bu_part[part + 1] * kWave, P.n_sweep);
-        ms_pull_range(P, v0, v1, fcur, fnext, L + 1, examined, done, s_st, qn, qpack);
+        ms_pull_range(P, v0, v1, fcur, fnext, (int)(P.base + (uint32_t)(L + 1)), examined, done,
+                      s_st, qn, qpack);
       }
       ms_flush(s_st, P, qn, qpack);
     }
@@ -574,7 +577,8 @@ constexpr int kTrTile = 128;   // vertices per tile
 
 __global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
     int64_t n_g, const int32_t* perm, int64_t n_sweep_g, int64_t ubase, int32_t k, uint64_t* dp,
-    const int32_t* oid, int32_t* out_dep, int32_t* out_par) {
+    uint32_t base, int64_t n_sweep_u, int clear, const int32_t* oid, int32_t* out_dep,
+    int32_t* out_par) {
   constexpr int kWaves = kTrBlock / kWave;
   constexpr int kRows = kTrTile / kWaves;   // vertices per wave in the read phase
   constexpr int kRoots = kWave / kWaves;    // roots per wave in the write phase
@@ -597,7 +601,7 @@ __global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
 #pragma unroll
     for (int t = 0; t < kRows; ++t) {
       tile[wv * kRows + t][l] = xv[t];
-      if (l < k && iv[t] < n_sweep_g) dp[(ubase + iv[t]) * 64 + l] = ~0ull;
+      if (clear && l < k && iv[t] < n_sweep_g) dp[(ubase + iv[t]) * 64 + l] = ~0ull;
     }
     __syncthreads();
     // write phase: 8 roots per wave, lane = vertex, two halves of 64
@@ -609,8 +613,11 @@ __global__ __launch_bounds__(kTrBlock) void ms_translate_kernel(
 #pragma unroll
       for (int t = 0; t < kRoots; ++t) {
         const uint64_t x = tile[vv][wv * kRoots + t];
-        d[t] = (int32_t)(x >> 32);
-        p[t] = d[t] < 0 ? -1 : (int32_t)~(uint32_t)x;
+        // written by this batch: its depth field lies within n_sweep of the base
+        const uint32_t df = (uint32_t)(x >> 32) - base;
+        const bool cur = (uint64_t)df <= (uint64_t)n_sweep_u;
+        d[t] = cur ? (int32_t)df : -1;
+        p[t] = cur ? (int32_t)~(uint32_t)x : -1;
       }
       if (oid) {
 #pragma unroll
@@ -780,6 +787,13 @@ int ms_apply_tuning(MsEngine* m, const rbfs_tuning_t& t, hipStream_t stream) {
 
 // Enqueues one search of up to 64 roots (internal union IDs already in
 // m->roots_dev): control reset + persistent kernel.
+static uint64_t ms_base_step(const MsEngine* m) {
+  return std::max<uint64_t>((uint64_t)m->n_sweep + 1, 1ull << 26);
+}
+static uint32_t ms_top_base(const MsEngine* m) {
+  return (uint32_t)(0xFFFFFFFFull - ms_base_step(m));
+}
+
 int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alpha, int beta,
                       hipStream_t stream) {
   const int bits_n = bits_for(m->n_sweep + 2);
@@ -796,6 +810,27 @@ int ms_enqueue_search(MsEngine* m, int32_t k, int32_t nroots, int mode, int alph
   P.vis = m->vis;
   for (int i = 0; i < 3; ++i) P.front[i] = m->front + (size_t)i * (m->n_sweep > 0 ? m->n_sweep : 1);
   P.dp = m->dp;
+  {
+    // each batch lowers the base by at least n_sweep + 1; the all-ones state
+    // (base 0xFFFFFFFF) is the start of a run
+    const uint64_t step = ms_base_step(m);
+    if (m->fixed_base) {
+      P.base = ms_top_base(m);
+    } else {
+      if (m->base_valid && (uint64_t)m->base >= step) {
+        P.base = (uint32_t)(m->base - step);
+      } else {
+        // a new run of bases: every pair back to all ones first
+        hipLaunchKernelGGL(ms_fill_kernel, dim3(grid_blocks(64 * (m->n_sweep > 0 ? m->n_sweep : 1))),
+                           dim3(256), 0, stream, m->dp, 64 * (m->n_sweep > 0 ? m->n_sweep : 1),
+                           ~0ull);
+        MS_CHECK(hipGetLastError());
+        P.base = ms_top_base(m);
+      }
+      m->base = P.base;
+      m->base_valid = true;
+    }
+  }
   for (int i = 0; i < 2; ++i) {
     P.qv[i] = m->qv[i];
     P.qe[i] = m->qe[i];
@@ -833,7 +868,8 @@ int ms_enqueue_translate(MsEngine* m, int64_t n_g, const int32_t* perm, int64_t 
                          int32_t* out_dep, int32_t* out_par, hipStream_t stream) {
   const int64_t tiles = std::max<int64_t>(1, std::min<int64_t>(ceil_div(n_g, kTrTile), 1 << 20));
   hipLaunchKernelGGL(ms_translate_kernel, dim3((unsigned)tiles), dim3(kTrBlock), 0, stream, n_g,
-                     perm, n_sweep_g, ubase, k, m->dp, m->uoid ? m->uoid : m->oid, out_dep,
+                     perm, n_sweep_g, ubase, k, m->dp, m->fixed_base ? ms_top_base(m) : m->base,
+                     m->n_sweep, m->fixed_base ? 1 : 0, m->uoid ? m->uoid : m->oid, out_dep,
                      out_par);
   MS_CHECK(hipGetLastError());
   hipLaunchKernelGGL(ms_roots_fixup_kernel, dim3(1), dim3(64), 0, stream, n_g, perm, n_sweep_g,
@@ -869,6 +905,7 @@ int ms_read_stats(MsEngine* m, hipStream_t stream, void* stats_v) {
   }
   delete h;
   if (st != 0) {
+    m->base_valid = false;  // the next batch starts a new run of bases
     set_error("bfs_batch: device status " + std::to_string(st));
     return RBFS_E_DEVICE;
   }
