@@ -200,6 +200,7 @@ SWITCH_VALIDATION_GRAPHS = [("kronecker", 24, 2299, 8), ("kronecker", 26, 2626, 
                             ("chung-lu", 300_000, 5998, 8, 2.1),
                             ("chung-lu", 1_000_000, 5997, 8, 2.5),
                             ("chung-lu-52.5M", 50_000_000, 4001, 8)]
+SWITCH_NETS = 4
 SWITCH_MARGINS = (0.25, 0.5, 1.0, 2.0, 1e9)
 
 
@@ -235,8 +236,9 @@ def train_switch(rb, graphgen):
     """Per-level costs of both directions (rbfs_collect_level_samples: the
     alpha/beta path up to the level, then each direction) on Kronecker graphs
     of scales 18-24 and on Chung-Lu graphs, GPU training of one network for
-    every graph family, and the decision margin chosen on held-out graphs of
-    the same families and sizes: the margin whose worst ratio of learned to
+    every graph family (several, from their own initial weights and sample
+    orders), and the network and decision margin chosen on held-out graphs of
+    the same families and sizes: the pair whose worst ratio of learned to
     alpha/beta search time over them is smallest (a margin that never lets
     the network decide is among the candidates), the geometric mean
     breaking near-ties.  Returns the switch blob and a summary."""
@@ -251,50 +253,62 @@ def train_switch(rb, graphgen):
         torch.cuda.empty_cache()
     rows = np.vstack(rows)
     t_collect = time.perf_counter() - t0
-    order = graphgen.epoch_orders(rows.shape[0], 200, 1)
+    # several networks (their own initial weights and sample orders), since
+    # one trained network sometimes mispredicts a family badly
     t0 = time.perf_counter()
-    w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(0).astype(np.float32), order,
-                            batch=64, lr=3e-3)
+    nets = []
+    for j in range(SWITCH_NETS):
+        order = graphgen.epoch_orders(rows.shape[0], 200, 1 + j)
+        w, curve = rb.mlp_train(rows[:, :10], graphgen.mlp_init_weights(j).astype(np.float32),
+                                order, batch=64, lr=3e-3)
+        nets.append((w, curve))
     t_train = time.perf_counter() - t0
-    # margin on the validation graphs
+    # every (network, margin) on the validation graphs; a margin that never
+    # lets the network decide is timed once
     t0 = time.perf_counter()
-    ratios = {m: [] for m in SWITCH_MARGINS}
-    blobs = {m: rb.make_switch_blob(w, rows, margin=m) for m in SWITCH_MARGINS}
+    cands = [(j, m) for j in range(SWITCH_NETS) for m in SWITCH_MARGINS if m < 1e8]
+    cands.append((0, max(SWITCH_MARGINS)))
+    blobs = {c: rb.make_switch_blob(nets[c[0]][0], rows, margin=c[1]) for c in cands}
+    ratios = {c: [] for c in cands}
     for spec in SWITCH_VALIDATION_GRAPHS:
         G, roots = switch_graph(rb, graphgen, spec)
         for r in roots[:2]:
             G.bfs(r)
-        # root by root, alpha/beta and every margin in turn, so that a drift
-        # of the clocks over the run weighs on all of them alike
-        t_ab, t_m = 0.0, {m: 0.0 for m in SWITCH_MARGINS}
+        # root by root, alpha/beta and every candidate in turn, so that a
+        # drift of the clocks over the run weighs on all of them alike
+        t_ab, t_c = 0.0, {c: 0.0 for c in cands}
         for r in roots:
             t_ab += kernel_ms_sum(rb, G, [r], rb.make_opts())
-            for m in SWITCH_MARGINS:
-                rb.switch_load(blobs[m])
-                t_m[m] += kernel_ms_sum(rb, G, [r], rb.make_opts(rb.DIR_LEARNED))
-        for m in SWITCH_MARGINS:
-            ratios[m].append(t_m[m] / t_ab)
+            for c in cands:
+                rb.switch_load(blobs[c])
+                t_c[c] += kernel_ms_sum(rb, G, [r], rb.make_opts(rb.DIR_LEARNED))
+        for c in cands:
+            ratios[c].append(t_c[c] / t_ab)
         G.close()
         torch.cuda.empty_cache()
-    # the smallest worst ratio; margins within 1.5 % of it (timing noise) are
-    # ranked by their geometric mean ratio
-    best_worst = min(max(ratios[m]) for m in SWITCH_MARGINS)
-    margin = min((m for m in SWITCH_MARGINS if max(ratios[m]) <= best_worst + 0.015),
-                 key=lambda m: sum(math.log(x) for x in ratios[m]))
+    # the smallest worst ratio; candidates within 1.5 % of it (timing noise)
+    # are ranked by their geometric mean ratio
+    best_worst = min(max(ratios[c]) for c in cands)
+    pick = min((c for c in cands if max(ratios[c]) <= best_worst + 0.015),
+               key=lambda c: sum(math.log(x) for x in ratios[c]))
+    w, curve = nets[pick[0]]
+    margin = pick[1]
     t_val = time.perf_counter() - t0
-    log("# switch: %d samples (%.1f s), trained %.2f s, loss %.3f -> %.3f; margin %.2f "
-        "(worst learned/alpha-beta time on validation %.3f)"
-        % (rows.shape[0], t_collect, t_train, curve[0], curve[-1], margin, max(ratios[margin])))
+    log("# switch: %d samples (%.1f s), %d networks trained %.2f s, loss %.3f -> %.3f; network "
+        "%d, margin %g (worst learned/alpha-beta time on validation %.3f)"
+        % (rows.shape[0], t_collect, SWITCH_NETS, t_train, curve[0], curve[-1], pick[0], margin,
+           max(ratios[pick])))
     return rb.make_switch_blob(w, rows, margin=margin), {
         "samples": int(rows.shape[0]),
         "train_graphs": "kronecker scales 18,20,22 x 4 (32 roots each), 24 x 2 (16 roots); "
                         "chung-lu n = 0.3M, 1M, 3M x 4, exponent 2.1, mean degree 30 (40 roots "
                         "each); n = 0.3M, 1M x 2, exponent 2.5, mean degree 10 (32 roots)",
         "collect_s": t_collect, "train_s": t_train, "validate_s": t_val, "epochs": 200,
+        "networks": SWITCH_NETS, "network": pick[0],
         "loss_first": float(curve[0]), "loss_last": float(curve[-1]),
         "margin": margin,
         "validation_learned_over_alpha_beta_time": {
-            ("%g" % m): [round(x, 4) for x in ratios[m]] for m in SWITCH_MARGINS},
+            ("net%d margin %g" % c): [round(x, 4) for x in ratios[c]] for c in cands},
         "validation_graphs": "kronecker 24 seed 2299, kronecker 26 seed 2626; chung-lu 3M and "
                              "0.3M exponent 2.1; chung-lu 1M exponent 2.5; chung-lu 52.5M seed "
                              "4001 (8 roots each)"}
