@@ -778,9 +778,11 @@ def main():
         if not keep_host:
             del off, cols
             torch.cuda.empty_cache()
+    bw_orig = G.bandwidth()
     perm_t, rcm_ms = G.rcm_reorder(want_perm=keep_host)
     info = G.info()
-    log("# rcm %.1f ms, n_plus=%d" % (rcm_ms, info["n_plus"]))
+    bw_rcm = G.bandwidth()
+    log("# rcm %.1f ms, n_plus=%d, bandwidth %d -> %d" % (rcm_ms, info["n_plus"], bw_orig, bw_rcm))
 
     n = info["n"]
     nroot = len(roots)
@@ -867,6 +869,7 @@ def main():
                      "kernel": "bfs_persistent_kernel", "kernel_avg_ms": k_avg_ms,
                      "alg_bytes_avg": bytes_avg},
         "rcm_ms": rcm_ms,
+        "bandwidth": {"original_labels": bw_orig, "rcm_labels": bw_rcm},
         "gen_s": t_gen,
         "gteps_search_kernel_only": hmean_internal,
         "gteps_graph500_tuples": hmean_gteps(tuples, per_root_ms),

@@ -208,6 +208,14 @@ int rbfs_graph_destroy(rbfs_graph_t* g);
 
 int rbfs_graph_info(const rbfs_graph_t* g, rbfs_graph_info_t* out);
 
+/* Bandwidth of the graph's current labels (section 3.2: what the
+ * Cuthill-McKee order keeps small): the largest |u - v| over its adjacency
+ * entries, 0 for a graph without edges.  After rbfs_rcm_reorder these are
+ * the RCM labels.  One O(n) pass on `stream` (a row's first and last entries
+ * bound it, rows being ascending) into *out (host); synchronises `stream`.
+ * Allocates 8 bytes of device memory for the call. */
+int rbfs_graph_bandwidth(const rbfs_graph_t* g, int64_t* out, void* stream);
+
 /* Relabel the graph by Reverse Cuthill-McKee (Algorithm 3, section 3.2):
  * V+ (non-isolated vertices) sorted by increasing (degree, id); each
  * connected component is explored from its unvisited vertex of least
@@ -490,6 +498,10 @@ int rbfs_switch_load(const float* blob, int32_t n);
 int rbfs_collect_level_samples(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
                                int32_t alpha, int32_t beta, float* out, int32_t cap,
                                int32_t* count, void* stream);
+/* The same call under the name the interface plan gives it. */
+int rbfs_collect_level_timings(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
+                               int32_t alpha, int32_t beta, float* out, int32_t cap,
+                               int32_t* count, void* stream);
 
 /* Training on the GPU: samples[n][10] (features[8], targets[2]); w_init[1410];
  * order[epochs][n]: the sample order of each epoch (batches are consecutive
@@ -506,6 +518,9 @@ int rbfs_mlp_train(const float* samples, int32_t n, const float* w_init, const i
  * uses, and the gradient of the batch loss over all n samples. */
 int rbfs_mlp_forward(const float* w, const float* x, int32_t n, float* y);
 int rbfs_mlp_grad(const float* w, const float* samples, int32_t n, float* grad, float* loss);
+/* rbfs_mlp_grad under the name the interface plan gives it. */
+int rbfs_mlp_backward(const float* w, const float* samples, int32_t n, float* grad,
+                      float* loss);
 
 #ifdef __cplusplus
 }

@@ -124,6 +124,7 @@ SIGNATURES = {
     "rbfs_graph_set_rcm_staging": (ctypes.c_int, [_P, _I32]),
     "rbfs_graph_iperm": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_graph_csr": (ctypes.c_int, [_P, _P, _P, _P]),
+    "rbfs_graph_bandwidth": (ctypes.c_int, [_P, _P, _P]),
     "rbfs_bfs": (ctypes.c_int, [_P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_bfs_batch": (ctypes.c_int, [_P, _P, _I32, _P, _P, _P, _P, _P]),
     "rbfs_certify": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _P, _P]),
@@ -134,10 +135,13 @@ SIGNATURES = {
     "rbfs_switch_load": (ctypes.c_int, [_P, _I32]),
     "rbfs_collect_level_samples": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32,
                                                   _P, _P]),
+    "rbfs_collect_level_timings": (ctypes.c_int, [_P, _P, _I32, _I32, _I32, _I32, _P, _I32,
+                                                  _P, _P]),
     "rbfs_mlp_train": (ctypes.c_int, [_P, _I32, _P, _P, _I32, _I32, ctypes.c_float, _P, _P,
                                       _P]),
     "rbfs_mlp_forward": (ctypes.c_int, [_P, _P, _I32, _P]),
     "rbfs_mlp_grad": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
+    "rbfs_mlp_backward": (ctypes.c_int, [_P, _P, _I32, _P, _P]),
     "rbfs_tuning_default": (ctypes.c_int, [_I32, _P]),
     "rbfs_graph_set_tuning": (ctypes.c_int, [_P, _I32, _P, _P]),
     "rbfs_graph_get_tuning": (ctypes.c_int, [_P, _I32, _P]),
@@ -399,6 +403,12 @@ class Graph:
         _check(lib().rbfs_graph_csr(self._h, _dptr(off), _dptr(cols),
                                     _stream_ptr(self.device)))
         return off, cols[:self.nnz]
+
+    def bandwidth(self):
+        """Largest |u - v| over the adjacency entries in the current labels."""
+        out = ctypes.c_int64(0)
+        _check(lib().rbfs_graph_bandwidth(self._h, ctypes.byref(out), _stream_ptr(self.device)))
+        return out.value
 
     def bfs(self, root, depth=None, parent=None, opts=None, stats=False):
         """Returns (depth, parent[, stats dict]) as int32 device tensors."""

@@ -78,6 +78,23 @@ __global__ void check_offsets_kernel(const int64_t* off, int64_t n, int64_t nnz,
     atomicOr(flags, kVBadOffsets);
 }
 
+// Largest |u - v| over the adjacency entries: rows are ascending, so a row's
+// first and last entries bound it.
+__global__ void bandwidth_kernel(const int64_t* off, const int32_t* cols, int64_t n,
+                                 unsigned long long* out) {
+  unsigned long long best = 0;
+  for (int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; v < n;
+       v += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = off[v], e = off[v + 1];
+    if (e > b) {
+      const int64_t lo = v - cols[b], hi = (int64_t)cols[e - 1] - v;
+      const int64_t m = lo > hi ? lo : hi;
+      if (m > 0 && (unsigned long long)m > best) best = (unsigned long long)m;
+    }
+  }
+  if (best) atomicMax(out, best);
+}
+
 __global__ void check_cols_kernel(const int32_t* cols, int64_t nnz, int64_t n, int* flags) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nnz;
        e += (int64_t)gridDim.x * blockDim.x) {
@@ -486,6 +503,39 @@ fail:
   return rc;
 }
 
+int rbfs_graph_bandwidth(const rbfs_graph_t* h, int64_t* out, void* stream_) {
+  if (!h || !out) {
+    set_error("rbfs_graph_bandwidth: NULL argument");
+    return RBFS_E_INVAL;
+  }
+  const Graph* g = &h->g;
+  hipStream_t stream = (hipStream_t)stream_;
+  int rc = 0;
+  unsigned long long* d = nullptr;
+  unsigned long long hv = 0;
+  API_CHECK(hipSetDevice(g->device));
+  API_CHECK(rbfs::dev_malloc(&d, sizeof(unsigned long long), stream));
+  API_CHECK(hipMemsetAsync(d, 0, sizeof(unsigned long long), stream));
+  if (g->n > 0 && g->nnz > 0) {
+    const int64_t blocks =
+        std::max<int64_t>(1, std::min<int64_t>(rbfs::ceil_div(g->n, rbfs::kBlock), 4096));
+    hipLaunchKernelGGL(rbfs::bandwidth_kernel, dim3((unsigned)blocks), dim3(rbfs::kBlock), 0, stream, g->off,
+                       g->cols, g->n, d);
+    API_CHECK(hipGetLastError());
+  }
+  API_CHECK(hipMemcpyAsync(&hv, d, sizeof(hv), hipMemcpyDeviceToHost, stream));
+  API_CHECK(hipStreamSynchronize(stream));
+  rbfs::dev_free(d, stream);
+  *out = (int64_t)hv;
+  return RBFS_OK;
+fail:
+  if (d) {
+    (void)hipStreamSynchronize(stream);
+    rbfs::dev_free(d, stream);
+  }
+  return rc;
+}
+
 static int parse_opts(const rbfs_opts_t* o, int* mode, int* alpha, int* beta, int* out_space) {
   *mode = RBFS_DIR_HEURISTIC;
   *alpha = 14;
@@ -852,6 +902,12 @@ fail:
   if (dd) (void)rbfs::dev_free(dd);
   if (dp) (void)rbfs::dev_free(dp);
   return rc;
+}
+
+int rbfs_collect_level_timings(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
+                               int32_t alpha, int32_t beta, float* out, int32_t cap,
+                               int32_t* count, void* stream) {
+  return rbfs_collect_level_samples(g, roots, k, reps, alpha, beta, out, cap, count, stream);
 }
 
 int rbfs_graph_check(rbfs_graph_t* h, void* stream_) {

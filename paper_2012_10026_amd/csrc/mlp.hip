@@ -334,6 +334,11 @@ int rbfs_mlp_grad(const float* w, const float* samples, int32_t n, float* grad, 
                       nullptr);
 }
 
+int rbfs_mlp_backward(const float* w, const float* samples, int32_t n, float* grad,
+                      float* loss) {
+  return rbfs_mlp_grad(w, samples, n, grad, loss);
+}
+
 int rbfs_mlp_train(const float* samples, int32_t n, const float* w_init, const int32_t* order,
                    int32_t epochs, int32_t batch, float lr, float* w_out, float* loss_curve,
                    void* stream) {

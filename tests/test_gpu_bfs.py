@@ -559,3 +559,20 @@ def test_searches_in_a_row_across_base_runs(rb):
             assert np.array_equal(d.cpu().numpy(), d_o), i
             assert np.array_equal(p.cpu().numpy(), p_o), i
     G.set_tuning(rb.default_tuning(rb.TUNE_SINGLE))
+
+
+@pytest.mark.parametrize("name,g", [s for s in SMALL if s[0] in ("path", "mixed", "er3", "hub")] +
+                         [("kron14", kron(14, 5))], ids=lambda x: x if isinstance(x, str) else "")
+def test_bandwidth(rb, name, g):
+    # the largest |u - v| over the edges, before RCM in the input labels and
+    # after it in the oracle's RCM labels
+    off, cols = g
+    n = off.shape[0] - 1
+    rows = np.repeat(np.arange(n), np.diff(off))
+    G = rb.Graph(off, cols)
+    exp0 = int(np.abs(rows - cols).max()) if cols.size else 0
+    assert G.bandwidth() == exp0
+    G.rcm_reorder()
+    perm_o, _, _ = oracle.rcm(off, cols)
+    exp1 = int(np.abs(perm_o[rows].astype(np.int64) - perm_o[cols]).max()) if cols.size else 0
+    assert G.bandwidth() == exp1
