@@ -172,6 +172,7 @@ struct GridBarrier {
 };
 
 __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks) {
+  __shared__ bool s_ok;
   __syncthreads();
   if (threadIdx.x == 0) {
     const unsigned gen0 = __hip_atomic_load(&b->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -204,9 +205,11 @@ __device__ __forceinline__ bool grid_sync(GridBarrier* b, uint64_t timeout_ticks
       }
     }
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    s_ok = __hip_atomic_load(&b->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
   }
   __syncthreads();
-  return __hip_atomic_load(&b->status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+  // the status as thread 0 read it, one read per workgroup
+  return s_ok;
 }
 
 // ---------------------------------------------------------------------------
