@@ -361,8 +361,8 @@ template <class Cand, class Done>
 __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const int32_t* cols,
                                             const int32_t* top, const uint64_t* bits,
                                             const uint32_t* filt, bool use_filt, int fs,
-                                            int lane_row, int64_t& examined, Cand&& cand,
-                                            Done&& done) {
+                                            uint32_t hi0, int lane_row, int64_t& examined,
+                                            Cand&& cand, Done&& done) {
   int next = 0;  // next candidate to hand out (same in every lane)
   bool busy = false, queued = false;
   int64_t v = 0, b = 0, j = 0, e = 0;  // current candidate
@@ -398,7 +398,7 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
     const bool hub = fresh && (e - b) > lane_row;
     bool found = false;
     int32_t par = 0;
-    wave_hub_first_hit(hub, b, e, cols, bits, filt, use_filt, fs, found, par, examined);
+    wave_hub_first_hit(hub, b, e, cols, bits, filt, use_filt, fs, hi0, found, par, examined);
     bool fin = hub;
     if (busy && !hub && j <= b) {
       fin = true;  // empty row
@@ -406,7 +406,7 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
       // the row's highest entry from the dense copy: one probe and no
       // column load; against a dense frontier most rows end here
       examined += 1;
-      if ((!use_filt || lds_bit(filt, (uint32_t)t >> fs)) && test_bit(bits, (uint32_t)t)) {
+      if (probe_bit(bits, filt, use_filt, fs, hi0, (uint32_t)t)) {
         found = true;
         par = t;
         fin = true;
@@ -437,9 +437,8 @@ __device__ __forceinline__ void refill_scan(int total, const int64_t* off, const
 #pragma unroll
       for (int q = 0; q < kScanStep; ++q) {
         const int r = q < 4 ? q : q - 8;
-        bool in = (q < 4 || two) && r >= rb && r < rj;
-        if (use_filt) in = in && lds_bit(filt, (uint32_t)w[q] >> fs);
-        h[q] = in && test_bit(bits, (uint32_t)w[q]);
+        const bool in = (q < 4 || two) && r >= rb && r < rj;
+        h[q] = in && probe_bit(bits, filt, use_filt, fs, hi0, (uint32_t)w[q]);
       }
       // the first hit downwards is the highest entry: visit the entries in
       // increasing position order (w[4..7], then w[0..3]), keep the last hit
@@ -757,6 +756,18 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
         }
         __syncthreads();
       }
+      // a dense frontier: the exact bits of the highest labels (the hubs
+      // after RCM, which most rows meet first) go to LDS for the probes
+      uint32_t hi0 = 0xFFFFFFFFu;
+      if (!use_filt) {
+        constexpr int64_t kBits = (int64_t)StepLds<BLOCK>::kFiltWords * 32;
+        const int64_t lo = P.n_sweep > kBits ? ((P.n_sweep - kBits + 63) & ~(int64_t)63) : 0;
+        hi0 = (uint32_t)lo;
+        const uint32_t* src = (const uint32_t*)fcur + (lo >> 5);
+        const int nw = (int)((P.n_sweep - lo + 31) >> 5);
+        for (int i = threadIdx.x; i < nw; i += BLOCK) s_step.filt[i] = src[i];
+        __syncthreads();
+      }
       int64_t nranges = P.n_part;
       if (listed) {
         nranges = 0;
@@ -780,7 +791,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           const int total = (int)std::min<int64_t>(kListRange, s_lcnt[q] - lr * kListRange);
           refill_scan(
               total, P.off, P.cols, use_filt ? nullptr : P.top, fcur, s_step.filt, use_filt, fs,
-              P.lane_row, examined,
+              hi0, P.lane_row, examined,
               [&](int t) -> int64_t {
                 if (t < 0) return -1;
                 const int32_t u = vl_in[i0 + t];
@@ -824,7 +835,7 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
           __builtin_amdgcn_wave_barrier();
           refill_scan(
               total, P.off, P.cols, use_filt ? nullptr : P.top, fcur, s_step.filt, use_filt, fs,
-              P.lane_row, examined,
+              hi0, P.lane_row, examined,
               [&](int t) -> int64_t {
                 // the word holding the t-th unvisited vertex of the batch:
                 // the first lane whose inclusive count exceeds t

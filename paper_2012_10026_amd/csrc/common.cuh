@@ -314,17 +314,24 @@ __device__ __forceinline__ int64_t next_range(unsigned long long* ctrs, int64_t 
 // the first hit (in row order).  Sets found / par on the hub lanes; adds the
 // entries read (up to and including the hit) to lane 0's `examined`.  All
 // lanes must call.
-// filt (LDS, used when use_filt): a coarse summary of bits, bit k set when
-// any of the vertices [k << fs, (k + 1) << fs) is set; entries it rules out
-// skip the probe of bits.
+// filt (LDS) holds, when use_filt, a coarse summary of bits, bit k set when
+// any of the vertices [k << fs, (k + 1) << fs) is set, and entries it rules
+// out skip the probe of bits; otherwise it holds the exact bits of the
+// vertices from hi0 up (the highest labels), which are probed there.
 __device__ __forceinline__ bool lds_bit(const uint32_t* filt, uint32_t k) {
   return (filt[k >> 5] >> (k & 31)) & 1u;
+}
+
+__device__ __forceinline__ bool probe_bit(const uint64_t* bits, const uint32_t* filt,
+                                          bool use_filt, int fs, uint32_t hi0, uint32_t x) {
+  if (x >= hi0) return lds_bit(filt, x - hi0);
+  return (!use_filt || lds_bit(filt, x >> fs)) && test_bit(bits, x);
 }
 
 __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t e,
                                                    const int32_t* cols, const uint64_t* bits,
                                                    const uint32_t* filt, bool use_filt,
-                                                   int fs,
+                                                   int fs, uint32_t hi0,
                                                    bool& found, int32_t& par,
                                                    int64_t& examined) {
   const int l = lane_id();
@@ -343,7 +350,7 @@ __device__ __forceinline__ void wave_hub_first_hit(bool hub, int64_t b, int64_t 
       bool hit = false;
       if (j >= hb) {
         w = cols[j];
-        hit = (!use_filt || lds_bit(filt, (uint32_t)w >> fs)) && test_bit(bits, (uint32_t)w);
+        hit = probe_bit(bits, filt, use_filt, fs, hi0, (uint32_t)w);
       }
       const uint64_t hm = ballot(hit);
       if (hm) {
