@@ -201,7 +201,7 @@ SWITCH_VALIDATION_GRAPHS = [("kronecker", 24, 2299, 8), ("kronecker", 26, 2626, 
                             ("chung-lu", 1_000_000, 5997, 8, 2.5),
                             ("chung-lu-52.5M", 50_000_000, 4001, 8)]
 SWITCH_NETS = 4
-SWITCH_MARGINS = (0.25, 0.5, 1.0, 2.0, 1e9)
+SWITCH_MARGINS = (0.05, 0.1, 0.25, 0.5, 1.0, 1e9)
 
 
 def switch_graph(rb, graphgen, spec):
@@ -233,15 +233,17 @@ def kernel_ms_sum(rb, G, roots, opts, reps=3):
 
 
 def train_switch(rb, graphgen):
-    """Per-level costs of both directions (rbfs_collect_level_samples: the
-    alpha/beta path up to the level, then each direction) on Kronecker graphs
-    of scales 18-24 and on Chung-Lu graphs, GPU training of one network for
-    every graph family (several, from their own initial weights and sample
-    orders), and the network and decision margin chosen on held-out graphs of
-    the same families and sizes: the pair whose worst ratio of learned to
-    alpha/beta search time over them is smallest (a margin that never lets
-    the network decide is among the candidates), the geometric mean
-    breaking near-ties.  Returns the switch blob and a summary."""
+    """Costs of both directions at every level (rbfs_collect_level_samples:
+    the alpha/beta path up to the level, each direction there, the alpha/beta
+    rule after it; the time from the level to the end of the search) on
+    Kronecker graphs of scales 18-24 and on Chung-Lu graphs, GPU training of
+    one network for every graph family (several, from their own initial
+    weights and sample orders), and the network and decision margin chosen
+    on held-out graphs of the same families and sizes: the pair whose worst
+    ratio of learned to alpha/beta search time over them is smallest (a
+    margin that never lets the network decide is among the candidates), the
+    geometric mean breaking near-ties.  Returns the switch blob and a
+    summary."""
     import numpy as np
     import torch
     rows = []
@@ -317,8 +319,9 @@ def train_switch(rb, graphgen):
 def schedule_costs(rb, G, roots, learned_opts, plain_opts, reps=3):
     """Per root, search-kernel times (median of reps) of three schedules run
     end to end: alpha/beta, learned, and the per-level best (at each level
-    the direction with the smaller measured cost after the alpha/beta path,
-    from rbfs_collect_level_samples), run with DIR_SCHEDULE."""
+    the direction with the smaller measured cost from there to the end, the
+    alpha/beta path before it and the alpha/beta rule after it, from
+    rbfs_collect_level_samples), run with DIR_SCHEDULE."""
     tot = {"alpha_beta_ms": 0.0, "learned_ms": 0.0, "best_schedule_ms": 0.0}
     agree_l = agree_h = nlev = 0
     for r in roots:

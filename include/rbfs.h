@@ -485,16 +485,21 @@ int rbfs_multi_tune(rbfs_multi_t* m, const int32_t* roots, int32_t k, int32_t re
 int rbfs_switch_load(const float* blob, int32_t n);
 
 /* Training samples: for each root and each level d >= 1, searches that
- * follow the alpha/beta rule's directions up to level d - 1 and then take
- * level d top-down, or bottom-up, `reps` times each; the median device time
- * of level d is that direction's cost, including whatever the switch costs
- * there (a first bottom-up level sweeps the component's words, a later one
- * walks the vertex list the last bottom-up level left).  From level 2 on the
- * same is done once more with level d - 1 taken the other way, which samples
- * the other value of the current-direction feature (the frontiers, hence the
- * other features, do not depend on the directions).  Rows of 11 floats:
- * features[8], ln(us TD), ln(us BU), level.  Writes at most `cap` rows;
- * *count receives the number. */
+ * follow the alpha/beta rule's directions up to level d - 1, take level d
+ * top-down, or bottom-up, and follow the alpha/beta rule again from there
+ * on, `reps` times each.  A direction's cost at level d is the median device
+ * time from the start of level d to the end of the search: the level itself,
+ * including whatever the switch costs there (a first bottom-up level sweeps
+ * the component's words, a later one walks the vertex list the last
+ * bottom-up level left), and what the choice does to the levels after it (a
+ * bottom-up level taken early spares the next one the word sweep).  A
+ * network that picks the cheaper of the two predicted costs improves on the
+ * rule it was labelled with, one level at a time.  From level 2 on the same
+ * is done once more with level d - 1 taken the other way, which samples the
+ * other value of the current-direction feature (the frontiers, hence the
+ * other features and the rule's later decisions, do not depend on the
+ * directions).  Rows of 11 floats: features[8], ln(us TD), ln(us BU), level.
+ * Writes at most `cap` rows; *count receives the number. */
 int rbfs_collect_level_samples(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
                                int32_t alpha, int32_t beta, float* out, int32_t cap,
                                int32_t* count, void* stream);

@@ -874,12 +874,21 @@ int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k,
           float lab[2];
           for (int x = 0; x < 2; ++x) {
             sched[d] = (int8_t)x;
+            // the levels after d follow the alpha/beta rule from direction x
+            // (its inputs, the frontier sizes, do not depend on the directions)
+            for (int e = d + 1; e < D; ++e)
+              sched[e] = (int8_t)rbfs::heuristic_dir(sched[e - 1], sh.nf[e], sh.mf[e], sh.mu[e],
+                                                     sh.nf[e - 1], g->n_sweep, alpha, beta);
             t.clear();
             for (int32_t r = 0; r < reps; ++r) {
               rc = rbfs::bfs_impl(g, roots[j], dd, dp, RBFS_DIR_SCHEDULE, alpha, beta, sched,
-                                  d + 1, RBFS_OUT_INTERNAL, 0, 0, stream, &st);
+                                  std::max(D, d + 1), RBFS_OUT_INTERNAL, 0, 0, stream, &st);
               if (rc) goto fail;
-              if (st.levels > d) t.push_back(st.level_us[d]);
+              // the cost from level d to the end of the search
+              const int De = std::min(st.levels, RBFS_STATS_MAX_LEVELS);
+              float c2g = 0.f;
+              for (int e = d; e < De; ++e) c2g += st.level_us[e];
+              if (De > d) t.push_back(c2g);
             }
             if (t.empty()) break;
             std::sort(t.begin(), t.end());

@@ -486,13 +486,6 @@ __device__ __forceinline__ int64_t block_sum(int64_t v) {
   return t;
 }
 
-__device__ __forceinline__ int heuristic_dir(int dir, long long nf, long long mf, long long mu,
-                                             long long nf_prev, long long n, int alpha,
-                                             int beta) {
-  if (dir == 0) return (mf * (long long)alpha > mu) ? 1 : 0;
-  return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
-}
-
 // LDS of the learned direction decision: wave 0's hidden layer and the
 // decision it takes.  The network is read from the switch blob in global
 // memory (5.7 KB, cache resident after the first level): an LDS copy made at

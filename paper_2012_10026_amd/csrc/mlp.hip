@@ -357,13 +357,9 @@ int rbfs_mlp_train(const float* samples, int32_t n, const float* w_init, const i
                       nullptr, (hipStream_t)stream);
 }
 
-// Per-level training samples: for each root, the search is run with every
-// level top-down and with every level (after the first) bottom-up, `reps`
-// times each; the level state does not depend on the directions taken, so
-// level d of both runs starts from the same frontier and visited set, and
-// the median device time of level d in each run is that direction's cost.
-// Row layout (11 floats): features[8], ln(us top-down), ln(us bottom-up),
-// level.  The features use the alpha/beta run's direction for level d-1.
+// Training samples (defined with the search API): per root and level, the
+// cost of each direction from that level to the end of the search.  Row
+// layout (11 floats): features[8], ln(us top-down), ln(us bottom-up), level.
 int rbfs_collect_level_samples(rbfs_graph_t* h, const int32_t* roots, int32_t k, int32_t reps,
                                int32_t alpha, int32_t beta, float* out, int32_t cap,
                                int32_t* count, void* stream);

@@ -64,6 +64,17 @@ RBFS_HD void switch_features(float* f, long long nf, long long mf, long long mu,
   f[7] = clampf_(log2f((1.0f + (float)nf) / (1.0f + (float)nf_prev)) / 8.0f, -2.0f, 2.0f);
 }
 
+// The alpha/beta rule (Algorithm 2's switch, integer form): the direction of
+// the level that expands a frontier of nf vertices and mf edges, with mu
+// edges of unreached vertices left, nf_prev the previous frontier's size, dir
+// the previous level's direction (0 top-down, 1 bottom-up) and n the swept
+// vertex count.
+RBFS_HD int heuristic_dir(int dir, long long nf, long long mf, long long mu, long long nf_prev,
+                          long long n, int alpha, int beta) {
+  if (dir == 0) return (mf * (long long)alpha > mu) ? 1 : 0;
+  return (nf * (long long)beta < n && nf < nf_prev) ? 0 : 1;
+}
+
 // True when a feature vector lies outside the widened training range.
 RBFS_HD bool switch_ood(const float* blob, const float* f, int level) {
   if ((float)level > blob[kOffMaxLevel]) return true;

@@ -118,8 +118,9 @@ def _chung_lu_graph(rb, seed):
 
 @pytest.fixture(scope="module")
 def mixed_blob(rb):
-    """One network for both families: trained on the level costs of small
-    Kronecker graphs (scales 14-16) and of power-law Chung-Lu graphs
+    """One network for both families: trained on the costs of both
+    directions at each level (from the level to the end of the search) of
+    small Kronecker graphs (scales 14-16) and of power-law Chung-Lu graphs
     (300000 vertices, exponent 2.1), collected along the alpha/beta path."""
     rows = []
     for scale, seed in [(14, 1), (15, 2), (16, 3), (16, 4)]:
