@@ -638,9 +638,10 @@ def collect_level_samples(graph, roots, reps=3, alpha=14, beta=24, cap=4096):
     return out[:cnt.value].copy()
 
 
-def make_switch_blob(w, features, margin=0.25):
+def make_switch_blob(w, features, margin=0.1):
     """Weights plus the training feature range, the largest level and the
-    decision margin (ln microseconds)."""
+    decision margin (ln microseconds; the default is the margin that
+    validation picks for labels that run to the end of the search)."""
     features = np.asarray(features, np.float32)
     blob = np.zeros(SWITCH_BLOB, np.float32)
     blob[:MLP_PARAMS] = w
