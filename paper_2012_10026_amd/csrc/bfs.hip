@@ -90,7 +90,7 @@ struct alignas(128) BfsCtl {
 namespace {
 
 constexpr int kStage = 384;  // staged appends per wave
-constexpr int kListRange = 64;  // list vertices per bottom-up work range
+constexpr int kListRange = 128;  // list vertices per bottom-up work range
 constexpr int kScanStep = 8;    // row entries a lane tests per step (after the first)
 static_assert(kScanStep == 8, "the row scan loads two aligned groups of 4 entries");
 constexpr uint64_t kUnreached = ~0ull;  // packed pair of an unreached vertex
