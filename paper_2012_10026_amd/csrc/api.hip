@@ -10,7 +10,7 @@
 #include <vector>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
 #include "switch.h"
 

@@ -49,10 +49,10 @@
 #include <vector>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
-#include "expand.cuh"
+#include "common.h"
+#include "expand.h"
 #include "graph.h"
-#include "mlp_dev.cuh"
+#include "mlp_dev.h"
 #include "switch.h"
 
 namespace rbfs {

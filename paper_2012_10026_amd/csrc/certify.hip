@@ -19,7 +19,7 @@
 #include <string>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
 #include "handles.h"
 

@@ -12,7 +12,7 @@
 // even split of each frontier vertex's neighbours over the threads (top-down
 // load balancing, Algorithm 4 and Eq. 3).
 #pragma once
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
 
 namespace rbfs {

@@ -15,9 +15,9 @@
 #include <vector>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
-#include "mlp_dev.cuh"
+#include "mlp_dev.h"
 #include "switch.h"
 
 namespace rbfs {

@@ -3,7 +3,7 @@
 // run in a fixed order, so every workgroup computes bit-identical values and
 // takes the same decision.
 #pragma once
-#include "common.cuh"
+#include "common.h"
 #include "switch.h"
 
 namespace rbfs {

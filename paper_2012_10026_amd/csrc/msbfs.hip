@@ -36,8 +36,8 @@
 #include <vector>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
-#include "expand.cuh"
+#include "common.h"
+#include "expand.h"
 #include "graph.h"
 
 namespace rbfs {

@@ -11,7 +11,7 @@
 // that digit come from LDS.
 #include <hip/hip_runtime.h>
 
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
 #include "prim.h"
 

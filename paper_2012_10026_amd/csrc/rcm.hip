@@ -45,8 +45,8 @@
 #include <string>
 #include <vector>
 
-#include "common.cuh"
-#include "expand.cuh"
+#include "common.h"
+#include "expand.h"
 #include "graph.h"
 #include "prim.h"
 

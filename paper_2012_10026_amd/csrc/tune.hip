@@ -20,7 +20,7 @@
 #include <vector>
 
 #include "../../include/rbfs.h"
-#include "common.cuh"
+#include "common.h"
 #include "graph.h"
 #include "handles.h"
 
