@@ -659,10 +659,11 @@ __global__ __launch_bounds__(BLOCK) void bfs_persistent_kernel(BfsParams P) {
       // ---- top-down
       fold_frontier(P, qc, nf, fcur, W, gtid, gsz, s_qcnt);
       // the chunks of the sub-queues, one after the other, taken from the
-      // last: a level appends the vertices it reaches roughly in ascending
-      // label order (rows are expanded in ascending order), so the highest
-      // labels, whose proposals win, propose first, and the pre-check of the
-      // packed word drops most of the later proposals before their atomic
+      // last: the vertices a row reaches are appended in ascending label
+      // order (rows are expanded in ascending order), so this way higher
+      // labels, whose proposals win, tend to propose first, and the pre-check
+      // of the packed word drops more of the later proposals before their
+      // atomic
       int64_t nchunks = 0;
       for (int q = 0; q < kNQT; ++q) nchunks += ceil_div(s_qedg[q], (int64_t)1 << P.cshift);
       for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
