@@ -191,7 +191,8 @@ SWITCH_TRAIN_GRAPHS = (
     [("kronecker", 24, 2240 + j, 16) for j in range(2)] +
     [("chung-lu", n, 5000 + 10 * j + 21, 40, 2.1)
      for n in (300_000, 1_000_000, 3_000_000) for j in range(4)] +
-    [("chung-lu", n, 5000 + 10 * j + 25, 32, 2.5) for n in (300_000, 1_000_000) for j in range(2)])
+    [("chung-lu", n, 5000 + 10 * j + 25, 32, 2.5) for n in (300_000, 1_000_000) for j in range(2)] +
+    [("chung-lu", 10_000_000, 5100 + j, 16, 2.1) for j in range(2)])
 # held-out graphs on which the decision margin is chosen: the training
 # families, and one Kronecker scale-26 and one 52.5M-vertex Chung-Lu graph of
 # other seeds than the measured ones (the sizes the switch is deployed at)
@@ -304,7 +305,8 @@ def train_switch(rb, graphgen):
         "samples": int(rows.shape[0]),
         "train_graphs": "kronecker scales 18,20,22 x 4 (32 roots each), 24 x 2 (16 roots); "
                         "chung-lu n = 0.3M, 1M, 3M x 4, exponent 2.1, mean degree 30 (40 roots "
-                        "each); n = 0.3M, 1M x 2, exponent 2.5, mean degree 10 (32 roots)",
+                        "each), 10M x 2 (16 roots); n = 0.3M, 1M x 2, exponent 2.5, mean degree "
+                        "10 (32 roots)",
         "collect_s": t_collect, "train_s": t_train, "validate_s": t_val, "epochs": 200,
         "networks": SWITCH_NETS, "network": pick[0],
         "loss_first": float(curve[0]), "loss_last": float(curve[-1]),
@@ -510,7 +512,7 @@ def chung_lu_leg(rb, graphgen, args, cache, blob):
         per_l, _ = time_roots(G, roots, depth, parent, learned, args.steps)
         gl = hmean_gteps(m_c, per_l)
         out["learned"] = {"value": gl, "unit": "GTEPS", "vs_plain": gl / gp,
-                          "network": "the one trained in this run (Kronecker scales 18-24 and Chung-Lu graphs of 0.3-3M vertices), not retrained for this graph",
+                          "network": "the one trained in this run (Kronecker scales 18-24 and Chung-Lu graphs of 0.3-10M vertices), not retrained for this graph",
                           "certified_roots": certify_roots(G, roots, depth, parent, learned)}
         log("# chung-lu: learned %.1f GTEPS (%.3fx plain)" % (gl, gl / gp))
     if not args.no_batch:
