@@ -10,7 +10,7 @@ import graphgen
 def oracle_threads():
     """Host threads for independent oracle calls: the oracle's C functions
     release the GIL (ctypes), so roots run in parallel, each single-threaded.
-    At most 16, the CPU share of a one-GPU machine."""
+    At most 16, the host CPU share of a one-GPU machine."""
     return max(1, min(16, os.cpu_count() or 1))
 
 
