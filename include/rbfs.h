@@ -50,7 +50,7 @@ extern "C" {
 #define RBFS_E_DEVICE (-4)      /* HIP runtime or kernel error */
 #define RBFS_E_STATE (-5)       /* handles in incompatible states */
 #define RBFS_E_NODEV (-6)       /* no usable GPU */
-#define RBFS_E_UNSUPPORTED (-7) /* request outside what this build supports */
+#define RBFS_E_UNSUPPORTED (-7) /* request outside what the library supports */
 
 /* ---- graph creation flags --------------------------------------------- */
 #define RBFS_HOST_PTRS 1u /* row_offsets / cols are host pointers */
