@@ -1,6 +1,7 @@
 """Host-side helpers of bench.py (no GPU): the algorithmic-bytes model of
 the search kernel, the harmonic-mean TEPS, the workload check on the stored
-traffic figure, and the refusal of more than one GPU."""
+traffic figure, the refusal of more than one GPU, and that the learned
+switch is measured on graphs it was neither trained nor validated on."""
 import importlib.util
 import os
 import subprocess
@@ -45,3 +46,19 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_switch_graphs_are_held_out(bench):
+    """The learned switch trains on Kronecker scales 18-24 and on Chung-Lu
+    graphs, picks its network on other graphs, and is measured on graphs of
+    neither set: the Kronecker scale-26 graph (seed 1026), the 52.5M-vertex
+    Chung-Lu graph (seed 4000) and the heavy-tailed 300000-vertex graph
+    (seed 9)."""
+    key = lambda spec: (spec[0].split("-52.5M")[0], spec[1], spec[2])
+    train = {key(s) for s in bench.SWITCH_TRAIN_GRAPHS}
+    valid = {key(s) for s in bench.SWITCH_VALIDATION_GRAPHS}
+    measured = {("kronecker", 26, 1026), ("chung-lu", 50_000_000, 4000),
+                ("chung-lu", 300_000, 9)}
+    assert len(train) == len(bench.SWITCH_TRAIN_GRAPHS)
+    assert not train & valid and not train & measured and not valid & measured
+    assert all(18 <= s[1] <= 24 for s in bench.SWITCH_TRAIN_GRAPHS if s[0] == "kronecker")
