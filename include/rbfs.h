@@ -498,8 +498,11 @@ int rbfs_switch_load(const float* blob, int32_t n);
  * is done once more with level d - 1 taken the other way, which samples the
  * other value of the current-direction feature (the frontiers, hence the
  * other features and the rule's later decisions, do not depend on the
- * directions).  Rows of 11 floats: features[8], ln(us TD), ln(us BU), level.
- * Writes at most `cap` rows; *count receives the number. */
+ * directions).  Searches deeper than RBFS_STATS_MAX_LEVELS levels are
+ * labelled on their first RBFS_STATS_MAX_LEVELS levels, and their schedules
+ * repeat the last of those directions after them.  Rows of 11 floats:
+ * features[8], ln(us TD), ln(us BU), level.  Writes at most `cap` rows;
+ * *count receives the number. */
 int rbfs_collect_level_samples(rbfs_graph_t* g, const int32_t* roots, int32_t k, int32_t reps,
                                int32_t alpha, int32_t beta, float* out, int32_t cap,
                                int32_t* count, void* stream);
