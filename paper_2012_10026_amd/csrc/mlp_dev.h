@@ -78,25 +78,4 @@ __device__ __forceinline__ void mlp_forward_wave(const float* __restrict__ w,
   y1 = s1;
 }
 
-// Row stride of the second layer in the search kernel's LDS copy: 36 floats
-// put the 16-byte reads of 16 lanes on distinct banks.
-constexpr int kW2Pad = 36;
-
-// The search kernel's LDS copy of a switch blob: the blob itself (layers 1
-// and 3, biases, feature range, maximum level, margin) and, separately, the
-// second layer with padded rows.  Called by every thread of a workgroup.
-__device__ __forceinline__ void load_switch_blob_lds(float* __restrict__ blob,
-                                                     float* __restrict__ w2,
-                                                     const float* __restrict__ src,
-                                                     int nthreads) {
-  for (int i = threadIdx.x; i < kSwitchBlob; i += nthreads) {
-    const float x = src[i];
-    blob[i] = x;
-    if (i >= kOffW2 && i < kOffB2) {
-      const int r = i - kOffW2;
-      w2[(r / kMlpHid) * kW2Pad + r % kMlpHid] = x;
-    }
-  }
-}
-
 }  // namespace rbfs
