@@ -1,7 +1,8 @@
 """Host-side helpers of bench.py (no GPU): the algorithmic-bytes model of
 the search kernel, the harmonic-mean TEPS, the workload check on the stored
 traffic figure, the refusal of more than one GPU, and that the learned
-switch is measured on graphs it was neither trained nor validated on."""
+switch is measured on graphs it was neither trained nor validated on, and
+that the committed traffic profile belongs to the committed kernel sources."""
 import importlib.util
 import os
 import subprocess
@@ -62,3 +63,11 @@ def test_switch_graphs_are_held_out(bench):
     assert len(train) == len(bench.SWITCH_TRAIN_GRAPHS)
     assert not train & valid and not train & measured and not valid & measured
     assert all(18 <= s[1] <= 24 for s in bench.SWITCH_TRAIN_GRAPHS if s[0] == "kronecker")
+
+
+def test_committed_traffic_profile_matches_the_sources(bench):
+    """The committed traffic figure of the search kernel was taken from the
+    committed kernel sources (their digest matches), so bench.py reports it."""
+    import json
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic_bfs_persistent_kernel.json")))
+    assert bench.measured_traffic(rec["workload"]) == rec["traffic_bytes_per_launch"]
