@@ -100,3 +100,22 @@ def test_set_allocator_arguments_without_device():
     rb.set_allocator(before)
     with pytest.raises(ValueError):
         rb.set_allocator("cuda")
+
+
+def test_switch_blob_layout_matches_the_oracle():
+    """make_switch_blob writes the weights, the training feature range, the
+    largest training level and the margin where the oracle's decision reads
+    them (both follow the 1428-float layout of rbfs_switch_load)."""
+    from oracle import mlp
+    assert rb.SWITCH_BLOB == mlp.BLOB == 1428 and rb.MLP_PARAMS == mlp.NPARAMS == 1410
+    rng = np.random.default_rng(3)
+    w = rng.standard_normal(rb.MLP_PARAMS).astype(np.float32)
+    rows = rng.uniform(-1, 1, size=(50, 11)).astype(np.float32)
+    rows[:, 10] = rng.integers(1, 9, size=50)
+    blob = rb.make_switch_blob(w, rows, margin=0.3)
+    assert np.array_equal(blob[:mlp.NPARAMS], w)
+    assert np.array_equal(blob[mlp.NPARAMS:mlp.NPARAMS + 8], rows[:, :8].min(axis=0))
+    assert np.array_equal(blob[mlp.NPARAMS + 8:mlp.NPARAMS + 16], rows[:, :8].max(axis=0))
+    assert blob[mlp.NPARAMS + 16] == rows[:, 10].max()
+    assert blob[mlp.BLOB - 1] == np.float32(0.3)
+    assert rb.make_switch_blob(w, rows)[mlp.BLOB - 1] == np.float32(0.1)  # the default
